@@ -1,0 +1,184 @@
+/*
+ * lsw.h -- C ABI of the L-sweeps Helmholtz library for MI355X (gfx950).
+ *
+ * Solves the PML-truncated Helmholtz system A u = b (eq. LS, Sec. 1.1 and App. A of
+ * Taus, Zepeda-Nunez, Hewett, Demanet, "L-Sweeps", arXiv:1909.01467) with flexible
+ * GMRES right-preconditioned by the L-sweeps preconditioner M ~ A^-1 (Sec. 3,
+ * eq. PrecLS; Alg. Scenario3 of App. C) over a q x r checkerboard domain
+ * decomposition (CDD, Sec. 2.1-2.2).  Every subdomain problem is factorised once
+ * (Phase 2 of Sec. 3) and solved up to nine times per preconditioner application.
+ *
+ * Discretisation (App. A): per axis n bulk points at x = h..n h and n_pml PML points
+ * on each side; cubic PML profile sigma = (C/delta)(dist/delta)^3, delta = n_pml h,
+ * alpha = 1/(1 + i sigma/omega); symmetric 5-point form
+ *   -div(Lambda grad u) - omega^2 m/(alpha_1 alpha_2) u = b,  Lambda = diag(s1, s2),
+ *   s1 = alpha_1/alpha_2, s2 = alpha_2/alpha_1, coefficients at half points,
+ * homogeneous Dirichlet data one point beyond the extended grid.  A is complex
+ * symmetric (A = A^T), which the adjoint solve uses.
+ *
+ * Conventions shared by every entry point:
+ *  - Vectors live on the extended grid of N = N_x * N_y points (N_k = n_k + 2 n_pml_k),
+ *    x fastest.  Complex values are interleaved (re, im) doubles, the layout of
+ *    torch.complex128.  Several right-hand sides are stored one after the other:
+ *    element (rhs, p) is at rhs * N + p.
+ *  - Pointers named d_* are DEVICE pointers owned by the caller; they must stay valid
+ *    until the call returns (all calls synchronise their stream before returning,
+ *    except where stated).  Pointers named h_* are host pointers.
+ *  - All device work is ordered on the stream given in lsw_opts_t.
+ *  - Return value: LSW_OK (0) or a negative lsw_status; nothing aborts and no C++
+ *    exception crosses the ABI.  lsw_last_error() describes the last failure.
+ *  - A handle must not be used by two threads at once.  Different handles are
+ *    independent.
+ */
+#ifndef LSW_H
+#define LSW_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lsw_plan* lsw_handle_t;
+
+typedef enum {
+    LSW_OK = 0,
+    LSW_EINVAL = -1,     /* invalid argument or geometry */
+    LSW_ENOMEM = -2,     /* device allocation failed */
+    LSW_EHIP = -3,       /* a HIP runtime call failed */
+    LSW_ESINGULAR = -4,  /* zero pivot while factorising a subdomain block */
+    LSW_ENAN = -5,       /* non-finite value in the input data */
+    LSW_ENOCONV = -6     /* GMRES reached maxit before tol (u holds the last iterate) */
+} lsw_status;
+
+typedef enum {
+    LSW_FP64 = 0,        /* complex128 factors, sweeps and Krylov */
+    LSW_MIXED = 1        /* complex64 factors and sweeps (FP32 accumulation), FP64 Krylov */
+} lsw_precision;
+
+typedef struct {
+    int dim;             /* 2 (the only dimension built so far) */
+    int n[3];            /* bulk points per axis (x, y, z) */
+    int n_pml[3];        /* global PML points per side, per axis */
+} lsw_grid_t;
+
+typedef struct {
+    int q;               /* CDD rows (groups along y, row 0 at the bottom) */
+    int r;               /* CDD columns (groups along x, column 0 at the left) */
+} lsw_cdd_t;
+
+typedef struct {
+    double C;            /* absorption constant of the cubic profile (App. A); <= 0 selects 4 ln(omega) */
+    int n_pml_local;     /* PML points of each interior side of a local problem; < 0 selects n_pml[x] */
+} lsw_pml_t;
+
+typedef struct {
+    int precision;       /* lsw_precision */
+    int restart;         /* FGMRES restart length (default 50 when <= 0) */
+    int maxit;           /* maximum preconditioner applications per solve (default 500 when <= 0) */
+    double tol;          /* relative true-residual tolerance ||b - A u|| <= tol ||b|| (default 1e-6 when <= 0) */
+    int nrhs_max;        /* largest nrhs any later call will pass (default 1 when <= 0) */
+    void* stream;        /* hipStream_t for all device work (NULL = default stream) */
+} lsw_opts_t;
+
+typedef struct {
+    int iterations;      /* preconditioner applications used */
+    int converged;       /* 1 if the true relative residual reached tol */
+    double relres;       /* final true relative residual ||b - A u|| / ||b|| (FP64) */
+} lsw_rhs_info_t;
+
+typedef struct {
+    lsw_rhs_info_t* h_rhs;   /* host array of nrhs entries filled by solve/adjoint (may be NULL) */
+    double* h_history;       /* host array [nrhs][history_len]: residual estimate after each iteration (may be NULL) */
+    int history_len;
+    double t_solve_ms;       /* wall time of the call (stream-synchronised) */
+    int applies;             /* preconditioner applications (batched over the active right-hand sides) */
+} lsw_info_t;
+
+typedef struct {
+    int q, r, n_subdomains;
+    int W_max, H_max;            /* largest local window (points along x / y) */
+    long long N;                 /* extended-grid points */
+    long long factor_elems;      /* complex entries of all stored block inverses G_k */
+    int factor_elem_bytes;       /* 8 (complex64) or 16 (complex128) */
+    int solves_per_apply;        /* (3q-2)(3r-2)-type count of local solves per application */
+    int fronts_per_apply;        /* dependent launch steps per application */
+    double apply_G_bytes;        /* algorithmic bytes of G read by one application (one RHS) */
+    double factor_flops;         /* real flops of the block factorisation */
+    double t_setup_ms, t_factor_ms;
+    double last_apply_ms;        /* device time of the most recent lsw_apply (events) */
+    double last_sweep_ms;        /* ... of its local-solve fronts only (without the final z assembly) */
+} lsw_stats_t;
+
+/*
+ * lsw_setup -- Setup and Factorise phases (Sec. 3, Phases 1-2).
+ *   out    : receives the new handle (host pointer to a handle).
+ *   d_m    : DEVICE, N doubles: squared slowness m = 1/c^2 on the EXTENDED grid
+ *            (the caller extends the bulk medium into the PML, Sec. 1.1).  Read only
+ *            during the call.
+ *   omega  : angular frequency (> 0).
+ *   h      : grid step (> 0); the bulk interval of axis k is [0, (n_k + 1) h].
+ *   grid, cdd, pml, opts : HOST pointers to the structures above (opts may be NULL).
+ * Builds the CDD (bulk points split as evenly as possible, the first n mod q groups
+ * one larger, edge groups owning the global PML), the local problems (Omega_ij plus
+ * 2 overlap lines and n_pml_local PML lines on every interior side, Sec. 2.2) and
+ * factorises every local matrix by block-tridiagonal LU along y.
+ * Errors: LSW_EINVAL (dim != 2, sizes, a window that does not fit the grid),
+ * LSW_ENAN (non-finite m), LSW_ENOMEM, LSW_EHIP, LSW_ESINGULAR.  On error *out is NULL
+ * and nothing is leaked.
+ */
+int lsw_setup(lsw_handle_t* out, const double* d_m, double omega, double h,
+              const lsw_grid_t* grid, const lsw_cdd_t* cdd, const lsw_pml_t* pml,
+              const lsw_opts_t* opts);
+
+/*
+ * lsw_apply -- one application z = M^-1 r of the L-sweeps preconditioner
+ * (Alg. Scenario3: stage 1, four cardinal sweeps, four diagonal sweeps).
+ *   d_r : DEVICE, nrhs*N complex128 (read only).   d_z : DEVICE, nrhs*N complex128 (written).
+ *   1 <= nrhs <= nrhs_max.  In LSW_MIXED the sweeps run in complex64.
+ */
+int lsw_apply(lsw_handle_t handle, const double* d_r, double* d_z, int nrhs);
+
+/*
+ * lsw_solve -- FGMRES(restart) for A u = f, right-preconditioned by M (Sec. 3, Phase 3).
+ *   d_f : DEVICE, nrhs*N complex128 right-hand sides b (read only).
+ *   d_u : DEVICE, nrhs*N complex128, in: initial guess (zeros reproduce the paper's
+ *         setting), out: solution.  Stops when ||b - A u||_2 <= tol ||b||_2 (true
+ *         residual, FP64) or after maxit applications (then LSW_ENOCONV, u = last iterate).
+ *   info: HOST, optional (may be NULL).
+ * Each right-hand side runs its own Krylov process; applications are batched.
+ */
+int lsw_solve(lsw_handle_t handle, const double* d_f, double* d_u, int nrhs, lsw_info_t* info);
+
+/*
+ * lsw_adjoint -- solves A^H v = g with the same factors: since A = A^T,
+ * v = conj(A^-1 conj(g)).  Arguments as lsw_solve (d_v in/out, initial guess).
+ */
+int lsw_adjoint(lsw_handle_t handle, const double* d_g, double* d_v, int nrhs, lsw_info_t* info);
+
+/*
+ * lsw_matvec -- y = A x in FP64 (the global 5-point operator of App. A).
+ *   d_x, d_y : DEVICE, nrhs*N complex128; may not alias.
+ */
+int lsw_matvec(lsw_handle_t handle, const double* d_x, double* d_y, int nrhs);
+
+/*
+ * lsw_mass_gradient -- FWI gradient term  d_grad[p] += omega^2 Re( sum_s lam_s[p] w[p] u_s[p] ),
+ * w = 1/(alpha_1 alpha_2) (the weight of m in the mass term of App. A), summed over nrhs
+ * right-hand sides.  d_lam, d_u : DEVICE nrhs*N complex128; d_grad : DEVICE N doubles (accumulated).
+ */
+int lsw_mass_gradient(lsw_handle_t handle, const double* d_lam, const double* d_u, int nrhs,
+                      double* d_grad);
+
+/* lsw_query -- fills *stats (HOST pointer) with sizes, algorithmic work and timings. */
+int lsw_query(lsw_handle_t handle, lsw_stats_t* stats);
+
+/* lsw_last_error -- text of the last error on this handle (or of the last failed setup
+ * when handle is NULL).  The string stays valid until the next call on the handle. */
+const char* lsw_last_error(lsw_handle_t handle);
+
+/* lsw_destroy -- frees every device and host resource of the handle.  NULL is accepted. */
+int lsw_destroy(lsw_handle_t handle);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LSW_H */

@@ -1,0 +1,115 @@
+// Shared device/host definitions of the L-sweeps library: complex arithmetic, the
+// per-subdomain and per-solve descriptors that drive the batched kernels, and the
+// kernel launch interface.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace lsw {
+
+// ---------------------------------------------------------------- complex numbers
+template <typename T>
+struct cx {
+    T re, im;
+};
+
+template <typename T>
+__host__ __device__ inline cx<T> mk(T re, T im) { return cx<T>{re, im}; }
+template <typename T>
+__host__ __device__ inline cx<T> operator+(cx<T> a, cx<T> b) { return {a.re + b.re, a.im + b.im}; }
+template <typename T>
+__host__ __device__ inline cx<T> operator-(cx<T> a, cx<T> b) { return {a.re - b.re, a.im - b.im}; }
+template <typename T>
+__host__ __device__ inline cx<T> operator-(cx<T> a) { return {-a.re, -a.im}; }
+template <typename T>
+__host__ __device__ inline cx<T> operator*(cx<T> a, cx<T> b) {
+    return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+template <typename T>
+__host__ __device__ inline cx<T> operator*(T s, cx<T> a) { return {s * a.re, s * a.im}; }
+template <typename T>
+__host__ __device__ inline cx<T> conj(cx<T> a) { return {a.re, -a.im}; }
+template <typename T>
+__host__ __device__ inline T abs2(cx<T> a) { return a.re * a.re + a.im * a.im; }
+template <typename T>
+__host__ __device__ inline cx<T> cinv(cx<T> a) {
+    T d = abs2(a);
+    return {a.re / d, -a.im / d};
+}
+// acc + a*b
+template <typename T>
+__host__ __device__ inline cx<T> fma(cx<T> acc, cx<T> a, cx<T> b) {
+    acc.re = acc.re + a.re * b.re - a.im * b.im;
+    acc.im = acc.im + a.re * b.im + a.im * b.re;
+    return acc;
+}
+template <typename T, typename U>
+__host__ __device__ inline cx<T> cvt(cx<U> a) { return {static_cast<T>(a.re), static_cast<T>(a.im)}; }
+
+using c64 = cx<float>;
+using c128 = cx<double>;
+
+// ---------------------------------------------------------------- plan descriptors
+
+// Sides of a subdomain; trace lines are ordered by increasing grid index.
+enum Side : int { SIDE_B = 0, SIDE_R = 1, SIDE_T = 2, SIDE_L = 3 };
+
+// What a local solve computes (its right-hand side and receiving region chi).
+enum Kind : int {
+    KIND_STAGE1 = 0,  // r restricted to Omega_ij (Alg. computeLocSol)
+    KIND_B = 1,       // polarized from the bottom trace, chi = rows >= lo   (up sweep)
+    KIND_T = 2,       // from the top trace, chi = rows < hi                 (down sweep)
+    KIND_L = 3,       // from the left trace, chi = cols >= lo               (right sweep)
+    KIND_R = 4,       // from the right trace, chi = cols < hi               (left sweep)
+    KIND_BL = 5,      // L-shaped, bottom + left legs, upper-right quadrant  (BL->TR sweep)
+    KIND_TR = 6,      // top + right legs, lower-left quadrant               (TR->BL sweep)
+    KIND_BR = 7,      // bottom + right legs, upper-left quadrant            (BR->TL sweep)
+    KIND_TL = 8       // top + left legs, lower-right quadrant               (TL->BR sweep)
+};
+
+// One local problem (window of one CDD cell).
+struct SubDesc {
+    int W, H;            // window points along x and y
+    int wx0, wy0;        // window origin on the extended grid
+    int r0, r1, c0, c1;  // Omega_ij inside the window: rows [r0, r1), cols [c0, c1)
+    int i, j;            // CDD row / column
+    int tx, ty;          // offsets of this window's x and y tables in the table pool
+    long long g_off;     // offset (elements) of G_0 in the factor pool; G_k at g_off + k*W*W
+};
+
+// Layout of one axis table of a window with P points (offset t in the table pool):
+//   t + a        : 1/alpha at integer point a            (a = 0..P-1)
+//   t + P + a    : alpha at half point a - 1/2           (a = 0..P)
+// so the coupling of points a and a+1 uses index t + P + a + 1.
+
+static constexpr int kMaxOut = 4;
+
+// One local solve inside a front.  Trace offsets are element offsets into the trace
+// pool of right-hand side 0 (add rhs * trace_stride).
+struct SolveDesc {
+    int sub;                     // SubDesc index
+    int kind;                    // Kind
+    int zpart;                   // which per-sweep accumulator receives U on Omega_ij
+    int kf0;                     // first block row with a nonzero right-hand side
+    int kb0;                     // last block row (going down) whose solution is needed
+    int nout;                    // number of trace outputs
+    long long in_h;              // incoming horizontal trace (2 x W), -1 if none
+    long long in_v;              // incoming vertical trace (2 x H), -1 if none
+    long long out_off[kMaxOut];  // output trace offsets
+    int out_side[kMaxOut];       // Side of each output
+    int out_acc[kMaxOut];        // 1: accumulate (+=), 0: assign (=)
+};
+
+// Everything a kernel needs to evaluate the local or global 5-point coefficients.
+struct Geometry {
+    const c128* tab;      // table pool
+    const double* m;      // squared slowness on the extended grid, [y][x]
+    int Nx, Ny;           // extended grid
+    double h, omega;
+    int gtx, gty;         // offsets of the global x and y tables
+};
+
+}  // namespace lsw

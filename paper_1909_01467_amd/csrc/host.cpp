@@ -1,0 +1,898 @@
+// Host runtime and C ABI of the L-sweeps library.
+//
+//  - CDD partition and local windows (Sec. 2.1-2.2): bulk points split as evenly as
+//    possible, edge groups owning the global PML, windows grown by 2 overlap lines and
+//    n_pml_local PML lines on every interior side.
+//  - PML tables (App. A): 1/alpha at integer points and alpha at half points, global
+//    and per window (global sigma plus the local cubic layers).
+//  - Front schedule of Alg. Scenario3 (App. C): stage 1; the four cardinal sweeps run
+//    together (each reads only stage-1 traces and writes its own arrays); the four
+//    diagonal sweeps run together (each reads only cardinal outputs), one anti-diagonal
+//    per front.  Every front is one launch of the batched local-solve kernel.
+//  - Flexible GMRES (Sec. 3, Phase 3), right preconditioned, CGS2 on the device in FP64,
+//    Givens least squares on the host, true-residual stop test.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <complex>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "launch.h"
+#include "lsw.h"
+
+using namespace lsw;
+using cd = std::complex<double>;
+
+namespace {
+
+enum HArr { H_B_RUN = 0, H_T_RUN, H_B_LF, H_T_LF, H_B_RT, H_T_RT, H_COUNT };
+enum VArr { V_L_RUN = 0, V_R_RUN, V_R_UP, V_L_UP, V_R_DN, V_L_DN, V_COUNT };
+
+struct Front {
+    int offset, count;
+};
+
+}  // namespace
+
+struct lsw_plan {
+    // problem
+    int nx = 0, ny = 0, px = 0, py = 0, q = 0, r = 0, pl = 0, e = 0;
+    int Nx = 0, Ny = 0;
+    size_t N = 0;
+    double h = 0, omega = 0, C = 0;
+    int precision = LSW_FP64, restart = 50, maxit = 500, nrhs_max = 1;
+    double tol = 1e-6;
+    hipStream_t stream = nullptr;
+    // geometry
+    std::vector<int> xlo, xhi, ylo, yhi, xw0, xw1, yw0, yw1;
+    std::vector<SubDesc> subs;
+    std::vector<SolveDesc> descs;
+    std::vector<Front> fronts;
+    int Wmax = 0, Hmax = 0, max_front = 0;
+    size_t HT = 0, VT = 0;
+    std::vector<size_t> hbase, vbase;
+    // device
+    double* d_m = nullptr;
+    c128* d_tab = nullptr;
+    SubDesc* d_subs = nullptr;
+    SolveDesc* d_descs = nullptr;
+    void* d_G = nullptr;
+    size_t G_elems = 0;
+    void* d_traces = nullptr;
+    size_t trace_stride = 0;
+    void* d_zpart = nullptr;
+    size_t zpart_stride = 0;
+    void* d_Y = nullptr;
+    size_t Y_stride = 0;
+    int* d_xgroup = nullptr;
+    int* d_ygroup = nullptr;
+    int* d_status = nullptr;
+    Geometry geo{};
+    // Krylov workspace
+    c128* d_V = nullptr;
+    c128* d_Z = nullptr;
+    c128* d_w = nullptr;
+    c128* d_partial = nullptr;
+    c128* d_hbuf = nullptr;
+    c128* d_coef = nullptr;
+    c128* d_tmp1 = nullptr;
+    c128* d_tmp2 = nullptr;
+    double* d_scale = nullptr;
+    int* d_active = nullptr;
+    c128* h_hbuf = nullptr;   // pinned
+    double* h_scale = nullptr;
+    int* h_active = nullptr;
+    c128* h_coef = nullptr;
+    int nblk = 256;
+    // bookkeeping
+    std::vector<void*> allocs;
+    std::string err;
+    double t_setup_ms = 0, t_factor_ms = 0, last_apply_ms = 0, last_sweep_ms = 0;
+    double apply_G_bytes = 0, factor_flops = 0;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr, evm = nullptr;
+};
+
+namespace {
+
+std::string g_setup_error;
+
+#define HIPCK(plan, expr)                                                        \
+    do {                                                                         \
+        hipError_t e_ = (expr);                                                  \
+        if (e_ != hipSuccess) {                                                  \
+            (plan)->err = std::string(#expr) + ": " + hipGetErrorString(e_);     \
+            return LSW_EHIP;                                                     \
+        }                                                                        \
+    } while (0)
+
+template <typename T>
+int dalloc(lsw_plan* p, T** out, size_t count) {
+    void* ptr = nullptr;
+    if (count == 0) count = 1;
+    hipError_t e = hipMalloc(&ptr, count * sizeof(T));
+    if (e != hipSuccess) {
+        p->err = "hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes failed: " + hipGetErrorString(e);
+        return LSW_ENOMEM;
+    }
+    p->allocs.push_back(ptr);
+    *out = static_cast<T*>(ptr);
+    return LSW_OK;
+}
+
+void free_plan(lsw_plan* p) {
+    if (!p) return;
+    for (void* a : p->allocs) (void)hipFree(a);
+    if (p->h_hbuf) (void)hipHostFree(p->h_hbuf);
+    if (p->h_scale) (void)hipHostFree(p->h_scale);
+    if (p->h_active) (void)hipHostFree(p->h_active);
+    if (p->h_coef) (void)hipHostFree(p->h_coef);
+    if (p->ev0) (void)hipEventDestroy(p->ev0);
+    if (p->ev1) (void)hipEventDestroy(p->ev1);
+    if (p->evm) (void)hipEventDestroy(p->evm);
+    delete p;
+}
+
+// ---------------------------------------------------------------- geometry
+void split(int n_bulk, int n_pml, int groups, std::vector<int>& lo, std::vector<int>& hi) {
+    lo.assign(groups, 0);
+    hi.assign(groups, 0);
+    int start = n_pml;
+    for (int g = 0; g < groups; ++g) {
+        const int size = n_bulk / groups + (g < n_bulk % groups ? 1 : 0);
+        lo[g] = (g == 0) ? 0 : start;
+        start += size;
+        hi[g] = start + (g == groups - 1 ? n_pml : 0);
+    }
+}
+
+double sigma_cubic(double dist, double delta, double C) {
+    if (delta <= 0.0 || dist <= 0.0) return 0.0;
+    const double t = dist / delta;
+    return (C / delta) * t * t * t;
+}
+
+// coordinate of integer point a (2a even) or half point a - 1/2 (pass 2a - 1) on an axis
+double coord2(int twice_a, int n_pml, double h) { return (0.5 * twice_a - n_pml + 1) * h; }
+
+// 1/alpha and alpha for sigma at coordinate x on axis (n, p), plus optional local layers
+struct AxisLayers {
+    double L, delta;          // bulk [0, L], global layer width
+    bool left, right;         // local layers present
+    double xs_left, xs_right; // layer starts (sigma = 0 there)
+    double delta_loc;
+};
+
+double sigma_at(const AxisLayers& a, double x, double C) {
+    double s = 0.0;
+    if (a.delta > 0) s += sigma_cubic(std::max(0.0, std::max(-x, x - a.L)), a.delta, C);
+    if (a.left) s += sigma_cubic(a.xs_left - x, a.delta_loc, C);
+    if (a.right) s += sigma_cubic(x - a.xs_right, a.delta_loc, C);
+    return s;
+}
+
+// append the table of points [w0, w1) of an axis to the pool; returns its offset
+int append_table(std::vector<c128>& pool, int w0, int w1, int n_pml, double h, double omega, double C,
+                 const AxisLayers& lay) {
+    const int off = (int)pool.size();
+    for (int a = w0; a < w1; ++a) {
+        const double s = sigma_at(lay, coord2(2 * a, n_pml, h), C);
+        pool.push_back(c128{1.0, s / omega});                     // 1/alpha = 1 + i sigma/omega
+    }
+    for (int a = w0; a <= w1; ++a) {
+        const double s = sigma_at(lay, coord2(2 * a - 1, n_pml, h), C);
+        const cd alpha = 1.0 / cd(1.0, s / omega);
+        pool.push_back(c128{alpha.real(), alpha.imag()});
+    }
+    return off;
+}
+
+void add_out(SolveDesc& d, long long off, int side, int acc) {
+    d.out_off[d.nout] = off;
+    d.out_side[d.nout] = side;
+    d.out_acc[d.nout] = acc;
+    d.nout++;
+}
+
+SolveDesc blank(int sub, int kind, int zpart, int kf0, int kb0) {
+    SolveDesc d;
+    std::memset(&d, 0, sizeof(d));
+    d.sub = sub;
+    d.kind = kind;
+    d.zpart = zpart;
+    d.kf0 = kf0;
+    d.kb0 = kb0;
+    d.in_h = -1;
+    d.in_v = -1;
+    return d;
+}
+
+void build_schedule(lsw_plan* p) {
+    const int q = p->q, r = p->r;
+    auto sid = [&](int i, int j) { return i * r + j; };
+    auto offH = [&](int a, int i, int j) { return (long long)(a * p->HT + p->hbase[sid(i, j)]); };
+    auto offV = [&](int b, int i, int j) {
+        return (long long)(H_COUNT * p->HT + b * p->VT + p->vbase[sid(i, j)]);
+    };
+    p->descs.clear();
+    p->fronts.clear();
+    auto push_front = [&](std::vector<SolveDesc>& f) {
+        if (f.empty()) return;
+        p->fronts.push_back(Front{(int)p->descs.size(), (int)f.size()});
+        p->descs.insert(p->descs.end(), f.begin(), f.end());
+        p->max_front = std::max(p->max_front, (int)f.size());
+    };
+    std::vector<SolveDesc> f;
+    // stage 1 (addLocSols): all subdomains
+    for (int i = 0; i < q; ++i)
+        for (int j = 0; j < r; ++j) {
+            const SubDesc& s = p->subs[sid(i, j)];
+            SolveDesc d = blank(sid(i, j), KIND_STAGE1, 0, s.r0, 0);
+            if (i > 0) add_out(d, offH(H_B_RUN, i, j), SIDE_B, 0);
+            if (i < q - 1) add_out(d, offH(H_T_RUN, i, j), SIDE_T, 0);
+            if (j > 0) add_out(d, offV(V_L_RUN, i, j), SIDE_L, 0);
+            if (j < r - 1) add_out(d, offV(V_R_RUN, i, j), SIDE_R, 0);
+            f.push_back(d);
+        }
+    push_front(f);
+    // cardinal sweeps, one row / column step per front
+    const int nc = std::max(q, r) - 1;
+    for (int t = 0; t < nc; ++t) {
+        f.clear();
+        if (t + 1 <= q - 1) {  // up: row i = t+1, incoming bottom trace T_run(i-1, j)
+            const int i = t + 1;
+            for (int j = 0; j < r; ++j) {
+                const SubDesc& s = p->subs[sid(i, j)];
+                SolveDesc d = blank(sid(i, j), KIND_B, 1, s.r0 - 1, s.r0);
+                d.in_h = offH(H_T_RUN, i - 1, j);
+                if (i < q - 1) add_out(d, offH(H_T_RUN, i, j), SIDE_T, 1);
+                if (j < r - 1) add_out(d, offV(V_R_UP, i, j), SIDE_R, 0);
+                if (j > 0) add_out(d, offV(V_L_UP, i, j), SIDE_L, 0);
+                f.push_back(d);
+            }
+        }
+        if (q - 2 - t >= 0) {  // down: row i = q-2-t, incoming top trace B_run(i+1, j)
+            const int i = q - 2 - t;
+            for (int j = 0; j < r; ++j) {
+                const SubDesc& s = p->subs[sid(i, j)];
+                SolveDesc d = blank(sid(i, j), KIND_T, 2, s.r1 - 1, 0);
+                d.in_h = offH(H_B_RUN, i + 1, j);
+                if (i > 0) add_out(d, offH(H_B_RUN, i, j), SIDE_B, 1);
+                if (j < r - 1) add_out(d, offV(V_R_DN, i, j), SIDE_R, 0);
+                if (j > 0) add_out(d, offV(V_L_DN, i, j), SIDE_L, 0);
+                f.push_back(d);
+            }
+        }
+        if (t + 1 <= r - 1) {  // right: column j = t+1, incoming left trace R_run(i, j-1)
+            const int j = t + 1;
+            for (int i = 0; i < q; ++i) {
+                SolveDesc d = blank(sid(i, j), KIND_L, 3, 0, 0);
+                d.in_v = offV(V_R_RUN, i, j - 1);
+                if (j < r - 1) add_out(d, offV(V_R_RUN, i, j), SIDE_R, 1);
+                if (i > 0) add_out(d, offH(H_B_RT, i, j), SIDE_B, 0);
+                if (i < q - 1) add_out(d, offH(H_T_RT, i, j), SIDE_T, 0);
+                f.push_back(d);
+            }
+        }
+        if (r - 2 - t >= 0) {  // left: column j = r-2-t, incoming right trace L_run(i, j+1)
+            const int j = r - 2 - t;
+            for (int i = 0; i < q; ++i) {
+                SolveDesc d = blank(sid(i, j), KIND_R, 4, 0, 0);
+                d.in_v = offV(V_L_RUN, i, j + 1);
+                if (j > 0) add_out(d, offV(V_L_RUN, i, j), SIDE_L, 1);
+                if (i > 0) add_out(d, offH(H_B_LF, i, j), SIDE_B, 0);
+                if (i < q - 1) add_out(d, offH(H_T_LF, i, j), SIDE_T, 0);
+                f.push_back(d);
+            }
+        }
+        push_front(f);
+    }
+    // diagonal sweeps, one anti-diagonal per front, inputs bound as in Alg. Scenario3
+    const int nd = (q - 1) + (r - 1) - 1;
+    for (int dd = 0; dd < nd; ++dd) {
+        f.clear();
+        for (int i = 0; i < q; ++i)
+            for (int j = 0; j < r; ++j) {
+                const SubDesc& s = p->subs[sid(i, j)];
+                if (i >= 1 && j >= 1 && (i - 1) + (j - 1) == dd) {  // BL->TR (R^up, T^right)
+                    SolveDesc d = blank(sid(i, j), KIND_BL, 5, s.r0 - 1, s.r0);
+                    d.in_h = offH(H_T_RT, i - 1, j);
+                    d.in_v = offV(V_R_UP, i, j - 1);
+                    if (j < r - 1) add_out(d, offV(V_R_UP, i, j), SIDE_R, 1);
+                    if (i < q - 1) add_out(d, offH(H_T_RT, i, j), SIDE_T, 1);
+                    f.push_back(d);
+                }
+                if (i <= q - 2 && j <= r - 2 && (q - 2 - i) + (r - 2 - j) == dd) {  // TR->BL (L^down, B^left)
+                    SolveDesc d = blank(sid(i, j), KIND_TR, 6, 0, 0);
+                    d.in_h = offH(H_B_LF, i + 1, j);
+                    d.in_v = offV(V_L_DN, i, j + 1);
+                    if (j > 0) add_out(d, offV(V_L_DN, i, j), SIDE_L, 1);
+                    if (i > 0) add_out(d, offH(H_B_LF, i, j), SIDE_B, 1);
+                    f.push_back(d);
+                }
+                if (i >= 1 && j <= r - 2 && (i - 1) + (r - 2 - j) == dd) {  // BR->TL (L^up, T^left)
+                    SolveDesc d = blank(sid(i, j), KIND_BR, 7, s.r0 - 1, s.r0);
+                    d.in_h = offH(H_T_LF, i - 1, j);
+                    d.in_v = offV(V_L_UP, i, j + 1);
+                    if (j > 0) add_out(d, offV(V_L_UP, i, j), SIDE_L, 1);
+                    if (i < q - 1) add_out(d, offH(H_T_LF, i, j), SIDE_T, 1);
+                    f.push_back(d);
+                }
+                if (i <= q - 2 && j >= 1 && (q - 2 - i) + (j - 1) == dd) {  // TL->BR (R^down, B^right)
+                    SolveDesc d = blank(sid(i, j), KIND_TL, 8, 0, 0);
+                    d.in_h = offH(H_B_RT, i + 1, j);
+                    d.in_v = offV(V_R_DN, i, j - 1);
+                    if (j < r - 1) add_out(d, offV(V_R_DN, i, j), SIDE_R, 1);
+                    if (i > 0) add_out(d, offH(H_B_RT, i, j), SIDE_B, 1);
+                    f.push_back(d);
+                }
+            }
+        push_front(f);
+    }
+}
+
+int fail(lsw_plan* p, int code, const std::string& msg) {
+    p->err = msg;
+    return code;
+}
+
+// ---------------------------------------------------------------- the preconditioner
+int apply_impl(lsw_plan* p, const c128* d_r, c128* d_z, int nrhs, bool timed) {
+    const bool c64 = p->precision == LSW_MIXED;
+    SweepArgs a{};
+    a.subs = p->d_subs;
+    a.geo = p->geo;
+    a.G = p->d_G;
+    a.traces = p->d_traces;
+    a.trace_stride = p->trace_stride;
+    a.Y = p->d_Y;
+    a.Y_stride = p->Y_stride;
+    a.zpart = p->d_zpart;
+    a.zpart_stride = p->zpart_stride;
+    a.r = d_r;
+    if (timed) HIPCK(p, hipEventRecord(p->ev0, p->stream));
+    for (const Front& f : p->fronts) {
+        a.descs = p->d_descs + f.offset;
+        HIPCK(p, launch_sweep(a, f.count, nrhs, p->Wmax, c64, p->stream));
+    }
+    if (timed) HIPCK(p, hipEventRecord(p->evm, p->stream));
+    ZsumArgs zs{p->d_zpart, p->zpart_stride, d_z, p->d_xgroup, p->d_ygroup, p->Nx, p->Ny, p->q, p->r};
+    HIPCK(p, launch_zsum(zs, nrhs, c64, p->stream));
+    if (timed) HIPCK(p, hipEventRecord(p->ev1, p->stream));
+    return LSW_OK;
+}
+
+int matvec_impl(lsw_plan* p, const c128* x, c128* y, const c128* b, int nrhs) {
+    MatvecArgs a{p->geo, x, y, b};
+    HIPCK(p, launch_matvec(a, nrhs, p->stream));
+    return LSW_OK;
+}
+
+// out[rhs*ostride + l] = <V_l, w>  for l < nv
+int dots_impl(lsw_plan* p, const c128* V, size_t vl, size_t vr, const c128* w, size_t ws, int nv, int nrhs,
+              c128* out, int ostride) {
+    DotsArgs a{V, vl, vr, w, ws, p->N, nv, p->nblk, p->d_partial};
+    HIPCK(p, launch_dots(a, nrhs, out, ostride, 0, p->stream));
+    return LSW_OK;
+}
+
+// ---------------------------------------------------------------- FGMRES
+int solve_impl(lsw_plan* p, const c128* d_b, c128* d_x, int nrhs, lsw_info_t* info) {
+    const auto t0 = std::chrono::steady_clock::now();
+    const int m = p->restart;
+    const size_t N = p->N;
+    const int HS = 2 * (m + 1) + 1;           // host buffer stride per rhs: h1 | h2 | norm
+    const size_t vl = (size_t)nrhs * N;       // basis stride between Krylov vectors
+    int rc;
+    // ||b||
+    if ((rc = dots_impl(p, d_b, 0, N, d_b, N, 1, nrhs, p->d_hbuf, HS)) != LSW_OK) return rc;
+    HIPCK(p, hipMemcpyAsync(p->h_hbuf, p->d_hbuf, sizeof(c128) * HS * nrhs, hipMemcpyDeviceToHost, p->stream));
+    HIPCK(p, hipStreamSynchronize(p->stream));
+    std::vector<double> bnorm(nrhs), relres(nrhs, 1.0);
+    for (int s = 0; s < nrhs; ++s) bnorm[s] = std::sqrt(std::max(0.0, p->h_hbuf[(size_t)s * HS].re));
+    std::vector<int> its(nrhs, 0), conv(nrhs, 0);
+    std::vector<std::vector<double>> hist(nrhs);
+    std::vector<cd> H((size_t)nrhs * (m + 1) * m), cs((size_t)nrhs * m), sn((size_t)nrhs * m),
+        g((size_t)nrhs * (m + 1));
+    std::vector<int> kend(nrhs), live(nrhs);
+    int applies = 0;
+    c128* V = p->d_V;
+    c128* Z = p->d_Z;
+    while (true) {
+        // r = b - A x into V_0, beta = ||r||
+        if ((rc = matvec_impl(p, d_x, V, d_b, nrhs)) != LSW_OK) return rc;
+        if ((rc = dots_impl(p, V, 0, N, V, N, 1, nrhs, p->d_hbuf, HS)) != LSW_OK) return rc;
+        HIPCK(p, hipMemcpyAsync(p->h_hbuf, p->d_hbuf, sizeof(c128) * HS * nrhs, hipMemcpyDeviceToHost, p->stream));
+        HIPCK(p, hipStreamSynchronize(p->stream));
+        int nlive = 0;
+        for (int s = 0; s < nrhs; ++s) {
+            const double beta = std::sqrt(std::max(0.0, p->h_hbuf[(size_t)s * HS].re));
+            relres[s] = bnorm[s] > 0 ? beta / bnorm[s] : 0.0;
+            conv[s] = relres[s] <= p->tol;
+            live[s] = !conv[s] && its[s] < p->maxit;
+            kend[s] = 0;
+            p->h_active[s] = live[s];
+            p->h_scale[s] = (live[s] && beta > 0) ? 1.0 / beta : 0.0;
+            std::fill(g.begin() + (size_t)s * (m + 1), g.begin() + (size_t)(s + 1) * (m + 1), cd(0));
+            g[(size_t)s * (m + 1)] = beta;
+            nlive += live[s];
+        }
+        if (nlive == 0) break;
+        HIPCK(p, hipMemcpyAsync(p->d_active, p->h_active, sizeof(int) * nrhs, hipMemcpyHostToDevice, p->stream));
+        HIPCK(p, hipMemcpyAsync(p->d_scale, p->h_scale, sizeof(double) * nrhs, hipMemcpyHostToDevice, p->stream));
+        HIPCK(p, launch_scale(V, V, p->d_scale, p->d_active, N, N, N, nrhs, p->stream));
+        for (int k = 0; k < m; ++k) {
+            c128* Vk = V + (size_t)k * vl;
+            c128* Zk = Z + (size_t)k * vl;
+            if ((rc = apply_impl(p, Vk, Zk, nrhs, false)) != LSW_OK) return rc;
+            applies++;
+            if ((rc = matvec_impl(p, Zk, p->d_w, nullptr, nrhs)) != LSW_OK) return rc;
+            // classical Gram-Schmidt, twice
+            for (int pass = 0; pass < 2; ++pass) {
+                c128* hcoef = p->d_hbuf + pass * (m + 1);
+                if ((rc = dots_impl(p, V, vl, N, p->d_w, N, k + 1, nrhs, hcoef, HS)) != LSW_OK) return rc;
+                GsArgs ga{V, vl, N, hcoef, HS, p->d_w, N, N, k + 1, -1, p->d_active};
+                HIPCK(p, launch_gs_update(ga, nrhs, p->stream));
+            }
+            if ((rc = dots_impl(p, p->d_w, 0, N, p->d_w, N, 1, nrhs, p->d_hbuf + 2 * (m + 1), HS)) != LSW_OK)
+                return rc;
+            HIPCK(p, hipMemcpyAsync(p->h_hbuf, p->d_hbuf, sizeof(c128) * HS * nrhs, hipMemcpyDeviceToHost,
+                                    p->stream));
+            HIPCK(p, hipStreamSynchronize(p->stream));
+            int still = 0;
+            for (int s = 0; s < nrhs; ++s) {
+                if (!live[s]) {
+                    p->h_scale[s] = 0.0;
+                    continue;
+                }
+                const c128* hb = p->h_hbuf + (size_t)s * HS;
+                std::vector<cd> h(k + 2);
+                for (int l = 0; l <= k; ++l) h[l] = cd(hb[l].re + hb[m + 1 + l].re, hb[l].im + hb[m + 1 + l].im);
+                const double nrm = std::sqrt(std::max(0.0, hb[2 * (m + 1)].re));
+                h[k + 1] = nrm;
+                cd* CS = cs.data() + (size_t)s * m;
+                cd* SN = sn.data() + (size_t)s * m;
+                cd* gg = g.data() + (size_t)s * (m + 1);
+                for (int l = 0; l < k; ++l) {   // previous rotations [[conj c, conj s], [-s, c]]
+                    const cd a0 = h[l], b0 = h[l + 1];
+                    h[l] = std::conj(CS[l]) * a0 + std::conj(SN[l]) * b0;
+                    h[l + 1] = -SN[l] * a0 + CS[l] * b0;
+                }
+                const double rho = std::sqrt(std::norm(h[k]) + std::norm(h[k + 1]));
+                if (rho == 0.0) {
+                    CS[k] = 1.0;
+                    SN[k] = 0.0;
+                } else {
+                    CS[k] = h[k] / rho;
+                    SN[k] = h[k + 1] / rho;
+                }
+                h[k] = rho;
+                h[k + 1] = 0.0;
+                gg[k + 1] = -SN[k] * gg[k];
+                gg[k] = std::conj(CS[k]) * gg[k];
+                for (int l = 0; l <= k; ++l) H[((size_t)s * (m + 1) + l) * m + k] = h[l];
+                its[s]++;
+                kend[s] = k + 1;
+                const double est = bnorm[s] > 0 ? std::abs(gg[k + 1]) / bnorm[s] : 0.0;
+                hist[s].push_back(est);
+                p->h_scale[s] = nrm > 0 ? 1.0 / nrm : 0.0;
+                if (est <= p->tol || its[s] >= p->maxit || nrm == 0.0) live[s] = 0;
+                p->h_active[s] = live[s];
+                still += live[s];
+            }
+            if (still == 0 || k == m - 1) break;
+            HIPCK(p, hipMemcpyAsync(p->d_active, p->h_active, sizeof(int) * nrhs, hipMemcpyHostToDevice, p->stream));
+            HIPCK(p, hipMemcpyAsync(p->d_scale, p->h_scale, sizeof(double) * nrhs, hipMemcpyHostToDevice, p->stream));
+            HIPCK(p, launch_scale(p->d_w, V + (size_t)(k + 1) * vl, p->d_scale, p->d_active, N, N, N, nrhs,
+                                  p->stream));
+        }
+        // x += Z y with y = H^-1 g (upper triangular back substitution on the host)
+        int kmax = 0;
+        for (int s = 0; s < nrhs; ++s) {
+            const int kk = kend[s];
+            kmax = std::max(kmax, kk);
+            std::vector<cd> y(m, cd(0));
+            for (int l = kk - 1; l >= 0; --l) {
+                cd acc = g[(size_t)s * (m + 1) + l];
+                for (int c = l + 1; c < kk; ++c) acc -= H[((size_t)s * (m + 1) + l) * m + c] * y[c];
+                y[l] = acc / H[((size_t)s * (m + 1) + l) * m + l];
+            }
+            for (int l = 0; l < m; ++l) p->h_coef[(size_t)s * m + l] = c128{y[l].real(), y[l].imag()};
+            p->h_active[s] = kk > 0;
+        }
+        if (kmax > 0) {
+            HIPCK(p, hipMemcpyAsync(p->d_coef, p->h_coef, sizeof(c128) * m * nrhs, hipMemcpyHostToDevice, p->stream));
+            HIPCK(p, hipMemcpyAsync(p->d_active, p->h_active, sizeof(int) * nrhs, hipMemcpyHostToDevice, p->stream));
+            GsArgs ga{Z, vl, N, p->d_coef, m, d_x, N, N, kmax, +1, p->d_active};
+            HIPCK(p, launch_gs_update(ga, nrhs, p->stream));
+        }
+        bool any_left = false;
+        for (int s = 0; s < nrhs; ++s) any_left |= (!conv[s] && its[s] < p->maxit);
+        if (!any_left) {
+            // final true residual for the report
+            if ((rc = matvec_impl(p, d_x, V, d_b, nrhs)) != LSW_OK) return rc;
+            if ((rc = dots_impl(p, V, 0, N, V, N, 1, nrhs, p->d_hbuf, HS)) != LSW_OK) return rc;
+            HIPCK(p, hipMemcpyAsync(p->h_hbuf, p->d_hbuf, sizeof(c128) * HS * nrhs, hipMemcpyDeviceToHost,
+                                    p->stream));
+            HIPCK(p, hipStreamSynchronize(p->stream));
+            for (int s = 0; s < nrhs; ++s) {
+                const double beta = std::sqrt(std::max(0.0, p->h_hbuf[(size_t)s * HS].re));
+                relres[s] = bnorm[s] > 0 ? beta / bnorm[s] : 0.0;
+                conv[s] = relres[s] <= p->tol;
+            }
+            break;
+        }
+    }
+    HIPCK(p, hipStreamSynchronize(p->stream));
+    const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    bool all = true;
+    for (int s = 0; s < nrhs; ++s) all &= conv[s] != 0;
+    if (info) {
+        info->t_solve_ms = ms;
+        info->applies = applies;
+        for (int s = 0; s < nrhs; ++s) {
+            if (info->h_rhs) info->h_rhs[s] = lsw_rhs_info_t{its[s], conv[s], relres[s]};
+            if (info->h_history && info->history_len > 0)
+                for (int t = 0; t < info->history_len; ++t)
+                    info->h_history[(size_t)s * info->history_len + t] = t < (int)hist[s].size() ? hist[s][t] : 0.0;
+        }
+    }
+    if (!all) return fail(p, LSW_ENOCONV, "GMRES did not reach tol within maxit");
+    return LSW_OK;
+}
+
+int check_nrhs(lsw_plan* p, int nrhs) {
+    if (nrhs < 1 || nrhs > p->nrhs_max)
+        return fail(p, LSW_EINVAL, "nrhs must be in [1, nrhs_max=" + std::to_string(p->nrhs_max) + "]");
+    return LSW_OK;
+}
+
+int setup_impl(lsw_plan* p, const double* d_m, double omega, double h, const lsw_grid_t* grid,
+               const lsw_cdd_t* cdd, const lsw_pml_t* pml, const lsw_opts_t* opts) {
+    const auto t0 = std::chrono::steady_clock::now();
+    if (!grid || !cdd || !d_m) return fail(p, LSW_EINVAL, "grid, cdd and m are required");
+    if (grid->dim != 2) return fail(p, LSW_EINVAL, "only dim = 2 is supported");
+    if (!(omega > 0) || !(h > 0) || !std::isfinite(omega) || !std::isfinite(h))
+        return fail(p, LSW_EINVAL, "omega and h must be positive and finite");
+    p->nx = grid->n[0];
+    p->ny = grid->n[1];
+    p->px = grid->n_pml[0];
+    p->py = grid->n_pml[1];
+    if (p->nx < 1 || p->ny < 1 || p->px < 0 || p->py < 0) return fail(p, LSW_EINVAL, "bad grid sizes");
+    p->q = cdd->q;
+    p->r = cdd->r;
+    if (p->q < 1 || p->r < 1) return fail(p, LSW_EINVAL, "q and r must be >= 1");
+    p->omega = omega;
+    p->h = h;
+    p->C = (pml && pml->C > 0) ? pml->C : 4.0 * std::log(omega);
+    p->pl = (pml && pml->n_pml_local >= 0) ? pml->n_pml_local : p->px;
+    p->e = 2 + p->pl;
+    if (opts) {
+        p->precision = opts->precision == LSW_MIXED ? LSW_MIXED : LSW_FP64;
+        if (opts->restart > 0) p->restart = opts->restart;
+        if (opts->maxit > 0) p->maxit = opts->maxit;
+        if (opts->tol > 0) p->tol = opts->tol;
+        if (opts->nrhs_max > 0) p->nrhs_max = opts->nrhs_max;
+        p->stream = static_cast<hipStream_t>(opts->stream);
+    }
+    p->Nx = p->nx + 2 * p->px;
+    p->Ny = p->ny + 2 * p->py;
+    p->N = (size_t)p->Nx * p->Ny;
+    split(p->nx, p->px, p->r, p->xlo, p->xhi);
+    split(p->ny, p->py, p->q, p->ylo, p->yhi);
+    auto windows = [&](const std::vector<int>& lo, const std::vector<int>& hi, int Nax, std::vector<int>& w0,
+                       std::vector<int>& w1) -> bool {
+        const int G = (int)lo.size();
+        w0.resize(G);
+        w1.resize(G);
+        for (int g = 0; g < G; ++g) {
+            if (hi[g] - lo[g] < 2) return false;
+            w0[g] = lo[g] - (g > 0 ? p->e : 0);
+            w1[g] = hi[g] + (g < G - 1 ? p->e : 0);
+            if (w0[g] < 0 || w1[g] > Nax) return false;
+        }
+        return true;
+    };
+    if (!windows(p->xlo, p->xhi, p->Nx, p->xw0, p->xw1) || !windows(p->ylo, p->yhi, p->Ny, p->yw0, p->yw1))
+        return fail(p, LSW_EINVAL, "every CDD group needs >= 2 points and its window (2 + n_pml_local extra "
+                                   "lines per interior side) must fit in the extended grid");
+    // tables
+    std::vector<c128> pool;
+    AxisLayers gx{(p->nx + 1) * h, p->px * h, false, false, 0, 0, 0};
+    AxisLayers gy{(p->ny + 1) * h, p->py * h, false, false, 0, 0, 0};
+    p->geo.gtx = append_table(pool, 0, p->Nx, p->px, h, omega, p->C, gx);
+    p->geo.gty = append_table(pool, 0, p->Ny, p->py, h, omega, p->C, gy);
+    std::vector<int> txj(p->r), tyi(p->q);
+    for (int j = 0; j < p->r; ++j) {
+        AxisLayers a = gx;
+        a.delta_loc = p->pl * h;
+        a.left = p->pl > 0 && j > 0;
+        a.right = p->pl > 0 && j < p->r - 1;
+        if (a.left) a.xs_left = coord2(2 * (p->xlo[j] - 3), p->px, h);
+        if (a.right) a.xs_right = coord2(2 * (p->xhi[j] + 2), p->px, h);
+        txj[j] = append_table(pool, p->xw0[j], p->xw1[j], p->px, h, omega, p->C, a);
+    }
+    for (int i = 0; i < p->q; ++i) {
+        AxisLayers a = gy;
+        a.delta_loc = p->pl * h;
+        a.left = p->pl > 0 && i > 0;
+        a.right = p->pl > 0 && i < p->q - 1;
+        if (a.left) a.xs_left = coord2(2 * (p->ylo[i] - 3), p->py, h);
+        if (a.right) a.xs_right = coord2(2 * (p->yhi[i] + 2), p->py, h);
+        tyi[i] = append_table(pool, p->yw0[i], p->yw1[i], p->py, h, omega, p->C, a);
+    }
+    // subdomains
+    p->subs.clear();
+    p->G_elems = 0;
+    p->hbase.clear();
+    p->vbase.clear();
+    p->HT = p->VT = 0;
+    p->factor_flops = 0;
+    for (int i = 0; i < p->q; ++i)
+        for (int j = 0; j < p->r; ++j) {
+            SubDesc s{};
+            s.W = p->xw1[j] - p->xw0[j];
+            s.H = p->yw1[i] - p->yw0[i];
+            s.wx0 = p->xw0[j];
+            s.wy0 = p->yw0[i];
+            s.r0 = p->ylo[i] - p->yw0[i];
+            s.r1 = p->yhi[i] - p->yw0[i];
+            s.c0 = p->xlo[j] - p->xw0[j];
+            s.c1 = p->xhi[j] - p->xw0[j];
+            s.i = i;
+            s.j = j;
+            s.tx = txj[j];
+            s.ty = tyi[i];
+            s.g_off = (long long)p->G_elems;
+            p->G_elems += (size_t)s.H * s.W * s.W;
+            p->hbase.push_back(p->HT);
+            p->vbase.push_back(p->VT);
+            p->HT += 2 * (size_t)s.W;
+            p->VT += 2 * (size_t)s.H;
+            p->Wmax = std::max(p->Wmax, s.W);
+            p->Hmax = std::max(p->Hmax, s.H);
+            p->factor_flops += 8.0 * s.H * (double)s.W * s.W * s.W;
+            p->subs.push_back(s);
+        }
+    if (p->Wmax > kMaxWindow)
+        return fail(p, LSW_EINVAL, "local window wider than " + std::to_string(kMaxWindow) + " points");
+    build_schedule(p);
+    const size_t eb = p->precision == LSW_MIXED ? sizeof(c64) : sizeof(c128);
+    p->apply_G_bytes = 0;
+    for (const SolveDesc& d : p->descs) {
+        const SubDesc& s = p->subs[d.sub];
+        const double blocks = (s.H - d.kf0) + (s.H - 1 - d.kb0);
+        p->apply_G_bytes += blocks * s.W * (double)s.W * eb;
+    }
+    // m: copy, validate
+    std::vector<double> hm(p->N);
+    int rc;
+    if ((rc = dalloc(p, &p->d_m, p->N)) != LSW_OK) return rc;
+    HIPCK(p, hipMemcpy(hm.data(), d_m, sizeof(double) * p->N, hipMemcpyDeviceToHost));
+    for (double v : hm)
+        if (!std::isfinite(v)) return fail(p, LSW_ENAN, "non-finite value in m");
+    HIPCK(p, hipMemcpy(p->d_m, hm.data(), sizeof(double) * p->N, hipMemcpyHostToDevice));
+    // device buffers
+    if ((rc = dalloc(p, &p->d_tab, pool.size())) != LSW_OK) return rc;
+    HIPCK(p, hipMemcpy(p->d_tab, pool.data(), sizeof(c128) * pool.size(), hipMemcpyHostToDevice));
+    if ((rc = dalloc(p, &p->d_subs, p->subs.size())) != LSW_OK) return rc;
+    HIPCK(p, hipMemcpy(p->d_subs, p->subs.data(), sizeof(SubDesc) * p->subs.size(), hipMemcpyHostToDevice));
+    if ((rc = dalloc(p, &p->d_descs, p->descs.size())) != LSW_OK) return rc;
+    HIPCK(p, hipMemcpy(p->d_descs, p->descs.data(), sizeof(SolveDesc) * p->descs.size(), hipMemcpyHostToDevice));
+    std::vector<int> xg(p->Nx), yg(p->Ny);
+    for (int j = 0; j < p->r; ++j)
+        for (int x = p->xlo[j]; x < p->xhi[j]; ++x) xg[x] = j;
+    for (int i = 0; i < p->q; ++i)
+        for (int y = p->ylo[i]; y < p->yhi[i]; ++y) yg[y] = i;
+    if ((rc = dalloc(p, &p->d_xgroup, p->Nx)) != LSW_OK) return rc;
+    if ((rc = dalloc(p, &p->d_ygroup, p->Ny)) != LSW_OK) return rc;
+    HIPCK(p, hipMemcpy(p->d_xgroup, xg.data(), sizeof(int) * p->Nx, hipMemcpyHostToDevice));
+    HIPCK(p, hipMemcpy(p->d_ygroup, yg.data(), sizeof(int) * p->Ny, hipMemcpyHostToDevice));
+    const int nsub = (int)p->subs.size();
+    if ((rc = dalloc(p, &p->d_status, nsub)) != LSW_OK) return rc;
+    HIPCK(p, hipMemset(p->d_status, 0, sizeof(int) * nsub));
+    char* G = nullptr;
+    if ((rc = dalloc(p, &G, p->G_elems * eb)) != LSW_OK) return rc;
+    p->d_G = G;
+    p->trace_stride = H_COUNT * p->HT + V_COUNT * p->VT;
+    char* tr = nullptr;
+    if ((rc = dalloc(p, &tr, p->trace_stride * p->nrhs_max * eb)) != LSW_OK) return rc;
+    p->d_traces = tr;
+    HIPCK(p, hipMemset(tr, 0, p->trace_stride * p->nrhs_max * eb));
+    p->zpart_stride = (size_t)p->nrhs_max * p->N;
+    char* zp = nullptr;
+    if ((rc = dalloc(p, &zp, 9 * p->zpart_stride * eb)) != LSW_OK) return rc;
+    p->d_zpart = zp;
+    HIPCK(p, hipMemset(zp, 0, 9 * p->zpart_stride * eb));
+    p->Y_stride = (size_t)p->Wmax * p->Hmax;
+    char* Y = nullptr;
+    if ((rc = dalloc(p, &Y, p->Y_stride * p->max_front * p->nrhs_max * eb)) != LSW_OK) return rc;
+    p->d_Y = Y;
+    // Krylov
+    const int m = p->restart, nr = p->nrhs_max;
+    const int HS = 2 * (m + 1) + 1;
+    if ((rc = dalloc(p, &p->d_V, (size_t)(m + 1) * nr * p->N)) != LSW_OK) return rc;
+    if ((rc = dalloc(p, &p->d_Z, (size_t)m * nr * p->N)) != LSW_OK) return rc;
+    if ((rc = dalloc(p, &p->d_w, (size_t)nr * p->N)) != LSW_OK) return rc;
+    if ((rc = dalloc(p, &p->d_tmp1, (size_t)nr * p->N)) != LSW_OK) return rc;
+    if ((rc = dalloc(p, &p->d_tmp2, (size_t)nr * p->N)) != LSW_OK) return rc;
+    if ((rc = dalloc(p, &p->d_partial, (size_t)nr * (m + 1) * p->nblk)) != LSW_OK) return rc;
+    if ((rc = dalloc(p, &p->d_hbuf, (size_t)nr * HS)) != LSW_OK) return rc;
+    if ((rc = dalloc(p, &p->d_coef, (size_t)nr * m)) != LSW_OK) return rc;
+    if ((rc = dalloc(p, &p->d_scale, (size_t)nr)) != LSW_OK) return rc;
+    if ((rc = dalloc(p, &p->d_active, (size_t)nr)) != LSW_OK) return rc;
+    HIPCK(p, hipHostMalloc((void**)&p->h_hbuf, sizeof(c128) * nr * HS, hipHostMallocDefault));
+    HIPCK(p, hipHostMalloc((void**)&p->h_scale, sizeof(double) * nr, hipHostMallocDefault));
+    HIPCK(p, hipHostMalloc((void**)&p->h_active, sizeof(int) * nr, hipHostMallocDefault));
+    HIPCK(p, hipHostMalloc((void**)&p->h_coef, sizeof(c128) * nr * m, hipHostMallocDefault));
+    HIPCK(p, hipEventCreate(&p->ev0));
+    HIPCK(p, hipEventCreate(&p->ev1));
+    HIPCK(p, hipEventCreate(&p->evm));
+    p->geo.tab = p->d_tab;
+    p->geo.m = p->d_m;
+    p->geo.Nx = p->Nx;
+    p->geo.Ny = p->Ny;
+    p->geo.h = h;
+    p->geo.omega = omega;
+    // factorisation
+    int dev = 0;
+    HIPCK(p, hipGetDevice(&dev));
+    int max_lds = 0;
+    HIPCK(p, hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+    const size_t static_lds = sizeof(c128) * kMaxWindow + sizeof(int) * kMaxWindow + 64;
+    const size_t lds_bytes = sizeof(c128) * (size_t)p->Wmax * p->Wmax;
+    const bool use_lds = lds_bytes + static_lds <= (size_t)max_lds;
+    FactorArgs fa{};
+    fa.subs = p->d_subs;
+    fa.geo = p->geo;
+    fa.G = p->d_G;
+    fa.status = p->d_status;
+    if (!use_lds) {
+        if ((rc = dalloc(p, &fa.work, (size_t)nsub * p->Wmax * p->Wmax)) != LSW_OK) return rc;
+        fa.work_stride = (size_t)p->Wmax * p->Wmax;
+    }
+    HIPCK(p, hipStreamSynchronize(p->stream));
+    const auto tf = std::chrono::steady_clock::now();
+    HIPCK(p, launch_factor(fa, nsub, p->Wmax, use_lds, use_lds ? lds_bytes : 0, p->precision == LSW_MIXED,
+                           p->stream));
+    HIPCK(p, hipStreamSynchronize(p->stream));
+    p->t_factor_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tf).count();
+    std::vector<int> status(nsub);
+    HIPCK(p, hipMemcpy(status.data(), p->d_status, sizeof(int) * nsub, hipMemcpyDeviceToHost));
+    for (int s = 0; s < nsub; ++s)
+        if (status[s])
+            return fail(p, LSW_ESINGULAR, "zero pivot in the block factorisation of subdomain (" +
+                                              std::to_string(p->subs[s].i) + "," + std::to_string(p->subs[s].j) + ")");
+    p->t_setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    return LSW_OK;
+}
+
+}  // namespace
+
+// ============================================================================ C ABI
+extern "C" {
+
+int lsw_setup(lsw_handle_t* out, const double* d_m, double omega, double h, const lsw_grid_t* grid,
+              const lsw_cdd_t* cdd, const lsw_pml_t* pml, const lsw_opts_t* opts) {
+    if (!out) return LSW_EINVAL;
+    *out = nullptr;
+    lsw_plan* p = new (std::nothrow) lsw_plan();
+    if (!p) return LSW_ENOMEM;
+    int rc;
+    try {
+        rc = setup_impl(p, d_m, omega, h, grid, cdd, pml, opts);
+    } catch (const std::bad_alloc&) {
+        p->err = "host allocation failed";
+        rc = LSW_ENOMEM;
+    } catch (...) {
+        p->err = "unexpected host exception";
+        rc = LSW_EINVAL;
+    }
+    if (rc != LSW_OK) {
+        g_setup_error = p->err;
+        free_plan(p);
+        return rc;
+    }
+    *out = p;
+    return LSW_OK;
+}
+
+int lsw_apply(lsw_handle_t p, const double* d_r, double* d_z, int nrhs) {
+    if (!p || !d_r || !d_z) return LSW_EINVAL;
+    int rc = check_nrhs(p, nrhs);
+    if (rc != LSW_OK) return rc;
+    rc = apply_impl(p, reinterpret_cast<const c128*>(d_r), reinterpret_cast<c128*>(d_z), nrhs, true);
+    if (rc != LSW_OK) return rc;
+    HIPCK(p, hipEventSynchronize(p->ev1));
+    float ms = 0;
+    HIPCK(p, hipEventElapsedTime(&ms, p->ev0, p->ev1));
+    p->last_apply_ms = ms;
+    HIPCK(p, hipEventElapsedTime(&ms, p->ev0, p->evm));
+    p->last_sweep_ms = ms;
+    return LSW_OK;
+}
+
+int lsw_solve(lsw_handle_t p, const double* d_f, double* d_u, int nrhs, lsw_info_t* info) {
+    if (!p || !d_f || !d_u) return LSW_EINVAL;
+    int rc = check_nrhs(p, nrhs);
+    if (rc != LSW_OK) return rc;
+    try {
+        return solve_impl(p, reinterpret_cast<const c128*>(d_f), reinterpret_cast<c128*>(d_u), nrhs, info);
+    } catch (...) {
+        p->err = "host exception in solve";
+        return LSW_ENOMEM;
+    }
+}
+
+int lsw_adjoint(lsw_handle_t p, const double* d_g, double* d_v, int nrhs, lsw_info_t* info) {
+    if (!p || !d_g || !d_v) return LSW_EINVAL;
+    int rc = check_nrhs(p, nrhs);
+    if (rc != LSW_OK) return rc;
+    const size_t n = (size_t)nrhs * p->N;
+    c128* v = reinterpret_cast<c128*>(d_v);
+    HIPCK(p, launch_conj(reinterpret_cast<const c128*>(d_g), p->d_tmp1, n, p->stream));
+    HIPCK(p, launch_conj(v, p->d_tmp2, n, p->stream));
+    try {
+        rc = solve_impl(p, p->d_tmp1, p->d_tmp2, nrhs, info);
+    } catch (...) {
+        p->err = "host exception in adjoint";
+        return LSW_ENOMEM;
+    }
+    HIPCK(p, launch_conj(p->d_tmp2, v, n, p->stream));
+    HIPCK(p, hipStreamSynchronize(p->stream));
+    return rc;
+}
+
+int lsw_matvec(lsw_handle_t p, const double* d_x, double* d_y, int nrhs) {
+    if (!p || !d_x || !d_y || d_x == d_y) return LSW_EINVAL;
+    int rc = check_nrhs(p, nrhs);
+    if (rc != LSW_OK) return rc;
+    rc = matvec_impl(p, reinterpret_cast<const c128*>(d_x), reinterpret_cast<c128*>(d_y), nullptr, nrhs);
+    if (rc != LSW_OK) return rc;
+    HIPCK(p, hipStreamSynchronize(p->stream));
+    return LSW_OK;
+}
+
+int lsw_mass_gradient(lsw_handle_t p, const double* d_lam, const double* d_u, int nrhs, double* d_grad) {
+    if (!p || !d_lam || !d_u || !d_grad || nrhs < 1) return LSW_EINVAL;
+    HIPCK(p, launch_mass_gradient(reinterpret_cast<const c128*>(d_lam), reinterpret_cast<const c128*>(d_u), nrhs,
+                                  p->geo, d_grad, p->stream));
+    HIPCK(p, hipStreamSynchronize(p->stream));
+    return LSW_OK;
+}
+
+int lsw_query(lsw_handle_t p, lsw_stats_t* st) {
+    if (!p || !st) return LSW_EINVAL;
+    st->q = p->q;
+    st->r = p->r;
+    st->n_subdomains = (int)p->subs.size();
+    st->W_max = p->Wmax;
+    st->H_max = p->Hmax;
+    st->N = (long long)p->N;
+    st->factor_elems = (long long)p->G_elems;
+    st->factor_elem_bytes = p->precision == LSW_MIXED ? 8 : 16;
+    st->solves_per_apply = (int)p->descs.size();
+    st->fronts_per_apply = (int)p->fronts.size();
+    st->apply_G_bytes = p->apply_G_bytes;
+    st->factor_flops = p->factor_flops;
+    st->t_setup_ms = p->t_setup_ms;
+    st->t_factor_ms = p->t_factor_ms;
+    st->last_apply_ms = p->last_apply_ms;
+    st->last_sweep_ms = p->last_sweep_ms;
+    return LSW_OK;
+}
+
+const char* lsw_last_error(lsw_handle_t p) { return p ? p->err.c_str() : g_setup_error.c_str(); }
+
+int lsw_destroy(lsw_handle_t p) {
+    if (!p) return LSW_OK;
+    (void)hipStreamSynchronize(p->stream);
+    free_plan(p);
+    return LSW_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,86 @@
+// Argument blocks and launch wrappers of the device kernels (kernels.hip).
+#pragma once
+
+#include "common.h"
+
+namespace lsw {
+
+static constexpr int kMaxWindow = 256;   // largest local window edge the kernels accept
+
+struct FactorArgs {
+    const SubDesc* subs;
+    Geometry geo;
+    void* G;              // factor pool (complex64 or complex128)
+    c128* work;           // global workspace (only when the block does not fit in LDS)
+    size_t work_stride;   // elements per subdomain in work
+    int* status;          // per subdomain: 1 if a zero pivot was met
+};
+
+struct SweepArgs {
+    const SolveDesc* descs;
+    const SubDesc* subs;
+    Geometry geo;
+    const void* G;          // factor pool
+    void* traces;           // trace pool of rhs 0
+    size_t trace_stride;    // elements between right-hand sides
+    void* Y;                // forward-substitution scratch, one slab per (solve, rhs)
+    size_t Y_stride;
+    void* zpart;            // [9][nrhs_max][N] per-sweep accumulators
+    size_t zpart_stride;    // nrhs_max * N
+    const c128* r;          // stage-1 input [nrhs][N]
+};
+
+struct ZsumArgs {
+    const void* zpart;
+    size_t zpart_stride;
+    c128* z;
+    const int* xgroup;
+    const int* ygroup;
+    int Nx, Ny, q, r;
+};
+
+struct MatvecArgs {
+    Geometry geo;
+    const c128* x;
+    c128* y;
+    const c128* b;   // if non-null: y = b - A x
+};
+
+struct DotsArgs {
+    const c128* V;
+    size_t vstride_l, vstride_rhs;
+    const c128* w;
+    size_t wstride;
+    size_t N;
+    int nv;
+    int nblk;
+    c128* partial;   // [nrhs][nv][nblk]
+};
+
+struct GsArgs {
+    const c128* V;
+    size_t vstride_l, vstride_rhs;
+    const c128* coef;
+    int cstride;
+    c128* w;
+    size_t wstride;
+    size_t N;
+    int nv;
+    int sign;          // -1: w -= V c ; +1: w += V c
+    const int* active; // optional per-rhs mask
+};
+
+hipError_t launch_factor(const FactorArgs& a, int nsub, int Wmax, bool use_lds, size_t lds_bytes,
+                         bool store_c64, hipStream_t st);
+hipError_t launch_sweep(const SweepArgs& a, int nsolves, int nrhs, int Wmax, bool c64mode, hipStream_t st);
+hipError_t launch_zsum(const ZsumArgs& a, int nrhs, bool c64mode, hipStream_t st);
+hipError_t launch_matvec(const MatvecArgs& a, int nrhs, hipStream_t st);
+hipError_t launch_dots(const DotsArgs& a, int nrhs, c128* out, int ostride, int accumulate, hipStream_t st);
+hipError_t launch_gs_update(const GsArgs& a, int nrhs, hipStream_t st);
+hipError_t launch_scale(const c128* src, c128* dst, const double* scale, const int* active, size_t N,
+                        size_t sstride, size_t dstride, int nrhs, hipStream_t st);
+hipError_t launch_conj(const c128* src, c128* dst, size_t n, hipStream_t st);
+hipError_t launch_mass_gradient(const c128* lam, const c128* u, int nrhs, const Geometry& g, double* grad,
+                                hipStream_t st);
+
+}  // namespace lsw

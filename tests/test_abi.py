@@ -1,0 +1,104 @@
+"""CPU checks of the C ABI: the library loads, exports every function include/lsw.h declares,
+the ctypes structures match the C layouts, and argument errors are reported without a GPU."""
+import ctypes
+import os
+import re
+import subprocess
+import tempfile
+
+import pytest
+
+from paper_1909_01467_amd import lsweeps
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lsw.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lsw_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("lsw_setup", "lsw_apply", "lsw_solve", "lsw_adjoint"):
+        assert required in names
+    assert set(names) == set(lsweeps.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = lsweeps.load_library()
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+    out = subprocess.run(["nm", "-D", "--defined-only", lsweeps.library_path()], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(re.findall(r"\bT (lsw_\w+)", out))
+    assert set(declared_functions()) <= exported
+
+
+STRUCTS = ["lsw_grid_t", "lsw_cdd_t", "lsw_pml_t", "lsw_opts_t", "lsw_rhs_info_t", "lsw_info_t", "lsw_stats_t"]
+
+
+def test_ctypes_structures_match_the_c_layout():
+    """Compile a C probe against lsw.h and compare sizeof/offsetof with the binding."""
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "lsw.h"', "int main(void) {"]
+    for s in STRUCTS:
+        lines.append(f'  printf("{s} size %zu\\n", sizeof({s}));')
+        for fname, _ in getattr(lsweeps, s)._fields_:
+            lines.append(f'  printf("{s}.{fname} %zu\\n", offsetof({s}, {fname}));')
+    lines.append("  return 0; }")
+    with tempfile.TemporaryDirectory() as d:
+        src = os.path.join(d, "probe.c")
+        exe = os.path.join(d, "probe")
+        open(src, "w").write("\n".join(lines))
+        subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), src, "-o", exe], check=True)
+        out = subprocess.run([exe], capture_output=True, text=True, check=True).stdout
+    got = dict(line.rsplit(" ", 1) for line in out.strip().splitlines())
+    for s in STRUCTS:
+        cls = getattr(lsweeps, s)
+        assert int(got[f"{s} size"]) == ctypes.sizeof(cls), s
+        for fname, _ in cls._fields_:
+            assert int(got[f"{s}.{fname}"]) == getattr(cls, fname).offset, (s, fname)
+
+
+def test_argument_errors_need_no_gpu():
+    lib = lsweeps.load_library()
+    assert lib.lsw_setup(None, None, 1.0, 1.0, None, None, None, None) == lsweeps.LSW_EINVAL
+    assert lib.lsw_apply(None, None, None, 1) == lsweeps.LSW_EINVAL
+    assert lib.lsw_solve(None, None, None, 1, None) == lsweeps.LSW_EINVAL
+    assert lib.lsw_adjoint(None, None, None, 1, None) == lsweeps.LSW_EINVAL
+    assert lib.lsw_matvec(None, None, None, 1) == lsweeps.LSW_EINVAL
+    assert lib.lsw_query(None, None) == lsweeps.LSW_EINVAL
+    assert lib.lsw_destroy(None) == lsweeps.LSW_OK
+    assert isinstance(lib.lsw_last_error(None), bytes)
+
+
+def test_setup_rejects_bad_geometry_before_touching_memory():
+    lib = lsweeps.load_library()
+    h = ctypes.c_void_p()
+    grid = lsweeps.lsw_grid_t(3, (ctypes.c_int * 3)(8, 8, 8), (ctypes.c_int * 3)(2, 2, 2))
+    cdd = lsweeps.lsw_cdd_t(2, 2)
+    rc = lib.lsw_setup(ctypes.byref(h), ctypes.c_void_p(1), 10.0, 0.1, ctypes.byref(grid), ctypes.byref(cdd),
+                       None, None)
+    assert rc == lsweeps.LSW_EINVAL and h.value is None
+    assert b"dim" in lib.lsw_last_error(None)
+    grid = lsweeps.lsw_grid_t(2, (ctypes.c_int * 3)(20, 20, 0), (ctypes.c_int * 3)(5, 5, 0))
+    cdd = lsweeps.lsw_cdd_t(16, 16)   # groups of a single point
+    rc = lib.lsw_setup(ctypes.byref(h), ctypes.c_void_p(1), 10.0, 0.1, ctypes.byref(grid), ctypes.byref(cdd),
+                       None, None)
+    assert rc == lsweeps.LSW_EINVAL and b"window" in lib.lsw_last_error(None)
+    grid = lsweeps.lsw_grid_t(2, (ctypes.c_int * 3)(20, 20, 0), (ctypes.c_int * 3)(2, 2, 0))
+    cdd = lsweeps.lsw_cdd_t(2, 2)
+    pml = lsweeps.lsw_pml_t(0.0, 11)  # local layers wider than the grid allows
+    rc = lib.lsw_setup(ctypes.byref(h), ctypes.c_void_p(1), 10.0, 0.1, ctypes.byref(grid), ctypes.byref(cdd),
+                       ctypes.byref(pml), None)
+    assert rc == lsweeps.LSW_EINVAL and b"window" in lib.lsw_last_error(None)
+
+
+def test_solver_refuses_to_run_without_a_gpu():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("GPU present")
+    with pytest.raises(RuntimeError):
+        lsweeps.Solver(torch.ones(30, 30, dtype=torch.float64), 10.0, 0.05, 20, 5, 2)
