@@ -54,6 +54,11 @@ typedef enum {
     LSW_MIXED = 1        /* complex64 factors and sweeps (FP32 accumulation), FP64 Krylov */
 } lsw_precision;
 
+typedef enum {
+    LSW_SWEEP_COMPRESSED = 0,  /* sweeps as trace-to-trace products with Q = A_ij^-1 on the trace lines */
+    LSW_SWEEP_CHAIN = 1        /* every sweep solve as a full block forward/back substitution */
+} lsw_sweep_mode;
+
 typedef struct {
     int dim;             /* 2 (the only dimension built so far) */
     int n[3];            /* bulk points per axis (x, y, z) */
@@ -77,6 +82,7 @@ typedef struct {
     double tol;          /* relative true-residual tolerance ||b - A u|| <= tol ||b|| (default 1e-6 when <= 0) */
     int nrhs_max;        /* largest nrhs any later call will pass (default 1 when <= 0) */
     void* stream;        /* hipStream_t for all device work (NULL = default stream) */
+    int sweep_mode;      /* lsw_sweep_mode; both compute the same M^-1 r up to rounding */
 } lsw_opts_t;
 
 typedef struct {
@@ -101,11 +107,16 @@ typedef struct {
     int factor_elem_bytes;       /* 8 (complex64) or 16 (complex128) */
     int solves_per_apply;        /* (3q-2)(3r-2)-type count of local solves per application */
     int fronts_per_apply;        /* dependent launch steps per application */
-    double apply_G_bytes;        /* algorithmic bytes of G read by one application (one RHS) */
+    double apply_chain_bytes;    /* algorithmic bytes of G read by the block substitutions of one application */
+    double apply_gemv_bytes;     /* algorithmic bytes of Q read by the trace-compressed fronts of one application */
+    int chain_launches;          /* block-substitution launches per application */
+    int gemv_launches;           /* trace-compressed launches per application */
+    long long q_elems;           /* complex entries of all trace-line operators Q */
     double factor_flops;         /* real flops of the block factorisation */
-    double t_setup_ms, t_factor_ms;
+    double t_setup_ms, t_factor_ms, t_q_ms;
     double last_apply_ms;        /* device time of the most recent lsw_apply (events) */
-    double last_sweep_ms;        /* ... of its local-solve fronts only (without the final z assembly) */
+    double last_chain_ms;        /* ... spent in its block-substitution launches */
+    double last_gemv_ms;         /* ... spent in its trace-compressed launches */
 } lsw_stats_t;
 
 /*

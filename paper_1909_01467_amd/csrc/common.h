@@ -67,8 +67,19 @@ enum Kind : int {
     KIND_BL = 5,      // L-shaped, bottom + left legs, upper-right quadrant  (BL->TR sweep)
     KIND_TR = 6,      // top + right legs, lower-left quadrant               (TR->BL sweep)
     KIND_BR = 7,      // bottom + right legs, upper-left quadrant            (BR->TL sweep)
-    KIND_TL = 8       // top + left legs, lower-right quadrant               (TL->BR sweep)
+    KIND_TL = 8,      // top + left legs, lower-right quadrant               (TL->BR sweep)
+    KIND_FINAL = 9,   // r on Omega_ij plus the accumulated sweep right-hand sides -> z
+    KIND_UNIT = 10    // unit source on one trace-line point -> one column of Q (setup)
 };
+
+// Trace-line slots of a window (W x H): the 8 lines adjacent to the 4 interfaces, each
+// over the full window extent, concatenated as B0 B1 T0 T1 (W points each) and
+// L0 L1 R0 R1 (H points each); line 0 of a side has the smaller grid index.
+__host__ __device__ inline int slot_B0(int W, int H) { return 0; }
+__host__ __device__ inline int slot_T0(int W, int H) { return 2 * W; }
+__host__ __device__ inline int slot_L0(int W, int H) { return 4 * W; }
+__host__ __device__ inline int slot_R0(int W, int H) { return 4 * W + 2 * H; }
+__host__ __device__ inline int slot_count(int W, int H) { return 4 * W + 4 * H; }
 
 // One local problem (window of one CDD cell).
 struct SubDesc {
@@ -77,7 +88,11 @@ struct SubDesc {
     int r0, r1, c0, c1;  // Omega_ij inside the window: rows [r0, r1), cols [c0, c1)
     int i, j;            // CDD row / column
     int tx, ty;          // offsets of this window's x and y tables in the table pool
+    int sides;           // bit s set if side s (Side) is an interior interface
+    int L;               // number of trace-line slots, 4W + 4H
     long long g_off;     // offset (elements) of G_0 in the factor pool; G_k at g_off + k*W*W
+    long long q_off;     // offset of Q = A_ij^-1[lines, lines] (L x L, column-major) in the Q pool
+    long long gp_off;    // offset of this window's slots in each accumulated-RHS array
 };
 
 // Layout of one axis table of a window with P points (offset t in the table pool):
@@ -101,6 +116,27 @@ struct SolveDesc {
     long long out_off[kMaxOut];  // output trace offsets
     int out_side[kMaxOut];       // Side of each output
     int out_acc[kMaxOut];        // 1: accumulate (+=), 0: assign (=)
+    int unit_k, unit_c;          // KIND_UNIT: window point of the unit source
+    long long q_col;             // KIND_UNIT: element offset of the Q column written
+};
+
+// One local solve of a sweep front in the trace-compressed form: the outgoing traces are
+// Q[out lines, in slots] * g[in slots], where g is the polarized right-hand side on the
+// (at most four) slot ranges that carry it.
+struct GemvSolve {
+    int sub, kind, sweep;        // sweep 1..8 selects the accumulated-RHS array
+    int nin;
+    int in_start[4], in_len[4];  // slot ranges of g
+    int nout;
+    long long in_h, in_v;        // incoming traces (offsets in the trace pool), -1 if none
+    long long out_off[kMaxOut];
+    int out_side[kMaxOut];
+    int out_acc[kMaxOut];
+};
+
+// One workgroup of a trace-compressed front: 64 outputs of one output side of one solve.
+struct GemvItem {
+    int solve, out, chunk, first;  // first: this workgroup also stores g for the final solve
 };
 
 // Everything a kernel needs to evaluate the local or global 5-point coefficients.

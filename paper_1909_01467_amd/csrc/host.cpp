@@ -33,8 +33,12 @@ namespace {
 enum HArr { H_B_RUN = 0, H_T_RUN, H_B_LF, H_T_LF, H_B_RT, H_T_RT, H_COUNT };
 enum VArr { V_L_RUN = 0, V_R_RUN, V_R_UP, V_L_UP, V_R_DN, V_L_DN, V_COUNT };
 
+// One dependent step of an application: a batch of block substitutions (descs[offset..])
+// or a trace-compressed batch (gsolves/gitems).
 struct Front {
-    int offset, count;
+    int gemv;
+    int offset, count;           // solves
+    int ioffset, icount;         // GEMV work items
 };
 
 }  // namespace
@@ -45,7 +49,7 @@ struct lsw_plan {
     int Nx = 0, Ny = 0;
     size_t N = 0;
     double h = 0, omega = 0, C = 0;
-    int precision = LSW_FP64, restart = 50, maxit = 500, nrhs_max = 1;
+    int precision = LSW_FP64, restart = 50, maxit = 500, nrhs_max = 1, sweep_mode = LSW_SWEEP_COMPRESSED;
     double tol = 1e-6;
     hipStream_t stream = nullptr;
     // geometry
@@ -53,7 +57,9 @@ struct lsw_plan {
     std::vector<SubDesc> subs;
     std::vector<SolveDesc> descs;
     std::vector<Front> fronts;
-    int Wmax = 0, Hmax = 0, max_front = 0;
+    std::vector<GemvSolve> gsolves;
+    std::vector<GemvItem> gitems;
+    int Wmax = 0, Hmax = 0, max_front = 0, ept = 1;
     size_t HT = 0, VT = 0;
     std::vector<size_t> hbase, vbase;
     // device
@@ -61,6 +67,12 @@ struct lsw_plan {
     c128* d_tab = nullptr;
     SubDesc* d_subs = nullptr;
     SolveDesc* d_descs = nullptr;
+    GemvSolve* d_gsolves = nullptr;
+    GemvItem* d_gitems = nullptr;
+    void* d_Q = nullptr;
+    size_t Q_elems = 0;
+    void* d_gparts = nullptr;
+    size_t LT = 0;
     void* d_G = nullptr;
     size_t G_elems = 0;
     void* d_traces = nullptr;
@@ -92,9 +104,10 @@ struct lsw_plan {
     // bookkeeping
     std::vector<void*> allocs;
     std::string err;
-    double t_setup_ms = 0, t_factor_ms = 0, last_apply_ms = 0, last_sweep_ms = 0;
-    double apply_G_bytes = 0, factor_flops = 0;
-    hipEvent_t ev0 = nullptr, ev1 = nullptr, evm = nullptr;
+    double t_setup_ms = 0, t_factor_ms = 0, t_q_ms = 0, last_apply_ms = 0, last_chain_ms = 0, last_gemv_ms = 0;
+    double apply_chain_bytes = 0, apply_gemv_bytes = 0, factor_flops = 0;
+    int chain_launches = 0, gemv_launches = 0;
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
 };
 
 namespace {
@@ -124,6 +137,13 @@ int dalloc(lsw_plan* p, T** out, size_t count) {
     return LSW_OK;
 }
 
+void dfree(lsw_plan* p, void* ptr) {
+    if (!ptr) return;
+    auto it = std::find(p->allocs.begin(), p->allocs.end(), ptr);
+    if (it != p->allocs.end()) p->allocs.erase(it);
+    (void)hipFree(ptr);
+}
+
 void free_plan(lsw_plan* p) {
     if (!p) return;
     for (void* a : p->allocs) (void)hipFree(a);
@@ -131,9 +151,8 @@ void free_plan(lsw_plan* p) {
     if (p->h_scale) (void)hipHostFree(p->h_scale);
     if (p->h_active) (void)hipHostFree(p->h_active);
     if (p->h_coef) (void)hipHostFree(p->h_coef);
-    if (p->ev0) (void)hipEventDestroy(p->ev0);
-    if (p->ev1) (void)hipEventDestroy(p->ev1);
-    if (p->evm) (void)hipEventDestroy(p->evm);
+    for (hipEvent_t e : p->ev)
+        if (e) (void)hipEventDestroy(e);
     delete p;
 }
 
@@ -222,7 +241,7 @@ void build_schedule(lsw_plan* p) {
     p->fronts.clear();
     auto push_front = [&](std::vector<SolveDesc>& f) {
         if (f.empty()) return;
-        p->fronts.push_back(Front{(int)p->descs.size(), (int)f.size()});
+        p->fronts.push_back(Front{0, (int)p->descs.size(), (int)f.size(), 0, 0});
         p->descs.insert(p->descs.end(), f.begin(), f.end());
         p->max_front = std::max(p->max_front, (int)f.size());
     };
@@ -335,15 +354,94 @@ void build_schedule(lsw_plan* p) {
     }
 }
 
+// slot ranges that carry the polarized right-hand side of each kind (the sets Gamma_1 and
+// Gamma_2 of eq. DiscPol2, each point once; the corner point of an L-shaped interface is
+// taken on its horizontal leg)
+void in_ranges(const SubDesc& s, int kind, GemvSolve& g) {
+    const int W = s.W, H = s.H, r0 = s.r0, r1 = s.r1, c0 = s.c0, c1 = s.c1;
+    const int B0 = 0, B1 = W, T0 = 2 * W, T1 = 3 * W, L0 = 4 * W, L1 = 4 * W + H, R0 = 4 * W + 2 * H,
+              R1 = 4 * W + 3 * H;
+    g.nin = 0;
+    auto add = [&](int start, int len) {
+        if (len <= 0) return;
+        g.in_start[g.nin] = start;
+        g.in_len[g.nin] = len;
+        g.nin++;
+    };
+    switch (kind) {
+        case KIND_B: add(B0, 2 * W); break;
+        case KIND_T: add(T0, 2 * W); break;
+        case KIND_L: add(L0, 2 * H); break;
+        case KIND_R: add(R0, 2 * H); break;
+        case KIND_BL: add(B0 + c0, W - c0); add(B1 + c0, W - c0); add(L0 + r0, H - r0); add(L1 + r0 + 1, H - r0 - 1); break;
+        case KIND_BR: add(B0, c1); add(B1, c1); add(R0 + r0 + 1, H - r0 - 1); add(R1 + r0, H - r0); break;
+        case KIND_TR: add(T0, c1); add(T1, c1); add(R0, r1 - 1); add(R1, r1); break;
+        case KIND_TL: add(T0 + c0, W - c0); add(T1 + c0, W - c0); add(L0, r1); add(L1, r1 - 1); break;
+        default: break;
+    }
+}
+
+// Trace-compressed schedule: stage 1 as block substitutions (traces only), every sweep front
+// as a batched GEMV with Q, and a final block substitution per subdomain for z.
+void compress_schedule(lsw_plan* p) {
+    std::vector<SolveDesc> descs;
+    std::vector<Front> fronts;
+    const Front f0 = p->fronts[0];
+    for (int n = 0; n < f0.count; ++n) {
+        SolveDesc d = p->descs[f0.offset + n];
+        d.zpart = -1;
+        descs.push_back(d);
+    }
+    fronts.push_back(Front{0, 0, f0.count, 0, 0});
+    p->gsolves.clear();
+    p->gitems.clear();
+    for (size_t fi = 1; fi < p->fronts.size(); ++fi) {
+        const Front& f = p->fronts[fi];
+        Front g{1, (int)p->gsolves.size(), f.count, (int)p->gitems.size(), 0};
+        for (int n = 0; n < f.count; ++n) {
+            const SolveDesc& d = p->descs[f.offset + n];
+            const SubDesc& s = p->subs[d.sub];
+            GemvSolve gs;
+            std::memset(&gs, 0, sizeof(gs));
+            gs.sub = d.sub;
+            gs.kind = d.kind;
+            gs.sweep = d.zpart;
+            gs.in_h = d.in_h;
+            gs.in_v = d.in_v;
+            in_ranges(s, d.kind, gs);
+            gs.nout = d.nout;
+            for (int o = 0; o < d.nout; ++o) {
+                gs.out_off[o] = d.out_off[o];
+                gs.out_side[o] = d.out_side[o];
+                gs.out_acc[o] = d.out_acc[o];
+            }
+            const int idx = (int)p->gsolves.size();
+            p->gsolves.push_back(gs);
+            if (d.nout == 0) p->gitems.push_back(GemvItem{idx, -1, 0, 1});
+            for (int o = 0; o < d.nout; ++o) {
+                const int len = (d.out_side[o] == SIDE_B || d.out_side[o] == SIDE_T) ? 2 * s.W : 2 * s.H;
+                for (int c = 0; c * 64 < len; ++c) p->gitems.push_back(GemvItem{idx, o, c, (o == 0 && c == 0) ? 1 : 0});
+            }
+        }
+        g.icount = (int)p->gitems.size() - g.ioffset;
+        fronts.push_back(g);
+    }
+    Front fin{0, (int)descs.size(), (int)p->subs.size(), 0, 0};
+    for (size_t n = 0; n < p->subs.size(); ++n) descs.push_back(blank((int)n, KIND_FINAL, -1, 0, p->subs[n].r0));
+    fronts.push_back(fin);
+    p->descs = descs;
+    p->fronts = fronts;
+    p->max_front = std::max(p->max_front, (int)p->subs.size());
+}
+
 int fail(lsw_plan* p, int code, const std::string& msg) {
     p->err = msg;
     return code;
 }
 
 // ---------------------------------------------------------------- the preconditioner
-int apply_impl(lsw_plan* p, const c128* d_r, c128* d_z, int nrhs, bool timed) {
-    const bool c64 = p->precision == LSW_MIXED;
-    SweepArgs a{};
+ChainArgs chain_args(lsw_plan* p, const c128* d_r, c128* d_z) {
+    ChainArgs a{};
     a.subs = p->d_subs;
     a.geo = p->geo;
     a.G = p->d_G;
@@ -353,16 +451,49 @@ int apply_impl(lsw_plan* p, const c128* d_r, c128* d_z, int nrhs, bool timed) {
     a.Y_stride = p->Y_stride;
     a.zpart = p->d_zpart;
     a.zpart_stride = p->zpart_stride;
+    a.z = d_z;
     a.r = d_r;
-    if (timed) HIPCK(p, hipEventRecord(p->ev0, p->stream));
-    for (const Front& f : p->fronts) {
-        a.descs = p->d_descs + f.offset;
-        HIPCK(p, launch_sweep(a, f.count, nrhs, p->Wmax, c64, p->stream));
+    a.gparts = p->d_gparts;
+    a.LT = p->LT;
+    a.Q = p->d_Q;
+    return a;
+}
+
+int apply_impl(lsw_plan* p, const c128* d_r, c128* d_z, int nrhs, bool timed) {
+    const bool c64 = p->precision == LSW_MIXED;
+    ChainArgs a = chain_args(p, d_r, d_z);
+    GemvArgs ga{p->d_gitems, p->d_gsolves, p->d_subs, p->geo, p->d_Q, p->d_traces, p->trace_stride,
+                p->d_gparts, p->LT};
+    const bool chain_mode = p->sweep_mode == LSW_SWEEP_CHAIN;
+    // events: [0] start, [1] end of the leading block substitutions, [2] end of the
+    // trace-compressed fronts (chained mode: end of z assembly), [3] end
+    if (timed) HIPCK(p, hipEventRecord(p->ev[0], p->stream));
+    if (chain_mode) {
+        for (const Front& f : p->fronts) {
+            a.descs = p->d_descs + f.offset;
+            HIPCK(p, launch_chain(a, f.count, nrhs, p->ept, c64, true, p->stream));
+        }
+        if (timed) HIPCK(p, hipEventRecord(p->ev[1], p->stream));
+        ZsumArgs zs{p->d_zpart, p->zpart_stride, d_z, p->d_xgroup, p->d_ygroup, p->Nx, p->Ny, p->q, p->r};
+        HIPCK(p, launch_zsum(zs, nrhs, c64, p->stream));
+        if (timed) HIPCK(p, hipEventRecord(p->ev[2], p->stream));
+    } else {
+        // fronts are [stage 1 (block substitution)] [sweeps (GEMV)]... [final z (block substitution)]
+        const size_t nf = p->fronts.size();
+        for (size_t fi = 0; fi < nf; ++fi) {
+            const Front& f = p->fronts[fi];
+            if (fi == nf - 1 && timed) HIPCK(p, hipEventRecord(p->ev[2], p->stream));
+            if (f.gemv) {
+                ga.items = p->d_gitems + f.ioffset;
+                HIPCK(p, launch_gemv(ga, f.icount, nrhs, c64, p->stream));
+            } else {
+                a.descs = p->d_descs + f.offset;
+                HIPCK(p, launch_chain(a, f.count, nrhs, p->ept, c64, false, p->stream));
+            }
+            if (fi == 0 && timed) HIPCK(p, hipEventRecord(p->ev[1], p->stream));
+        }
     }
-    if (timed) HIPCK(p, hipEventRecord(p->evm, p->stream));
-    ZsumArgs zs{p->d_zpart, p->zpart_stride, d_z, p->d_xgroup, p->d_ygroup, p->Nx, p->Ny, p->q, p->r};
-    HIPCK(p, launch_zsum(zs, nrhs, c64, p->stream));
-    if (timed) HIPCK(p, hipEventRecord(p->ev1, p->stream));
+    if (timed) HIPCK(p, hipEventRecord(p->ev[3], p->stream));
     return LSW_OK;
 }
 
@@ -578,6 +709,7 @@ int setup_impl(lsw_plan* p, const double* d_m, double omega, double h, const lsw
         if (opts->tol > 0) p->tol = opts->tol;
         if (opts->nrhs_max > 0) p->nrhs_max = opts->nrhs_max;
         p->stream = static_cast<hipStream_t>(opts->stream);
+        p->sweep_mode = opts->sweep_mode == LSW_SWEEP_CHAIN ? LSW_SWEEP_CHAIN : LSW_SWEEP_COMPRESSED;
     }
     p->Nx = p->nx + 2 * p->px;
     p->Ny = p->ny + 2 * p->py;
@@ -647,8 +779,16 @@ int setup_impl(lsw_plan* p, const double* d_m, double omega, double h, const lsw
             s.j = j;
             s.tx = txj[j];
             s.ty = tyi[i];
+            s.sides = (i > 0 ? 1 << SIDE_B : 0) | (i < p->q - 1 ? 1 << SIDE_T : 0) |
+                      (j > 0 ? 1 << SIDE_L : 0) | (j < p->r - 1 ? 1 << SIDE_R : 0);
+            s.L = slot_count(s.W, s.H);
             s.g_off = (long long)p->G_elems;
             p->G_elems += (size_t)s.H * s.W * s.W;
+            s.q_off = (long long)p->Q_elems;
+            p->Q_elems += (size_t)s.L * s.L;
+            s.gp_off = (long long)p->LT;
+            p->LT += (size_t)s.L;
+            p->ept = std::max(p->ept, (s.W + (1024 / s.W) - 1) / (1024 / s.W));
             p->hbase.push_back(p->HT);
             p->vbase.push_back(p->VT);
             p->HT += 2 * (size_t)s.W;
@@ -661,12 +801,33 @@ int setup_impl(lsw_plan* p, const double* d_m, double omega, double h, const lsw
     if (p->Wmax > kMaxWindow)
         return fail(p, LSW_EINVAL, "local window wider than " + std::to_string(kMaxWindow) + " points");
     build_schedule(p);
+    if (p->sweep_mode == LSW_SWEEP_COMPRESSED) compress_schedule(p);
+    else p->Q_elems = 0;
     const size_t eb = p->precision == LSW_MIXED ? sizeof(c64) : sizeof(c128);
-    p->apply_G_bytes = 0;
-    for (const SolveDesc& d : p->descs) {
-        const SubDesc& s = p->subs[d.sub];
-        const double blocks = (s.H - d.kf0) + (s.H - 1 - d.kb0);
-        p->apply_G_bytes += blocks * s.W * (double)s.W * eb;
+    p->apply_chain_bytes = p->apply_gemv_bytes = 0;
+    p->chain_launches = p->gemv_launches = 0;
+    for (const Front& f : p->fronts) {
+        if (f.gemv) {
+            p->gemv_launches++;
+            for (int n = 0; n < f.icount; ++n) {
+                const GemvItem& it = p->gitems[f.ioffset + n];
+                if (it.out < 0) continue;
+                const GemvSolve& g = p->gsolves[it.solve];
+                const SubDesc& s = p->subs[g.sub];
+                int nin = 0;
+                for (int r2 = 0; r2 < g.nin; ++r2) nin += g.in_len[r2];
+                const int len = (g.out_side[it.out] == SIDE_B || g.out_side[it.out] == SIDE_T) ? 2 * s.W : 2 * s.H;
+                p->apply_gemv_bytes += (double)nin * std::min(64, len - 64 * it.chunk) * eb;
+            }
+        } else {
+            p->chain_launches++;
+            for (int n = 0; n < f.count; ++n) {
+                const SolveDesc& d = p->descs[f.offset + n];
+                const SubDesc& s = p->subs[d.sub];
+                const double blocks = (s.H - d.kf0) + (s.H - 1 - d.kb0);
+                p->apply_chain_bytes += blocks * s.W * (double)s.W * eb;
+            }
+        }
     }
     // m: copy, validate
     std::vector<double> hm(p->N);
@@ -683,6 +844,14 @@ int setup_impl(lsw_plan* p, const double* d_m, double omega, double h, const lsw
     HIPCK(p, hipMemcpy(p->d_subs, p->subs.data(), sizeof(SubDesc) * p->subs.size(), hipMemcpyHostToDevice));
     if ((rc = dalloc(p, &p->d_descs, p->descs.size())) != LSW_OK) return rc;
     HIPCK(p, hipMemcpy(p->d_descs, p->descs.data(), sizeof(SolveDesc) * p->descs.size(), hipMemcpyHostToDevice));
+    if (!p->gsolves.empty()) {
+        if ((rc = dalloc(p, &p->d_gsolves, p->gsolves.size())) != LSW_OK) return rc;
+        HIPCK(p, hipMemcpy(p->d_gsolves, p->gsolves.data(), sizeof(GemvSolve) * p->gsolves.size(),
+                           hipMemcpyHostToDevice));
+        if ((rc = dalloc(p, &p->d_gitems, p->gitems.size())) != LSW_OK) return rc;
+        HIPCK(p, hipMemcpy(p->d_gitems, p->gitems.data(), sizeof(GemvItem) * p->gitems.size(),
+                           hipMemcpyHostToDevice));
+    }
     std::vector<int> xg(p->Nx), yg(p->Ny);
     for (int j = 0; j < p->r; ++j)
         for (int x = p->xlo[j]; x < p->xhi[j]; ++x) xg[x] = j;
@@ -695,19 +864,24 @@ int setup_impl(lsw_plan* p, const double* d_m, double omega, double h, const lsw
     const int nsub = (int)p->subs.size();
     if ((rc = dalloc(p, &p->d_status, nsub)) != LSW_OK) return rc;
     HIPCK(p, hipMemset(p->d_status, 0, sizeof(int) * nsub));
-    char* G = nullptr;
-    if ((rc = dalloc(p, &G, p->G_elems * eb)) != LSW_OK) return rc;
-    p->d_G = G;
     p->trace_stride = H_COUNT * p->HT + V_COUNT * p->VT;
     char* tr = nullptr;
     if ((rc = dalloc(p, &tr, p->trace_stride * p->nrhs_max * eb)) != LSW_OK) return rc;
     p->d_traces = tr;
     HIPCK(p, hipMemset(tr, 0, p->trace_stride * p->nrhs_max * eb));
-    p->zpart_stride = (size_t)p->nrhs_max * p->N;
-    char* zp = nullptr;
-    if ((rc = dalloc(p, &zp, 9 * p->zpart_stride * eb)) != LSW_OK) return rc;
-    p->d_zpart = zp;
-    HIPCK(p, hipMemset(zp, 0, 9 * p->zpart_stride * eb));
+    if (p->sweep_mode == LSW_SWEEP_CHAIN) {
+        p->zpart_stride = (size_t)p->nrhs_max * p->N;
+        char* zp = nullptr;
+        if ((rc = dalloc(p, &zp, 9 * p->zpart_stride * eb)) != LSW_OK) return rc;
+        p->d_zpart = zp;
+        HIPCK(p, hipMemset(zp, 0, 9 * p->zpart_stride * eb));
+    } else {
+        // accumulated sweep right-hand sides; slots a sweep never writes stay zero
+        char* gp = nullptr;
+        if ((rc = dalloc(p, &gp, (size_t)p->nrhs_max * 8 * p->LT * eb)) != LSW_OK) return rc;
+        p->d_gparts = gp;
+        HIPCK(p, hipMemset(gp, 0, (size_t)p->nrhs_max * 8 * p->LT * eb));
+    }
     p->Y_stride = (size_t)p->Wmax * p->Hmax;
     char* Y = nullptr;
     if ((rc = dalloc(p, &Y, p->Y_stride * p->max_front * p->nrhs_max * eb)) != LSW_OK) return rc;
@@ -729,16 +903,16 @@ int setup_impl(lsw_plan* p, const double* d_m, double omega, double h, const lsw
     HIPCK(p, hipHostMalloc((void**)&p->h_scale, sizeof(double) * nr, hipHostMallocDefault));
     HIPCK(p, hipHostMalloc((void**)&p->h_active, sizeof(int) * nr, hipHostMallocDefault));
     HIPCK(p, hipHostMalloc((void**)&p->h_coef, sizeof(c128) * nr * m, hipHostMallocDefault));
-    HIPCK(p, hipEventCreate(&p->ev0));
-    HIPCK(p, hipEventCreate(&p->ev1));
-    HIPCK(p, hipEventCreate(&p->evm));
+    for (hipEvent_t& e : p->ev) HIPCK(p, hipEventCreate(&e));
     p->geo.tab = p->d_tab;
     p->geo.m = p->d_m;
     p->geo.Nx = p->Nx;
     p->geo.Ny = p->Ny;
     p->geo.h = h;
     p->geo.omega = omega;
-    // factorisation
+    // factorisation, always in FP64 (complex64 factors are rounded copies)
+    c128* G128 = nullptr;
+    if ((rc = dalloc(p, &G128, p->G_elems)) != LSW_OK) return rc;
     int dev = 0;
     HIPCK(p, hipGetDevice(&dev));
     int max_lds = 0;
@@ -749,7 +923,7 @@ int setup_impl(lsw_plan* p, const double* d_m, double omega, double h, const lsw
     FactorArgs fa{};
     fa.subs = p->d_subs;
     fa.geo = p->geo;
-    fa.G = p->d_G;
+    fa.G = G128;
     fa.status = p->d_status;
     if (!use_lds) {
         if ((rc = dalloc(p, &fa.work, (size_t)nsub * p->Wmax * p->Wmax)) != LSW_OK) return rc;
@@ -757,16 +931,92 @@ int setup_impl(lsw_plan* p, const double* d_m, double omega, double h, const lsw
     }
     HIPCK(p, hipStreamSynchronize(p->stream));
     const auto tf = std::chrono::steady_clock::now();
-    HIPCK(p, launch_factor(fa, nsub, p->Wmax, use_lds, use_lds ? lds_bytes : 0, p->precision == LSW_MIXED,
-                           p->stream));
+    HIPCK(p, launch_factor(fa, nsub, p->Wmax, use_lds, use_lds ? lds_bytes : 0, false, p->stream));
     HIPCK(p, hipStreamSynchronize(p->stream));
     p->t_factor_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tf).count();
+    if (fa.work) dfree(p, fa.work);
     std::vector<int> status(nsub);
     HIPCK(p, hipMemcpy(status.data(), p->d_status, sizeof(int) * nsub, hipMemcpyDeviceToHost));
     for (int s = 0; s < nsub; ++s)
         if (status[s])
             return fail(p, LSW_ESINGULAR, "zero pivot in the block factorisation of subdomain (" +
                                               std::to_string(p->subs[s].i) + "," + std::to_string(p->subs[s].j) + ")");
+    // Q = A_ij^-1 restricted to the trace lines: one unit solve per slot of an interior side
+    if (p->sweep_mode == LSW_SWEEP_COMPRESSED) {
+        const auto tq = std::chrono::steady_clock::now();
+        c128* Q128 = nullptr;
+        if ((rc = dalloc(p, &Q128, p->Q_elems)) != LSW_OK) return rc;
+        HIPCK(p, hipMemsetAsync(Q128, 0, sizeof(c128) * p->Q_elems, p->stream));
+        std::vector<SolveDesc> units;
+        for (int n = 0; n < nsub; ++n) {
+            const SubDesc& s = p->subs[n];
+            const int W = s.W, H = s.H;
+            const int base[4] = {0, 4 * W + 2 * H, 2 * W, 4 * W};   // indexed by Side: B, R, T, L
+            const int len[4] = {2 * W, 2 * H, 2 * W, 2 * H};
+            for (int side = 0; side < 4; ++side) {
+                if (!((s.sides >> side) & 1)) continue;
+                for (int u = 0; u < len[side]; ++u) {
+                    const int sl = base[side] + u;
+                    int k, c;
+                    if (sl < 4 * W) {
+                        const int line = sl / W;
+                        c = sl - line * W;
+                        k = line == 0 ? s.r0 - 1 : line == 1 ? s.r0 : line == 2 ? s.r1 - 1 : s.r1;
+                    } else {
+                        const int v = sl - 4 * W, line = v / H;
+                        k = v - line * H;
+                        c = line == 0 ? s.c0 - 1 : line == 1 ? s.c0 : line == 2 ? s.c1 - 1 : s.c1;
+                    }
+                    SolveDesc d = blank(n, KIND_UNIT, -1, k, 0);
+                    d.unit_k = k;
+                    d.unit_c = c;
+                    d.q_col = s.q_off + (long long)sl * s.L;
+                    units.push_back(d);
+                }
+            }
+        }
+        const int batch = 1024;
+        SolveDesc* d_units = nullptr;
+        c128* Yq = nullptr;
+        if (!units.empty()) {
+            if ((rc = dalloc(p, &d_units, units.size())) != LSW_OK) return rc;
+            HIPCK(p, hipMemcpy(d_units, units.data(), sizeof(SolveDesc) * units.size(), hipMemcpyHostToDevice));
+            if ((rc = dalloc(p, &Yq, p->Y_stride * (size_t)std::min<size_t>(batch, units.size()))) != LSW_OK) return rc;
+        }
+        ChainArgs ua = chain_args(p, nullptr, nullptr);
+        ua.G = G128;
+        ua.Q = Q128;
+        ua.Y = Yq;
+        for (size_t off = 0; off < units.size(); off += batch) {
+            ua.descs = d_units + off;
+            const int cnt = (int)std::min<size_t>(batch, units.size() - off);
+            HIPCK(p, launch_chain(ua, cnt, 1, p->ept, false, false, p->stream));
+        }
+        HIPCK(p, hipStreamSynchronize(p->stream));
+        dfree(p, d_units);
+        dfree(p, Yq);
+        if (p->precision == LSW_MIXED) {
+            c64* Q64 = nullptr;
+            if ((rc = dalloc(p, &Q64, p->Q_elems)) != LSW_OK) return rc;
+            HIPCK(p, launch_cast(Q128, Q64, p->Q_elems, p->stream));
+            HIPCK(p, hipStreamSynchronize(p->stream));
+            dfree(p, Q128);
+            p->d_Q = Q64;
+        } else {
+            p->d_Q = Q128;
+        }
+        p->t_q_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tq).count();
+    }
+    if (p->precision == LSW_MIXED) {
+        c64* G64 = nullptr;
+        if ((rc = dalloc(p, &G64, p->G_elems)) != LSW_OK) return rc;
+        HIPCK(p, launch_cast(G128, G64, p->G_elems, p->stream));
+        HIPCK(p, hipStreamSynchronize(p->stream));
+        dfree(p, G128);
+        p->d_G = G64;
+    } else {
+        p->d_G = G128;
+    }
     p->t_setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     return LSW_OK;
 }
@@ -807,12 +1057,20 @@ int lsw_apply(lsw_handle_t p, const double* d_r, double* d_z, int nrhs) {
     if (rc != LSW_OK) return rc;
     rc = apply_impl(p, reinterpret_cast<const c128*>(d_r), reinterpret_cast<c128*>(d_z), nrhs, true);
     if (rc != LSW_OK) return rc;
-    HIPCK(p, hipEventSynchronize(p->ev1));
-    float ms = 0;
-    HIPCK(p, hipEventElapsedTime(&ms, p->ev0, p->ev1));
-    p->last_apply_ms = ms;
-    HIPCK(p, hipEventElapsedTime(&ms, p->ev0, p->evm));
-    p->last_sweep_ms = ms;
+    HIPCK(p, hipEventSynchronize(p->ev[3]));
+    float t01 = 0, t12 = 0, t23 = 0, t03 = 0;
+    HIPCK(p, hipEventElapsedTime(&t01, p->ev[0], p->ev[1]));
+    HIPCK(p, hipEventElapsedTime(&t12, p->ev[1], p->ev[2]));
+    HIPCK(p, hipEventElapsedTime(&t23, p->ev[2], p->ev[3]));
+    HIPCK(p, hipEventElapsedTime(&t03, p->ev[0], p->ev[3]));
+    p->last_apply_ms = t03;
+    if (p->sweep_mode == LSW_SWEEP_CHAIN) {
+        p->last_chain_ms = t01;
+        p->last_gemv_ms = 0;
+    } else {
+        p->last_chain_ms = t01 + t23;
+        p->last_gemv_ms = t12;
+    }
     return LSW_OK;
 }
 
@@ -877,12 +1135,18 @@ int lsw_query(lsw_handle_t p, lsw_stats_t* st) {
     st->factor_elem_bytes = p->precision == LSW_MIXED ? 8 : 16;
     st->solves_per_apply = (int)p->descs.size();
     st->fronts_per_apply = (int)p->fronts.size();
-    st->apply_G_bytes = p->apply_G_bytes;
+    st->apply_chain_bytes = p->apply_chain_bytes;
+    st->apply_gemv_bytes = p->apply_gemv_bytes;
+    st->chain_launches = p->chain_launches;
+    st->gemv_launches = p->gemv_launches;
+    st->q_elems = (long long)p->Q_elems;
     st->factor_flops = p->factor_flops;
     st->t_setup_ms = p->t_setup_ms;
     st->t_factor_ms = p->t_factor_ms;
+    st->t_q_ms = p->t_q_ms;
     st->last_apply_ms = p->last_apply_ms;
-    st->last_sweep_ms = p->last_sweep_ms;
+    st->last_chain_ms = p->last_chain_ms;
+    st->last_gemv_ms = p->last_gemv_ms;
     return LSW_OK;
 }
 

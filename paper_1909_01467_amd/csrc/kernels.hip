@@ -4,11 +4,15 @@
 //             S_0 = D_0, G_k = S_k^-1, S_{k+1} = D_{k+1} - C_k G_k C_k, one workgroup per
 //             subdomain, the W x W block held in LDS and inverted by Gauss-Jordan with
 //             partial pivoting in FP64; G_k stored column-major in complex64/complex128.
-//  k_sweep    one sweep front: a batch of independent local solves A_ij U = g.  The
-//             right-hand side g = A(chi u~) - chi(A u~) of eq. DiscPol2 is formed on the
-//             fly from the incoming traces (fused prologue), the block forward/back
-//             substitution streams G_k from HBM, and the epilogue writes U on Omega_ij to
-//             the sweep's accumulator and the outgoing 2-line traces (fused epilogue).
+//  k_chain    a batch of independent local solves A_ij U = g by block forward/back
+//             substitution streaming G_k from HBM (stage 1, the final z solve, the unit
+//             solves that build Q, and every front of the chained sweep mode).  The
+//             right-hand side (restricted residual, eq. DiscPol2 polarized source, or the
+//             accumulated sweep sources) is formed on the fly and the epilogue writes the
+//             outgoing 2-line traces, z, or a column of Q.
+//  k_gemv     one sweep front in trace-compressed form: the outgoing traces of each solve
+//             are Q[out lines, in slots] * g with Q = A_ij^-1 restricted to the 8 trace
+//             lines, so the front is one fully parallel batched GEMV.
 //  k_zsum     z on Omega_ij = sum of the per-sweep contributions (end of Alg. Scenario3).
 //  k_matvec   y = A x, FP64, 5-point stencil with coefficients evaluated from the 1-D
 //             PML tables (App. A).
@@ -140,189 +144,236 @@ __global__ __launch_bounds__(NT) void k_factor(FactorArgs a) {
 }
 
 // ------------------------------------------------------------------ K4/K5: one sweep front
+// Geometry and incoming traces of one polarized local solve, held by value so that the
+// compiler keeps everything in registers.
 template <typename T>
 struct Local {
-    const SubDesc& s;
-    const SolveDesc& d;
+    int kind, W, H, r0, r1, c0, c1, tx, ty;
     const c128* tab;
     const cx<T>* in_h;
     const cx<T>* in_v;
     double ih2;
 };
 
-__device__ inline bool chi_of(int kind, int k, int c, const SubDesc& s) {
-    switch (kind) {
-        case KIND_B: return k >= s.r0;
-        case KIND_T: return k < s.r1;
-        case KIND_L: return c >= s.c0;
-        case KIND_R: return c < s.c1;
-        case KIND_BL: return k >= s.r0 && c >= s.c0;
-        case KIND_TR: return k < s.r1 && c < s.c1;
-        case KIND_BR: return k >= s.r0 && c < s.c1;
-        case KIND_TL: return k < s.r1 && c >= s.c0;
+template <typename T>
+__device__ inline Local<T> make_local(const SubDesc& s, int kind, const c128* tab, const cx<T>* in_h,
+                                      const cx<T>* in_v, double ih2) {
+    return Local<T>{kind, s.W, s.H, s.r0, s.r1, s.c0, s.c1, s.tx, s.ty, tab, in_h, in_v, ih2};
+}
+
+template <typename T>
+__device__ inline bool chi_of(const Local<T>& L, int k, int c) {
+    switch (L.kind) {
+        case KIND_B: return k >= L.r0;
+        case KIND_T: return k < L.r1;
+        case KIND_L: return c >= L.c0;
+        case KIND_R: return c < L.c1;
+        case KIND_BL: return k >= L.r0 && c >= L.c0;
+        case KIND_TR: return k < L.r1 && c < L.c1;
+        case KIND_BR: return k >= L.r0 && c < L.c1;
+        case KIND_TL: return k < L.r1 && c >= L.c0;
         default: return false;
     }
 }
 
-// incoming trace value u~ at window point (k, c); 0 off the legs
+// incoming trace value u~ at window point (k, c); 0 off the legs.  The legs of an L-shaped
+// interface are restricted to the receiving quadrant and the horizontal leg is used on the
+// point they share.
 template <typename T>
 __device__ inline cx<T> utilde(const Local<T>& L, int k, int c) {
-    const SubDesc& s = L.s;
-    const int kind = L.d.kind;
+    const int kind = L.kind;
     const bool corner = kind >= KIND_BL;
     const bool hB = (kind == KIND_B || kind == KIND_BL || kind == KIND_BR);
     const bool hT = (kind == KIND_T || kind == KIND_TR || kind == KIND_TL);
     const bool vL = (kind == KIND_L || kind == KIND_BL || kind == KIND_TL);
     const bool vR = (kind == KIND_R || kind == KIND_TR || kind == KIND_BR);
     if (hB || hT) {
-        const int l0 = hB ? s.r0 - 1 : s.r1 - 1;
-        const bool in_cols = !corner || (vL ? c >= s.c0 : c < s.c1);
-        if ((k == l0 || k == l0 + 1) && in_cols) return L.in_h[(k - l0) * s.W + c];
+        const int l0 = hB ? L.r0 - 1 : L.r1 - 1;
+        const bool in_cols = !corner || (vL ? c >= L.c0 : c < L.c1);
+        if ((k == l0 || k == l0 + 1) && in_cols) return L.in_h[(k - l0) * L.W + c];
     }
     if (vL || vR) {
-        const int l0 = vL ? s.c0 - 1 : s.c1 - 1;
-        const bool in_rows = !corner || (hB ? k >= s.r0 : k < s.r1);
-        if ((c == l0 || c == l0 + 1) && in_rows) return L.in_v[(c - l0) * s.H + k];
+        const int l0 = vL ? L.c0 - 1 : L.c1 - 1;
+        const bool in_rows = !corner || (hB ? k >= L.r0 : k < L.r1);
+        if ((c == l0 || c == l0 + 1) && in_rows) return L.in_v[(c - l0) * L.H + k];
     }
     return cx<T>{T(0), T(0)};
 }
 
-// g at (k, c): sum over the 4 neighbours q across the boundary of chi of A_pq (chi_q - chi_p) u~_q
+// g at (k, c) = (A(chi u~) - chi (A u~))(k, c): sum over the 4 neighbours q across the
+// boundary of chi of A_pq (chi_q - chi_p) u~_q (eq. DiscPol2)
 template <typename T>
 __device__ inline cx<T> g_polarized(const Local<T>& L, int k, int c) {
-    const SubDesc& s = L.s;
-    const int kind = L.d.kind;
+    const int kind = L.kind;
     const bool has_v = !(kind == KIND_B || kind == KIND_T);
     if (!has_v) {  // straight horizontal interface: only its two lines carry g
-        const int l0 = (kind == KIND_B) ? s.r0 - 1 : s.r1 - 1;
+        const int l0 = (kind == KIND_B) ? L.r0 - 1 : L.r1 - 1;
         if (k != l0 && k != l0 + 1) return cx<T>{T(0), T(0)};
     }
-    const bool cp = chi_of(kind, k, c, s);
+    const bool cp = chi_of(L, k, c);
     c128 g = mk(0.0, 0.0);
-    const int W = s.W, H = s.H;
-    if (c > 0 && chi_of(kind, k, c - 1, s) != cp) {
-        c128 A = coup_x(L.tab, s.tx, W, s.ty, c - 1, k, L.ih2);
+    const int W = L.W, H = L.H;
+    if (c > 0 && chi_of(L, k, c - 1) != cp) {
+        c128 A = coup_x(L.tab, L.tx, W, L.ty, c - 1, k, L.ih2);
         c128 u = cvt<double>(utilde(L, k, c - 1));
         g = cp ? g - A * u : g + A * u;
     }
-    if (c + 1 < W && chi_of(kind, k, c + 1, s) != cp) {
-        c128 A = coup_x(L.tab, s.tx, W, s.ty, c, k, L.ih2);
+    if (c + 1 < W && chi_of(L, k, c + 1) != cp) {
+        c128 A = coup_x(L.tab, L.tx, W, L.ty, c, k, L.ih2);
         c128 u = cvt<double>(utilde(L, k, c + 1));
         g = cp ? g - A * u : g + A * u;
     }
-    if (k > 0 && chi_of(kind, k - 1, c, s) != cp) {
-        c128 A = coup_y(L.tab, s.tx, s.ty, H, c, k - 1, L.ih2);
+    if (k > 0 && chi_of(L, k - 1, c) != cp) {
+        c128 A = coup_y(L.tab, L.tx, L.ty, H, c, k - 1, L.ih2);
         c128 u = cvt<double>(utilde(L, k - 1, c));
         g = cp ? g - A * u : g + A * u;
     }
-    if (k + 1 < H && chi_of(kind, k + 1, c, s) != cp) {
-        c128 A = coup_y(L.tab, s.tx, s.ty, H, c, k, L.ih2);
+    if (k + 1 < H && chi_of(L, k + 1, c) != cp) {
+        c128 A = coup_y(L.tab, L.tx, L.ty, H, c, k, L.ih2);
         c128 u = cvt<double>(utilde(L, k + 1, c));
         g = cp ? g - A * u : g + A * u;
     }
     return cvt<T>(g);
 }
 
-template <typename T, int RC>
-__global__ __launch_bounds__(256) void k_sweep(SweepArgs a) {
-    constexpr int NT = 256, NW = NT / 64, WM = 64 * RC;
-    const SolveDesc d = a.descs[blockIdx.x];
+// right-hand side of a block row element (k, c) for the kinds that are not polarized
+template <typename T>
+__device__ inline cx<T> rhs_plain(const ChainArgs& a, const SolveDesc& d, const SubDesc& s, int rhs, int k, int c) {
+    const size_t N = (size_t)a.geo.Nx * a.geo.Ny;
+    if (d.kind == KIND_UNIT) return (k == d.unit_k && c == d.unit_c) ? cx<T>{T(1), T(0)} : cx<T>{T(0), T(0)};
+    c128 g = mk(0.0, 0.0);
+    if (k >= s.r0 && k < s.r1 && c >= s.c0 && c < s.c1)
+        g = a.r[(size_t)rhs * N + (size_t)(s.wy0 + k) * a.geo.Nx + s.wx0 + c];
+    cx<T> out = cvt<T>(g);
+    if (d.kind == KIND_FINAL) {
+        // sum of the sweeps' right-hand sides g_s (each supported on the trace-line slots)
+        const int W = s.W, H = s.H;
+        const cx<T>* gp = reinterpret_cast<const cx<T>*>(a.gparts) + (size_t)rhs * 8 * a.LT + s.gp_off;
+        for (int sw = 0; sw < 8; ++sw, gp += a.LT) {
+            if (k == s.r0 - 1) out = out + gp[c];
+            if (k == s.r0) out = out + gp[W + c];
+            if (k == s.r1 - 1) out = out + gp[2 * W + c];
+            if (k == s.r1 && k < H) out = out + gp[3 * W + c];
+            if (c == s.c0 - 1) out = out + gp[4 * W + k];
+            if (c == s.c0) out = out + gp[4 * W + H + k];
+            if (c == s.c1 - 1) out = out + gp[4 * W + 2 * H + k];
+            if (c == s.c1 && c < W) out = out + gp[4 * W + 3 * H + k];
+        }
+    }
+    return out;
+}
+
+// Batched block forward/back substitution, one workgroup per (local solve, rhs).
+// Thread tid < NA = floor(1024/W)*W owns block row t = tid % W and the columns
+// c = tid / W + NG*j (j < ept) of every W x W block G_k: its elements sit at the flat
+// offsets tid + NA*j of the column-major block, so the loads are fully coalesced.  A ring
+// of PD+1 register buffers keeps PD blocks in flight ahead of the current one.
+template <typename T, int EPT, int PD, bool POLAR>
+__global__ __launch_bounds__(1024) void k_chain(ChainArgs a) {
+    constexpr int NT = 1024;
+    const SolveDesc& d = a.descs[blockIdx.x];
     const SubDesc s = a.subs[d.sub];
     const int rhs = blockIdx.y;
-    const int W = s.W, H = s.H, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    __shared__ cx<T> v[WM], xk[WM];
-    __shared__ cx<T> part[NW][WM];
+    const int W = s.W, H = s.H, tid = threadIdx.x;
+    const int NG = NT / W, NA = NG * W;
+    const bool act = tid < NA;
+    const int cg = act ? tid / W : 0;
+    const int ept = (W + NG - 1) / NG;
+    const int WW = W * W;
+    __shared__ cx<T> v[kMaxWindow], xk[kMaxWindow];
+    __shared__ cx<T> part[NT];
 
     const c128* tab = a.geo.tab;
     const double ih2 = 1.0 / (a.geo.h * a.geo.h);
     const cx<T>* Gs = reinterpret_cast<const cx<T>*>(a.G) + s.g_off;
     cx<T>* tr = reinterpret_cast<cx<T>*>(a.traces) + (size_t)rhs * a.trace_stride;
     cx<T>* Y = reinterpret_cast<cx<T>*>(a.Y) + ((size_t)blockIdx.y * gridDim.x + blockIdx.x) * a.Y_stride;
-    cx<T>* z = reinterpret_cast<cx<T>*>(a.zpart) + (size_t)d.zpart * a.zpart_stride +
-               (size_t)rhs * a.geo.Nx * a.geo.Ny;
-    const c128* rin = a.r + (size_t)rhs * a.geo.Nx * a.geo.Ny;
-    Local<T> L{s, d, tab, d.in_h >= 0 ? tr + d.in_h : nullptr, d.in_v >= 0 ? tr + d.in_v : nullptr, ih2};
+    const bool polar = d.kind >= KIND_B && d.kind <= KIND_TL;
+    const Local<T> L = make_local<T>(s, d.kind, tab, d.in_h >= 0 ? tr + d.in_h : nullptr,
+                                     d.in_v >= 0 ? tr + d.in_v : nullptr, ih2);
+    const cx<T> zero{T(0), T(0)};
 
+    auto load = [&](int k, cx<T>* buf) {
+        const cx<T>* Gk = Gs + (size_t)k * WW;
+#pragma unroll
+        for (int j = 0; j < EPT; ++j) {
+            const int e = tid + NA * j;
+            buf[j] = (act && j < ept && e < WW) ? Gk[e] : zero;
+        }
+    };
+    // part[tid] = sum_j G_k[c_j][t] vin[c_j]
+    auto gemv = [&](const cx<T>* buf) {
+        cx<T> acc = zero;
+#pragma unroll
+        for (int j = 0; j < EPT; ++j) {
+            const int c = cg + NG * j;
+            if (j < ept && c < W) acc = fma(acc, buf[j], v[c]);
+        }
+        if (act) part[tid] = acc;
+    };
+    auto reduce = [&](int t) {
+        cx<T> y = part[t];
+        for (int g = 1; g < NG; ++g) y = y + part[g * W + t];
+        return y;
+    };
+
+    cx<T> ring[PD + 1][EPT];
     // ---- forward substitution: y_k = G_k (g_k - C_{k-1} y_{k-1})
-    for (int k = d.kf0; k < H; ++k) {
-        for (int c = tid; c < W; c += NT) {
+    auto fwd = [&](int k, const cx<T>* buf) {
+        if (tid < W) {
             cx<T> g;
-            if (d.kind == KIND_STAGE1) {
-                const bool in = (k >= s.r0 && k < s.r1 && c >= s.c0 && c < s.c1);
-                g = in ? cvt<T>(rin[(size_t)(s.wy0 + k) * a.geo.Nx + s.wx0 + c]) : cx<T>{T(0), T(0)};
-            } else {
-                g = g_polarized(L, k, c);
+            if constexpr (POLAR) g = polar ? g_polarized(L, k, tid) : rhs_plain<T>(a, d, s, rhs, k, tid);
+            else g = rhs_plain<T>(a, d, s, rhs, k, tid);
+            if (k > d.kf0) g = g - cvt<T>(coup_y(tab, s.tx, s.ty, H, tid, k - 1, ih2)) * xk[tid];
+            v[tid] = g;
+        }
+        __syncthreads();
+        gemv(buf);
+        __syncthreads();
+        if (tid < W) {
+            const cx<T> y = reduce(tid);
+            xk[tid] = y;
+            Y[(size_t)k * W + tid] = y;
+        }
+        __syncthreads();
+    };
+#pragma unroll
+    for (int p = 0; p < PD; ++p)
+        if (d.kf0 + p < H) load(d.kf0 + p, ring[p]);
+    for (int k0 = d.kf0; k0 < H; k0 += PD + 1) {
+#pragma unroll
+        for (int u = 0; u <= PD; ++u) {
+            const int k = k0 + u;
+            if (k < H) {
+                if (k + PD < H) load(k + PD, ring[(u + PD) % (PD + 1)]);
+                fwd(k, ring[u]);
             }
-            if (k > d.kf0) g = g - cvt<T>(coup_y(tab, s.tx, s.ty, H, c, k - 1, ih2)) * xk[c];
-            v[c] = g;
         }
-        __syncthreads();
-        const cx<T>* Gk = Gs + (size_t)k * W * W;
-        cx<T> acc[RC];
-#pragma unroll
-        for (int q = 0; q < RC; ++q) acc[q] = cx<T>{T(0), T(0)};
-#pragma unroll 4
-        for (int c = wv; c < W; c += NW) {
-            const cx<T> vc = v[c];
-            const cx<T>* col = Gk + (size_t)c * W;
-#pragma unroll
-            for (int q = 0; q < RC; ++q) {
-                const int t = lane + 64 * q;
-                if (t < W) acc[q] = fma(acc[q], col[t], vc);
-            }
-        }
-#pragma unroll
-        for (int q = 0; q < RC; ++q) {
-            const int t = lane + 64 * q;
-            if (t < W) part[wv][t] = acc[q];
-        }
-        __syncthreads();
-        for (int t = tid; t < W; t += NT) {
-            cx<T> y = part[0][t];
-#pragma unroll
-            for (int w = 1; w < NW; ++w) y = y + part[w][t];
-            xk[t] = y;
-            Y[(size_t)k * W + t] = y;
-        }
-        __syncthreads();
     }
 
-    // ---- backward substitution: x_k = y_k - G_k C_k x_{k+1}; xk holds x_{H-1} = y_{H-1}
-    for (int k = H - 1; k >= d.kb0; --k) {
-        if (k < H - 1) {
-            for (int c = tid; c < W; c += NT) v[c] = cvt<T>(coup_y(tab, s.tx, s.ty, H, c, k, ih2)) * xk[c];
-            __syncthreads();
-            const cx<T>* Gk = Gs + (size_t)k * W * W;
-            cx<T> acc[RC];
-#pragma unroll
-            for (int q = 0; q < RC; ++q) acc[q] = cx<T>{T(0), T(0)};
-#pragma unroll 4
-            for (int c = wv; c < W; c += NW) {
-                const cx<T> vc = v[c];
-                const cx<T>* col = Gk + (size_t)c * W;
-#pragma unroll
-                for (int q = 0; q < RC; ++q) {
-                    const int t = lane + 64 * q;
-                    if (t < W) acc[q] = fma(acc[q], col[t], vc);
-                }
+    // ---- epilogue of one block row (x_k in xk)
+    auto emit = [&](int k) {
+        if (d.kind == KIND_FINAL) {
+            if (k >= s.r0 && k < s.r1) {
+                c128* zrow = a.z + (size_t)rhs * a.geo.Nx * a.geo.Ny + (size_t)(s.wy0 + k) * a.geo.Nx + s.wx0;
+                for (int c = s.c0 + tid; c < s.c1; c += NT) zrow[c] = cvt<double>(xk[c]);
             }
-#pragma unroll
-            for (int q = 0; q < RC; ++q) {
-                const int t = lane + 64 * q;
-                if (t < W) part[wv][t] = acc[q];
-            }
-            __syncthreads();
-            for (int t = tid; t < W; t += NT) {
-                cx<T> y = (k >= d.kf0) ? Y[(size_t)k * W + t] : cx<T>{T(0), T(0)};
-#pragma unroll
-                for (int w = 0; w < NW; ++w) y = y - part[w][t];
-                xk[t] = y;
-            }
-            __syncthreads();
-        }
-        // ---- epilogue for block row k
-        if (k >= s.r0 && k < s.r1) {
-            cx<T>* zrow = z + (size_t)(s.wy0 + k) * a.geo.Nx + s.wx0;
+        } else if (d.kind == KIND_UNIT) {
+            cx<T>* col = reinterpret_cast<cx<T>*>(a.Q) + d.q_col;
+            const int hb = (s.sides >> SIDE_B) & 1, ht = (s.sides >> SIDE_T) & 1;
+            const int hl = (s.sides >> SIDE_L) & 1, hr = (s.sides >> SIDE_R) & 1;
+            int off = -1;
+            if (hb && k == s.r0 - 1) off = 0;
+            if (hb && k == s.r0) off = W;
+            if (ht && k == s.r1 - 1) off = 2 * W;
+            if (ht && k == s.r1) off = 3 * W;
+            if (off >= 0)
+                for (int c = tid; c < W; c += NT) col[off + c] = xk[c];
+            if (tid == 0 && hl) { col[4 * W + k] = xk[s.c0 - 1]; col[4 * W + H + k] = xk[s.c0]; }
+            if (tid == 1 && hr) { col[4 * W + 2 * H + k] = xk[s.c1 - 1]; col[4 * W + 3 * H + k] = xk[s.c1]; }
+        } else if (d.zpart >= 0 && k >= s.r0 && k < s.r1) {
+            cx<T>* zrow = reinterpret_cast<cx<T>*>(a.zpart) + (size_t)d.zpart * a.zpart_stride +
+                          (size_t)rhs * a.geo.Nx * a.geo.Ny + (size_t)(s.wy0 + k) * a.geo.Nx + s.wx0;
             for (int c = s.c0 + tid; c < s.c1; c += NT) zrow[c] = xk[c];
         }
         for (int o = 0; o < d.nout; ++o) {
@@ -343,7 +394,115 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs a) {
                 }
             }
         }
+    };
+
+    // ---- backward substitution: x_k = y_k - G_k C_k x_{k+1}; xk holds x_{H-1} = y_{H-1}
+    emit(H - 1);
+    auto bwd = [&](int k, const cx<T>* buf) {
+        if (tid < W) v[tid] = cvt<T>(coup_y(tab, s.tx, s.ty, H, tid, k, ih2)) * xk[tid];
+        __syncthreads();
+        gemv(buf);
+        __syncthreads();
+        if (tid < W) {
+            const cx<T> y = (k >= d.kf0) ? Y[(size_t)k * W + tid] : zero;
+            xk[tid] = y - reduce(tid);
+        }
+        __syncthreads();
+        emit(k);
+    };
+    const int kstart = H - 2;
+#pragma unroll
+    for (int p = 0; p < PD; ++p)
+        if (kstart - p >= d.kb0) load(kstart - p, ring[p]);
+    for (int k0 = kstart; k0 >= d.kb0; k0 -= PD + 1) {
+#pragma unroll
+        for (int u = 0; u <= PD; ++u) {
+            const int k = k0 - u;
+            if (k >= d.kb0) {
+                if (k - PD >= d.kb0) load(k - PD, ring[(u + PD) % (PD + 1)]);
+                bwd(k, ring[u]);
+            }
+        }
     }
+}
+
+// slot -> window point of the trace-line layout (see common.h)
+__device__ inline void slot_point(const SubDesc& s, int sl, int& k, int& c) {
+    const int W = s.W, H = s.H;
+    if (sl < 4 * W) {
+        const int line = sl / W;
+        c = sl - line * W;
+        k = (line == 0) ? s.r0 - 1 : (line == 1) ? s.r0 : (line == 2) ? s.r1 - 1 : s.r1;
+    } else {
+        const int v = sl - 4 * W, line = v / H;
+        k = v - line * H;
+        c = (line == 0) ? s.c0 - 1 : (line == 1) ? s.c0 : (line == 2) ? s.c1 - 1 : s.c1;
+    }
+}
+
+// Trace-compressed sweep front: out = Q[out side, in slots] g[in slots].
+template <typename T>
+__global__ __launch_bounds__(256) void k_gemv(GemvArgs a) {
+    constexpr int NT = 256, NW = 4;
+    const GemvItem it = a.items[blockIdx.x];
+    const GemvSolve& d = a.solves[it.solve];
+    const SubDesc s = a.subs[d.sub];
+    const int rhs = blockIdx.y, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    __shared__ cx<T> gv[4 * kMaxWindow];
+    __shared__ int slot[4 * kMaxWindow];
+    __shared__ cx<T> part[NW][64];
+    cx<T>* tr = reinterpret_cast<cx<T>*>(a.traces) + (size_t)rhs * a.trace_stride;
+    const double ih2 = 1.0 / (a.geo.h * a.geo.h);
+    const Local<T> L = make_local<T>(s, d.kind, a.geo.tab, d.in_h >= 0 ? tr + d.in_h : nullptr,
+                                     d.in_v >= 0 ? tr + d.in_v : nullptr, ih2);
+    int total = 0;
+    for (int r = 0; r < d.nin; ++r) total += d.in_len[r];
+    cx<T>* gp = reinterpret_cast<cx<T>*>(a.gparts) + ((size_t)rhs * 8 + (d.sweep - 1)) * a.LT + s.gp_off;
+    for (int idx = tid; idx < total; idx += NT) {
+        int r = 0, off = idx;
+        while (off >= d.in_len[r]) { off -= d.in_len[r]; ++r; }
+        const int sl = d.in_start[r] + off;
+        int k, c;
+        slot_point(s, sl, k, c);
+        const cx<T> g = g_polarized(L, k, c);
+        slot[idx] = sl;
+        gv[idx] = g;
+        if (it.first) gp[sl] = g;
+    }
+    __syncthreads();
+    if (it.out < 0) return;   // a solve without outgoing traces only stores its g
+    const int side = d.out_side[it.out];
+    const int sb = (side == SIDE_B) ? 0 : (side == SIDE_T) ? 2 * s.W : (side == SIDE_L) ? 4 * s.W : 4 * s.W + 2 * s.H;
+    const int len = (side == SIDE_B || side == SIDE_T) ? 2 * s.W : 2 * s.H;
+    const int o = it.chunk * 64 + lane;
+    const cx<T>* Qs = reinterpret_cast<const cx<T>*>(a.Q) + s.q_off + sb + o;
+    cx<T> acc{T(0), T(0)};
+    if (o < len) {
+        int idx = wv;
+        for (; idx + 3 * NW < total; idx += 4 * NW) {
+            const cx<T> q0 = Qs[(size_t)slot[idx] * s.L];
+            const cx<T> q1 = Qs[(size_t)slot[idx + NW] * s.L];
+            const cx<T> q2 = Qs[(size_t)slot[idx + 2 * NW] * s.L];
+            const cx<T> q3 = Qs[(size_t)slot[idx + 3 * NW] * s.L];
+            acc = fma(acc, q0, gv[idx]);
+            acc = fma(acc, q1, gv[idx + NW]);
+            acc = fma(acc, q2, gv[idx + 2 * NW]);
+            acc = fma(acc, q3, gv[idx + 3 * NW]);
+        }
+        for (; idx < total; idx += NW) acc = fma(acc, Qs[(size_t)slot[idx] * s.L], gv[idx]);
+    }
+    part[wv][lane] = acc;
+    __syncthreads();
+    if (wv == 0 && o < len) {
+        const cx<T> val = part[0][lane] + part[1][lane] + part[2][lane] + part[3][lane];
+        cx<T>* p = tr + d.out_off[it.out] + o;
+        *p = d.out_acc[it.out] ? *p + val : val;
+    }
+}
+
+__global__ void k_cast(const c128* src, c64* dst, size_t n) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        dst[i] = c64{static_cast<float>(src[i].re), static_cast<float>(src[i].im)};
 }
 
 // ------------------------------------------------------------------ z assembly
@@ -407,17 +566,24 @@ __global__ void k_dots_partial(DotsArgs a) {
     if (threadIdx.x == 0) a.partial[((size_t)rhs * a.nv + l) * gridDim.x + blk] = red[0];
 }
 
-// out[rhs * ostride + l] (+)= sum_blk partial ; one thread per (l, rhs)
+// out[rhs * ostride + l] (+)= sum_blk partial ; one workgroup per (l, rhs), fixed order
 __global__ void k_dots_finish(const c128* partial, int nblk, int nv, int nrhs, c128* out, int ostride,
                               int accumulate) {
-    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= nv * nrhs) return;
-    const int rhs = idx / nv, l = idx % nv;
-    c128 acc = mk(0.0, 0.0);
+    __shared__ c128 red[256];
+    const int l = blockIdx.x, rhs = blockIdx.y;
     const c128* pp = partial + ((size_t)rhs * nv + l) * nblk;
-    for (int b = 0; b < nblk; ++b) acc = acc + pp[b];
-    c128* o = out + (size_t)rhs * ostride + l;
-    *o = accumulate ? *o + acc : acc;
+    c128 acc = mk(0.0, 0.0);
+    for (int b = threadIdx.x; b < nblk; b += blockDim.x) acc = acc + pp[b];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int off = blockDim.x / 2; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) red[threadIdx.x] = red[threadIdx.x] + red[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        c128* o = out + (size_t)rhs * ostride + l;
+        *o = accumulate ? *o + red[0] : red[0];
+    }
 }
 
 // w -= sum_l V_l c_l   (c = coefficients on the device, [rhs * cstride + l]); masked rhs skipped
@@ -490,19 +656,41 @@ hipError_t launch_factor(const FactorArgs& a, int nsub, int Wmax, bool use_lds, 
     return hipGetLastError();
 }
 
-template <typename T>
-static hipError_t launch_sweep_t(const SweepArgs& a, int nsolves, int nrhs, int Wmax, hipStream_t st) {
+// prefetch depth: as many blocks in flight as the 128-VGPR budget of a 1024-thread
+// workgroup allows (complex64: 2 floats, complex128: 4 per element)
+template <typename T, bool POLAR>
+static void launch_chain_p(const ChainArgs& a, dim3 grid, int ept, hipStream_t st) {
+    constexpr bool dbl = sizeof(T) == 8;
+    if (ept <= 4) k_chain<T, 4, 2, POLAR><<<grid, 1024, 0, st>>>(a);
+    else if (ept <= 8) k_chain<T, 8, dbl ? 1 : 2, POLAR><<<grid, 1024, 0, st>>>(a);
+    else if (ept <= 16) k_chain<T, 16, dbl ? 0 : 1, POLAR><<<grid, 1024, 0, st>>>(a);
+    else if (ept <= 32) k_chain<T, 32, 0, POLAR><<<grid, 1024, 0, st>>>(a);
+    else k_chain<T, 64, 0, POLAR><<<grid, 1024, 0, st>>>(a);
+}
+
+hipError_t launch_chain(const ChainArgs& a, int nsolves, int nrhs, int ept, bool c64mode, bool polar,
+                        hipStream_t st) {
     dim3 grid(nsolves, nrhs);
-    if (Wmax <= 64) k_sweep<T, 1><<<grid, 256, 0, st>>>(a);
-    else if (Wmax <= 128) k_sweep<T, 2><<<grid, 256, 0, st>>>(a);
-    else if (Wmax <= 192) k_sweep<T, 3><<<grid, 256, 0, st>>>(a);
-    else k_sweep<T, 4><<<grid, 256, 0, st>>>(a);
+    if (c64mode) {
+        if (polar) launch_chain_p<float, true>(a, grid, ept, st);
+        else launch_chain_p<float, false>(a, grid, ept, st);
+    } else {
+        if (polar) launch_chain_p<double, true>(a, grid, ept, st);
+        else launch_chain_p<double, false>(a, grid, ept, st);
+    }
     return hipGetLastError();
 }
 
-hipError_t launch_sweep(const SweepArgs& a, int nsolves, int nrhs, int Wmax, bool c64mode, hipStream_t st) {
-    return c64mode ? launch_sweep_t<float>(a, nsolves, nrhs, Wmax, st)
-                   : launch_sweep_t<double>(a, nsolves, nrhs, Wmax, st);
+hipError_t launch_gemv(const GemvArgs& a, int nitems, int nrhs, bool c64mode, hipStream_t st) {
+    dim3 grid(nitems, nrhs);
+    if (c64mode) k_gemv<float><<<grid, 256, 0, st>>>(a);
+    else k_gemv<double><<<grid, 256, 0, st>>>(a);
+    return hipGetLastError();
+}
+
+hipError_t launch_cast(const c128* src, c64* dst, size_t n, hipStream_t st) {
+    k_cast<<<2048, 256, 0, st>>>(src, dst, n);
+    return hipGetLastError();
 }
 
 hipError_t launch_zsum(const ZsumArgs& a, int nrhs, bool c64mode, hipStream_t st) {
@@ -523,8 +711,7 @@ hipError_t launch_matvec(const MatvecArgs& a, int nrhs, hipStream_t st) {
 hipError_t launch_dots(const DotsArgs& a, int nrhs, c128* out, int ostride, int accumulate, hipStream_t st) {
     dim3 grid(a.nblk, a.nv, nrhs);
     k_dots_partial<<<grid, 256, 0, st>>>(a);
-    const int n = a.nv * nrhs;
-    k_dots_finish<<<blocks_for(n, 64), 64, 0, st>>>(a.partial, a.nblk, a.nv, nrhs, out, ostride, accumulate);
+    k_dots_finish<<<dim3(a.nv, nrhs), 256, 0, st>>>(a.partial, a.nblk, a.nv, nrhs, out, ostride, accumulate);
     return hipGetLastError();
 }
 

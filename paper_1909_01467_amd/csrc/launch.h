@@ -16,7 +16,7 @@ struct FactorArgs {
     int* status;          // per subdomain: 1 if a zero pivot was met
 };
 
-struct SweepArgs {
+struct ChainArgs {
     const SolveDesc* descs;
     const SubDesc* subs;
     Geometry geo;
@@ -25,9 +25,25 @@ struct SweepArgs {
     size_t trace_stride;    // elements between right-hand sides
     void* Y;                // forward-substitution scratch, one slab per (solve, rhs)
     size_t Y_stride;
-    void* zpart;            // [9][nrhs_max][N] per-sweep accumulators
+    void* zpart;            // [9][nrhs_max][N] per-sweep accumulators (chained sweep mode)
     size_t zpart_stride;    // nrhs_max * N
-    const c128* r;          // stage-1 input [nrhs][N]
+    c128* z;                // final output (KIND_FINAL)
+    const c128* r;          // input [nrhs][N]
+    const void* gparts;     // accumulated sweep right-hand sides [nrhs][8][LT] (KIND_FINAL)
+    size_t LT;              // slots of all windows
+    void* Q;                // Q pool (KIND_UNIT writes columns)
+};
+
+struct GemvArgs {
+    const GemvItem* items;
+    const GemvSolve* solves;
+    const SubDesc* subs;
+    Geometry geo;
+    const void* Q;
+    void* traces;
+    size_t trace_stride;
+    void* gparts;
+    size_t LT;
 };
 
 struct ZsumArgs {
@@ -72,7 +88,12 @@ struct GsArgs {
 
 hipError_t launch_factor(const FactorArgs& a, int nsub, int Wmax, bool use_lds, size_t lds_bytes,
                          bool store_c64, hipStream_t st);
-hipError_t launch_sweep(const SweepArgs& a, int nsolves, int nrhs, int Wmax, bool c64mode, hipStream_t st);
+// ept = max over the launched windows of ceil(W / floor(1024 / W)) (elements per thread)
+// polar: the batch may contain polarized kinds (chained sweep mode)
+hipError_t launch_chain(const ChainArgs& a, int nsolves, int nrhs, int ept, bool c64mode, bool polar,
+                        hipStream_t st);
+hipError_t launch_gemv(const GemvArgs& a, int nitems, int nrhs, bool c64mode, hipStream_t st);
+hipError_t launch_cast(const c128* src, c64* dst, size_t n, hipStream_t st);
 hipError_t launch_zsum(const ZsumArgs& a, int nrhs, bool c64mode, hipStream_t st);
 hipError_t launch_matvec(const MatvecArgs& a, int nrhs, hipStream_t st);
 hipError_t launch_dots(const DotsArgs& a, int nrhs, c128* out, int ostride, int accumulate, hipStream_t st);

@@ -24,6 +24,7 @@ _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "liblsw.so"
 
 LSW_OK, LSW_EINVAL, LSW_ENOMEM, LSW_EHIP, LSW_ESINGULAR, LSW_ENAN, LSW_ENOCONV = 0, -1, -2, -3, -4, -5, -6
 LSW_FP64, LSW_MIXED = 0, 1
+LSW_SWEEP_COMPRESSED, LSW_SWEEP_CHAIN = 0, 1
 _NAMES = {0: "LSW_OK", -1: "LSW_EINVAL", -2: "LSW_ENOMEM", -3: "LSW_EHIP", -4: "LSW_ESINGULAR",
           -5: "LSW_ENAN", -6: "LSW_ENOCONV"}
 EXPORTS = ("lsw_setup", "lsw_apply", "lsw_solve", "lsw_adjoint", "lsw_matvec", "lsw_mass_gradient",
@@ -44,7 +45,8 @@ class lsw_pml_t(ctypes.Structure):
 
 class lsw_opts_t(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("restart", ctypes.c_int), ("maxit", ctypes.c_int),
-                ("tol", ctypes.c_double), ("nrhs_max", ctypes.c_int), ("stream", ctypes.c_void_p)]
+                ("tol", ctypes.c_double), ("nrhs_max", ctypes.c_int), ("stream", ctypes.c_void_p),
+                ("sweep_mode", ctypes.c_int)]
 
 
 class lsw_rhs_info_t(ctypes.Structure):
@@ -61,9 +63,11 @@ class lsw_stats_t(ctypes.Structure):
                 ("W_max", ctypes.c_int), ("H_max", ctypes.c_int), ("N", ctypes.c_longlong),
                 ("factor_elems", ctypes.c_longlong), ("factor_elem_bytes", ctypes.c_int),
                 ("solves_per_apply", ctypes.c_int), ("fronts_per_apply", ctypes.c_int),
-                ("apply_G_bytes", ctypes.c_double), ("factor_flops", ctypes.c_double),
-                ("t_setup_ms", ctypes.c_double), ("t_factor_ms", ctypes.c_double),
-                ("last_apply_ms", ctypes.c_double), ("last_sweep_ms", ctypes.c_double)]
+                ("apply_chain_bytes", ctypes.c_double), ("apply_gemv_bytes", ctypes.c_double),
+                ("chain_launches", ctypes.c_int), ("gemv_launches", ctypes.c_int), ("q_elems", ctypes.c_longlong),
+                ("factor_flops", ctypes.c_double), ("t_setup_ms", ctypes.c_double),
+                ("t_factor_ms", ctypes.c_double), ("t_q_ms", ctypes.c_double), ("last_apply_ms", ctypes.c_double),
+                ("last_chain_ms", ctypes.c_double), ("last_gemv_ms", ctypes.c_double)]
 
 
 _lib = None
@@ -131,7 +135,8 @@ class Solver:
 
     def __init__(self, m_ext: torch.Tensor, omega: float, h: float, n, n_pml, q: int, r: int | None = None,
                  C: float | None = None, n_pml_local: int | None = None, precision: str = "fp64",
-                 restart: int = 50, maxit: int = 500, tol: float = 1e-6, nrhs_max: int = 1):
+                 restart: int = 50, maxit: int = 500, tol: float = 1e-6, nrhs_max: int = 1,
+                 sweep_mode: str = "compressed"):
         lib = load_library()
         if not torch.cuda.is_available():
             raise RuntimeError("the L-sweeps library needs a GPU")
@@ -151,8 +156,11 @@ class Solver:
         cdd = lsw_cdd_t(q, r)
         pml = lsw_pml_t(self.C, -1 if n_pml_local is None else n_pml_local)
         self.stream = torch.cuda.current_stream()
+        if sweep_mode not in ("compressed", "chain"):
+            raise ValueError("sweep_mode is 'compressed' or 'chain'")
         opts = lsw_opts_t(LSW_MIXED if precision == "mixed" else LSW_FP64, restart, maxit, tol, nrhs_max,
-                          ctypes.c_void_p(self.stream.cuda_stream))
+                          ctypes.c_void_p(self.stream.cuda_stream),
+                          LSW_SWEEP_CHAIN if sweep_mode == "chain" else LSW_SWEEP_COMPRESSED)
         handle = ctypes.c_void_p()
         torch.cuda.synchronize()
         rc = lib.lsw_setup(ctypes.byref(handle), ctypes.c_void_p(_dptr(m_ext)), omega, h, ctypes.byref(grid),

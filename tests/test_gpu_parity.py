@@ -101,15 +101,16 @@ def test_matvec_matches_oracle(name):
     s.close()
 
 
+@pytest.mark.parametrize("mode", ["compressed", "chain"])
 @pytest.mark.parametrize("name", list(CASES))
-def test_apply_fp64_matches_oracle(name):
+def test_apply_fp64_matches_oracle(name, mode):
     c = CASES[name]
     r = inputs.complex_normal(c.N, 2)
-    s = c.solver()
+    s = c.solver(sweep_mode=mode)
     z = to_np(s.apply(torch.from_numpy(r).cuda()))
     zo = c.oracle.apply(r)
     err = rel(z, zo)
-    say(name, "apply fp64 rel err", err)
+    say(name, mode, "apply fp64 rel err", err)
     assert err < 1e-10
     s.close()
 
@@ -123,11 +124,12 @@ def test_apply_single_subdomain_is_exact_inverse():
     s.close()
 
 
+@pytest.mark.parametrize("mode", ["compressed", "chain"])
 @pytest.mark.parametrize("name", ["const127_4x4", "ragged_45x38_3x2", "wide_4x5"])
-def test_apply_mixed_matches_oracle(name):
+def test_apply_mixed_matches_oracle(name, mode):
     c = CASES[name]
     r = inputs.complex_normal(c.N, 4)
-    s = c.solver(precision="mixed")
+    s = c.solver(precision="mixed", sweep_mode=mode)
     z = to_np(s.apply(torch.from_numpy(r).cuda()))
     err = rel(z, c.oracle.apply(r))
     say(name, "apply mixed rel err", err)
@@ -135,10 +137,11 @@ def test_apply_mixed_matches_oracle(name):
     s.close()
 
 
-def test_apply_is_deterministic_and_batches_rhs_exactly():
+@pytest.mark.parametrize("mode", ["compressed", "chain"])
+def test_apply_is_deterministic_and_batches_rhs_exactly(mode):
     c = CASES["ragged_45x38_3x2"]
     R = inputs.complex_normal((3, c.N), 5)
-    s = c.solver(nrhs_max=3)
+    s = c.solver(nrhs_max=3, sweep_mode=mode)
     Rt = torch.from_numpy(R).cuda()
     Z = s.apply(Rt)
     Z2 = s.apply(Rt)
@@ -299,13 +302,26 @@ def test_lens2d_full_size_apply_matches_oracle():
     r = inputs.complex_normal(m.size, 10)
     ls = LSweep2D(m, wl.omega, wl.n, wl.n_pml, wl.q, wl.r, wl.C)
     zo = ls.apply(r)
-    for precision, tol in (("fp64", 1e-10), ("mixed", 2e-4)):
-        s = Solver(torch.from_numpy(m).cuda(), wl.omega, wl.h, wl.n, wl.n_pml, wl.q, wl.r, C=wl.C,
-                   precision=precision)
-        err = rel(to_np(s.apply(torch.from_numpy(r).cuda())), zo)
-        say("lens2d apply", precision, err)
-        assert err < tol
-        s.close()
+    for mode in ("compressed", "chain"):
+        for precision, tol in (("fp64", 1e-10), ("mixed", 2e-4)):
+            s = Solver(torch.from_numpy(m).cuda(), wl.omega, wl.h, wl.n, wl.n_pml, wl.q, wl.r, C=wl.C,
+                       precision=precision, sweep_mode=mode)
+            err = rel(to_np(s.apply(torch.from_numpy(r).cuda())), zo)
+            say("lens2d apply", mode, precision, err)
+            assert err < tol
+            s.close()
+
+
+def test_sweep_modes_agree():
+    """The trace-compressed and the chained sweeps are two implementations of the same M^-1."""
+    c = CASES["wide_4x5"]
+    r = torch.from_numpy(inputs.complex_normal(c.N, 12)).cuda()
+    a = c.solver(sweep_mode="compressed")
+    b = c.solver(sweep_mode="chain")
+    za, zb = to_np(a.apply(r)), to_np(b.apply(r))
+    assert rel(za, zb) < 1e-11
+    a.close()
+    b.close()
 
 
 def test_lazy_conjugate_views_are_materialised():
