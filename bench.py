@@ -110,6 +110,8 @@ def main():
     ap.add_argument("--workload", default="lens2d")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--copy-probe-mb", type=int, default=0,
+                    help="first run one device copy of this many MiB (calibrates FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding is designed, not built "
@@ -121,6 +123,14 @@ def main():
     from paper_1909_01467_amd.lsweeps import Solver
 
     torch.cuda.set_device(0)
+    if args.copy_probe_mb > 0:
+        src = torch.ones(args.copy_probe_mb * 1024 * 1024 // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copy probe", args.copy_probe_mb, "MiB read and written once")
+        del src, dst
     wl, m_ext, b = make_problem(args.workload)
     log("workload", wl.name, "n", wl.n, "q", wl.q, "omega", round(wl.omega, 2))
     results = {}

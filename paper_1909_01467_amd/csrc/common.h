@@ -89,10 +89,12 @@ struct SubDesc {
     int i, j;            // CDD row / column
     int tx, ty;          // offsets of this window's x and y tables in the table pool
     int sides;           // bit s set if side s (Side) is an interior interface
+    int mid;             // middle block row of the twisted factorisation (H / 2)
     int L;               // number of trace-line slots, 4W + 4H
     long long g_off;     // offset (elements) of G_0 in the factor pool; G_k at g_off + k*W*W
     long long q_off;     // offset of Q = A_ij^-1[lines, lines] (L x L, column-major) in the Q pool
     long long gp_off;    // offset of this window's slots in each accumulated-RHS array
+    long long fw_off;    // offset of this window (H x W, row-major) in the final right-hand-side array
 };
 
 // Layout of one axis table of a window with P points (offset t in the table pool):
@@ -108,8 +110,8 @@ struct SolveDesc {
     int sub;                     // SubDesc index
     int kind;                    // Kind
     int zpart;                   // which per-sweep accumulator receives U on Omega_ij
-    int kf0;                     // first block row with a nonzero right-hand side
-    int kb0;                     // last block row (going down) whose solution is needed
+    int kf0, kf1;                // first and last block row with a nonzero right-hand side
+    int kb0, kb1;                // first and last block row whose solution is needed
     int nout;                    // number of trace outputs
     long long in_h;              // incoming horizontal trace (2 x W), -1 if none
     long long in_v;              // incoming vertical trace (2 x H), -1 if none

@@ -60,6 +60,7 @@ struct lsw_plan {
     std::vector<GemvSolve> gsolves;
     std::vector<GemvItem> gitems;
     int Wmax = 0, Hmax = 0, max_front = 0, ept = 1;
+    size_t ylds = 0, ylds128 = 0;   // LDS bytes for y/x in the block substitutions (0: global scratch)
     size_t HT = 0, VT = 0;
     std::vector<size_t> hbase, vbase;
     // device
@@ -73,6 +74,8 @@ struct lsw_plan {
     size_t Q_elems = 0;
     void* d_gparts = nullptr;
     size_t LT = 0;
+    c128* d_fw = nullptr;
+    size_t FWT = 0;
     void* d_G = nullptr;
     size_t G_elems = 0;
     void* d_traces = nullptr;
@@ -217,16 +220,33 @@ void add_out(SolveDesc& d, long long off, int side, int acc) {
     d.nout++;
 }
 
-SolveDesc blank(int sub, int kind, int zpart, int kf0, int kb0) {
+// Block rows where the right-hand side of a local solve can be nonzero ([kf0, kf1]) and
+// where its solution is read ([kb0, kb1]): stage 1 has data on Omega only, a sweep solve on
+// its incoming trace lines (the full height for a vertical interface, the receiving
+// quadrant for an L-shaped one), and the final solve is read on Omega only.
+SolveDesc blank(const SubDesc& s, int sub, int kind, int zpart) {
     SolveDesc d;
     std::memset(&d, 0, sizeof(d));
     d.sub = sub;
     d.kind = kind;
     d.zpart = zpart;
-    d.kf0 = kf0;
-    d.kb0 = kb0;
     d.in_h = -1;
     d.in_v = -1;
+    const int H = s.H;
+    int kf0 = 0, kf1 = H - 1, kb0 = 0, kb1 = H - 1;
+    switch (kind) {
+        case KIND_STAGE1: kf0 = s.r0; kf1 = s.r1 - 1; break;
+        case KIND_FINAL: kb0 = s.r0; kb1 = s.r1 - 1; break;
+        case KIND_B: kf0 = s.r0 - 1; kf1 = s.r0; kb0 = s.r0; break;
+        case KIND_T: kf0 = s.r1 - 1; kf1 = s.r1; break;
+        case KIND_BL: case KIND_BR: kf0 = s.r0 - 1; kb0 = s.r0; break;
+        case KIND_TR: case KIND_TL: kf1 = s.r1; break;
+        default: break;
+    }
+    d.kf0 = kf0;
+    d.kf1 = kf1;
+    d.kb0 = kb0;
+    d.kb1 = kb1;
     return d;
 }
 
@@ -250,7 +270,7 @@ void build_schedule(lsw_plan* p) {
     for (int i = 0; i < q; ++i)
         for (int j = 0; j < r; ++j) {
             const SubDesc& s = p->subs[sid(i, j)];
-            SolveDesc d = blank(sid(i, j), KIND_STAGE1, 0, s.r0, 0);
+            SolveDesc d = blank(s, sid(i, j), KIND_STAGE1, 0);
             if (i > 0) add_out(d, offH(H_B_RUN, i, j), SIDE_B, 0);
             if (i < q - 1) add_out(d, offH(H_T_RUN, i, j), SIDE_T, 0);
             if (j > 0) add_out(d, offV(V_L_RUN, i, j), SIDE_L, 0);
@@ -266,7 +286,7 @@ void build_schedule(lsw_plan* p) {
             const int i = t + 1;
             for (int j = 0; j < r; ++j) {
                 const SubDesc& s = p->subs[sid(i, j)];
-                SolveDesc d = blank(sid(i, j), KIND_B, 1, s.r0 - 1, s.r0);
+                SolveDesc d = blank(s, sid(i, j), KIND_B, 1);
                 d.in_h = offH(H_T_RUN, i - 1, j);
                 if (i < q - 1) add_out(d, offH(H_T_RUN, i, j), SIDE_T, 1);
                 if (j < r - 1) add_out(d, offV(V_R_UP, i, j), SIDE_R, 0);
@@ -278,7 +298,7 @@ void build_schedule(lsw_plan* p) {
             const int i = q - 2 - t;
             for (int j = 0; j < r; ++j) {
                 const SubDesc& s = p->subs[sid(i, j)];
-                SolveDesc d = blank(sid(i, j), KIND_T, 2, s.r1 - 1, 0);
+                SolveDesc d = blank(s, sid(i, j), KIND_T, 2);
                 d.in_h = offH(H_B_RUN, i + 1, j);
                 if (i > 0) add_out(d, offH(H_B_RUN, i, j), SIDE_B, 1);
                 if (j < r - 1) add_out(d, offV(V_R_DN, i, j), SIDE_R, 0);
@@ -289,7 +309,7 @@ void build_schedule(lsw_plan* p) {
         if (t + 1 <= r - 1) {  // right: column j = t+1, incoming left trace R_run(i, j-1)
             const int j = t + 1;
             for (int i = 0; i < q; ++i) {
-                SolveDesc d = blank(sid(i, j), KIND_L, 3, 0, 0);
+                SolveDesc d = blank(p->subs[sid(i, j)], sid(i, j), KIND_L, 3);
                 d.in_v = offV(V_R_RUN, i, j - 1);
                 if (j < r - 1) add_out(d, offV(V_R_RUN, i, j), SIDE_R, 1);
                 if (i > 0) add_out(d, offH(H_B_RT, i, j), SIDE_B, 0);
@@ -300,7 +320,7 @@ void build_schedule(lsw_plan* p) {
         if (r - 2 - t >= 0) {  // left: column j = r-2-t, incoming right trace L_run(i, j+1)
             const int j = r - 2 - t;
             for (int i = 0; i < q; ++i) {
-                SolveDesc d = blank(sid(i, j), KIND_R, 4, 0, 0);
+                SolveDesc d = blank(p->subs[sid(i, j)], sid(i, j), KIND_R, 4);
                 d.in_v = offV(V_L_RUN, i, j + 1);
                 if (j > 0) add_out(d, offV(V_L_RUN, i, j), SIDE_L, 1);
                 if (i > 0) add_out(d, offH(H_B_LF, i, j), SIDE_B, 0);
@@ -318,7 +338,7 @@ void build_schedule(lsw_plan* p) {
             for (int j = 0; j < r; ++j) {
                 const SubDesc& s = p->subs[sid(i, j)];
                 if (i >= 1 && j >= 1 && (i - 1) + (j - 1) == dd) {  // BL->TR (R^up, T^right)
-                    SolveDesc d = blank(sid(i, j), KIND_BL, 5, s.r0 - 1, s.r0);
+                    SolveDesc d = blank(s, sid(i, j), KIND_BL, 5);
                     d.in_h = offH(H_T_RT, i - 1, j);
                     d.in_v = offV(V_R_UP, i, j - 1);
                     if (j < r - 1) add_out(d, offV(V_R_UP, i, j), SIDE_R, 1);
@@ -326,7 +346,7 @@ void build_schedule(lsw_plan* p) {
                     f.push_back(d);
                 }
                 if (i <= q - 2 && j <= r - 2 && (q - 2 - i) + (r - 2 - j) == dd) {  // TR->BL (L^down, B^left)
-                    SolveDesc d = blank(sid(i, j), KIND_TR, 6, 0, 0);
+                    SolveDesc d = blank(s, sid(i, j), KIND_TR, 6);
                     d.in_h = offH(H_B_LF, i + 1, j);
                     d.in_v = offV(V_L_DN, i, j + 1);
                     if (j > 0) add_out(d, offV(V_L_DN, i, j), SIDE_L, 1);
@@ -334,7 +354,7 @@ void build_schedule(lsw_plan* p) {
                     f.push_back(d);
                 }
                 if (i >= 1 && j <= r - 2 && (i - 1) + (r - 2 - j) == dd) {  // BR->TL (L^up, T^left)
-                    SolveDesc d = blank(sid(i, j), KIND_BR, 7, s.r0 - 1, s.r0);
+                    SolveDesc d = blank(s, sid(i, j), KIND_BR, 7);
                     d.in_h = offH(H_T_LF, i - 1, j);
                     d.in_v = offV(V_L_UP, i, j + 1);
                     if (j > 0) add_out(d, offV(V_L_UP, i, j), SIDE_L, 1);
@@ -342,7 +362,7 @@ void build_schedule(lsw_plan* p) {
                     f.push_back(d);
                 }
                 if (i <= q - 2 && j >= 1 && (q - 2 - i) + (j - 1) == dd) {  // TL->BR (R^down, B^right)
-                    SolveDesc d = blank(sid(i, j), KIND_TL, 8, 0, 0);
+                    SolveDesc d = blank(s, sid(i, j), KIND_TL, 8);
                     d.in_h = offH(H_B_RT, i + 1, j);
                     d.in_v = offV(V_R_DN, i, j - 1);
                     if (j < r - 1) add_out(d, offV(V_R_DN, i, j), SIDE_R, 1);
@@ -427,7 +447,7 @@ void compress_schedule(lsw_plan* p) {
         fronts.push_back(g);
     }
     Front fin{0, (int)descs.size(), (int)p->subs.size(), 0, 0};
-    for (size_t n = 0; n < p->subs.size(); ++n) descs.push_back(blank((int)n, KIND_FINAL, -1, 0, p->subs[n].r0));
+    for (size_t n = 0; n < p->subs.size(); ++n) descs.push_back(blank(p->subs[n], (int)n, KIND_FINAL, -1));
     fronts.push_back(fin);
     p->descs = descs;
     p->fronts = fronts;
@@ -456,6 +476,8 @@ ChainArgs chain_args(lsw_plan* p, const c128* d_r, c128* d_z) {
     a.gparts = p->d_gparts;
     a.LT = p->LT;
     a.Q = p->d_Q;
+    a.fw = p->d_fw;
+    a.fw_stride = p->FWT;
     return a;
 }
 
@@ -471,7 +493,7 @@ int apply_impl(lsw_plan* p, const c128* d_r, c128* d_z, int nrhs, bool timed) {
     if (chain_mode) {
         for (const Front& f : p->fronts) {
             a.descs = p->d_descs + f.offset;
-            HIPCK(p, launch_chain(a, f.count, nrhs, p->ept, c64, true, p->stream));
+            HIPCK(p, launch_chain(a, f.count, nrhs, p->ept, c64, 3, p->ylds, p->stream));
         }
         if (timed) HIPCK(p, hipEventRecord(p->ev[1], p->stream));
         ZsumArgs zs{p->d_zpart, p->zpart_stride, d_z, p->d_xgroup, p->d_ygroup, p->Nx, p->Ny, p->q, p->r};
@@ -482,13 +504,16 @@ int apply_impl(lsw_plan* p, const c128* d_r, c128* d_z, int nrhs, bool timed) {
         const size_t nf = p->fronts.size();
         for (size_t fi = 0; fi < nf; ++fi) {
             const Front& f = p->fronts[fi];
-            if (fi == nf - 1 && timed) HIPCK(p, hipEventRecord(p->ev[2], p->stream));
+            if (fi == nf - 1) {
+                if (timed) HIPCK(p, hipEventRecord(p->ev[2], p->stream));
+                HIPCK(p, launch_final_rhs(a, (int)p->subs.size(), nrhs, c64, p->stream));
+            }
             if (f.gemv) {
                 ga.items = p->d_gitems + f.ioffset;
                 HIPCK(p, launch_gemv(ga, f.icount, nrhs, c64, p->stream));
             } else {
                 a.descs = p->d_descs + f.offset;
-                HIPCK(p, launch_chain(a, f.count, nrhs, p->ept, c64, false, p->stream));
+                HIPCK(p, launch_chain(a, f.count, nrhs, p->ept, c64, fi == 0 ? 0 : 1, p->ylds, p->stream));
             }
             if (fi == 0 && timed) HIPCK(p, hipEventRecord(p->ev[1], p->stream));
         }
@@ -769,6 +794,7 @@ int setup_impl(lsw_plan* p, const double* d_m, double omega, double h, const lsw
             SubDesc s{};
             s.W = p->xw1[j] - p->xw0[j];
             s.H = p->yw1[i] - p->yw0[i];
+            s.mid = s.H / 2;   // the twisted factorisation meets at this block row
             s.wx0 = p->xw0[j];
             s.wy0 = p->yw0[i];
             s.r0 = p->ylo[i] - p->yw0[i];
@@ -788,6 +814,8 @@ int setup_impl(lsw_plan* p, const double* d_m, double omega, double h, const lsw
             p->Q_elems += (size_t)s.L * s.L;
             s.gp_off = (long long)p->LT;
             p->LT += (size_t)s.L;
+            s.fw_off = (long long)p->FWT;
+            p->FWT += (size_t)s.H * s.W;
             p->ept = std::max(p->ept, (s.W + (1024 / s.W) - 1) / (1024 / s.W));
             p->hbase.push_back(p->HT);
             p->vbase.push_back(p->VT);
@@ -824,7 +852,10 @@ int setup_impl(lsw_plan* p, const double* d_m, double omega, double h, const lsw
             for (int n = 0; n < f.count; ++n) {
                 const SolveDesc& d = p->descs[f.offset + n];
                 const SubDesc& s = p->subs[d.sub];
-                const double blocks = (s.H - d.kf0) + (s.H - 1 - d.kb0);
+                // forward halves, the middle row, backward halves (each G_k read once per pass)
+                const int m = s.mid;
+                const double blocks = std::max(0, m - d.kf0) + std::max(0, d.kf1 - m) + 1 +
+                                      std::max(0, m - d.kb0) + std::max(0, d.kb1 - m);
                 p->apply_chain_bytes += blocks * s.W * (double)s.W * eb;
             }
         }
@@ -881,8 +912,10 @@ int setup_impl(lsw_plan* p, const double* d_m, double omega, double h, const lsw
         if ((rc = dalloc(p, &gp, (size_t)p->nrhs_max * 8 * p->LT * eb)) != LSW_OK) return rc;
         p->d_gparts = gp;
         HIPCK(p, hipMemset(gp, 0, (size_t)p->nrhs_max * 8 * p->LT * eb));
+        if ((rc = dalloc(p, &p->d_fw, (size_t)p->nrhs_max * p->FWT)) != LSW_OK) return rc;
     }
-    p->Y_stride = (size_t)p->Wmax * p->Hmax;
+    // y of both forward halves, then x when it does not stay in LDS
+    p->Y_stride = 2 * (size_t)p->Wmax * p->Hmax;
     char* Y = nullptr;
     if ((rc = dalloc(p, &Y, p->Y_stride * p->max_front * p->nrhs_max * eb)) != LSW_OK) return rc;
     p->d_Y = Y;
@@ -917,6 +950,16 @@ int setup_impl(lsw_plan* p, const double* d_m, double omega, double h, const lsw
     HIPCK(p, hipGetDevice(&dev));
     int max_lds = 0;
     HIPCK(p, hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+    {
+        // k_chain static LDS: v (kMaxWindow), part (1024) and the y table (kMaxWindow + 1)
+        const size_t stat64 = sizeof(c64) * (kMaxWindow + 1024), stat128 = sizeof(c128) * (kMaxWindow + 1024);
+        const size_t tabb = sizeof(c128) * (kMaxWindow + 1) + 256;
+        const size_t ywin = (size_t)p->Wmax * p->Hmax;
+        const size_t y64 = sizeof(c64) * ywin, y128 = sizeof(c128) * ywin;
+        const size_t want = p->precision == LSW_MIXED ? y64 + stat64 : y128 + stat128;
+        p->ylds = want + tabb <= (size_t)max_lds ? (p->precision == LSW_MIXED ? y64 : y128) : 0;
+        p->ylds128 = y128 + stat128 + tabb <= (size_t)max_lds ? y128 : 0;
+    }
     const size_t static_lds = sizeof(c128) * kMaxWindow + sizeof(int) * kMaxWindow + 64;
     const size_t lds_bytes = sizeof(c128) * (size_t)p->Wmax * p->Wmax;
     const bool use_lds = lds_bytes + static_lds <= (size_t)max_lds;
@@ -926,12 +969,12 @@ int setup_impl(lsw_plan* p, const double* d_m, double omega, double h, const lsw
     fa.G = G128;
     fa.status = p->d_status;
     if (!use_lds) {
-        if ((rc = dalloc(p, &fa.work, (size_t)nsub * p->Wmax * p->Wmax)) != LSW_OK) return rc;
+        if ((rc = dalloc(p, &fa.work, (size_t)nsub * 2 * p->Wmax * p->Wmax)) != LSW_OK) return rc;
         fa.work_stride = (size_t)p->Wmax * p->Wmax;
     }
     HIPCK(p, hipStreamSynchronize(p->stream));
     const auto tf = std::chrono::steady_clock::now();
-    HIPCK(p, launch_factor(fa, nsub, p->Wmax, use_lds, use_lds ? lds_bytes : 0, false, p->stream));
+    HIPCK(p, launch_factor(fa, nsub, use_lds, use_lds ? lds_bytes : 0, p->stream));
     HIPCK(p, hipStreamSynchronize(p->stream));
     p->t_factor_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tf).count();
     if (fa.work) dfree(p, fa.work);
@@ -967,7 +1010,8 @@ int setup_impl(lsw_plan* p, const double* d_m, double omega, double h, const lsw
                         k = v - line * H;
                         c = line == 0 ? s.c0 - 1 : line == 1 ? s.c0 : line == 2 ? s.c1 - 1 : s.c1;
                     }
-                    SolveDesc d = blank(n, KIND_UNIT, -1, k, 0);
+                    SolveDesc d = blank(s, n, KIND_UNIT, -1);
+                    d.kf0 = d.kf1 = k;
                     d.unit_k = k;
                     d.unit_c = c;
                     d.q_col = s.q_off + (long long)sl * s.L;
@@ -990,7 +1034,7 @@ int setup_impl(lsw_plan* p, const double* d_m, double omega, double h, const lsw
         for (size_t off = 0; off < units.size(); off += batch) {
             ua.descs = d_units + off;
             const int cnt = (int)std::min<size_t>(batch, units.size() - off);
-            HIPCK(p, launch_chain(ua, cnt, 1, p->ept, false, false, p->stream));
+            HIPCK(p, launch_chain(ua, cnt, 1, p->ept, false, 2, p->ylds128, p->stream));
         }
         HIPCK(p, hipStreamSynchronize(p->stream));
         dfree(p, d_units);

@@ -21,6 +21,23 @@
 
 namespace lsw {
 
+// ------------------------------------------------------------------ buffer loads
+// Raw buffer loads: 128-bit resource in SGPRs (base, byte size), 32-bit byte offset per lane.
+// Offsets past the size return zero instead of faulting.
+__device__ inline __amdgpu_buffer_rsrc_t make_rsrc(const void* base, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, (int)bytes, 0x00020000);
+}
+template <typename T>
+__device__ inline cx<T> bload(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff);
+template <>
+__device__ inline cx<float> bload<float>(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+    return __builtin_bit_cast(cx<float>, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+template <>
+__device__ inline cx<double> bload<double>(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+    return __builtin_bit_cast(cx<double>, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
+}
+
 // ------------------------------------------------------------------ coefficients
 // Couplings of the 5-point symmetric PML operator on a box whose x table starts at tx
 // (Px points) and y table at ty (Py points); see the table layout in common.h.
@@ -41,105 +58,157 @@ __device__ inline c128 diag_coef(const c128* tab, int tx, int Px, int ty, int Py
 }
 
 // ------------------------------------------------------------------ K3: factorisation
-template <int NT, bool kLds, typename TG>
+// In-place Gauss-Jordan inversion of the W x W block S (row-major) with row pivoting.
+template <int NT>
+__device__ void gj_invert(c128* S, int W, c128* colp, int* perm, int* sh_piv, int* sh_sing) {
+    constexpr int NTX = 32, NTY = NT / 32;
+    const int tid = threadIdx.x, tx = tid % NTX, ty = tid / NTX;
+    for (int p = 0; p < W; ++p) {
+        if (tid < 64) {
+            double best = -1.0;
+            int bi = p;
+            for (int r = p + tid; r < W; r += 64) {
+                const double v = abs2(S[r * W + p]);
+                if (v > best) { best = v; bi = r; }
+            }
+            for (int off = 32; off > 0; off >>= 1) {
+                const double ob = __shfl_xor(best, off);
+                const int oi = __shfl_xor(bi, off);
+                if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+            }
+            if (tid == 0) {
+                *sh_piv = bi;
+                perm[p] = bi;
+                if (!(best > 0.0)) *sh_sing = 1;
+            }
+        }
+        __syncthreads();
+        const int piv = *sh_piv;
+        if (piv != p)
+            for (int c = tid; c < W; c += NT) {
+                const c128 t = S[p * W + c];
+                S[p * W + c] = S[piv * W + c];
+                S[piv * W + c] = t;
+            }
+        __syncthreads();
+        const c128 inv = cinv(S[p * W + p]);
+        for (int r = tid; r < W; r += NT) colp[r] = S[r * W + p];
+        __syncthreads();
+        for (int c = tid; c < W; c += NT) S[p * W + c] = (c == p) ? inv : S[p * W + c] * inv;
+        __syncthreads();
+        for (int r = ty; r < W; r += NTY) {
+            if (r == p) continue;
+            const c128 f = colp[r];
+            for (int c = tx; c < W; c += NTX) {
+                if (c == p) S[r * W + c] = -(f * inv);
+                else S[r * W + c] = S[r * W + c] - f * S[p * W + c];
+            }
+        }
+        __syncthreads();
+    }
+    // undo the row interchanges as column interchanges, in reverse order
+    for (int p = W - 1; p >= 0; --p) {
+        const int pv = perm[p];
+        if (pv != p)
+            for (int r = tid; r < W; r += NT) {
+                const c128 t = S[r * W + p];
+                S[r * W + p] = S[r * W + pv];
+                S[r * W + pv] = t;
+            }
+        __syncthreads();
+    }
+}
+
+// D_k (tridiagonal along x) into S, minus sum over the given neighbour terms C G C.
+template <int NT>
+__device__ void build_block(c128* S, const SubDesc& s, const FactorArgs& a, int k, const c128* colA,
+                            const c128* GA, bool GA_rowmajor, const c128* colB, const c128* GB) {
+    constexpr int NTX = 32, NTY = NT / 32;
+    const int tid = threadIdx.x, tx = tid % NTX, ty = tid / NTX, W = s.W, H = s.H;
+    const c128* tab = a.geo.tab;
+    const double ih2 = 1.0 / (a.geo.h * a.geo.h), om2 = a.geo.omega * a.geo.omega;
+    const double* mrow = a.geo.m + (size_t)(s.wy0 + k) * a.geo.Nx + s.wx0;
+    for (int r = ty; r < W; r += NTY)
+        for (int c = tx; c < W; c += NTX) {
+            c128 val = mk(0.0, 0.0);
+            if (r == c) val = diag_coef(tab, s.tx, W, s.ty, H, c, k, ih2, om2 * mrow[c]);
+            else if (c == r + 1) val = coup_x(tab, s.tx, W, s.ty, r, k, ih2);
+            else if (r == c + 1) val = coup_x(tab, s.tx, W, s.ty, c, k, ih2);
+            if (GA) val = val - colA[r] * (GA_rowmajor ? GA[r * W + c] : GA[(size_t)c * W + r]) * colA[c];
+            if (GB) val = val - colB[r] * GB[(size_t)c * W + r] * colB[c];
+            S[r * W + c] = val;
+        }
+}
+
+// Twisted block factorisation of every local problem, one workgroup per (subdomain, half).
+// Half 0 eliminates upwards from block row 0:  S_0 = D_0, S_k = D_k - C_{k-1} G_{k-1} C_{k-1};
+// half 1 eliminates downwards from row H-1:  S_{H-1} = D_{H-1}, S_k = D_k - C_k G_{k+1} C_k;
+// both stop before the middle row m, which k_factor_mid completes.  G_k = S_k^-1 is stored
+// column-major; the previous block of the half stays in S (LDS) for the next Schur update.
+template <int NT, bool kLds>
 __global__ __launch_bounds__(NT) void k_factor(FactorArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     __shared__ c128 colp[kMaxWindow];
     __shared__ int perm[kMaxWindow];
     __shared__ int sh_piv, sh_sing;
     const SubDesc s = a.subs[blockIdx.x];
-    const int W = s.W, H = s.H, tid = threadIdx.x;
+    const int h = blockIdx.y;
+    const int W = s.W, H = s.H, m = s.mid, tid = threadIdx.x;
     constexpr int NTX = 32, NTY = NT / 32;
     const int tx = tid % NTX, ty = tid / NTX;
-    c128* S = kLds ? reinterpret_cast<c128*>(smem) : a.work + (size_t)blockIdx.x * a.work_stride;
+    c128* S = kLds ? reinterpret_cast<c128*>(smem) : a.work + ((size_t)blockIdx.x * 2 + h) * a.work_stride;
     const c128* tab = a.geo.tab;
-    const double ih2 = 1.0 / (a.geo.h * a.geo.h), om2 = a.geo.omega * a.geo.omega;
-    TG* G = reinterpret_cast<TG*>(a.G) + s.g_off;
+    const double ih2 = 1.0 / (a.geo.h * a.geo.h);
+    c128* G = reinterpret_cast<c128*>(a.G) + s.g_off;
     if (tid == 0) sh_sing = 0;
-
-    for (int k = 0; k < H; ++k) {
-        // couplings to the previous block row, C_{k-1} (diagonal)
-        if (k > 0)
-            for (int x = tid; x < W; x += NT) colp[x] = coup_y(tab, s.tx, s.ty, H, x, k - 1, ih2);
+    const int dk = h == 0 ? 1 : -1;
+    bool first = true;
+    for (int k = h == 0 ? 0 : H - 1; h == 0 ? k < m : k > m; k += dk) {
+        if (!first)
+            for (int x = tid; x < W; x += NT) colp[x] = coup_y(tab, s.tx, s.ty, H, x, h == 0 ? k - 1 : k, ih2);
         __syncthreads();
-        // S_k = D_k - C_{k-1} G_{k-1} C_{k-1}; G_{k-1} is the current content of S
-        const double* mrow = a.geo.m + (size_t)(s.wy0 + k) * a.geo.Nx + s.wx0;
-        for (int r = ty; r < W; r += NTY) {
-            for (int c = tx; c < W; c += NTX) {
-                c128 val = mk(0.0, 0.0);
-                if (r == c) val = diag_coef(tab, s.tx, W, s.ty, H, c, k, ih2, om2 * mrow[c]);
-                else if (c == r + 1) val = coup_x(tab, s.tx, W, s.ty, r, k, ih2);
-                else if (r == c + 1) val = coup_x(tab, s.tx, W, s.ty, c, k, ih2);
-                if (k > 0) val = val - colp[r] * S[r * W + c] * colp[c];
-                S[r * W + c] = val;
-            }
-        }
+        build_block<NT>(S, s, a, k, colp, first ? nullptr : S, true, nullptr, nullptr);
         __syncthreads();
-        // in-place Gauss-Jordan inversion with row pivoting
-        for (int p = 0; p < W; ++p) {
-            if (tid < 64) {
-                double best = -1.0;
-                int bi = p;
-                for (int r = p + tid; r < W; r += 64) {
-                    double v = abs2(S[r * W + p]);
-                    if (v > best) { best = v; bi = r; }
-                }
-                for (int off = 32; off > 0; off >>= 1) {
-                    double ob = __shfl_xor(best, off);
-                    int oi = __shfl_xor(bi, off);
-                    if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
-                }
-                if (tid == 0) {
-                    sh_piv = bi;
-                    perm[p] = bi;
-                    if (!(best > 0.0)) sh_sing = 1;
-                }
-            }
-            __syncthreads();
-            const int piv = sh_piv;
-            if (piv != p)
-                for (int c = tid; c < W; c += NT) {
-                    c128 t = S[p * W + c];
-                    S[p * W + c] = S[piv * W + c];
-                    S[piv * W + c] = t;
-                }
-            __syncthreads();
-            const c128 inv = cinv(S[p * W + p]);
-            for (int r = tid; r < W; r += NT) colp[r] = S[r * W + p];
-            __syncthreads();
-            for (int c = tid; c < W; c += NT) S[p * W + c] = (c == p) ? inv : S[p * W + c] * inv;
-            __syncthreads();
-            for (int r = ty; r < W; r += NTY) {
-                if (r == p) continue;
-                const c128 f = colp[r];
-                for (int c = tx; c < W; c += NTX) {
-                    if (c == p) S[r * W + c] = -(f * inv);
-                    else S[r * W + c] = S[r * W + c] - f * S[p * W + c];
-                }
-            }
-            __syncthreads();
-        }
-        // undo the row interchanges as column interchanges, in reverse order
-        for (int p = W - 1; p >= 0; --p) {
-            const int pv = perm[p];
-            if (pv != p)
-                for (int r = tid; r < W; r += NT) {
-                    c128 t = S[r * W + p];
-                    S[r * W + p] = S[r * W + pv];
-                    S[r * W + pv] = t;
-                }
-            __syncthreads();
-        }
-        // G_k, column-major: G[c*W + t] = (S_k^-1)[t][c]
-        TG* Gk = G + (size_t)k * W * W;
+        gj_invert<NT>(S, W, colp, perm, &sh_piv, &sh_sing);
+        c128* Gk = G + (size_t)k * W * W;
         for (int c = ty; c < W; c += NTY)
-            for (int t = tx; t < W; t += NTX) {
-                c128 v = S[t * W + c];
-                Gk[(size_t)c * W + t] = TG{static_cast<decltype(TG::re)>(v.re),
-                                           static_cast<decltype(TG::re)>(v.im)};
-            }
+            for (int t = tx; t < W; t += NTX) Gk[(size_t)c * W + t] = S[t * W + c];
         __syncthreads();
+        first = false;
     }
+    if (tid == 0 && sh_sing) a.status[blockIdx.x] = 1;
+}
+
+// Middle block of the twisted factorisation:
+// S_m = D_m - C_{m-1} G_{m-1} C_{m-1} - C_m G_{m+1} C_m,  G_m = S_m^-1.
+template <int NT, bool kLds>
+__global__ __launch_bounds__(NT) void k_factor_mid(FactorArgs a) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ c128 colA[kMaxWindow], colB[kMaxWindow];
+    __shared__ int perm[kMaxWindow];
+    __shared__ int sh_piv, sh_sing;
+    const SubDesc s = a.subs[blockIdx.x];
+    const int W = s.W, H = s.H, m = s.mid, tid = threadIdx.x;
+    constexpr int NTX = 32, NTY = NT / 32;
+    const int tx = tid % NTX, ty = tid / NTX;
+    c128* S = kLds ? reinterpret_cast<c128*>(smem) : a.work + (size_t)blockIdx.x * 2 * a.work_stride;
+    const c128* tab = a.geo.tab;
+    const double ih2 = 1.0 / (a.geo.h * a.geo.h);
+    c128* G = reinterpret_cast<c128*>(a.G) + s.g_off;
+    if (tid == 0) sh_sing = 0;
+    const bool below = m >= 1, above = m + 1 <= H - 1;
+    for (int x = tid; x < W; x += NT) {
+        if (below) colA[x] = coup_y(tab, s.tx, s.ty, H, x, m - 1, ih2);
+        if (above) colB[x] = coup_y(tab, s.tx, s.ty, H, x, m, ih2);
+    }
+    __syncthreads();
+    build_block<NT>(S, s, a, m, colA, below ? G + (size_t)(m - 1) * W * W : nullptr, false, colB,
+                    above ? G + (size_t)(m + 1) * W * W : nullptr);
+    __syncthreads();
+    gj_invert<NT>(S, W, colA, perm, &sh_piv, &sh_sing);
+    c128* Gm = G + (size_t)m * W * W;
+    for (int c = ty; c < W; c += NTY)
+        for (int t = tx; t < W; t += NTX) Gm[(size_t)c * W + t] = S[t * W + c];
     if (tid == 0 && sh_sing) a.status[blockIdx.x] = 1;
 }
 
@@ -236,80 +305,109 @@ __device__ inline cx<T> g_polarized(const Local<T>& L, int k, int c) {
     return cvt<T>(g);
 }
 
-// right-hand side of a block row element (k, c) for the kinds that are not polarized
-template <typename T>
-__device__ inline cx<T> rhs_plain(const ChainArgs& a, const SolveDesc& d, const SubDesc& s, int rhs, int k, int c) {
-    const size_t N = (size_t)a.geo.Nx * a.geo.Ny;
-    if (d.kind == KIND_UNIT) return (k == d.unit_k && c == d.unit_c) ? cx<T>{T(1), T(0)} : cx<T>{T(0), T(0)};
-    c128 g = mk(0.0, 0.0);
-    if (k >= s.r0 && k < s.r1 && c >= s.c0 && c < s.c1)
-        g = a.r[(size_t)rhs * N + (size_t)(s.wy0 + k) * a.geo.Nx + s.wx0 + c];
-    cx<T> out = cvt<T>(g);
-    if (d.kind == KIND_FINAL) {
-        // sum of the sweeps' right-hand sides g_s (each supported on the trace-line slots)
-        const int W = s.W, H = s.H;
-        const cx<T>* gp = reinterpret_cast<const cx<T>*>(a.gparts) + (size_t)rhs * 8 * a.LT + s.gp_off;
-        for (int sw = 0; sw < 8; ++sw, gp += a.LT) {
-            if (k == s.r0 - 1) out = out + gp[c];
-            if (k == s.r0) out = out + gp[W + c];
-            if (k == s.r1 - 1) out = out + gp[2 * W + c];
-            if (k == s.r1 && k < H) out = out + gp[3 * W + c];
-            if (c == s.c0 - 1) out = out + gp[4 * W + k];
-            if (c == s.c0) out = out + gp[4 * W + H + k];
-            if (c == s.c1 - 1) out = out + gp[4 * W + 2 * H + k];
-            if (c == s.c1 && c < W) out = out + gp[4 * W + 3 * H + k];
-        }
-    }
-    return out;
-}
+// Which right-hand sides and outputs one instantiation of k_chain handles.
+enum ChainSet : int { CS_STAGE1 = 0, CS_FINAL = 1, CS_UNIT = 2, CS_POLAR = 3 };
 
-// Batched block forward/back substitution, one workgroup per (local solve, rhs).
+// Batched block substitution with the twisted factorisation, two workgroups per
+// (local solve, rhs): half 0 owns block rows below the middle row m, half 1 those above.
+//   phase 0: forward elimination of each half towards m,
+//            half 0: y_k = G_k (g_k - C_{k-1} y_{k-1}),  half 1: y_k = G_k (g_k - C_k y_{k+1});
+//   phase 1: x_m = G_m (g_m - C_{m-1} y_{m-1} - C_m y_{m+1}) (computed by both halves), then
+//            half 0: x_k = y_k - G_k C_k x_{k+1} downwards,  half 1: x_k = y_k - G_k C_{k-1} x_{k-1} upwards.
 // Thread tid < NA = floor(1024/W)*W owns block row t = tid % W and the columns
 // c = tid / W + NG*j (j < ept) of every W x W block G_k: its elements sit at the flat
-// offsets tid + NA*j of the column-major block, so the loads are fully coalesced.  A ring
-// of PD+1 register buffers keeps PD blocks in flight ahead of the current one.
-template <typename T, int EPT, int PD, bool POLAR>
+// offsets tid + NA*j of the column-major block, so the loads are fully coalesced.
+// A register ring keeps PD blocks of G (and the right-hand-side / y values) in flight ahead
+// of the block in use; every load in the loop is unconditional (zero past the buffer,
+// masked at use) and nothing is stored to global memory inside the loop (the half's y or x
+// live in Ybuf, LDS when it fits), so waiting for a block never waits for the younger
+// prefetches.  Thread t < W carries its y/x entry in a register: two barriers per block.
+template <typename T, int EPT, int PD, int CS, bool YLDS>
 __global__ __launch_bounds__(1024) void k_chain(ChainArgs a) {
     constexpr int NT = 1024;
-    const SolveDesc& d = a.descs[blockIdx.x];
-    const SubDesc s = a.subs[d.sub];
+    extern __shared__ __align__(16) unsigned char dyn[];
+    const int sidx = blockIdx.x >> 1, h = blockIdx.x & 1, nsol = gridDim.x >> 1;
+    const SolveDesc& dref = a.descs[sidx];
+    const int sub = dref.sub, kind = dref.kind;
+    const int kf0 = dref.kf0, kf1 = dref.kf1, kb0 = dref.kb0, kb1 = dref.kb1;
+    const SubDesc s = a.subs[sub];
     const int rhs = blockIdx.y;
-    const int W = s.W, H = s.H, tid = threadIdx.x;
+    const int W = s.W, H = s.H, m = s.mid, tid = threadIdx.x;
     const int NG = NT / W, NA = NG * W;
     const bool act = tid < NA;
+    const bool mine = tid < W;
+    const int tc = mine ? tid : W - 1;          // clamped column for address arithmetic
     const int cg = act ? tid / W : 0;
     const int ept = (W + NG - 1) / NG;
     const int WW = W * W;
-    __shared__ cx<T> v[kMaxWindow], xk[kMaxWindow];
+    __shared__ cx<T> v[kMaxWindow];
     __shared__ cx<T> part[NT];
+    __shared__ c128 a2h[kMaxWindow + 1];
 
     const c128* tab = a.geo.tab;
     const double ih2 = 1.0 / (a.geo.h * a.geo.h);
+    for (int k = tid; k <= H; k += NT) a2h[k] = tab[s.ty + H + k];   // alpha_y at the half points
+    const c128 ia_c = tab[s.tx + tc];                                  // 1/alpha_x of my column
     const cx<T>* Gs = reinterpret_cast<const cx<T>*>(a.G) + s.g_off;
     cx<T>* tr = reinterpret_cast<cx<T>*>(a.traces) + (size_t)rhs * a.trace_stride;
-    cx<T>* Y = reinterpret_cast<cx<T>*>(a.Y) + ((size_t)blockIdx.y * gridDim.x + blockIdx.x) * a.Y_stride;
-    const bool polar = d.kind >= KIND_B && d.kind <= KIND_TL;
-    const Local<T> L = make_local<T>(s, d.kind, tab, d.in_h >= 0 ? tr + d.in_h : nullptr,
-                                     d.in_v >= 0 ? tr + d.in_v : nullptr, ih2);
-    const cx<T> zero{T(0), T(0)};
+    // y of both halves (written in phase 0, read in phase 1); x goes to Ybuf
+    cx<T>* Yg = reinterpret_cast<cx<T>*>(a.Y) + ((size_t)blockIdx.y * nsol + sidx) * a.Y_stride;
+    cx<T>* Ybuf = YLDS ? reinterpret_cast<cx<T>*>(dyn) : Yg + (a.phase == 1 ? (size_t)H * W : 0);
+    const size_t N = (size_t)a.geo.Nx * a.geo.Ny;
+    // a prvalue zero: a named zero in a conditional with an array element makes the
+    // compiler select between addresses and move the register rings to scratch
+    auto zero = []() { return cx<T>{T(0), T(0)}; };
+    // coupling of block rows l and l+1 at my column (diagonal of C_l)
+    auto cy = [&](int l) { return cvt<T>(-ih2 * (a2h[l + 1] * ia_c)); };
 
-    auto load = [&](int k, cx<T>* buf) {
-        const cx<T>* Gk = Gs + (size_t)k * WW;
-#pragma unroll
-        for (int j = 0; j < EPT; ++j) {
-            const int e = tid + NA * j;
-            buf[j] = (act && j < ept && e < WW) ? Gk[e] : zero;
-        }
+    // right-hand side sources (one unconditional load per block row and thread)
+    const bool from_r = CS == CS_STAGE1 || CS == CS_POLAR;
+    const c128* rptr = from_r ? a.r + (size_t)rhs * N : a.fw + (size_t)rhs * a.fw_stride + s.fw_off;
+    const __amdgpu_buffer_rsrc_t rsrc =
+        make_rsrc(rptr, CS == CS_UNIT ? 0u : (uint32_t)((from_r ? N : (size_t)H * W) * sizeof(c128)));
+    const uint32_t rbase = (uint32_t)((from_r ? (size_t)s.wy0 * a.geo.Nx + s.wx0 + tc : (size_t)tc) * sizeof(c128));
+    const uint32_t rstep = (uint32_t)((from_r ? (size_t)a.geo.Nx : (size_t)W) * sizeof(c128));
+    const __amdgpu_buffer_rsrc_t grsrc = make_rsrc(Gs, (uint32_t)((size_t)H * WW * sizeof(cx<T>)));
+    const __amdgpu_buffer_rsrc_t yrsrc = make_rsrc(Yg, (uint32_t)((size_t)H * W * sizeof(cx<T>)));
+    const bool in_cols = mine && tid >= s.c0 && tid < s.c1;
+    const int unit_k = dref.unit_k, unit_c = dref.unit_c;
+    Local<T> L = make_local<T>(s, kind, tab, nullptr, nullptr, ih2);
+    if constexpr (CS == CS_POLAR) {
+        L.in_h = dref.in_h >= 0 ? tr + dref.in_h : nullptr;
+        L.in_v = dref.in_v >= 0 ? tr + dref.in_v : nullptr;
+    }
+    // value of g_k at my column from the raw loaded value
+    auto rhs_use = [&](int k, c128 raw) -> cx<T> {
+        if (k < kf0 || k > kf1) return zero();
+        if constexpr (CS == CS_UNIT) return (k == unit_k && tid == unit_c) ? cx<T>{T(1), T(0)} : zero();
+        if constexpr (CS == CS_FINAL) return mine ? cvt<T>(raw) : zero();
+        if constexpr (CS == CS_POLAR)
+            if (kind != KIND_STAGE1) return mine ? g_polarized(L, k, tid) : zero();
+        return (in_cols && k >= s.r0 && k < s.r1) ? cvt<T>(raw) : zero();
     };
-    // part[tid] = sum_j G_k[c_j][t] vin[c_j]
+    auto rhs_load = [&](int k) -> c128 {
+        if constexpr (CS == CS_UNIT) return mk(0.0, 0.0);
+        else return bload<double>(rsrc, rbase, (uint32_t)k * rstep);
+    };
+    auto yload = [&](int k) -> cx<T> { return bload<T>(yrsrc, (uint32_t)tc * sizeof(cx<T>), (uint32_t)(k * W) * sizeof(cx<T>)); };
+    // G_k elements of this thread; lanes past the last block read zeros from the buffer
+    auto load = [&](int k, cx<T>* buf) {
+        const uint32_t kb = (uint32_t)k * (uint32_t)WW * (uint32_t)sizeof(cx<T>);
+#pragma unroll
+        for (int j = 0; j < EPT; ++j)
+            buf[j] = bload<T>(grsrc, (uint32_t)(tid + NA * j) * (uint32_t)sizeof(cx<T>), kb);
+    };
+    // part[tid] = sum_j G_k[c_j][t] v[c_j]
     auto gemv = [&](const cx<T>* buf) {
-        cx<T> acc = zero;
+        cx<T> acc = zero();
 #pragma unroll
         for (int j = 0; j < EPT; ++j) {
             const int c = cg + NG * j;
-            if (j < ept && c < W) acc = fma(acc, buf[j], v[c]);
+            const bool ok = act && j < ept && c < W;
+            const cx<T> t = buf[j] * v[ok ? c : 0];
+            if (ok) acc = acc + t;
         }
-        if (act) part[tid] = acc;
+        part[tid] = acc;
     };
     auto reduce = [&](int t) {
         cx<T> y = part[t];
@@ -318,111 +416,209 @@ __global__ __launch_bounds__(1024) void k_chain(ChainArgs a) {
     };
 
     cx<T> ring[PD + 1][EPT];
-    // ---- forward substitution: y_k = G_k (g_k - C_{k-1} y_{k-1})
-    auto fwd = [&](int k, const cx<T>* buf) {
-        if (tid < W) {
-            cx<T> g;
-            if constexpr (POLAR) g = polar ? g_polarized(L, k, tid) : rhs_plain<T>(a, d, s, rhs, k, tid);
-            else g = rhs_plain<T>(a, d, s, rhs, k, tid);
-            if (k > d.kf0) g = g - cvt<T>(coup_y(tab, s.tx, s.ty, H, tid, k - 1, ih2)) * xk[tid];
+    c128 rr[PD + 1];
+    cx<T> yr[PD + 1];
+    cx<T> yv = zero();   // the y (phase 0) or x (phase 1) entry of my column at the previous block row
+    __syncthreads();   // a2h
+
+    if (a.phase == 0) {
+        // ---- forward elimination of this half towards the middle row
+        const int kstart = h == 0 ? kf0 : kf1;
+        const int dir = h == 0 ? 1 : -1;
+        const int n = h == 0 ? m - kf0 : kf1 - m;   // block rows m-1..kf0 or kf1..m+1
+        auto kat = [&](int i) { return kstart + dir * min(i, n - 1); };
+#pragma unroll
+        for (int p = 0; p < PD; ++p)
+            if (n > 0) {
+                rr[p] = rhs_load(kat(p));
+                load(kat(p), ring[p]);
+            }
+        for (int i0 = 0; i0 < n; i0 += PD + 1) {
+#pragma unroll
+            for (int u = 0; u <= PD; ++u) {
+                const int i = i0 + u;
+                if (i < n) {
+                    const int k = kstart + dir * i;
+                    rr[(u + PD) % (PD + 1)] = rhs_load(kat(i + PD));
+                    load(kat(i + PD), ring[(u + PD) % (PD + 1)]);
+                    if (mine) {
+                        cx<T> g = rhs_use(k, rr[u]);
+                        if (i > 0) g = g - cy(h == 0 ? k - 1 : k) * yv;
+                        v[tid] = g;
+                    }
+                    __syncthreads();
+                    gemv(ring[u]);
+                    __syncthreads();
+                    if (mine) {
+                        yv = reduce(tid);
+                        Ybuf[(size_t)k * W + tid] = yv;
+                    }
+                }
+            }
+        }
+        if constexpr (YLDS) {
+            __syncthreads();
+            const int lo = h == 0 ? kf0 : m + 1, hi = h == 0 ? m - 1 : kf1;
+            for (int idx = tid; idx < (hi - lo + 1) * W; idx += NT) Yg[(size_t)lo * W + idx] = Ybuf[(size_t)lo * W + idx];
+        }
+        return;
+    }
+
+    // ---- phase 1: middle row, then back substitution of this half away from it
+    {
+        cx<T> gm[EPT];
+        load(m, gm);
+        const c128 rm = rhs_load(m);
+        const cx<T> ylo = (kf0 <= m - 1) ? yload(m - 1) : zero();
+        const cx<T> yhi = (kf1 >= m + 1) ? yload(m + 1) : zero();
+        if (mine) {
+            cx<T> g = rhs_use(m, rm);
+            if (m >= 1) g = g - cy(m - 1) * ylo;
+            if (m + 1 <= H - 1) g = g - cy(m) * yhi;
             v[tid] = g;
         }
         __syncthreads();
-        gemv(buf);
+        gemv(gm);
         __syncthreads();
-        if (tid < W) {
-            const cx<T> y = reduce(tid);
-            xk[tid] = y;
-            Y[(size_t)k * W + tid] = y;
+        if (mine) {
+            yv = reduce(tid);
+            Ybuf[(size_t)m * W + tid] = yv;
         }
-        __syncthreads();
-    };
+    }
+    {
+        const int kstart = h == 0 ? m - 1 : m + 1;
+        const int dir = h == 0 ? -1 : 1;
+        const int n = h == 0 ? m - kb0 : kb1 - m;   // block rows m-1..kb0 or m+1..kb1
+        auto kat = [&](int i) { return kstart + dir * min(i, n - 1); };
 #pragma unroll
-    for (int p = 0; p < PD; ++p)
-        if (d.kf0 + p < H) load(d.kf0 + p, ring[p]);
-    for (int k0 = d.kf0; k0 < H; k0 += PD + 1) {
+        for (int p = 0; p < PD; ++p)
+            if (n > 0) {
+                yr[p] = yload(kat(p));
+                load(kat(p), ring[p]);
+            }
+        for (int i0 = 0; i0 < n; i0 += PD + 1) {
 #pragma unroll
-        for (int u = 0; u <= PD; ++u) {
-            const int k = k0 + u;
-            if (k < H) {
-                if (k + PD < H) load(k + PD, ring[(u + PD) % (PD + 1)]);
-                fwd(k, ring[u]);
+            for (int u = 0; u <= PD; ++u) {
+                const int i = i0 + u;
+                if (i < n) {
+                    const int k = kstart + dir * i;
+                    yr[(u + PD) % (PD + 1)] = yload(kat(i + PD));
+                    load(kat(i + PD), ring[(u + PD) % (PD + 1)]);
+                    if (mine) v[tid] = cy(h == 0 ? k : k - 1) * yv;
+                    __syncthreads();
+                    gemv(ring[u]);
+                    __syncthreads();
+                    if (mine) {
+                        // y of the bottom half is zero below kf0, that of the top half above kf1
+                        const cx<T> y = (h == 0 ? k >= kf0 : k <= kf1) ? yr[u] : zero();
+                        yv = y - reduce(tid);
+                        Ybuf[(size_t)k * W + tid] = yv;
+                    }
+                }
             }
         }
     }
+    __syncthreads();
 
-    // ---- epilogue of one block row (x_k in xk)
-    auto emit = [&](int k) {
-        if (d.kind == KIND_FINAL) {
-            if (k >= s.r0 && k < s.r1) {
-                c128* zrow = a.z + (size_t)rhs * a.geo.Nx * a.geo.Ny + (size_t)(s.wy0 + k) * a.geo.Nx + s.wx0;
-                for (int c = s.c0 + tid; c < s.c1; c += NT) zrow[c] = cvt<double>(xk[c]);
-            }
-        } else if (d.kind == KIND_UNIT) {
-            cx<T>* col = reinterpret_cast<cx<T>*>(a.Q) + d.q_col;
-            const int hb = (s.sides >> SIDE_B) & 1, ht = (s.sides >> SIDE_T) & 1;
-            const int hl = (s.sides >> SIDE_L) & 1, hr = (s.sides >> SIDE_R) & 1;
-            int off = -1;
-            if (hb && k == s.r0 - 1) off = 0;
-            if (hb && k == s.r0) off = W;
-            if (ht && k == s.r1 - 1) off = 2 * W;
-            if (ht && k == s.r1) off = 3 * W;
-            if (off >= 0)
-                for (int c = tid; c < W; c += NT) col[off + c] = xk[c];
-            if (tid == 0 && hl) { col[4 * W + k] = xk[s.c0 - 1]; col[4 * W + H + k] = xk[s.c0]; }
-            if (tid == 1 && hr) { col[4 * W + 2 * H + k] = xk[s.c1 - 1]; col[4 * W + 3 * H + k] = xk[s.c1]; }
-        } else if (d.zpart >= 0 && k >= s.r0 && k < s.r1) {
-            cx<T>* zrow = reinterpret_cast<cx<T>*>(a.zpart) + (size_t)d.zpart * a.zpart_stride +
-                          (size_t)rhs * a.geo.Nx * a.geo.Ny + (size_t)(s.wy0 + k) * a.geo.Nx + s.wx0;
-            for (int c = s.c0 + tid; c < s.c1; c += NT) zrow[c] = xk[c];
+    // ---- outputs of the block rows this half owns, from Ybuf
+    const cx<T>* X = Ybuf;
+    const int olo = h == 0 ? kb0 : max(kb0, m + 1);
+    const int ohi = h == 0 ? min(kb1, m) : kb1;
+    auto own = [&](int k) { return k >= olo && k <= ohi; };
+    if constexpr (CS == CS_FINAL) {
+        const int r0 = max(s.r0, olo), r1 = min(s.r1, ohi + 1);
+        const int nc = s.c1 - s.c0, n = max(0, r1 - r0) * nc;
+        c128* z = a.z + (size_t)rhs * N + (size_t)(s.wy0 + r0) * a.geo.Nx + s.wx0 + s.c0;
+        for (int idx = tid; idx < n; idx += NT) {
+            const int rr0 = idx / nc, cc = idx - rr0 * nc;
+            z[(size_t)rr0 * a.geo.Nx + cc] = cvt<double>(X[(size_t)(r0 + rr0) * W + s.c0 + cc]);
         }
-        for (int o = 0; o < d.nout; ++o) {
-            const int side = d.out_side[o];
-            cx<T>* out = tr + d.out_off[o];
-            const bool acc = d.out_acc[o] != 0;
+    } else if constexpr (CS == CS_UNIT) {
+        cx<T>* col = reinterpret_cast<cx<T>*>(a.Q) + dref.q_col;
+        const int L8 = 4 * W + 4 * H;
+        for (int sl = tid; sl < L8; sl += NT) {
+            int k, c, side;
+            if (sl < 4 * W) {
+                const int line = sl / W;
+                c = sl - line * W;
+                side = line < 2 ? SIDE_B : SIDE_T;
+                k = line == 0 ? s.r0 - 1 : line == 1 ? s.r0 : line == 2 ? s.r1 - 1 : s.r1;
+            } else {
+                const int q = sl - 4 * W, line = q / H;
+                k = q - line * H;
+                side = line < 2 ? SIDE_L : SIDE_R;
+                c = line == 0 ? s.c0 - 1 : line == 1 ? s.c0 : line == 2 ? s.c1 - 1 : s.c1;
+            }
+            if (((s.sides >> side) & 1) && own(k)) col[sl] = X[(size_t)k * W + c];
+        }
+    } else {
+        if (dref.zpart >= 0) {
+            const int r0 = max(s.r0, olo), r1 = min(s.r1, ohi + 1);
+            const int nc = s.c1 - s.c0, n = max(0, r1 - r0) * nc;
+            cx<T>* z = reinterpret_cast<cx<T>*>(a.zpart) + (size_t)dref.zpart * a.zpart_stride + (size_t)rhs * N +
+                       (size_t)(s.wy0 + r0) * a.geo.Nx + s.wx0 + s.c0;
+            for (int idx = tid; idx < n; idx += NT) {
+                const int rr0 = idx / nc, cc = idx - rr0 * nc;
+                z[(size_t)rr0 * a.geo.Nx + cc] = X[(size_t)(r0 + rr0) * W + s.c0 + cc];
+            }
+        }
+        const int nout = dref.nout;
+        for (int o = 0; o < nout; ++o) {
+            const int side = dref.out_side[o];
+            cx<T>* out = tr + dref.out_off[o];
+            const bool acc = dref.out_acc[o] != 0;
             if (side == SIDE_B || side == SIDE_T) {
                 const int l0 = (side == SIDE_B) ? s.r0 - 1 : s.r1 - 1;
-                if (k == l0 || k == l0 + 1) {
-                    cx<T>* line = out + (size_t)(k - l0) * W;
-                    for (int c = tid; c < W; c += NT) line[c] = acc ? line[c] + xk[c] : xk[c];
+                for (int idx = tid; idx < 2 * W; idx += NT) {
+                    const int line = idx / W, c = idx - line * W;
+                    if (!own(l0 + line)) continue;
+                    const cx<T> xv = X[(size_t)(l0 + line) * W + c];
+                    out[idx] = acc ? out[idx] + xv : xv;
                 }
             } else {
                 const int l0 = (side == SIDE_L) ? s.c0 - 1 : s.c1 - 1;
-                if (tid < 2) {
-                    cx<T>* p = out + (size_t)tid * H + k;
-                    *p = acc ? *p + xk[l0 + tid] : xk[l0 + tid];
+                for (int idx = tid; idx < 2 * H; idx += NT) {
+                    const int line = idx / H, k = idx - line * H;
+                    if (!own(k)) continue;
+                    const cx<T> xv = X[(size_t)k * W + l0 + line];
+                    out[idx] = acc ? out[idx] + xv : xv;
                 }
             }
         }
-    };
+    }
+}
 
-    // ---- backward substitution: x_k = y_k - G_k C_k x_{k+1}; xk holds x_{H-1} = y_{H-1}
-    emit(H - 1);
-    auto bwd = [&](int k, const cx<T>* buf) {
-        if (tid < W) v[tid] = cvt<T>(coup_y(tab, s.tx, s.ty, H, tid, k, ih2)) * xk[tid];
-        __syncthreads();
-        gemv(buf);
-        __syncthreads();
-        if (tid < W) {
-            const cx<T> y = (k >= d.kf0) ? Y[(size_t)k * W + tid] : zero;
-            xk[tid] = y - reduce(tid);
-        }
-        __syncthreads();
-        emit(k);
-    };
-    const int kstart = H - 2;
-#pragma unroll
-    for (int p = 0; p < PD; ++p)
-        if (kstart - p >= d.kb0) load(kstart - p, ring[p]);
-    for (int k0 = kstart; k0 >= d.kb0; k0 -= PD + 1) {
-#pragma unroll
-        for (int u = 0; u <= PD; ++u) {
-            const int k = k0 - u;
-            if (k >= d.kb0) {
-                if (k - PD >= d.kb0) load(k - PD, ring[(u + PD) % (PD + 1)]);
-                bwd(k, ring[u]);
+// Right-hand side of the final z solve of each window: r on Omega_ij plus the sum of the
+// polarized sources g_s of all sweeps (stored on the trace-line slots).
+template <typename T>
+__global__ void k_final_rhs(ChainArgs a) {
+    const SubDesc s = a.subs[blockIdx.x];
+    const int rhs = blockIdx.y;
+    const int W = s.W, H = s.H;
+    const size_t N = (size_t)a.geo.Nx * a.geo.Ny;
+    const cx<T>* gp = reinterpret_cast<const cx<T>*>(a.gparts) + (size_t)rhs * 8 * a.LT + s.gp_off;
+    c128* out = a.fw + (size_t)rhs * a.fw_stride + s.fw_off;
+    for (int idx = threadIdx.x; idx < H * W; idx += blockDim.x) {
+        const int k = idx / W, c = idx - k * W;
+        c128 val = mk(0.0, 0.0);
+        if (k >= s.r0 && k < s.r1 && c >= s.c0 && c < s.c1)
+            val = a.r[(size_t)rhs * N + (size_t)(s.wy0 + k) * a.geo.Nx + s.wx0 + c];
+        int hs = -1, vs = -1;
+        if (k == s.r0 - 1) hs = c;
+        else if (k == s.r0) hs = W + c;
+        else if (k == s.r1 - 1) hs = 2 * W + c;
+        else if (k == s.r1) hs = 3 * W + c;
+        if (c == s.c0 - 1) vs = 4 * W + k;
+        else if (c == s.c0) vs = 4 * W + H + k;
+        else if (c == s.c1 - 1) vs = 4 * W + 2 * H + k;
+        else if (c == s.c1) vs = 4 * W + 3 * H + k;
+        if (hs >= 0 || vs >= 0)
+            for (int sw = 0; sw < 8; ++sw) {
+                const cx<T>* b = gp + (size_t)sw * a.LT;
+                if (hs >= 0) val = val + cvt<double>(b[hs]);
+                if (vs >= 0) val = val + cvt<double>(b[vs]);
             }
-        }
+        out[idx] = val;
     }
 }
 
@@ -440,10 +636,12 @@ __device__ inline void slot_point(const SubDesc& s, int sl, int& k, int& c) {
     }
 }
 
-// Trace-compressed sweep front: out = Q[out side, in slots] g[in slots].
+// Trace-compressed sweep front: out = Q[out side, in slots] g[in slots].  One workgroup
+// computes 64 outputs (one per lane); its 16 waves split the input slots and issue their
+// Q loads in batches of KB ahead of the multiply-adds.
 template <typename T>
-__global__ __launch_bounds__(256) void k_gemv(GemvArgs a) {
-    constexpr int NT = 256, NW = 4;
+__global__ __launch_bounds__(1024) void k_gemv(GemvArgs a) {
+    constexpr int NT = 1024, NW = NT / 64, KB = 16;
     const GemvItem it = a.items[blockIdx.x];
     const GemvSolve& d = a.solves[it.solve];
     const SubDesc s = a.subs[d.sub];
@@ -475,26 +673,28 @@ __global__ __launch_bounds__(256) void k_gemv(GemvArgs a) {
     const int sb = (side == SIDE_B) ? 0 : (side == SIDE_T) ? 2 * s.W : (side == SIDE_L) ? 4 * s.W : 4 * s.W + 2 * s.H;
     const int len = (side == SIDE_B || side == SIDE_T) ? 2 * s.W : 2 * s.H;
     const int o = it.chunk * 64 + lane;
-    const cx<T>* Qs = reinterpret_cast<const cx<T>*>(a.Q) + s.q_off + sb + o;
+    const bool valid = o < len;
+    const cx<T>* Qs = reinterpret_cast<const cx<T>*>(a.Q) + s.q_off + sb + (valid ? o : 0);
+    const int per = (total + NW - 1) / NW;
+    const int i0 = wv * per, i1 = min(total, i0 + per);
     cx<T> acc{T(0), T(0)};
-    if (o < len) {
-        int idx = wv;
-        for (; idx + 3 * NW < total; idx += 4 * NW) {
-            const cx<T> q0 = Qs[(size_t)slot[idx] * s.L];
-            const cx<T> q1 = Qs[(size_t)slot[idx + NW] * s.L];
-            const cx<T> q2 = Qs[(size_t)slot[idx + 2 * NW] * s.L];
-            const cx<T> q3 = Qs[(size_t)slot[idx + 3 * NW] * s.L];
-            acc = fma(acc, q0, gv[idx]);
-            acc = fma(acc, q1, gv[idx + NW]);
-            acc = fma(acc, q2, gv[idx + 2 * NW]);
-            acc = fma(acc, q3, gv[idx + 3 * NW]);
+    for (int base = i0; base < i1; base += KB) {
+        cx<T> q[KB];
+#pragma unroll
+        for (int u = 0; u < KB; ++u) {
+            const int idx = base + u;
+            q[u] = (valid && idx < i1) ? Qs[(size_t)slot[idx] * s.L] : cx<T>{T(0), T(0)};
         }
-        for (; idx < total; idx += NW) acc = fma(acc, Qs[(size_t)slot[idx] * s.L], gv[idx]);
+#pragma unroll
+        for (int u = 0; u < KB; ++u)
+            if (base + u < i1) acc = fma(acc, q[u], gv[base + u]);
     }
     part[wv][lane] = acc;
     __syncthreads();
-    if (wv == 0 && o < len) {
-        const cx<T> val = part[0][lane] + part[1][lane] + part[2][lane] + part[3][lane];
+    if (wv == 0 && valid) {
+        cx<T> val = part[0][lane];
+#pragma unroll
+        for (int w = 1; w < NW; ++w) val = val + part[w][lane];
         cx<T>* p = tr + d.out_off[it.out] + o;
         *p = d.out_acc[it.out] ? *p + val : val;
     }
@@ -632,59 +832,100 @@ __global__ void k_mass_gradient(const c128* lam, const c128* u, int nrhs, Geomet
 // ------------------------------------------------------------------ launchers
 static inline unsigned blocks_for(size_t n, unsigned bs) { return (unsigned)((n + bs - 1) / bs); }
 
-hipError_t launch_factor(const FactorArgs& a, int nsub, int Wmax, bool use_lds, size_t lds_bytes,
-                         bool store_c64, hipStream_t st) {
+hipError_t launch_factor(const FactorArgs& a, int nsub, bool use_lds, size_t lds_bytes, hipStream_t st) {
     constexpr int NT = 1024;
     if (use_lds) {
-        hipError_t e;
-        if (store_c64) {
-            e = hipFuncSetAttribute((const void*)k_factor<NT, true, c64>,
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
-            if (e != hipSuccess) return e;
-            k_factor<NT, true, c64><<<nsub, NT, lds_bytes, st>>>(a);
-        } else {
-            e = hipFuncSetAttribute((const void*)k_factor<NT, true, c128>,
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
-            if (e != hipSuccess) return e;
-            k_factor<NT, true, c128><<<nsub, NT, lds_bytes, st>>>(a);
-        }
+        hipError_t e = hipFuncSetAttribute((const void*)k_factor<NT, true>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+        if (e != hipSuccess) return e;
+        e = hipFuncSetAttribute((const void*)k_factor_mid<NT, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)lds_bytes);
+        if (e != hipSuccess) return e;
+        k_factor<NT, true><<<dim3(nsub, 2), NT, lds_bytes, st>>>(a);
+        k_factor_mid<NT, true><<<nsub, NT, lds_bytes, st>>>(a);
     } else {
-        if (store_c64) k_factor<NT, false, c64><<<nsub, NT, 0, st>>>(a);
-        else k_factor<NT, false, c128><<<nsub, NT, 0, st>>>(a);
+        k_factor<NT, false><<<dim3(nsub, 2), NT, 0, st>>>(a);
+        k_factor_mid<NT, false><<<nsub, NT, 0, st>>>(a);
     }
-    (void)Wmax;
     return hipGetLastError();
 }
 
 // prefetch depth: as many blocks in flight as the 128-VGPR budget of a 1024-thread
 // workgroup allows (complex64: 2 floats, complex128: 4 per element)
-template <typename T, bool POLAR>
-static void launch_chain_p(const ChainArgs& a, dim3 grid, int ept, hipStream_t st) {
+template <typename T, int CS, bool YLDS>
+static void launch_chain_c(const ChainArgs& a, dim3 grid, int ept, size_t lds, hipStream_t st) {
     constexpr bool dbl = sizeof(T) == 8;
-    if (ept <= 4) k_chain<T, 4, 2, POLAR><<<grid, 1024, 0, st>>>(a);
-    else if (ept <= 8) k_chain<T, 8, dbl ? 1 : 2, POLAR><<<grid, 1024, 0, st>>>(a);
-    else if (ept <= 16) k_chain<T, 16, dbl ? 0 : 1, POLAR><<<grid, 1024, 0, st>>>(a);
-    else if (ept <= 32) k_chain<T, 32, 0, POLAR><<<grid, 1024, 0, st>>>(a);
-    else k_chain<T, 64, 0, POLAR><<<grid, 1024, 0, st>>>(a);
+    if (ept <= 4) k_chain<T, 4, 2, CS, YLDS><<<grid, 1024, lds, st>>>(a);
+    else if (ept <= 8) k_chain<T, 8, dbl ? 1 : 2, CS, YLDS><<<grid, 1024, lds, st>>>(a);
+    else if (ept <= 16) k_chain<T, 16, dbl ? 0 : 1, CS, YLDS><<<grid, 1024, lds, st>>>(a);
+    else if (ept <= 32) k_chain<T, 32, 0, CS, YLDS><<<grid, 1024, lds, st>>>(a);
+    else k_chain<T, 64, 0, CS, YLDS><<<grid, 1024, lds, st>>>(a);
 }
 
-hipError_t launch_chain(const ChainArgs& a, int nsolves, int nrhs, int ept, bool c64mode, bool polar,
-                        hipStream_t st) {
-    dim3 grid(nsolves, nrhs);
-    if (c64mode) {
-        if (polar) launch_chain_p<float, true>(a, grid, ept, st);
-        else launch_chain_p<float, false>(a, grid, ept, st);
-    } else {
-        if (polar) launch_chain_p<double, true>(a, grid, ept, st);
-        else launch_chain_p<double, false>(a, grid, ept, st);
+template <typename T>
+static hipError_t set_lds(int cs, int ept, size_t lds) {
+    // dynamic LDS beyond the default needs the attribute on every instantiation that may run
+    auto one = [&](const void* f) { return hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds); };
+    constexpr bool dbl = sizeof(T) == 8;
+    hipError_t e = hipSuccess;
+#define LSW_SET(CSV)                                                                                      \
+    if (cs == CSV) {                                                                                      \
+        if (ept <= 4) e = one((const void*)k_chain<T, 4, 2, CSV, true>);                                  \
+        else if (ept <= 8) e = one((const void*)k_chain<T, 8, dbl ? 1 : 2, CSV, true>);                  \
+        else if (ept <= 16) e = one((const void*)k_chain<T, 16, dbl ? 0 : 1, CSV, true>);                \
+        else if (ept <= 32) e = one((const void*)k_chain<T, 32, 0, CSV, true>);                          \
+        else e = one((const void*)k_chain<T, 64, 0, CSV, true>);                                         \
+    }
+    LSW_SET(CS_STAGE1)
+    LSW_SET(CS_FINAL)
+    LSW_SET(CS_UNIT)
+    LSW_SET(CS_POLAR)
+#undef LSW_SET
+    return e;
+}
+
+template <typename T>
+static hipError_t launch_chain_t(const ChainArgs& a0, int nsolves, int nrhs, int ept, int cs, size_t ylds,
+                                 hipStream_t st) {
+    dim3 grid(2 * nsolves, nrhs);
+    if (ylds > 0) {
+        hipError_t e = set_lds<T>(cs, ept, ylds);
+        if (e != hipSuccess) return e;
+    }
+    for (int phase = 0; phase < 2; ++phase) {
+        ChainArgs a = a0;
+        a.phase = phase;
+#define LSW_GO(CSV)                                                                 \
+        if (cs == CSV) {                                                            \
+            if (ylds > 0) launch_chain_c<T, CSV, true>(a, grid, ept, ylds, st);     \
+            else launch_chain_c<T, CSV, false>(a, grid, ept, 0, st);                \
+        }
+        LSW_GO(CS_STAGE1)
+        LSW_GO(CS_FINAL)
+        LSW_GO(CS_UNIT)
+        LSW_GO(CS_POLAR)
+#undef LSW_GO
     }
     return hipGetLastError();
 }
 
+hipError_t launch_chain(const ChainArgs& a, int nsolves, int nrhs, int ept, bool c64mode, int cs, size_t ylds,
+                        hipStream_t st) {
+    return c64mode ? launch_chain_t<float>(a, nsolves, nrhs, ept, cs, ylds, st)
+                   : launch_chain_t<double>(a, nsolves, nrhs, ept, cs, ylds, st);
+}
+
 hipError_t launch_gemv(const GemvArgs& a, int nitems, int nrhs, bool c64mode, hipStream_t st) {
     dim3 grid(nitems, nrhs);
-    if (c64mode) k_gemv<float><<<grid, 256, 0, st>>>(a);
-    else k_gemv<double><<<grid, 256, 0, st>>>(a);
+    if (c64mode) k_gemv<float><<<grid, 1024, 0, st>>>(a);
+    else k_gemv<double><<<grid, 1024, 0, st>>>(a);
+    return hipGetLastError();
+}
+
+hipError_t launch_final_rhs(const ChainArgs& a, int nsub, int nrhs, bool c64mode, hipStream_t st) {
+    dim3 grid(nsub, nrhs);
+    if (c64mode) k_final_rhs<float><<<grid, 256, 0, st>>>(a);
+    else k_final_rhs<double><<<grid, 256, 0, st>>>(a);
     return hipGetLastError();
 }
 

@@ -12,7 +12,7 @@ struct FactorArgs {
     Geometry geo;
     void* G;              // factor pool (complex64 or complex128)
     c128* work;           // global workspace (only when the block does not fit in LDS)
-    size_t work_stride;   // elements per subdomain in work
+    size_t work_stride;   // elements per (subdomain, half) in work
     int* status;          // per subdomain: 1 if a zero pivot was met
 };
 
@@ -32,6 +32,9 @@ struct ChainArgs {
     const void* gparts;     // accumulated sweep right-hand sides [nrhs][8][LT] (KIND_FINAL)
     size_t LT;              // slots of all windows
     void* Q;                // Q pool (KIND_UNIT writes columns)
+    c128* fw;               // right-hand sides of the final z solves, window layout [nrhs][sum H*W]
+    size_t fw_stride;       // sum over windows of H*W
+    int phase;              // set by launch_chain: 0 forward halves, 1 middle + backward halves
 };
 
 struct GemvArgs {
@@ -86,13 +89,17 @@ struct GsArgs {
     const int* active; // optional per-rhs mask
 };
 
-hipError_t launch_factor(const FactorArgs& a, int nsub, int Wmax, bool use_lds, size_t lds_bytes,
-                         bool store_c64, hipStream_t st);
+// twisted block factorisation (complex128 factors); work: 2 blocks per subdomain when not in LDS
+hipError_t launch_factor(const FactorArgs& a, int nsub, bool use_lds, size_t lds_bytes, hipStream_t st);
 // ept = max over the launched windows of ceil(W / floor(1024 / W)) (elements per thread)
-// polar: the batch may contain polarized kinds (chained sweep mode)
-hipError_t launch_chain(const ChainArgs& a, int nsolves, int nrhs, int ept, bool c64mode, bool polar,
+// Two launches (forward halves, then middle + backward halves) of 2 workgroups per solve.
+// cs: 0 stage 1, 1 final z solves, 2 unit solves (Q), 3 any kind (chained sweep mode).
+// ylds: bytes of LDS for y/x (H_max * W_max elements), or 0 to keep x in a.Y as well
+// (then a.Y_stride must hold 2 * H_max * W_max elements).
+hipError_t launch_chain(const ChainArgs& a, int nsolves, int nrhs, int ept, bool c64mode, int cs, size_t ylds,
                         hipStream_t st);
 hipError_t launch_gemv(const GemvArgs& a, int nitems, int nrhs, bool c64mode, hipStream_t st);
+hipError_t launch_final_rhs(const ChainArgs& a, int nsub, int nrhs, bool c64mode, hipStream_t st);
 hipError_t launch_cast(const c128* src, c64* dst, size_t n, hipStream_t st);
 hipError_t launch_zsum(const ZsumArgs& a, int nrhs, bool c64mode, hipStream_t st);
 hipError_t launch_matvec(const MatvecArgs& a, int nrhs, hipStream_t st);
