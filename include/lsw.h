@@ -109,14 +109,19 @@ typedef struct {
     int fronts_per_apply;        /* dependent launch steps per application */
     double apply_chain_bytes;    /* algorithmic bytes of G read by the block substitutions of one application */
     double apply_gemv_bytes;     /* algorithmic bytes of Q read by the trace-compressed fronts of one application */
-    int chain_launches;          /* block-substitution launches per application */
+    int chain_launches;          /* block-substitution kernel launches per application (2 per front) */
     int gemv_launches;           /* trace-compressed launches per application */
-    long long q_elems;           /* complex entries of all trace-line operators Q */
+    long long q_elems;           /* complex entries of all trace-to-trace sweep operators Q' */
     double factor_flops;         /* real flops of the block factorisation */
     double t_setup_ms, t_factor_ms, t_q_ms;
     double last_apply_ms;        /* device time of the most recent lsw_apply (events) */
     double last_chain_ms;        /* ... spent in its block-substitution launches */
     double last_gemv_ms;         /* ... spent in its trace-compressed launches */
+    double apply_stage1_bytes;   /* part of apply_chain_bytes read by the stage-1 substitutions */
+    double apply_final_bytes;    /* part of apply_chain_bytes read by the final z substitutions */
+    double last_stage1_ms;       /* device time of the stage-1 substitutions (2 launches) */
+    double last_final_ms;        /* device time of the final z substitutions (2 launches) */
+    double last_final_rhs_ms;    /* device time of the final right-hand-side assembly */
 } lsw_stats_t;
 
 /*

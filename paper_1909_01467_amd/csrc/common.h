@@ -93,7 +93,6 @@ struct SubDesc {
     int L;               // number of trace-line slots, 4W + 4H
     long long g_off;     // offset (elements) of G_0 in the factor pool; G_k at g_off + k*W*W
     long long q_off;     // offset of Q = A_ij^-1[lines, lines] (L x L, column-major) in the Q pool
-    long long gp_off;    // offset of this window's slots in each accumulated-RHS array
     long long fw_off;    // offset of this window (H x W, row-major) in the final right-hand-side array
 };
 
@@ -126,19 +125,36 @@ struct SolveDesc {
 // Q[out lines, in slots] * g[in slots], where g is the polarized right-hand side on the
 // (at most four) slot ranges that carry it.
 struct GemvSolve {
-    int sub, kind, sweep;        // sweep 1..8 selects the accumulated-RHS array
+    int sub, kind, sweep;        // sweep 1..8
     int nin;
-    int in_start[4], in_len[4];  // slot ranges of g
+    int in_start[4], in_len[4];  // slot ranges of the polarized right-hand side g (= the ranges of u~)
     int nout;
     long long in_h, in_v;        // incoming traces (offsets in the trace pool), -1 if none
     long long out_off[kMaxOut];
     int out_side[kMaxOut];
     int out_acc[kMaxOut];
+    long long qp_off;            // Q'_s = Q P_s of this solve: column-major [nin][ld] block in the Q' pool
+    int ld;                      // rows of Q'_s: the outgoing slots of all its output sides, side by side
+    int row_base[kMaxOut];       // first row of each output side in Q'_s
 };
 
-// One workgroup of a trace-compressed front: 64 outputs of one output side of one solve.
+// One workgroup of a trace-compressed front: up to 64 outgoing trace values of one output
+// side of one solve, out = Q'_s[rows, :] u~, with u~ gathered from the trace pool.
 struct GemvItem {
-    int solve, out, chunk, first;  // first: this workgroup also stores g for the final solve
+    long long qoff;              // Q' pool element (first row of this chunk, column 0)
+    long long qlen;              // elements from qoff to the end of the Q'_s block
+    long long rng_off[4];        // trace-pool offsets of the contiguous ranges holding u~
+    long long out_off;           // trace-pool offset of the first output
+    int rng_len[4];
+    int ld, nrow, nin, nrng, out_acc, pad;
+};
+
+// One term of the polarization map of a sweep solve: g at window point `point` of window
+// `sub` receives coef * (trace-pool value at `pool`).  Used to rebuild the final right-hand side.
+struct PEntry {
+    c128 coef;
+    long long pool;
+    int sub, point;
 };
 
 // Everything a kernel needs to evaluate the local or global 5-point coefficients.

@@ -72,8 +72,11 @@ struct lsw_plan {
     GemvItem* d_gitems = nullptr;
     void* d_Q = nullptr;
     size_t Q_elems = 0;
-    void* d_gparts = nullptr;
-    size_t LT = 0;
+    size_t QP_elems = 0;          // Q' pool (what the sweeps read)
+    int max_nin = 0;
+    int* d_frp = nullptr;           // final right-hand side: polarization terms per window point
+    long long* d_fpool = nullptr;
+    c128* d_fcoef = nullptr;
     c128* d_fw = nullptr;
     size_t FWT = 0;
     void* d_G = nullptr;
@@ -110,7 +113,9 @@ struct lsw_plan {
     double t_setup_ms = 0, t_factor_ms = 0, t_q_ms = 0, last_apply_ms = 0, last_chain_ms = 0, last_gemv_ms = 0;
     double apply_chain_bytes = 0, apply_gemv_bytes = 0, factor_flops = 0;
     int chain_launches = 0, gemv_launches = 0;
-    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    double last_stage1_ms = 0, last_final_ms = 0, last_final_rhs_ms = 0;
+    double apply_stage1_bytes = 0, apply_final_bytes = 0;
 };
 
 namespace {
@@ -415,6 +420,8 @@ void compress_schedule(lsw_plan* p) {
     fronts.push_back(Front{0, 0, f0.count, 0, 0});
     p->gsolves.clear();
     p->gitems.clear();
+    p->QP_elems = 0;
+    p->max_nin = 0;
     for (size_t fi = 1; fi < p->fronts.size(); ++fi) {
         const Front& f = p->fronts[fi];
         Front g{1, (int)p->gsolves.size(), f.count, (int)p->gitems.size(), 0};
@@ -435,12 +442,45 @@ void compress_schedule(lsw_plan* p) {
                 gs.out_side[o] = d.out_side[o];
                 gs.out_acc[o] = d.out_acc[o];
             }
-            const int idx = (int)p->gsolves.size();
+            // Q'_s block: rows = the slots of every output side, columns = the in entries
+            int nin = 0;
+            for (int r2 = 0; r2 < gs.nin; ++r2) nin += gs.in_len[r2];
+            int ld = 0;
+            for (int o = 0; o < d.nout; ++o) {
+                gs.row_base[o] = ld;
+                ld += (d.out_side[o] == SIDE_B || d.out_side[o] == SIDE_T) ? 2 * s.W : 2 * s.H;
+            }
+            gs.ld = ld;
+            gs.qp_off = (long long)p->QP_elems;
+            p->QP_elems += (size_t)ld * nin;
+            p->max_nin = std::max(p->max_nin, nin);
             p->gsolves.push_back(gs);
-            if (d.nout == 0) p->gitems.push_back(GemvItem{idx, -1, 0, 1});
+            // trace-pool ranges of u~, in the order of the in-slot ranges
+            GemvItem base;
+            std::memset(&base, 0, sizeof(base));
+            base.nin = nin;
+            base.ld = ld;
+            base.nrng = gs.nin;
+            for (int r2 = 0; r2 < gs.nin; ++r2) {
+                const int st = gs.in_start[r2];
+                long long off;
+                if (st < 4 * s.W) off = gs.in_h + (st < 2 * s.W ? st : st - 2 * s.W);
+                else off = gs.in_v + (st < 4 * s.W + 2 * s.H ? st - 4 * s.W : st - 4 * s.W - 2 * s.H);
+                base.rng_off[r2] = off;
+                base.rng_len[r2] = gs.in_len[r2];
+            }
             for (int o = 0; o < d.nout; ++o) {
                 const int len = (d.out_side[o] == SIDE_B || d.out_side[o] == SIDE_T) ? 2 * s.W : 2 * s.H;
-                for (int c = 0; c * 64 < len; ++c) p->gitems.push_back(GemvItem{idx, o, c, (o == 0 && c == 0) ? 1 : 0});
+                for (int c = 0; c * 64 < len; ++c) {
+                    GemvItem it = base;
+                    const long long row = gs.row_base[o] + 64LL * c;
+                    it.qoff = gs.qp_off + row;
+                    it.qlen = (long long)nin * ld - row;
+                    it.nrow = std::min(64, len - 64 * c);
+                    it.out_off = d.out_off[o] + 64LL * c;
+                    it.out_acc = d.out_acc[o];
+                    p->gitems.push_back(it);
+                }
             }
         }
         g.icount = (int)p->gitems.size() - g.ioffset;
@@ -473,8 +513,9 @@ ChainArgs chain_args(lsw_plan* p, const c128* d_r, c128* d_z) {
     a.zpart_stride = p->zpart_stride;
     a.z = d_z;
     a.r = d_r;
-    a.gparts = p->d_gparts;
-    a.LT = p->LT;
+    a.frp = p->d_frp;
+    a.fpool = p->d_fpool;
+    a.fcoef = p->d_fcoef;
     a.Q = p->d_Q;
     a.fw = p->d_fw;
     a.fw_stride = p->FWT;
@@ -484,11 +525,11 @@ ChainArgs chain_args(lsw_plan* p, const c128* d_r, c128* d_z) {
 int apply_impl(lsw_plan* p, const c128* d_r, c128* d_z, int nrhs, bool timed) {
     const bool c64 = p->precision == LSW_MIXED;
     ChainArgs a = chain_args(p, d_r, d_z);
-    GemvArgs ga{p->d_gitems, p->d_gsolves, p->d_subs, p->geo, p->d_Q, p->d_traces, p->trace_stride,
-                p->d_gparts, p->LT};
+    GemvArgs ga{p->d_gitems, p->d_Q, p->d_traces, p->trace_stride};
     const bool chain_mode = p->sweep_mode == LSW_SWEEP_CHAIN;
     // events: [0] start, [1] end of the leading block substitutions, [2] end of the
-    // trace-compressed fronts (chained mode: end of z assembly), [3] end
+    // trace-compressed fronts (chained mode: end of all sweeps), [3] start of the final
+    // block substitutions (chained mode: end of z assembly), [4] end
     if (timed) HIPCK(p, hipEventRecord(p->ev[0], p->stream));
     if (chain_mode) {
         for (const Front& f : p->fronts) {
@@ -499,6 +540,7 @@ int apply_impl(lsw_plan* p, const c128* d_r, c128* d_z, int nrhs, bool timed) {
         ZsumArgs zs{p->d_zpart, p->zpart_stride, d_z, p->d_xgroup, p->d_ygroup, p->Nx, p->Ny, p->q, p->r};
         HIPCK(p, launch_zsum(zs, nrhs, c64, p->stream));
         if (timed) HIPCK(p, hipEventRecord(p->ev[2], p->stream));
+        if (timed) HIPCK(p, hipEventRecord(p->ev[3], p->stream));
     } else {
         // fronts are [stage 1 (block substitution)] [sweeps (GEMV)]... [final z (block substitution)]
         const size_t nf = p->fronts.size();
@@ -510,15 +552,16 @@ int apply_impl(lsw_plan* p, const c128* d_r, c128* d_z, int nrhs, bool timed) {
             }
             if (f.gemv) {
                 ga.items = p->d_gitems + f.ioffset;
-                HIPCK(p, launch_gemv(ga, f.icount, nrhs, c64, p->stream));
+                if (f.icount > 0) HIPCK(p, launch_gemv(ga, f.icount, nrhs, c64, p->stream));
             } else {
+                if (fi == nf - 1 && timed) HIPCK(p, hipEventRecord(p->ev[3], p->stream));
                 a.descs = p->d_descs + f.offset;
                 HIPCK(p, launch_chain(a, f.count, nrhs, p->ept, c64, fi == 0 ? 0 : 1, p->ylds, p->stream));
             }
             if (fi == 0 && timed) HIPCK(p, hipEventRecord(p->ev[1], p->stream));
         }
     }
-    if (timed) HIPCK(p, hipEventRecord(p->ev[3], p->stream));
+    if (timed) HIPCK(p, hipEventRecord(p->ev[4], p->stream));
     return LSW_OK;
 }
 
@@ -812,8 +855,6 @@ int setup_impl(lsw_plan* p, const double* d_m, double omega, double h, const lsw
             p->G_elems += (size_t)s.H * s.W * s.W;
             s.q_off = (long long)p->Q_elems;
             p->Q_elems += (size_t)s.L * s.L;
-            s.gp_off = (long long)p->LT;
-            p->LT += (size_t)s.L;
             s.fw_off = (long long)p->FWT;
             p->FWT += (size_t)s.H * s.W;
             p->ept = std::max(p->ept, (s.W + (1024 / s.W) - 1) / (1024 / s.W));
@@ -832,23 +873,17 @@ int setup_impl(lsw_plan* p, const double* d_m, double omega, double h, const lsw
     if (p->sweep_mode == LSW_SWEEP_COMPRESSED) compress_schedule(p);
     else p->Q_elems = 0;
     const size_t eb = p->precision == LSW_MIXED ? sizeof(c64) : sizeof(c128);
-    p->apply_chain_bytes = p->apply_gemv_bytes = 0;
+    p->apply_chain_bytes = p->apply_gemv_bytes = p->apply_stage1_bytes = p->apply_final_bytes = 0;
     p->chain_launches = p->gemv_launches = 0;
     for (const Front& f : p->fronts) {
         if (f.gemv) {
             p->gemv_launches++;
             for (int n = 0; n < f.icount; ++n) {
                 const GemvItem& it = p->gitems[f.ioffset + n];
-                if (it.out < 0) continue;
-                const GemvSolve& g = p->gsolves[it.solve];
-                const SubDesc& s = p->subs[g.sub];
-                int nin = 0;
-                for (int r2 = 0; r2 < g.nin; ++r2) nin += g.in_len[r2];
-                const int len = (g.out_side[it.out] == SIDE_B || g.out_side[it.out] == SIDE_T) ? 2 * s.W : 2 * s.H;
-                p->apply_gemv_bytes += (double)nin * std::min(64, len - 64 * it.chunk) * eb;
+                p->apply_gemv_bytes += (double)it.nin * it.nrow * eb;
             }
         } else {
-            p->chain_launches++;
+            p->chain_launches += 2;   // forward halves, then middle row and backward halves
             for (int n = 0; n < f.count; ++n) {
                 const SolveDesc& d = p->descs[f.offset + n];
                 const SubDesc& s = p->subs[d.sub];
@@ -856,7 +891,10 @@ int setup_impl(lsw_plan* p, const double* d_m, double omega, double h, const lsw
                 const int m = s.mid;
                 const double blocks = std::max(0, m - d.kf0) + std::max(0, d.kf1 - m) + 1 +
                                       std::max(0, m - d.kb0) + std::max(0, d.kb1 - m);
-                p->apply_chain_bytes += blocks * s.W * (double)s.W * eb;
+                const double bytes = blocks * s.W * (double)s.W * eb;
+                p->apply_chain_bytes += bytes;
+                if (&f == &p->fronts.front()) p->apply_stage1_bytes += bytes;
+                else if (&f == &p->fronts.back()) p->apply_final_bytes += bytes;
             }
         }
     }
@@ -879,7 +917,7 @@ int setup_impl(lsw_plan* p, const double* d_m, double omega, double h, const lsw
         if ((rc = dalloc(p, &p->d_gsolves, p->gsolves.size())) != LSW_OK) return rc;
         HIPCK(p, hipMemcpy(p->d_gsolves, p->gsolves.data(), sizeof(GemvSolve) * p->gsolves.size(),
                            hipMemcpyHostToDevice));
-        if ((rc = dalloc(p, &p->d_gitems, p->gitems.size())) != LSW_OK) return rc;
+        if ((rc = dalloc(p, &p->d_gitems, std::max<size_t>(1, p->gitems.size()))) != LSW_OK) return rc;
         HIPCK(p, hipMemcpy(p->d_gitems, p->gitems.data(), sizeof(GemvItem) * p->gitems.size(),
                            hipMemcpyHostToDevice));
     }
@@ -907,11 +945,6 @@ int setup_impl(lsw_plan* p, const double* d_m, double omega, double h, const lsw
         p->d_zpart = zp;
         HIPCK(p, hipMemset(zp, 0, 9 * p->zpart_stride * eb));
     } else {
-        // accumulated sweep right-hand sides; slots a sweep never writes stay zero
-        char* gp = nullptr;
-        if ((rc = dalloc(p, &gp, (size_t)p->nrhs_max * 8 * p->LT * eb)) != LSW_OK) return rc;
-        p->d_gparts = gp;
-        HIPCK(p, hipMemset(gp, 0, (size_t)p->nrhs_max * 8 * p->LT * eb));
         if ((rc = dalloc(p, &p->d_fw, (size_t)p->nrhs_max * p->FWT)) != LSW_OK) return rc;
     }
     // y of both forward halves, then x when it does not stay in LDS
@@ -986,6 +1019,52 @@ int setup_impl(lsw_plan* p, const double* d_m, double omega, double h, const lsw
                                               std::to_string(p->subs[s].i) + "," + std::to_string(p->subs[s].j) + ")");
     // Q = A_ij^-1 restricted to the trace lines: one unit solve per slot of an interior side
     if (p->sweep_mode == LSW_SWEEP_COMPRESSED) {
+        // polarization terms of every sweep solve, grouped by window point for the final solve
+        {
+            const size_t nent = p->gsolves.size() * (size_t)p->max_nin * 4;
+            PEntry* d_pe = nullptr;
+            if ((rc = dalloc(p, &d_pe, std::max<size_t>(1, nent))) != LSW_OK) return rc;
+            HIPCK(p, launch_pmap(p->d_gsolves, (int)p->gsolves.size(), p->max_nin, p->d_subs, p->geo, d_pe, p->stream));
+            std::vector<PEntry> pe(nent);
+            HIPCK(p, hipStreamSynchronize(p->stream));
+            if (nent) HIPCK(p, hipMemcpy(pe.data(), d_pe, sizeof(PEntry) * nent, hipMemcpyDeviceToHost));
+            dfree(p, d_pe);
+            // row pointers over the points of every window: window n's H*W+1 entries start at fw_off + n
+            std::vector<int> cnt(p->FWT + nsub, 0);
+            for (const PEntry& t : pe)
+                if (t.sub >= 0) cnt[p->subs[t.sub].fw_off + t.sub + t.point + 1]++;
+            std::vector<int> rp(p->FWT + nsub, 0);
+            for (int n = 0; n < nsub; ++n) {
+                const size_t b = p->subs[n].fw_off + n, np = (size_t)p->subs[n].H * p->subs[n].W;
+                rp[b] = 0;
+                for (size_t i = 1; i <= np; ++i) rp[b + i] = rp[b + i - 1] + cnt[b + i];
+            }
+            // global term offsets: window n's terms follow those of windows < n
+            std::vector<int> wbase(nsub + 1, 0);
+            for (int n = 0; n < nsub; ++n)
+                wbase[n + 1] = wbase[n] + rp[p->subs[n].fw_off + n + (size_t)p->subs[n].H * p->subs[n].W];
+            for (int n = 0; n < nsub; ++n) {
+                const size_t b = p->subs[n].fw_off + n, np = (size_t)p->subs[n].H * p->subs[n].W;
+                for (size_t i = 0; i <= np; ++i) rp[b + i] += wbase[n];
+            }
+            const int nterm = wbase[nsub];
+            std::vector<long long> fpool(std::max(1, nterm));
+            std::vector<c128> fcoef(std::max(1, nterm));
+            std::vector<int> fill(p->FWT + nsub, 0);
+            for (const PEntry& t : pe) {
+                if (t.sub < 0) continue;
+                const size_t row = p->subs[t.sub].fw_off + t.sub + t.point;
+                const int at = rp[row] + fill[row]++;
+                fpool[at] = t.pool;
+                fcoef[at] = t.coef;
+            }
+            if ((rc = dalloc(p, &p->d_frp, rp.size())) != LSW_OK) return rc;
+            if ((rc = dalloc(p, &p->d_fpool, fpool.size())) != LSW_OK) return rc;
+            if ((rc = dalloc(p, &p->d_fcoef, fcoef.size())) != LSW_OK) return rc;
+            HIPCK(p, hipMemcpy(p->d_frp, rp.data(), sizeof(int) * rp.size(), hipMemcpyHostToDevice));
+            HIPCK(p, hipMemcpy(p->d_fpool, fpool.data(), sizeof(long long) * fpool.size(), hipMemcpyHostToDevice));
+            HIPCK(p, hipMemcpy(p->d_fcoef, fcoef.data(), sizeof(c128) * fcoef.size(), hipMemcpyHostToDevice));
+        }
         const auto tq = std::chrono::steady_clock::now();
         c128* Q128 = nullptr;
         if ((rc = dalloc(p, &Q128, p->Q_elems)) != LSW_OK) return rc;
@@ -1039,15 +1118,22 @@ int setup_impl(lsw_plan* p, const double* d_m, double omega, double h, const lsw
         HIPCK(p, hipStreamSynchronize(p->stream));
         dfree(p, d_units);
         dfree(p, Yq);
+        // fold the polarization map of every sweep solve into its trace-to-trace operator
+        c128* QP128 = nullptr;
+        if ((rc = dalloc(p, &QP128, std::max<size_t>(1, p->QP_elems))) != LSW_OK) return rc;
+        HIPCK(p, launch_qprime(p->d_gsolves, (int)p->gsolves.size(), p->max_nin, p->d_subs, p->geo, Q128, QP128,
+                               p->stream));
+        HIPCK(p, hipStreamSynchronize(p->stream));
+        dfree(p, Q128);
         if (p->precision == LSW_MIXED) {
             c64* Q64 = nullptr;
-            if ((rc = dalloc(p, &Q64, p->Q_elems)) != LSW_OK) return rc;
-            HIPCK(p, launch_cast(Q128, Q64, p->Q_elems, p->stream));
+            if ((rc = dalloc(p, &Q64, std::max<size_t>(1, p->QP_elems))) != LSW_OK) return rc;
+            HIPCK(p, launch_cast(QP128, Q64, p->QP_elems, p->stream));
             HIPCK(p, hipStreamSynchronize(p->stream));
-            dfree(p, Q128);
+            dfree(p, QP128);
             p->d_Q = Q64;
         } else {
-            p->d_Q = Q128;
+            p->d_Q = QP128;
         }
         p->t_q_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tq).count();
     }
@@ -1101,19 +1187,24 @@ int lsw_apply(lsw_handle_t p, const double* d_r, double* d_z, int nrhs) {
     if (rc != LSW_OK) return rc;
     rc = apply_impl(p, reinterpret_cast<const c128*>(d_r), reinterpret_cast<c128*>(d_z), nrhs, true);
     if (rc != LSW_OK) return rc;
-    HIPCK(p, hipEventSynchronize(p->ev[3]));
-    float t01 = 0, t12 = 0, t23 = 0, t03 = 0;
+    HIPCK(p, hipEventSynchronize(p->ev[4]));
+    float t01 = 0, t12 = 0, t23 = 0, t34 = 0, t04 = 0;
     HIPCK(p, hipEventElapsedTime(&t01, p->ev[0], p->ev[1]));
     HIPCK(p, hipEventElapsedTime(&t12, p->ev[1], p->ev[2]));
     HIPCK(p, hipEventElapsedTime(&t23, p->ev[2], p->ev[3]));
-    HIPCK(p, hipEventElapsedTime(&t03, p->ev[0], p->ev[3]));
-    p->last_apply_ms = t03;
+    HIPCK(p, hipEventElapsedTime(&t34, p->ev[3], p->ev[4]));
+    HIPCK(p, hipEventElapsedTime(&t04, p->ev[0], p->ev[4]));
+    p->last_apply_ms = t04;
     if (p->sweep_mode == LSW_SWEEP_CHAIN) {
         p->last_chain_ms = t01;
         p->last_gemv_ms = 0;
+        p->last_stage1_ms = p->last_final_ms = p->last_final_rhs_ms = 0;
     } else {
-        p->last_chain_ms = t01 + t23;
+        p->last_stage1_ms = t01;
         p->last_gemv_ms = t12;
+        p->last_final_rhs_ms = t23;
+        p->last_final_ms = t34;
+        p->last_chain_ms = t01 + t34;
     }
     return LSW_OK;
 }
@@ -1183,7 +1274,7 @@ int lsw_query(lsw_handle_t p, lsw_stats_t* st) {
     st->apply_gemv_bytes = p->apply_gemv_bytes;
     st->chain_launches = p->chain_launches;
     st->gemv_launches = p->gemv_launches;
-    st->q_elems = (long long)p->Q_elems;
+    st->q_elems = (long long)p->QP_elems;
     st->factor_flops = p->factor_flops;
     st->t_setup_ms = p->t_setup_ms;
     st->t_factor_ms = p->t_factor_ms;
@@ -1191,6 +1282,11 @@ int lsw_query(lsw_handle_t p, lsw_stats_t* st) {
     st->last_apply_ms = p->last_apply_ms;
     st->last_chain_ms = p->last_chain_ms;
     st->last_gemv_ms = p->last_gemv_ms;
+    st->apply_stage1_bytes = p->apply_stage1_bytes;
+    st->apply_final_bytes = p->apply_final_bytes;
+    st->last_stage1_ms = p->last_stage1_ms;
+    st->last_final_ms = p->last_final_ms;
+    st->last_final_rhs_ms = p->last_final_rhs_ms;
     return LSW_OK;
 }
 

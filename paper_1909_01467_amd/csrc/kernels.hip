@@ -588,36 +588,26 @@ __global__ __launch_bounds__(1024) void k_chain(ChainArgs a) {
     }
 }
 
-// Right-hand side of the final z solve of each window: r on Omega_ij plus the sum of the
-// polarized sources g_s of all sweeps (stored on the trace-line slots).
+// Right-hand side of the final z solve of each window: r on Omega_ij plus the polarized
+// sources g_s of all its sweep solves.  Every incoming trace keeps, after the application, the
+// value its sweep solve read (each is written before it is consumed and never after), so the
+// g_s are rebuilt here from the trace pool with the polarization maps tabulated at setup.
 template <typename T>
 __global__ void k_final_rhs(ChainArgs a) {
     const SubDesc s = a.subs[blockIdx.x];
     const int rhs = blockIdx.y;
     const int W = s.W, H = s.H;
     const size_t N = (size_t)a.geo.Nx * a.geo.Ny;
-    const cx<T>* gp = reinterpret_cast<const cx<T>*>(a.gparts) + (size_t)rhs * 8 * a.LT + s.gp_off;
+    const cx<T>* tr = reinterpret_cast<const cx<T>*>(a.traces) + (size_t)rhs * a.trace_stride;
+    const int* rp = a.frp + s.fw_off + blockIdx.x;
     c128* out = a.fw + (size_t)rhs * a.fw_stride + s.fw_off;
     for (int idx = threadIdx.x; idx < H * W; idx += blockDim.x) {
         const int k = idx / W, c = idx - k * W;
         c128 val = mk(0.0, 0.0);
         if (k >= s.r0 && k < s.r1 && c >= s.c0 && c < s.c1)
             val = a.r[(size_t)rhs * N + (size_t)(s.wy0 + k) * a.geo.Nx + s.wx0 + c];
-        int hs = -1, vs = -1;
-        if (k == s.r0 - 1) hs = c;
-        else if (k == s.r0) hs = W + c;
-        else if (k == s.r1 - 1) hs = 2 * W + c;
-        else if (k == s.r1) hs = 3 * W + c;
-        if (c == s.c0 - 1) vs = 4 * W + k;
-        else if (c == s.c0) vs = 4 * W + H + k;
-        else if (c == s.c1 - 1) vs = 4 * W + 2 * H + k;
-        else if (c == s.c1) vs = 4 * W + 3 * H + k;
-        if (hs >= 0 || vs >= 0)
-            for (int sw = 0; sw < 8; ++sw) {
-                const cx<T>* b = gp + (size_t)sw * a.LT;
-                if (hs >= 0) val = val + cvt<double>(b[hs]);
-                if (vs >= 0) val = val + cvt<double>(b[vs]);
-            }
+        const int j1 = rp[idx + 1];
+        for (int j = rp[idx]; j < j1; ++j) val = val + a.fcoef[j] * cvt<double>(tr[a.fpool[j]]);
         out[idx] = val;
     }
 }
@@ -636,58 +626,174 @@ __device__ inline void slot_point(const SubDesc& s, int sl, int& k, int& c) {
     }
 }
 
-// Trace-compressed sweep front: out = Q[out side, in slots] g[in slots].  One workgroup
-// computes 64 outputs (one per lane); its 16 waves split the input slots and issue their
-// Q loads in batches of KB ahead of the multiply-adds.
-template <typename T>
-__global__ __launch_bounds__(1024) void k_gemv(GemvArgs a) {
-    constexpr int NT = 1024, NW = NT / 64, KB = 16;
-    const GemvItem it = a.items[blockIdx.x];
-    const GemvSolve& d = a.solves[it.solve];
-    const SubDesc s = a.subs[d.sub];
-    const int rhs = blockIdx.y, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    __shared__ cx<T> gv[4 * kMaxWindow];
-    __shared__ int slot[4 * kMaxWindow];
-    __shared__ cx<T> part[NW][64];
-    cx<T>* tr = reinterpret_cast<cx<T>*>(a.traces) + (size_t)rhs * a.trace_stride;
-    const double ih2 = 1.0 / (a.geo.h * a.geo.h);
-    const Local<T> L = make_local<T>(s, d.kind, a.geo.tab, d.in_h >= 0 ? tr + d.in_h : nullptr,
-                                     d.in_v >= 0 ? tr + d.in_v : nullptr, ih2);
+// slot of window point (k, c) among the in-slot ranges of a sweep solve, -1 if none; a point on
+// both a horizontal and a vertical trace line is looked up on the horizontal one first
+__device__ inline int in_slot(const GemvSolve& d, const SubDesc& s, int k, int c) {
+    const int kind = d.kind, W = s.W, H = s.H;
+    const bool hB = kind == KIND_B || kind == KIND_BL || kind == KIND_BR;
+    const bool hT = kind == KIND_T || kind == KIND_TR || kind == KIND_TL;
+    const bool vL = kind == KIND_L || kind == KIND_BL || kind == KIND_TL;
+    const bool vR = kind == KIND_R || kind == KIND_TR || kind == KIND_BR;
+    auto member = [&](int sl) {
+        for (int r = 0; r < d.nin; ++r)
+            if (sl >= d.in_start[r] && sl < d.in_start[r] + d.in_len[r]) return true;
+        return false;
+    };
+    if (hB || hT) {
+        const int l0 = hB ? s.r0 - 1 : s.r1 - 1;
+        if (k == l0 || k == l0 + 1) {
+            const int sl = (hB ? 0 : 2 * W) + (k - l0) * W + c;
+            if (member(sl)) return sl;
+        }
+    }
+    if (vL || vR) {
+        const int l0 = vL ? s.c0 - 1 : s.c1 - 1;
+        if (c == l0 || c == l0 + 1) {
+            const int sl = (vL ? 4 * W : 4 * W + 2 * H) + (c - l0) * H + k;
+            if (member(sl)) return sl;
+        }
+    }
+    return -1;
+}
+
+// Column e of the polarization map P_s of a sweep solve.  The polarized source (eq. DiscPol2)
+// is linear in the incoming trace values: g_p = sum_q A_pq (chi_q - chi_p) u~_q over the
+// neighbours q of p.  Column e is u~ at the point q of in-slot e (the in-slot set and the
+// support of u~ coincide); its nonzeros are the neighbours p of q across the boundary of chi.
+struct PolColumn {
+    int np;
+    int slot[4], point[4];
+    c128 coef[4];
+    long long pool;   // trace-pool offset of u~_q (relative to the right-hand side's pool)
+};
+
+__device__ inline PolColumn pol_column(const GemvSolve& d, const SubDesc& s, const Geometry& geo, int e) {
+    PolColumn col;
+    col.np = 0;
+    int r = 0, off = e;
+    while (off >= d.in_len[r]) { off -= d.in_len[r]; ++r; }
+    const int sq = d.in_start[r] + off;
+    const int W = s.W, H = s.H;
+    if (sq < 4 * W) col.pool = d.in_h + (sq < 2 * W ? sq : sq - 2 * W);
+    else col.pool = d.in_v + (sq < 4 * W + 2 * H ? sq - 4 * W : sq - 4 * W - 2 * H);
+    int kq, cq;
+    slot_point(s, sq, kq, cq);
+    const double ih2 = 1.0 / (geo.h * geo.h);
+    const Local<double> L = make_local<double>(s, d.kind, geo.tab, nullptr, nullptr, ih2);
+    const bool chq = chi_of(L, kq, cq);
+#pragma unroll
+    for (int n = 0; n < 4; ++n) {
+        const int kp = kq + (n == 2 ? -1 : n == 3 ? 1 : 0), cp = cq + (n == 0 ? -1 : n == 1 ? 1 : 0);
+        if (kp < 0 || kp >= H || cp < 0 || cp >= W) continue;
+        if (chi_of(L, kp, cp) == chq) continue;
+        const int sl = in_slot(d, s, kp, cp);
+        if (sl < 0) continue;
+        const c128 A = n < 2 ? coup_x(geo.tab, s.tx, W, s.ty, min(cp, cq), kq, ih2)
+                             : coup_y(geo.tab, s.tx, s.ty, H, cq, min(kp, kq), ih2);
+        col.slot[col.np] = sl;
+        col.point[col.np] = kp * W + cp;
+        col.coef[col.np] = chq ? A : -A;   // A_pq (chi_q - chi_p)
+        ++col.np;
+    }
+    return col;
+}
+
+// Q'_s[:, e] = sum over p of Q[out slots, slot(p)] P_s[p, e]: the trace-to-trace map of a sweep
+// solve (its outgoing traces from its incoming ones), complex128.
+__global__ void k_qprime(const GemvSolve* gsv, const SubDesc* subs, Geometry geo, const c128* Q, c128* Qp) {
+    const GemvSolve& d = gsv[blockIdx.x];
+    const SubDesc s = subs[d.sub];
+    const int e = blockIdx.y;
     int total = 0;
     for (int r = 0; r < d.nin; ++r) total += d.in_len[r];
-    cx<T>* gp = reinterpret_cast<cx<T>*>(a.gparts) + ((size_t)rhs * 8 + (d.sweep - 1)) * a.LT + s.gp_off;
-    for (int idx = tid; idx < total; idx += NT) {
-        int r = 0, off = idx;
-        while (off >= d.in_len[r]) { off -= d.in_len[r]; ++r; }
-        const int sl = d.in_start[r] + off;
-        int k, c;
-        slot_point(s, sl, k, c);
-        const cx<T> g = g_polarized(L, k, c);
-        slot[idx] = sl;
-        gv[idx] = g;
-        if (it.first) gp[sl] = g;
+    if (e >= total) return;
+    const PolColumn col = pol_column(d, s, geo, e);
+    const c128* Qs = Q + s.q_off;
+    c128* out = Qp + d.qp_off + (size_t)e * d.ld;
+    for (int t = threadIdx.x; t < d.ld; t += blockDim.x) {
+        int o = 0;
+        while (o + 1 < d.nout && t >= d.row_base[o + 1]) ++o;
+        const int side = d.out_side[o];
+        const int sb = (side == SIDE_B) ? 0 : (side == SIDE_T) ? 2 * s.W : (side == SIDE_L) ? 4 * s.W : 4 * s.W + 2 * s.H;
+        const int os = sb + t - d.row_base[o];
+        c128 v = mk(0.0, 0.0);
+        for (int j = 0; j < col.np; ++j) v = v + Qs[(size_t)col.slot[j] * s.L + os] * col.coef[j];
+        out[t] = v;
+    }
+}
+
+// the polarization maps as terms (window point, trace-pool offset, coefficient)
+__global__ void k_pmap(const GemvSolve* gsv, int max_nin, const SubDesc* subs, Geometry geo, PEntry* out) {
+    const GemvSolve& d = gsv[blockIdx.x];
+    const int e = blockIdx.y * blockDim.x + threadIdx.x;
+    if (e >= max_nin) return;
+    PEntry* o = out + ((size_t)blockIdx.x * max_nin + e) * 4;
+    int total = 0;
+    for (int r = 0; r < d.nin; ++r) total += d.in_len[r];
+    int np = 0;
+    if (e < total) {
+        const SubDesc s = subs[d.sub];
+        const PolColumn col = pol_column(d, s, geo, e);
+        np = col.np;
+        for (int j = 0; j < np; ++j) {
+            o[j].coef = col.coef[j];
+            o[j].pool = col.pool;
+            o[j].sub = d.sub;
+            o[j].point = col.point[j];
+        }
+    }
+    for (int j = np; j < 4; ++j) {
+        o[j].coef = mk(0.0, 0.0);
+        o[j].pool = 0;
+        o[j].sub = -1;
+        o[j].point = 0;
+    }
+}
+
+// Trace-compressed sweep front: out = Q'_s[rows, :] u~ for one chunk of up to 64 outputs of one
+// output side (one output per lane).  The 16 waves split the input entries.  Every load
+// depends only on the work item, so the Q' stream starts at once, next to the gather of u~.
+template <typename T>
+__global__ __launch_bounds__(1024) void k_gemv(GemvArgs a) {
+    constexpr int NT = 1024, NW = NT / 64, KB = sizeof(T) == 4 ? 32 : 16;
+    const GemvItem& it = a.items[blockIdx.x];
+    const int rhs = blockIdx.y, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    __shared__ cx<T> gv[4 * kMaxWindow + KB * NW];
+    __shared__ cx<T> part[NW][64];
+    cx<T>* tr = reinterpret_cast<cx<T>*>(a.traces) + (size_t)rhs * a.trace_stride;
+    const int nin = it.nin, ld = it.ld;
+    const bool valid = lane < it.nrow;
+    const cx<T>* Qb = reinterpret_cast<const cx<T>*>(a.Q) + it.qoff;
+    const __amdgpu_buffer_rsrc_t qr = make_rsrc(Qb, (uint32_t)((size_t)it.qlen * sizeof(cx<T>)));
+    const int per = (nin + NW - 1) / NW;
+    const int i0 = wv * per, i1 = min(nin, i0 + per);
+    const uint32_t lo = (uint32_t)lane * (uint32_t)sizeof(cx<T>);
+    const uint32_t cs = (uint32_t)ld * (uint32_t)sizeof(cx<T>);
+    cx<T> q[KB];
+#pragma unroll
+    for (int u = 0; u < KB; ++u) q[u] = bload<T>(qr, lo, (uint32_t)(i0 + u) * cs);
+    cx<T> old{T(0), T(0)};
+    if (it.out_acc && wv == 0) old = tr[it.out_off + (valid ? lane : 0)];
+    // gather u~ (zero past nin so that the tail of a batch adds nothing)
+    for (int idx = tid; idx < per * NW; idx += NT) {
+        cx<T> v{T(0), T(0)};
+        if (idx < nin) {
+            int r = 0, off = idx;
+            while (off >= it.rng_len[r]) { off -= it.rng_len[r]; ++r; }
+            v = tr[it.rng_off[r] + off];
+        }
+        gv[idx] = v;
     }
     __syncthreads();
-    if (it.out < 0) return;   // a solve without outgoing traces only stores its g
-    const int side = d.out_side[it.out];
-    const int sb = (side == SIDE_B) ? 0 : (side == SIDE_T) ? 2 * s.W : (side == SIDE_L) ? 4 * s.W : 4 * s.W + 2 * s.H;
-    const int len = (side == SIDE_B || side == SIDE_T) ? 2 * s.W : 2 * s.H;
-    const int o = it.chunk * 64 + lane;
-    const bool valid = o < len;
-    const cx<T>* Qs = reinterpret_cast<const cx<T>*>(a.Q) + s.q_off + sb + (valid ? o : 0);
-    const int per = (total + NW - 1) / NW;
-    const int i0 = wv * per, i1 = min(total, i0 + per);
     cx<T> acc{T(0), T(0)};
-    for (int base = i0; base < i1; base += KB) {
-        cx<T> q[KB];
-#pragma unroll
-        for (int u = 0; u < KB; ++u) {
-            const int idx = base + u;
-            q[u] = (valid && idx < i1) ? Qs[(size_t)slot[idx] * s.L] : cx<T>{T(0), T(0)};
-        }
+    for (int base = i0;; ) {
 #pragma unroll
         for (int u = 0; u < KB; ++u)
-            if (base + u < i1) acc = fma(acc, q[u], gv[base + u]);
+            if (base + u < i0 + per) acc = fma(acc, q[u], gv[base + u]);
+        base += KB;
+        if (base >= i1) break;
+#pragma unroll
+        for (int u = 0; u < KB; ++u) q[u] = bload<T>(qr, lo, (uint32_t)(base + u) * cs);
     }
     part[wv][lane] = acc;
     __syncthreads();
@@ -695,8 +801,7 @@ __global__ __launch_bounds__(1024) void k_gemv(GemvArgs a) {
         cx<T> val = part[0][lane];
 #pragma unroll
         for (int w = 1; w < NW; ++w) val = val + part[w][lane];
-        cx<T>* p = tr + d.out_off[it.out] + o;
-        *p = d.out_acc[it.out] ? *p + val : val;
+        tr[it.out_off + lane] = it.out_acc ? old + val : val;
     }
 }
 
@@ -924,8 +1029,22 @@ hipError_t launch_gemv(const GemvArgs& a, int nitems, int nrhs, bool c64mode, hi
 
 hipError_t launch_final_rhs(const ChainArgs& a, int nsub, int nrhs, bool c64mode, hipStream_t st) {
     dim3 grid(nsub, nrhs);
-    if (c64mode) k_final_rhs<float><<<grid, 256, 0, st>>>(a);
-    else k_final_rhs<double><<<grid, 256, 0, st>>>(a);
+    if (c64mode) k_final_rhs<float><<<grid, 1024, 0, st>>>(a);
+    else k_final_rhs<double><<<grid, 1024, 0, st>>>(a);
+    return hipGetLastError();
+}
+
+hipError_t launch_qprime(const GemvSolve* gs, int ngs, int max_nin, const SubDesc* subs, const Geometry& geo,
+                         const c128* Q, c128* Qp, hipStream_t st) {
+    if (ngs == 0 || max_nin == 0) return hipSuccess;
+    k_qprime<<<dim3(ngs, max_nin), 256, 0, st>>>(gs, subs, geo, Q, Qp);
+    return hipGetLastError();
+}
+
+hipError_t launch_pmap(const GemvSolve* gs, int ngs, int max_nin, const SubDesc* subs, const Geometry& geo,
+                       PEntry* out, hipStream_t st) {
+    if (ngs == 0 || max_nin == 0) return hipSuccess;
+    k_pmap<<<dim3(ngs, (max_nin + 255) / 256), 256, 0, st>>>(gs, max_nin, subs, geo, out);
     return hipGetLastError();
 }
 

@@ -29,8 +29,9 @@ struct ChainArgs {
     size_t zpart_stride;    // nrhs_max * N
     c128* z;                // final output (KIND_FINAL)
     const c128* r;          // input [nrhs][N]
-    const void* gparts;     // accumulated sweep right-hand sides [nrhs][8][LT] (KIND_FINAL)
-    size_t LT;              // slots of all windows
+    const int* frp;         // final right-hand side: per window, row pointers over its H*W points (H*W+1)
+    const long long* fpool; // ... trace-pool offsets of the polarization terms
+    const c128* fcoef;      // ... and their coefficients
     void* Q;                // Q pool (KIND_UNIT writes columns)
     c128* fw;               // right-hand sides of the final z solves, window layout [nrhs][sum H*W]
     size_t fw_stride;       // sum over windows of H*W
@@ -39,14 +40,9 @@ struct ChainArgs {
 
 struct GemvArgs {
     const GemvItem* items;
-    const GemvSolve* solves;
-    const SubDesc* subs;
-    Geometry geo;
-    const void* Q;
+    const void* Q;          // Q' pool
     void* traces;
     size_t trace_stride;
-    void* gparts;
-    size_t LT;
 };
 
 struct ZsumArgs {
@@ -101,6 +97,12 @@ hipError_t launch_chain(const ChainArgs& a, int nsolves, int nrhs, int ept, bool
 hipError_t launch_gemv(const GemvArgs& a, int nitems, int nrhs, bool c64mode, hipStream_t st);
 hipError_t launch_final_rhs(const ChainArgs& a, int nsub, int nrhs, bool c64mode, hipStream_t st);
 hipError_t launch_cast(const c128* src, c64* dst, size_t n, hipStream_t st);
+// the polarization maps of all sweep solves as PEntry terms, 4 per (solve, entry) slot (sub = -1: none)
+hipError_t launch_pmap(const GemvSolve* gs, int ngs, int max_nin, const SubDesc* subs, const Geometry& geo,
+                       PEntry* out, hipStream_t st);
+// Q'_s = Q_sub P_s for every sweep solve (complex128), P_s the polarization map from u~ to g
+hipError_t launch_qprime(const GemvSolve* gs, int ngs, int max_nin, const SubDesc* subs, const Geometry& geo,
+                         const c128* Q, c128* Qp, hipStream_t st);
 hipError_t launch_zsum(const ZsumArgs& a, int nrhs, bool c64mode, hipStream_t st);
 hipError_t launch_matvec(const MatvecArgs& a, int nrhs, hipStream_t st);
 hipError_t launch_dots(const DotsArgs& a, int nrhs, c128* out, int ostride, int accumulate, hipStream_t st);

@@ -67,7 +67,10 @@ class lsw_stats_t(ctypes.Structure):
                 ("chain_launches", ctypes.c_int), ("gemv_launches", ctypes.c_int), ("q_elems", ctypes.c_longlong),
                 ("factor_flops", ctypes.c_double), ("t_setup_ms", ctypes.c_double),
                 ("t_factor_ms", ctypes.c_double), ("t_q_ms", ctypes.c_double), ("last_apply_ms", ctypes.c_double),
-                ("last_chain_ms", ctypes.c_double), ("last_gemv_ms", ctypes.c_double)]
+                ("last_chain_ms", ctypes.c_double), ("last_gemv_ms", ctypes.c_double),
+                ("apply_stage1_bytes", ctypes.c_double), ("apply_final_bytes", ctypes.c_double),
+                ("last_stage1_ms", ctypes.c_double), ("last_final_ms", ctypes.c_double),
+                ("last_final_rhs_ms", ctypes.c_double)]
 
 
 _lib = None
