@@ -138,7 +138,7 @@ struct GemvSolve {
     int row_base[kMaxOut];       // first row of each output side in Q'_s
 };
 
-// One workgroup of a trace-compressed front: up to 64 outgoing trace values of one output
+// One work item of the trace-compressed sweeps: up to 64 outgoing trace values of one output
 // side of one solve, out = Q'_s[rows, :] u~, with u~ gathered from the trace pool.
 struct GemvItem {
     long long qoff;              // Q' pool element (first row of this chunk, column 0)
@@ -146,7 +146,8 @@ struct GemvItem {
     long long rng_off[4];        // trace-pool offsets of the contiguous ranges holding u~
     long long out_off;           // trace-pool offset of the first output
     int rng_len[4];
-    int ld, nrow, nin, nrng, out_acc, pad;
+    int ld, nrow, nin, nrng, out_acc;
+    int solve;                   // index of the solve
 };
 
 // One term of the polarization map of a sweep solve: g at window point `point` of window

@@ -18,7 +18,9 @@
 #include <cmath>
 #include <complex>
 #include <cstring>
+#include <map>
 #include <new>
+#include <set>
 #include <string>
 #include <vector>
 
@@ -74,6 +76,7 @@ struct lsw_plan {
     size_t Q_elems = 0;
     size_t QP_elems = 0;          // Q' pool (what the sweeps read)
     int max_nin = 0;
+    int sweep_depth = 0;            // dependency levels of the sweep work items (one launch each)
     int* d_frp = nullptr;           // final right-hand side: polarization terms per window point
     long long* d_fpool = nullptr;
     c128* d_fcoef = nullptr;
@@ -406,9 +409,14 @@ void in_ranges(const SubDesc& s, int kind, GemvSolve& g) {
     }
 }
 
-// Trace-compressed schedule: stage 1 as block substitutions (traces only), every sweep front
-// as a batched GEMV with Q, and a final block substitution per subdomain for z.
-void compress_schedule(lsw_plan* p) {
+int fail(lsw_plan* p, int code, const std::string& msg) {
+    p->err = msg;
+    return code;
+}
+
+// Trace-compressed schedule: stage 1 as block substitutions (traces only), all sweep fronts as
+// one dataflow launch of GEMV work items with Q', and a final block substitution per window.
+int compress_schedule(lsw_plan* p) {
     std::vector<SolveDesc> descs;
     std::vector<Front> fronts;
     const Front f0 = p->fronts[0];
@@ -424,7 +432,6 @@ void compress_schedule(lsw_plan* p) {
     p->max_nin = 0;
     for (size_t fi = 1; fi < p->fronts.size(); ++fi) {
         const Front& f = p->fronts[fi];
-        Front g{1, (int)p->gsolves.size(), f.count, (int)p->gitems.size(), 0};
         for (int n = 0; n < f.count; ++n) {
             const SolveDesc& d = p->descs[f.offset + n];
             const SubDesc& s = p->subs[d.sub];
@@ -479,12 +486,58 @@ void compress_schedule(lsw_plan* p) {
                     it.nrow = std::min(64, len - 64 * c);
                     it.out_off = d.out_off[o] + 64LL * c;
                     it.out_acc = d.out_acc[o];
+                    it.solve = (int)p->gsolves.size() - 1;
                     p->gitems.push_back(it);
                 }
             }
         }
-        g.icount = (int)p->gitems.size() - g.ioffset;
-        fronts.push_back(g);
+    }
+    // Dependencies between sweep solves through the trace pool, in the front order of
+    // Alg. Scenario3: a solve waits for the last writer of every trace it reads or updates
+    // (and of every trace it overwrites).  The final right-hand side re-reads every incoming
+    // trace after the sweeps, which is exact only if no trace is written after a solve read it.
+    const int ngs = (int)p->gsolves.size();
+    std::map<long long, int> last_writer;
+    std::set<long long> read_once;
+    std::vector<std::vector<int>> deps(ngs);
+    std::vector<int> level(ngs, 0);
+    for (int g2 = 0; g2 < ngs; ++g2) {
+        const GemvSolve& gs = p->gsolves[g2];
+        std::vector<int> dl;
+        auto dep_on = [&](long long off) {
+            auto w = last_writer.find(off);
+            if (w != last_writer.end() && std::find(dl.begin(), dl.end(), w->second) == dl.end()) dl.push_back(w->second);
+        };
+        for (long long off : {gs.in_h, gs.in_v})
+            if (off >= 0) {
+                dep_on(off);
+                read_once.insert(off);
+            }
+        for (int o = 0; o < gs.nout; ++o) {
+            if (read_once.count(gs.out_off[o]))
+                return fail(p, LSW_EINVAL, "internal: a sweep trace is written after it was read");
+            dep_on(gs.out_off[o]);
+        }
+        for (int o = 0; o < gs.nout; ++o) last_writer[gs.out_off[o]] = g2;
+        for (int d2 : dl) level[g2] = std::max(level[g2], level[d2] + 1);
+        deps[g2] = dl;
+    }
+    // items grouped by dependency level: one launch per level, so independent sweeps overlap
+    // (depth about 2q instead of the 3q-3 fronts of the front order)
+    std::vector<int> order(ngs);
+    for (int g2 = 0; g2 < ngs; ++g2) order[g2] = g2;
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return level[x] < level[y]; });
+    std::vector<std::vector<GemvItem>> by_solve(ngs);
+    for (const GemvItem& it : p->gitems) by_solve[it.solve].push_back(it);
+    p->gitems.clear();
+    p->sweep_depth = ngs ? *std::max_element(level.begin(), level.end()) + 1 : 0;
+    size_t at = 0;
+    for (int lv = 0; lv < p->sweep_depth; ++lv) {
+        const int start = (int)p->gitems.size();
+        int nsol = 0;
+        for (; at < order.size() && level[order[at]] == lv; ++at, ++nsol)
+            for (const GemvItem& it : by_solve[order[at]]) p->gitems.push_back(it);
+        fronts.push_back(Front{1, 0, nsol, start, (int)p->gitems.size() - start});
     }
     Front fin{0, (int)descs.size(), (int)p->subs.size(), 0, 0};
     for (size_t n = 0; n < p->subs.size(); ++n) descs.push_back(blank(p->subs[n], (int)n, KIND_FINAL, -1));
@@ -492,12 +545,9 @@ void compress_schedule(lsw_plan* p) {
     p->descs = descs;
     p->fronts = fronts;
     p->max_front = std::max(p->max_front, (int)p->subs.size());
+    return LSW_OK;
 }
 
-int fail(lsw_plan* p, int code, const std::string& msg) {
-    p->err = msg;
-    return code;
-}
 
 // ---------------------------------------------------------------- the preconditioner
 ChainArgs chain_args(lsw_plan* p, const c128* d_r, c128* d_z) {
@@ -525,7 +575,11 @@ ChainArgs chain_args(lsw_plan* p, const c128* d_r, c128* d_z) {
 int apply_impl(lsw_plan* p, const c128* d_r, c128* d_z, int nrhs, bool timed) {
     const bool c64 = p->precision == LSW_MIXED;
     ChainArgs a = chain_args(p, d_r, d_z);
-    GemvArgs ga{p->d_gitems, p->d_Q, p->d_traces, p->trace_stride};
+    GemvArgs ga{};
+    ga.nrhs = nrhs;
+    ga.Q = p->d_Q;
+    ga.traces = p->d_traces;
+    ga.trace_stride = p->trace_stride;
     const bool chain_mode = p->sweep_mode == LSW_SWEEP_CHAIN;
     // events: [0] start, [1] end of the leading block substitutions, [2] end of the
     // trace-compressed fronts (chained mode: end of all sweeps), [3] start of the final
@@ -552,7 +606,8 @@ int apply_impl(lsw_plan* p, const c128* d_r, c128* d_z, int nrhs, bool timed) {
             }
             if (f.gemv) {
                 ga.items = p->d_gitems + f.ioffset;
-                if (f.icount > 0) HIPCK(p, launch_gemv(ga, f.icount, nrhs, c64, p->stream));
+                ga.nitems = f.icount;
+                HIPCK(p, launch_gemv(ga, c64, p->stream));
             } else {
                 if (fi == nf - 1 && timed) HIPCK(p, hipEventRecord(p->ev[3], p->stream));
                 a.descs = p->d_descs + f.offset;
@@ -870,7 +925,10 @@ int setup_impl(lsw_plan* p, const double* d_m, double omega, double h, const lsw
     if (p->Wmax > kMaxWindow)
         return fail(p, LSW_EINVAL, "local window wider than " + std::to_string(kMaxWindow) + " points");
     build_schedule(p);
-    if (p->sweep_mode == LSW_SWEEP_COMPRESSED) compress_schedule(p);
+    if (p->sweep_mode == LSW_SWEEP_COMPRESSED) {
+        const int rc0 = compress_schedule(p);
+        if (rc0 != LSW_OK) return rc0;
+    }
     else p->Q_elems = 0;
     const size_t eb = p->precision == LSW_MIXED ? sizeof(c64) : sizeof(c128);
     p->apply_chain_bytes = p->apply_gemv_bytes = p->apply_stage1_bytes = p->apply_final_bytes = 0;

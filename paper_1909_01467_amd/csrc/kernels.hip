@@ -601,7 +601,10 @@ __global__ void k_final_rhs(ChainArgs a) {
     const cx<T>* tr = reinterpret_cast<const cx<T>*>(a.traces) + (size_t)rhs * a.trace_stride;
     const int* rp = a.frp + s.fw_off + blockIdx.x;
     c128* out = a.fw + (size_t)rhs * a.fw_stride + s.fw_off;
-    for (int idx = threadIdx.x; idx < H * W; idx += blockDim.x) {
+    // gridDim.z workgroups share a window
+    const int chunk = (H * W + gridDim.z - 1) / gridDim.z;
+    const int e0 = blockIdx.z * chunk, e1 = min(H * W, e0 + chunk);
+    for (int idx = e0 + threadIdx.x; idx < e1; idx += blockDim.x) {
         const int k = idx / W, c = idx - k * W;
         c128 val = mk(0.0, 0.0);
         if (k >= s.r0 && k < s.r1 && c >= s.c0 && c < s.c1)
@@ -750,58 +753,68 @@ __global__ void k_pmap(const GemvSolve* gsv, int max_nin, const SubDesc* subs, G
     }
 }
 
-// Trace-compressed sweep front: out = Q'_s[rows, :] u~ for one chunk of up to 64 outputs of one
-// output side (one output per lane).  The 16 waves split the input entries.  Every load
-// depends only on the work item, so the Q' stream starts at once, next to the gather of u~.
+// One dependency level of the trace-compressed sweeps (Alg. Scenario3 after stage 1): every
+// work item of the level is one workgroup computing up to 64 outgoing trace values
+// out = Q'_s[rows, :] u~ (one per lane, the waves splitting the input entries) for every
+// right-hand side.  Levels are separate launches, so every trace an item reads or updates was
+// completed by an earlier launch.  The Q' loads depend only on the work item and start at
+// once, next to the gather of u~; the Q' share of a wave stays in registers across the
+// right-hand sides when it fits.
 template <typename T>
-__global__ __launch_bounds__(1024) void k_gemv(GemvArgs a) {
-    constexpr int NT = 1024, NW = NT / 64, KB = sizeof(T) == 4 ? 32 : 16;
-    const GemvItem& it = a.items[blockIdx.x];
-    const int rhs = blockIdx.y, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+__global__ __launch_bounds__(512) void k_gemv(GemvArgs a) {
+    constexpr int NT = 512, NW = NT / 64, KB = sizeof(T) == 4 ? 24 : 12;
     __shared__ cx<T> gv[4 * kMaxWindow + KB * NW];
     __shared__ cx<T> part[NW][64];
-    cx<T>* tr = reinterpret_cast<cx<T>*>(a.traces) + (size_t)rhs * a.trace_stride;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const GemvItem& it = a.items[blockIdx.x];
     const int nin = it.nin, ld = it.ld;
     const bool valid = lane < it.nrow;
     const cx<T>* Qb = reinterpret_cast<const cx<T>*>(a.Q) + it.qoff;
     const __amdgpu_buffer_rsrc_t qr = make_rsrc(Qb, (uint32_t)((size_t)it.qlen * sizeof(cx<T>)));
     const int per = (nin + NW - 1) / NW;
     const int i0 = wv * per, i1 = min(nin, i0 + per);
+    const bool resident = per <= KB;
     const uint32_t lo = (uint32_t)lane * (uint32_t)sizeof(cx<T>);
     const uint32_t cs = (uint32_t)ld * (uint32_t)sizeof(cx<T>);
     cx<T> q[KB];
 #pragma unroll
     for (int u = 0; u < KB; ++u) q[u] = bload<T>(qr, lo, (uint32_t)(i0 + u) * cs);
-    cx<T> old{T(0), T(0)};
-    if (it.out_acc && wv == 0) old = tr[it.out_off + (valid ? lane : 0)];
-    // gather u~ (zero past nin so that the tail of a batch adds nothing)
-    for (int idx = tid; idx < per * NW; idx += NT) {
-        cx<T> v{T(0), T(0)};
-        if (idx < nin) {
-            int r = 0, off = idx;
-            while (off >= it.rng_len[r]) { off -= it.rng_len[r]; ++r; }
-            v = tr[it.rng_off[r] + off];
+    for (int rhs = 0; rhs < a.nrhs; ++rhs) {
+        cx<T>* tr = reinterpret_cast<cx<T>*>(a.traces) + (size_t)rhs * a.trace_stride;
+        cx<T> old{T(0), T(0)};
+        if (it.out_acc && wv == 0) old = tr[it.out_off + (valid ? lane : 0)];
+        // gather u~ (zero past nin so that the tail of a batch adds nothing)
+        for (int idx = tid; idx < per * NW; idx += NT) {
+            cx<T> v{T(0), T(0)};
+            if (idx < nin) {
+                int r = 0, off = idx;
+                while (off >= it.rng_len[r]) { off -= it.rng_len[r]; ++r; }
+                v = tr[it.rng_off[r] + off];
+            }
+            gv[idx] = v;
         }
-        gv[idx] = v;
-    }
-    __syncthreads();
-    cx<T> acc{T(0), T(0)};
-    for (int base = i0;; ) {
+        __syncthreads();
+        cx<T> acc{T(0), T(0)};
+        for (int base = i0;;) {
+            if (base != i0 || (rhs > 0 && !resident)) {
 #pragma unroll
-        for (int u = 0; u < KB; ++u)
-            if (base + u < i0 + per) acc = fma(acc, q[u], gv[base + u]);
-        base += KB;
-        if (base >= i1) break;
+                for (int u = 0; u < KB; ++u) q[u] = bload<T>(qr, lo, (uint32_t)(base + u) * cs);
+            }
 #pragma unroll
-        for (int u = 0; u < KB; ++u) q[u] = bload<T>(qr, lo, (uint32_t)(base + u) * cs);
-    }
-    part[wv][lane] = acc;
-    __syncthreads();
-    if (wv == 0 && valid) {
-        cx<T> val = part[0][lane];
+            for (int u = 0; u < KB; ++u)
+                if (base + u < i0 + per) acc = fma(acc, q[u], gv[base + u]);
+            base += KB;
+            if (base >= i1) break;
+        }
+        part[wv][lane] = acc;
+        __syncthreads();
+        if (wv == 0 && valid) {
+            cx<T> val = part[0][lane];
 #pragma unroll
-        for (int w = 1; w < NW; ++w) val = val + part[w][lane];
-        tr[it.out_off + lane] = it.out_acc ? old + val : val;
+            for (int w = 1; w < NW; ++w) val = val + part[w][lane];
+            tr[it.out_off + lane] = it.out_acc ? old + val : val;
+        }
+        __syncthreads();
     }
 }
 
@@ -1020,17 +1033,17 @@ hipError_t launch_chain(const ChainArgs& a, int nsolves, int nrhs, int ept, bool
                    : launch_chain_t<double>(a, nsolves, nrhs, ept, cs, ylds, st);
 }
 
-hipError_t launch_gemv(const GemvArgs& a, int nitems, int nrhs, bool c64mode, hipStream_t st) {
-    dim3 grid(nitems, nrhs);
-    if (c64mode) k_gemv<float><<<grid, 1024, 0, st>>>(a);
-    else k_gemv<double><<<grid, 1024, 0, st>>>(a);
+hipError_t launch_gemv(const GemvArgs& a, bool c64mode, hipStream_t st) {
+    if (a.nitems <= 0) return hipSuccess;
+    if (c64mode) k_gemv<float><<<a.nitems, 512, 0, st>>>(a);
+    else k_gemv<double><<<a.nitems, 512, 0, st>>>(a);
     return hipGetLastError();
 }
 
 hipError_t launch_final_rhs(const ChainArgs& a, int nsub, int nrhs, bool c64mode, hipStream_t st) {
-    dim3 grid(nsub, nrhs);
-    if (c64mode) k_final_rhs<float><<<grid, 1024, 0, st>>>(a);
-    else k_final_rhs<double><<<grid, 1024, 0, st>>>(a);
+    dim3 grid(nsub, nrhs, 8);
+    if (c64mode) k_final_rhs<float><<<grid, 256, 0, st>>>(a);
+    else k_final_rhs<double><<<grid, 256, 0, st>>>(a);
     return hipGetLastError();
 }
 

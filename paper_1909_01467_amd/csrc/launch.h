@@ -39,7 +39,9 @@ struct ChainArgs {
 };
 
 struct GemvArgs {
-    const GemvItem* items;
+    const GemvItem* items;  // the work items of one dependency level
+    int nitems;
+    int nrhs;
     const void* Q;          // Q' pool
     void* traces;
     size_t trace_stride;
@@ -94,7 +96,8 @@ hipError_t launch_factor(const FactorArgs& a, int nsub, bool use_lds, size_t lds
 // (then a.Y_stride must hold 2 * H_max * W_max elements).
 hipError_t launch_chain(const ChainArgs& a, int nsolves, int nrhs, int ept, bool c64mode, int cs, size_t ylds,
                         hipStream_t st);
-hipError_t launch_gemv(const GemvArgs& a, int nitems, int nrhs, bool c64mode, hipStream_t st);
+// one dependency level of the trace-compressed sweeps: one workgroup per work item
+hipError_t launch_gemv(const GemvArgs& a, bool c64mode, hipStream_t st);
 hipError_t launch_final_rhs(const ChainArgs& a, int nsub, int nrhs, bool c64mode, hipStream_t st);
 hipError_t launch_cast(const c128* src, c64* dst, size_t n, hipStream_t st);
 // the polarization maps of all sweep solves as PEntry terms, 4 per (solve, entry) slot (sub = -1: none)
