@@ -77,6 +77,27 @@ def time_applies(solver, b, reps: int = 20):
     return med, solver.stats()
 
 
+def counter_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary (scaled
+    FETCH_SIZE + WRITE_SIZE), or None when the kernels changed since the counters were taken."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", "lens2d_mixed_hbm_traffic.txt")
+    src = os.path.join(ROOT, "paper_1909_01467_amd", "csrc", "kernels.hip")
+    try:
+        text = open(path).read()
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    except OSError:
+        return None
+    if f"sha256[:16] = {sha}" not in text:
+        return None
+    for line in text.splitlines():
+        parts = line.split()
+        if len(parts) == 3 and parts[0] == "traffic" and parts[1] == kernel:
+            return int(parts[2])
+    return None
+
+
 def cpu_baseline(workload: str, budget_s: float = 60.0):
     """The FP64 oracle (Alg. Scenario3 with SuperLU local solves inside FGMRES), timed on the
     host on the same workload: setup and one solve to 1e-6."""
@@ -206,7 +227,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": None,
+            "traffic": (counter_traffic(dom_name) if args.workload == "lens2d" else None),
             "algorithmic_bytes_per_launch": round(dom["bytes_per_launch"]),
             "avg_launch_ms": round(dom["avg_launch_ms"], 5),
         },

@@ -134,7 +134,8 @@ struct GemvSolve {
     int out_side[kMaxOut];
     int out_acc[kMaxOut];
     long long qp_off;            // Q'_s = Q P_s of this solve: column-major [nin][ld] block in the Q' pool
-    int ld;                      // rows of Q'_s: the outgoing slots of all its output sides, side by side
+    int rows;                    // rows of Q'_s: the outgoing slots of all its output sides, side by side
+    int ld;                      // leading dimension: rows rounded up to 16 (128-byte aligned columns)
     int row_base[kMaxOut];       // first row of each output side in Q'_s
 };
 

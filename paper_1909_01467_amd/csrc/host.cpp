@@ -457,6 +457,8 @@ int compress_schedule(lsw_plan* p) {
                 gs.row_base[o] = ld;
                 ld += (d.out_side[o] == SIDE_B || d.out_side[o] == SIDE_T) ? 2 * s.W : 2 * s.H;
             }
+            gs.rows = ld;
+            ld = (ld + 15) & ~15;
             gs.ld = ld;
             gs.qp_off = (long long)p->QP_elems;
             p->QP_elems += (size_t)ld * nin;

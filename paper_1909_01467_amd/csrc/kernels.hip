@@ -23,19 +23,21 @@ namespace lsw {
 
 // ------------------------------------------------------------------ buffer loads
 // Raw buffer loads: 128-bit resource in SGPRs (base, byte size), 32-bit byte offset per lane.
-// Offsets past the size return zero instead of faulting.
+// The whole offset goes in the per-lane operand, which the range check covers: offsets past
+// the size (kOob for a lane that must read nothing) return zero without a memory access.
+constexpr uint32_t kOob = 0x80000000u;
 __device__ inline __amdgpu_buffer_rsrc_t make_rsrc(const void* base, uint32_t bytes) {
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, (int)bytes, 0x00020000);
 }
 template <typename T>
-__device__ inline cx<T> bload(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff);
+__device__ inline cx<T> bload(__amdgpu_buffer_rsrc_t r, uint32_t off);
 template <>
-__device__ inline cx<float> bload<float>(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
-    return __builtin_bit_cast(cx<float>, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+__device__ inline cx<float> bload<float>(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+    return __builtin_bit_cast(cx<float>, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
 }
 template <>
-__device__ inline cx<double> bload<double>(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
-    return __builtin_bit_cast(cx<double>, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
+__device__ inline cx<double> bload<double>(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+    return __builtin_bit_cast(cx<double>, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
 }
 
 // ------------------------------------------------------------------ coefficients
@@ -387,15 +389,15 @@ __global__ __launch_bounds__(1024) void k_chain(ChainArgs a) {
     };
     auto rhs_load = [&](int k) -> c128 {
         if constexpr (CS == CS_UNIT) return mk(0.0, 0.0);
-        else return bload<double>(rsrc, rbase, (uint32_t)k * rstep);
+        else return bload<double>(rsrc, rbase + (uint32_t)k * rstep);
     };
-    auto yload = [&](int k) -> cx<T> { return bload<T>(yrsrc, (uint32_t)tc * sizeof(cx<T>), (uint32_t)(k * W) * sizeof(cx<T>)); };
+    auto yload = [&](int k) -> cx<T> { return bload<T>(yrsrc, (uint32_t)(k * W + tc) * (uint32_t)sizeof(cx<T>)); };
     // G_k elements of this thread; lanes past the last block read zeros from the buffer
     auto load = [&](int k, cx<T>* buf) {
         const uint32_t kb = (uint32_t)k * (uint32_t)WW * (uint32_t)sizeof(cx<T>);
 #pragma unroll
         for (int j = 0; j < EPT; ++j)
-            buf[j] = bload<T>(grsrc, (uint32_t)(tid + NA * j) * (uint32_t)sizeof(cx<T>), kb);
+            buf[j] = bload<T>(grsrc, kb + (uint32_t)(tid + NA * j) * (uint32_t)sizeof(cx<T>));
     };
     // part[tid] = sum_j G_k[c_j][t] v[c_j]
     auto gemv = [&](const cx<T>* buf) {
@@ -714,6 +716,10 @@ __global__ void k_qprime(const GemvSolve* gsv, const SubDesc* subs, Geometry geo
     const c128* Qs = Q + s.q_off;
     c128* out = Qp + d.qp_off + (size_t)e * d.ld;
     for (int t = threadIdx.x; t < d.ld; t += blockDim.x) {
+        if (t >= d.rows) {   // alignment padding
+            out[t] = mk(0.0, 0.0);
+            continue;
+        }
         int o = 0;
         while (o + 1 < d.nout && t >= d.row_base[o + 1]) ++o;
         const int side = d.out_side[o];
@@ -762,7 +768,7 @@ __global__ void k_pmap(const GemvSolve* gsv, int max_nin, const SubDesc* subs, G
 // right-hand sides when it fits.
 template <typename T>
 __global__ __launch_bounds__(512) void k_gemv(GemvArgs a) {
-    constexpr int NT = 512, NW = NT / 64, KB = sizeof(T) == 4 ? 24 : 12;
+    constexpr int NT = 512, NW = NT / 64, KB = sizeof(T) == 4 ? 16 : 8;
     __shared__ cx<T> gv[4 * kMaxWindow + KB * NW];
     __shared__ cx<T> part[NW][64];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -776,9 +782,12 @@ __global__ __launch_bounds__(512) void k_gemv(GemvArgs a) {
     const bool resident = per <= KB;
     const uint32_t lo = (uint32_t)lane * (uint32_t)sizeof(cx<T>);
     const uint32_t cs = (uint32_t)ld * (uint32_t)sizeof(cx<T>);
+    // column c of this wave's share at my row, or nothing (no overlap with the next wave's
+    // share, no rows past the chunk): every byte fetched is used
+    auto qoff = [&](int c) { return (valid && c < i1) ? lo + (uint32_t)c * cs : kOob; };
     cx<T> q[KB];
 #pragma unroll
-    for (int u = 0; u < KB; ++u) q[u] = bload<T>(qr, lo, (uint32_t)(i0 + u) * cs);
+    for (int u = 0; u < KB; ++u) q[u] = bload<T>(qr, qoff(i0 + u));
     for (int rhs = 0; rhs < a.nrhs; ++rhs) {
         cx<T>* tr = reinterpret_cast<cx<T>*>(a.traces) + (size_t)rhs * a.trace_stride;
         cx<T> old{T(0), T(0)};
@@ -798,7 +807,7 @@ __global__ __launch_bounds__(512) void k_gemv(GemvArgs a) {
         for (int base = i0;;) {
             if (base != i0 || (rhs > 0 && !resident)) {
 #pragma unroll
-                for (int u = 0; u < KB; ++u) q[u] = bload<T>(qr, lo, (uint32_t)(base + u) * cs);
+                for (int u = 0; u < KB; ++u) q[u] = bload<T>(qr, qoff(base + u));
             }
 #pragma unroll
             for (int u = 0; u < KB; ++u)
