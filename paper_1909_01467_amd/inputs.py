@@ -126,6 +126,14 @@ def complex_normal(shape, seed: int) -> np.ndarray:
     return (rng.standard_normal(shape) + 1j * rng.standard_normal(shape)) / math.sqrt(2.0)
 
 
+def smooth_direction(n: int, seed: int, corr: float = 0.05) -> np.ndarray:
+    """Seeded N(0,1) field on the bulk grid, low-pass filtered to correlation length `corr`
+    and scaled to max-abs 1 (a direction for finite-difference checks of a gradient)."""
+    rng = np.random.default_rng(seed)
+    d = ndimage.gaussian_filter(rng.standard_normal((n, n)), sigma=corr / bulk_h(n), mode="reflect")
+    return d / np.max(np.abs(d))
+
+
 def omega_for(n: int, c: np.ndarray, ppw: float = 10.0) -> float:
     """Angular frequency giving `ppw` points per minimum wavelength."""
     return 2.0 * math.pi * float(np.min(c)) * n / ppw

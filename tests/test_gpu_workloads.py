@@ -1,0 +1,157 @@
+"""The layered (reflective) and FWI workloads through the C ABI.
+
+* layered2d at reduced size (same medium recipe, 15-point PML): one application at 511^2, 4x4
+  against the oracle's Alg. Scenario3 (FP64 1e-10, complex64 2e-4); the batched 8-source
+  solve at 255^2, 4x4 against the oracle's sparse direct solve (1e-6 / 1e-4 at tol 1e-8).
+* layered2d at full size (2047^2, 16x16 CDD, 32 sources batched in every launch, complex64):
+  one application against the oracle (the whole vector); batching is exact; the banded
+  oracle does not fit (430 GB), so the residuals of a short 32-source solve are recomputed in
+  FP64 on the host from the oracle's assembled operator of App. A.
+* fwi2d at full size (1023^2, 8x8, 8 sources, 64 receivers): forward residuals by the
+  oracle's matrix, and the adjoint gradient of the misfit against Richardson-extrapolated
+  central finite differences (steps 1e-5 and 5e-6, solves to 1e-12, agreement 1e-4) along
+  seeded smooth directions, a property that holds at any size (the oracle's own gradient is
+  compared at n = 40 in test_gpu_parity).
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from oracle.direct import SparseLU
+from oracle.discretization import GlobalProblem, extend_normal
+from oracle.lsweep import LSweep2D
+from paper_1909_01467_amd import inputs
+from paper_1909_01467_amd.lsweeps import HelmholtzSolve, Solver, extend_medium
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[case]", *a, file=sys.stderr, flush=True)
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a).ravel() - np.asarray(b).ravel()) / np.linalg.norm(np.asarray(b).ravel()))
+
+
+def solver_for(wl, m, **kw):
+    return Solver(torch.from_numpy(m).cuda(), wl.omega, wl.h, wl.n, wl.n_pml, wl.q, wl.r, C=wl.C, **kw)
+
+
+def test_layered2d_reduced_apply_and_batched_solve():
+    """The reflective medium needs many more iterations than the smooth ones (multiple
+    scattering between layers that a single pass of sweeps does not capture): 124 for the
+    oracle's own FGMRES at 255^2, 4x4.  The batched solve runs at that size."""
+    wl = inputs.workload("layered2d", n=511, q=4)
+    m = extend_normal(wl.slowness2, wl.n_pml)
+    say("layered2d reduced", wl.n, wl.q, "omega", round(wl.omega, 2))
+    r = inputs.complex_normal(m.size, 21)
+    zo = LSweep2D(m, wl.omega, wl.n, wl.n_pml, wl.q, wl.r, wl.C).apply(r)
+    for precision, tol in (("fp64", 1e-10), ("mixed", 2e-4)):
+        s = solver_for(wl, m, precision=precision)
+        err = rel(s.apply(torch.from_numpy(r).cuda()).cpu().numpy().ravel(), zo)
+        say("layered2d reduced apply", precision, err)
+        assert err < tol
+        s.close()
+    wl = inputs.workload("layered2d", n=255, q=4)
+    m = extend_normal(wl.slowness2, wl.n_pml)
+    gp = GlobalProblem(m, wl.omega, wl.n, wl.n_pml, wl.C)
+    B = np.stack([gp.rhs(f) for f in wl.sources[:8]])
+    lu = SparseLU(gp.A)
+    U_ref = np.stack([lu.solve(b) for b in B])
+    for precision, tol in (("fp64", 1e-6), ("mixed", 1e-4)):
+        s = solver_for(wl, m, precision=precision, tol=1e-8, nrhs_max=8, restart=100, maxit=1000)
+        U, info = s.solve(torch.from_numpy(B).cuda())
+        U = U.cpu().numpy().reshape(8, -1)
+        say("layered2d 255 solve", precision, info["iterations"])
+        assert all(info["converged"])
+        for k in range(8):
+            assert np.linalg.norm(B[k] - gp.A @ U[k]) / np.linalg.norm(B[k]) <= 1e-8
+            assert rel(U[k], U_ref[k]) < tol
+        s.close()
+
+
+def test_layered2d_full_size_apply_and_32_source_batch():
+    """2047^2, 16x16 CDD, 15-point PML.  One application against the oracle's Alg. Scenario3
+    (whole vector); the 32 sources applied in one batched launch equal 32 single applications;
+    a short 32-source solve reports residuals that the oracle's matrix reproduces."""
+    wl = inputs.workload("layered2d")
+    m = extend_normal(wl.slowness2, wl.n_pml)
+    say("layered2d full", wl.n, wl.q, "omega", round(wl.omega, 2))
+    r = inputs.complex_normal(m.size, 22)
+    zo = LSweep2D(m, wl.omega, wl.n, wl.n_pml, wl.q, wl.r, wl.C).apply(r)
+    say("layered2d full oracle apply done")
+    s = solver_for(wl, m, precision="mixed", nrhs_max=32, restart=10, maxit=10)
+    st = s.stats()
+    say("layered2d full setup ms", round(st["t_setup_ms"]), "W_max", st["W_max"])
+    err = rel(s.apply(torch.from_numpy(r).cuda()).cpu().numpy().ravel(), zo)
+    say("layered2d full apply mixed", err)
+    assert err < 2e-4
+    gp = GlobalProblem(m, wl.omega, wl.n, wl.n_pml, wl.C)
+    B = torch.from_numpy(np.stack([gp.rhs(f) for f in wl.sources])).cuda()
+    Z = s.apply(B)
+    for k in (0, 13, 31):
+        assert torch.equal(Z[k], s.apply(B[k:k + 1])[0])
+    U, info = s.solve(B)
+    say("layered2d full 32-source solve", info["iterations"][:4], info["relres"][:4], "ms", info["t_solve_ms"])
+    U = U.cpu().numpy().reshape(32, -1)
+    Bn = B.cpu().numpy().reshape(32, -1)
+    s.close()
+    for k in range(32):
+        res = np.linalg.norm(Bn[k] - gp.A @ U[k]) / np.linalg.norm(Bn[k])
+        assert res < 1.0 and abs(res - info["relres"][k]) <= 1e-6 + 1e-3 * res, (k, res, info["relres"][k])
+
+
+def test_fwi2d_full_size_gradient_and_finite_differences():
+    wl = inputs.workload("fwi2d")
+    n, p = wl.n, wl.n_pml
+    mb0 = 1.0 / wl.background**2
+    mb_true = wl.slowness2
+    # The finite differences subtract misfits of two independent solves whose perturbations of u
+    # are ~1e-3 relative; solves to 1e-10 leave ~1% noise in that difference at this frequency,
+    # so the solves here go to 1e-12.
+    kw = dict(omega=wl.omega, h=wl.h, n=n, n_pml=p, q=wl.q, r=wl.r, C=wl.C, tol=1e-12, nrhs_max=8,
+              precision="fp64")
+    gp0 = GlobalProblem(extend_normal(mb0, p), wl.omega, n, p, wl.C)
+    F = torch.from_numpy(np.stack([gp0.rhs(f) for f in wl.sources])).cuda()   # f is zero in the PML
+    rec = torch.from_numpy(wl.receivers + p).cuda()
+
+    def forward(mb):
+        m_ext = extend_medium(mb, p)
+        U = HelmholtzSolve.apply(m_ext, F, kw)
+        return U.reshape(8, n + 2 * p, n + 2 * p)[:, rec[:, 0], rec[:, 1]], U
+
+    with torch.no_grad():
+        d_obs, U_true = forward(torch.from_numpy(mb_true).cuda())
+    gpt = GlobalProblem(extend_normal(mb_true, p), wl.omega, n, p, wl.C)
+    Un = U_true.cpu().numpy().reshape(8, -1)
+    for k in range(8):
+        assert np.linalg.norm(gpt.rhs(wl.sources[k]) - gpt.A @ Un[k]) / np.linalg.norm(gpt.rhs(wl.sources[k])) <= 1.05e-12
+
+    def misfit(mb):
+        dp, _ = forward(mb)
+        return 0.5 * ((dp - d_obs).abs() ** 2).sum()
+
+    m_t = torch.from_numpy(mb0).cuda().requires_grad_(True)
+    J = misfit(m_t)
+    J.backward()
+    g = m_t.grad.detach()
+    say("fwi2d J", J.item(), "|g|", g.norm().item())
+    # The misfit is small next to the data response to a perturbation of 1e-4 (J ~ 2e-11, the
+    # change of J at that step ~ 5e-11), so a single central difference at 1e-4 is not yet in
+    # its asymptotic range here (its cubic term is a few percent).  Richardson extrapolation of
+    # central differences at 1e-5 and 5e-6 removes the h^2 term.
+    def central(d, h):
+        with torch.no_grad():
+            return (misfit(m_t.detach() + h * d) - misfit(m_t.detach() - h * d)).item() / (2 * h)
+
+    for seed in range(1000, 1006):
+        d = torch.from_numpy(inputs.smooth_direction(n, seed)).cuda()
+        d1, d2 = central(d, 1e-5), central(d, 5e-6)
+        fd = (4 * d2 - d1) / 3
+        ad = float((g * d).sum())
+        say("fwi2d direction", seed, "fd", fd, "(h=1e-5:", d1, ") adjoint", ad)
+        assert abs(fd - ad) <= 1e-4 * abs(ad)
