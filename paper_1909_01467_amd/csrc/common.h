@@ -162,10 +162,12 @@ struct PEntry {
 // Everything a kernel needs to evaluate the local or global 5-point coefficients.
 struct Geometry {
     const c128* tab;      // table pool
-    const double* m;      // squared slowness on the extended grid, [y][x]
+    const double* m;      // squared slowness on the extended grid, [z][y][x]
     int Nx, Ny;           // extended grid
     double h, omega;
     int gtx, gty;         // offsets of the global x and y tables
+    int Nz;               // 1 in 2D
+    int gtz;              // offset of the global z table (3D)
 };
 
 }  // namespace lsw

@@ -24,7 +24,10 @@
 #include <string>
 #include <vector>
 
+#include <rocblas/rocblas.h>
+
 #include "launch.h"
+#include "launch3d.h"
 #include "lsw.h"
 
 using namespace lsw;
@@ -52,6 +55,11 @@ struct lsw_plan {
     size_t N = 0;
     double h = 0, omega = 0, C = 0;
     int precision = LSW_FP64, restart = 50, maxit = 500, nrhs_max = 1, sweep_mode = LSW_SWEEP_COMPRESSED;
+    // 3D (beam CDD): nz bulk / pz PML points along z, Nz extended; planes of up to Smax points
+    int dim = 2, nz = 1, pz = 0, Nz = 1, Smax = 0;
+    void* d_rhs3 = nullptr;     // [nrhs][front slot][Nz][Smax] right-hand sides of a front
+    void* d_Y3 = nullptr;       // same layout: y then x
+    rocblas_handle rb = nullptr;
     double tol = 1e-6;
     hipStream_t stream = nullptr;
     // geometry
@@ -164,6 +172,7 @@ void free_plan(lsw_plan* p) {
     if (p->h_coef) (void)hipHostFree(p->h_coef);
     for (hipEvent_t e : p->ev)
         if (e) (void)hipEventDestroy(e);
+    if (p->rb) (void)rocblas_destroy_handle(p->rb);
     delete p;
 }
 
@@ -574,7 +583,10 @@ ChainArgs chain_args(lsw_plan* p, const c128* d_r, c128* d_z) {
     return a;
 }
 
+int apply3d_impl(lsw_plan* p, const c128* d_r, c128* d_z, int nrhs, bool timed);
+
 int apply_impl(lsw_plan* p, const c128* d_r, c128* d_z, int nrhs, bool timed) {
+    if (p->dim == 3) return apply3d_impl(p, d_r, d_z, nrhs, timed);
     const bool c64 = p->precision == LSW_MIXED;
     ChainArgs a = chain_args(p, d_r, d_z);
     GemvArgs ga{};
@@ -623,6 +635,10 @@ int apply_impl(lsw_plan* p, const c128* d_r, c128* d_z, int nrhs, bool timed) {
 }
 
 int matvec_impl(lsw_plan* p, const c128* x, c128* y, const c128* b, int nrhs) {
+    if (p->dim == 3) {
+        HIPCK(p, launch_matvec3(p->geo, x, y, b, nrhs, p->stream));
+        return LSW_OK;
+    }
     MatvecArgs a{p->geo, x, y, b};
     HIPCK(p, launch_matvec(a, nrhs, p->stream));
     return LSW_OK;
@@ -807,11 +823,165 @@ int check_nrhs(lsw_plan* p, int nrhs) {
     return LSW_OK;
 }
 
+// ---------------------------------------------------------------- 3D (beam CDD)
+// Twisted block factorisation along z of every beam: plane blocks S_k (s = W*H unknowns,
+// the xy plane of the window) are inverted in batches, one batch per elimination step of
+// both halves of every subdomain, by blocked Gauss-Jordan: a panel kernel eliminates b
+// columns with row pivoting and the accumulated transformation reaches the other columns as
+// one rank-b update, a batched complex GEMM (rocBLAS).
+int setup3d_factor(lsw_plan* p) {
+    int rc;
+    const int nsub = (int)p->subs.size(), Nz = p->Nz, m = Nz / 2;
+    const int n = p->Smax, b = std::min(32, n);
+    c128* G128 = nullptr;
+    if ((rc = dalloc(p, &G128, p->G_elems)) != LSW_OK) return rc;
+    // batches: step t of half 0 (plane t, from below) and half 1 (plane Nz-1-t, from above), then the middle
+    std::vector<std::vector<Fact3Item>> batches;
+    for (int t = 0; t < std::max(m, Nz - 1 - m); ++t) {
+        std::vector<Fact3Item> bt;
+        for (int sidx = 0; sidx < nsub; ++sidx) {
+            if (t < m) bt.push_back(Fact3Item{sidx, t, t > 0 ? t - 1 : -1, -1});
+            if (t < Nz - 1 - m) bt.push_back(Fact3Item{sidx, Nz - 1 - t, -1, t > 0 ? Nz - t : -1});
+        }
+        batches.push_back(bt);
+    }
+    {
+        std::vector<Fact3Item> bt;
+        for (int sidx = 0; sidx < nsub; ++sidx) bt.push_back(Fact3Item{sidx, m, m >= 1 ? m - 1 : -1, m + 1 <= Nz - 1 ? m + 1 : -1});
+        batches.push_back(bt);
+    }
+    std::vector<Fact3Item> all;
+    std::vector<size_t> boff;
+    size_t maxb = 0;
+    for (auto& bt : batches) {
+        boff.push_back(all.size());
+        all.insert(all.end(), bt.begin(), bt.end());
+        maxb = std::max(maxb, bt.size());
+    }
+    Fact3Item* d_items = nullptr;
+    c128 *ws = nullptr, *Pbar = nullptr, *T = nullptr;
+    int* perm = nullptr;
+    if ((rc = dalloc(p, &d_items, all.size())) != LSW_OK) return rc;
+    if ((rc = dalloc(p, &ws, maxb * n * (size_t)n)) != LSW_OK) return rc;
+    if ((rc = dalloc(p, &Pbar, maxb * n * (size_t)b)) != LSW_OK) return rc;
+    if ((rc = dalloc(p, &T, maxb * n * (size_t)b)) != LSW_OK) return rc;
+    if ((rc = dalloc(p, &perm, maxb * (size_t)n)) != LSW_OK) return rc;
+    HIPCK(p, hipMemcpy(d_items, all.data(), sizeof(Fact3Item) * all.size(), hipMemcpyHostToDevice));
+    if (!p->rb) {
+        if (rocblas_create_handle(&p->rb) != rocblas_status_success) return fail(p, LSW_EHIP, "rocblas_create_handle failed");
+    }
+    if (rocblas_set_stream(p->rb, p->stream) != rocblas_status_success) return fail(p, LSW_EHIP, "rocblas_set_stream failed");
+    Fact3Args fa{};
+    fa.subs = p->d_subs;
+    fa.geo = p->geo;
+    fa.ws = ws;
+    fa.n = n;
+    fa.G = G128;
+    fa.perm = perm;
+    fa.status = p->d_status;
+    const rocblas_double_complex one(1.0, 0.0);
+    HIPCK(p, hipStreamSynchronize(p->stream));
+    const auto tf = std::chrono::steady_clock::now();
+    for (size_t bi = 0; bi < batches.size(); ++bi) {
+        const int nb = (int)batches[bi].size();
+        fa.items = d_items + boff[bi];
+        HIPCK(p, launch_fact3_build(fa, nb, p->stream));
+        for (int p0 = 0; p0 < n; p0 += b) {
+            const int bb = std::min(b, n - p0);
+            HIPCK(p, launch_fact3_panel(fa, nb, p0, bb, p->stream));
+            HIPCK(p, launch_fact3_prep(fa, nb, p0, bb, Pbar, T, p->stream));
+            // other columns += Pbar T : columns [0, p0) and [p0 + bb, n)
+            const int parts[2][2] = {{0, p0}, {p0 + bb, n - p0 - bb}};
+            for (const auto& pt : parts) {
+                if (pt[1] <= 0) continue;
+                const rocblas_status st = rocblas_zgemm_strided_batched(
+                    p->rb, rocblas_operation_none, rocblas_operation_none, n, pt[1], bb, &one,
+                    reinterpret_cast<const rocblas_double_complex*>(Pbar), n, (rocblas_stride)n * bb,
+                    reinterpret_cast<const rocblas_double_complex*>(T + (size_t)pt[0] * bb), bb, (rocblas_stride)n * bb,
+                    &one, reinterpret_cast<rocblas_double_complex*>(ws + (size_t)pt[0] * n), n,
+                    (rocblas_stride)n * n, nb);
+                if (st != rocblas_status_success) return fail(p, LSW_EHIP, "rocblas_zgemm_strided_batched failed");
+            }
+        }
+        HIPCK(p, launch_fact3_finish(fa, nb, p->stream));
+    }
+    HIPCK(p, hipStreamSynchronize(p->stream));
+    p->t_factor_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tf).count();
+    dfree(p, ws);
+    dfree(p, Pbar);
+    dfree(p, T);
+    dfree(p, perm);
+    dfree(p, d_items);
+    std::vector<int> status(nsub);
+    HIPCK(p, hipMemcpy(status.data(), p->d_status, sizeof(int) * nsub, hipMemcpyDeviceToHost));
+    for (int sidx = 0; sidx < nsub; ++sidx)
+        if (status[sidx])
+            return fail(p, LSW_ESINGULAR, "zero pivot in the block factorisation of beam (" +
+                                              std::to_string(p->subs[sidx].i) + "," + std::to_string(p->subs[sidx].j) + ")");
+    if (p->precision == LSW_MIXED) {
+        c64* G64 = nullptr;
+        if ((rc = dalloc(p, &G64, p->G_elems)) != LSW_OK) return rc;
+        HIPCK(p, launch_cast(G128, G64, p->G_elems, p->stream));
+        HIPCK(p, hipStreamSynchronize(p->stream));
+        dfree(p, G128);
+        p->d_G = G64;
+    } else {
+        p->d_G = G128;
+    }
+    const size_t eb = p->precision == LSW_MIXED ? sizeof(c64) : sizeof(c128);
+    const size_t slots = (size_t)p->nrhs_max * p->max_front * Nz * p->Smax;
+    char *r3 = nullptr, *y3 = nullptr;
+    if ((rc = dalloc(p, &r3, slots * eb)) != LSW_OK) return rc;
+    if ((rc = dalloc(p, &y3, slots * eb)) != LSW_OK) return rc;
+    p->d_rhs3 = r3;
+    p->d_Y3 = y3;
+    return LSW_OK;
+}
+
+// One application over a beam CDD: every front (Alg. Scenario3, concurrent sweeps) is a
+// twisted block substitution along z of all its solves, one launch per plane step.
+int apply3d_impl(lsw_plan* p, const c128* d_r, c128* d_z, int nrhs, bool timed) {
+    const bool c64 = p->precision == LSW_MIXED;
+    const int Nz = p->Nz, m = Nz / 2, mh = std::max(m, Nz - 1 - m);
+    Chain3Args a{};
+    a.subs = p->d_subs;
+    a.geo = p->geo;
+    a.G = p->d_G;
+    a.traces = p->d_traces;
+    a.trace_stride = p->trace_stride;
+    a.rhs = p->d_rhs3;
+    a.Y = p->d_Y3;
+    a.slot_stride = (size_t)Nz * p->Smax;
+    a.zpart = p->d_zpart;
+    a.zpart_stride = p->zpart_stride;
+    a.r = d_r;
+    if (timed) HIPCK(p, hipEventRecord(p->ev[0], p->stream));
+    for (size_t fi = 0; fi < p->fronts.size(); ++fi) {
+        const Front& f = p->fronts[fi];
+        a.descs = p->d_descs + f.offset;
+        a.nslots = f.count;
+        HIPCK(p, launch_rhs3(a, p->Smax, nrhs, c64, p->stream));
+        for (int t = 0; t < mh; ++t) HIPCK(p, launch_step3(a, p->Smax, nrhs, 0, t, c64, p->stream));
+        HIPCK(p, launch_step3(a, p->Smax, nrhs, 1, 0, c64, p->stream));
+        for (int t = 0; t < mh; ++t) HIPCK(p, launch_step3(a, p->Smax, nrhs, 2, t, c64, p->stream));
+        HIPCK(p, launch_epi3(a, p->Smax, nrhs, c64, p->stream));
+        if (fi == 0 && timed) HIPCK(p, hipEventRecord(p->ev[1], p->stream));
+    }
+    if (timed) {
+        HIPCK(p, hipEventRecord(p->ev[2], p->stream));
+        HIPCK(p, hipEventRecord(p->ev[3], p->stream));
+    }
+    HIPCK(p, launch_zsum3(p->d_zpart, p->zpart_stride, d_z, (size_t)nrhs * p->N, c64, p->stream));
+    if (timed) HIPCK(p, hipEventRecord(p->ev[4], p->stream));
+    return LSW_OK;
+}
+
 int setup_impl(lsw_plan* p, const double* d_m, double omega, double h, const lsw_grid_t* grid,
                const lsw_cdd_t* cdd, const lsw_pml_t* pml, const lsw_opts_t* opts) {
     const auto t0 = std::chrono::steady_clock::now();
     if (!grid || !cdd || !d_m) return fail(p, LSW_EINVAL, "grid, cdd and m are required");
-    if (grid->dim != 2) return fail(p, LSW_EINVAL, "only dim = 2 is supported");
+    if (grid->dim != 2 && grid->dim != 3) return fail(p, LSW_EINVAL, "dim must be 2 or 3");
+    p->dim = grid->dim;
     if (!(omega > 0) || !(h > 0) || !std::isfinite(omega) || !std::isfinite(h))
         return fail(p, LSW_EINVAL, "omega and h must be positive and finite");
     p->nx = grid->n[0];
@@ -819,6 +989,11 @@ int setup_impl(lsw_plan* p, const double* d_m, double omega, double h, const lsw
     p->px = grid->n_pml[0];
     p->py = grid->n_pml[1];
     if (p->nx < 1 || p->ny < 1 || p->px < 0 || p->py < 0) return fail(p, LSW_EINVAL, "bad grid sizes");
+    if (p->dim == 3) {
+        p->nz = grid->n[2];
+        p->pz = grid->n_pml[2];
+        if (p->nz < 1 || p->pz < 0) return fail(p, LSW_EINVAL, "bad grid sizes");
+    }
     p->q = cdd->q;
     p->r = cdd->r;
     if (p->q < 1 || p->r < 1) return fail(p, LSW_EINVAL, "q and r must be >= 1");
@@ -836,9 +1011,11 @@ int setup_impl(lsw_plan* p, const double* d_m, double omega, double h, const lsw
         p->stream = static_cast<hipStream_t>(opts->stream);
         p->sweep_mode = opts->sweep_mode == LSW_SWEEP_CHAIN ? LSW_SWEEP_CHAIN : LSW_SWEEP_COMPRESSED;
     }
+    if (p->dim == 3) p->sweep_mode = LSW_SWEEP_CHAIN;   // trace planes are too large to compress
     p->Nx = p->nx + 2 * p->px;
     p->Ny = p->ny + 2 * p->py;
-    p->N = (size_t)p->Nx * p->Ny;
+    p->Nz = p->dim == 3 ? p->nz + 2 * p->pz : 1;
+    p->N = (size_t)p->Nx * p->Ny * p->Nz;
     split(p->nx, p->px, p->r, p->xlo, p->xhi);
     split(p->ny, p->py, p->q, p->ylo, p->yhi);
     auto windows = [&](const std::vector<int>& lo, const std::vector<int>& hi, int Nax, std::vector<int>& w0,
@@ -863,6 +1040,11 @@ int setup_impl(lsw_plan* p, const double* d_m, double omega, double h, const lsw
     AxisLayers gy{(p->ny + 1) * h, p->py * h, false, false, 0, 0, 0};
     p->geo.gtx = append_table(pool, 0, p->Nx, p->px, h, omega, p->C, gx);
     p->geo.gty = append_table(pool, 0, p->Ny, p->py, h, omega, p->C, gy);
+    p->geo.Nz = p->Nz;
+    if (p->dim == 3) {
+        AxisLayers gz{(p->nz + 1) * h, p->pz * h, false, false, 0, 0, 0};
+        p->geo.gtz = append_table(pool, 0, p->Nz, p->pz, h, omega, p->C, gz);
+    }
     std::vector<int> txj(p->r), tyi(p->q);
     for (int j = 0; j < p->r; ++j) {
         AxisLayers a = gx;
@@ -894,7 +1076,7 @@ int setup_impl(lsw_plan* p, const double* d_m, double omega, double h, const lsw
             SubDesc s{};
             s.W = p->xw1[j] - p->xw0[j];
             s.H = p->yw1[i] - p->yw0[i];
-            s.mid = s.H / 2;   // the twisted factorisation meets at this block row
+            s.mid = p->dim == 3 ? p->Nz / 2 : s.H / 2;   // the twisted factorisation meets at this block
             s.wx0 = p->xw0[j];
             s.wy0 = p->yw0[i];
             s.r0 = p->ylo[i] - p->yw0[i];
@@ -909,7 +1091,9 @@ int setup_impl(lsw_plan* p, const double* d_m, double omega, double h, const lsw
                       (j > 0 ? 1 << SIDE_L : 0) | (j < p->r - 1 ? 1 << SIDE_R : 0);
             s.L = slot_count(s.W, s.H);
             s.g_off = (long long)p->G_elems;
-            p->G_elems += (size_t)s.H * s.W * s.W;
+            const size_t S3 = (size_t)s.W * s.H;
+            p->G_elems += p->dim == 3 ? (size_t)p->Nz * S3 * S3 : (size_t)s.H * s.W * s.W;
+            p->Smax = std::max(p->Smax, (int)S3);
             s.q_off = (long long)p->Q_elems;
             p->Q_elems += (size_t)s.L * s.L;
             s.fw_off = (long long)p->FWT;
@@ -917,15 +1101,17 @@ int setup_impl(lsw_plan* p, const double* d_m, double omega, double h, const lsw
             p->ept = std::max(p->ept, (s.W + (1024 / s.W) - 1) / (1024 / s.W));
             p->hbase.push_back(p->HT);
             p->vbase.push_back(p->VT);
-            p->HT += 2 * (size_t)s.W;
-            p->VT += 2 * (size_t)s.H;
+            p->HT += 2 * (size_t)s.W * p->Nz;   // trace arrays: [line][z][along the side]
+            p->VT += 2 * (size_t)s.H * p->Nz;
             p->Wmax = std::max(p->Wmax, s.W);
             p->Hmax = std::max(p->Hmax, s.H);
-            p->factor_flops += 8.0 * s.H * (double)s.W * s.W * s.W;
+            p->factor_flops += p->dim == 3 ? 8.0 * p->Nz * (double)S3 * S3 * S3 : 8.0 * s.H * (double)s.W * s.W * s.W;
             p->subs.push_back(s);
         }
     if (p->Wmax > kMaxWindow)
         return fail(p, LSW_EINVAL, "local window wider than " + std::to_string(kMaxWindow) + " points");
+    if (p->dim == 3 && p->Smax > 4096)
+        return fail(p, LSW_EINVAL, "3D local windows are limited to 4096 points per xy plane");
     build_schedule(p);
     if (p->sweep_mode == LSW_SWEEP_COMPRESSED) {
         const int rc0 = compress_schedule(p);
@@ -941,6 +1127,17 @@ int setup_impl(lsw_plan* p, const double* d_m, double omega, double h, const lsw
             for (int n = 0; n < f.icount; ++n) {
                 const GemvItem& it = p->gitems[f.ioffset + n];
                 p->apply_gemv_bytes += (double)it.nin * it.nrow * eb;
+            }
+        } else if (p->dim == 3) {
+            // forward planes of both halves, the middle plane, backward planes: 2 Nz - 1 blocks
+            const int mh = std::max(p->Nz / 2, p->Nz - 1 - p->Nz / 2);
+            p->chain_launches += 2 * mh + 1;
+            for (int n = 0; n < f.count; ++n) {
+                const SubDesc& s = p->subs[p->descs[f.offset + n].sub];
+                const double S3 = (double)s.W * s.H;
+                const double bytes = (2.0 * p->Nz - 1.0) * S3 * S3 * eb;
+                p->apply_chain_bytes += bytes;
+                if (&f == &p->fronts.front()) p->apply_stage1_bytes += bytes;
             }
         } else {
             p->chain_launches += 2;   // forward halves, then middle row and backward halves
@@ -1036,6 +1233,11 @@ int setup_impl(lsw_plan* p, const double* d_m, double omega, double h, const lsw
     p->geo.Ny = p->Ny;
     p->geo.h = h;
     p->geo.omega = omega;
+    if (p->dim == 3) {
+        if ((rc = setup3d_factor(p)) != LSW_OK) return rc;
+        p->t_setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        return LSW_OK;
+    }
     // factorisation, always in FP64 (complex64 factors are rounded copies)
     c128* G128 = nullptr;
     if ((rc = dalloc(p, &G128, p->G_elems)) != LSW_OK) return rc;

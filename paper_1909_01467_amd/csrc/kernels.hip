@@ -943,11 +943,12 @@ __global__ void k_conj(const c128* src, c128* dst, size_t n) {
 }
 
 __global__ void k_mass_gradient(const c128* lam, const c128* u, int nrhs, Geometry g, double* grad) {
-    const size_t N = (size_t)g.Nx * g.Ny;
+    const size_t N = (size_t)g.Nx * g.Ny * g.Nz;
     const size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= N) return;
-    const int x = (int)(p % g.Nx), y = (int)(p / g.Nx);
-    const c128 w = g.tab[g.gtx + x] * g.tab[g.gty + y];   // 1/(alpha_x alpha_y)
+    const int x = (int)(p % g.Nx), y = (int)((p / g.Nx) % g.Ny), z = (int)(p / ((size_t)g.Nx * g.Ny));
+    c128 w = g.tab[g.gtx + x] * g.tab[g.gty + y];   // 1/(alpha_x alpha_y) [ / alpha_z in 3D ]
+    if (g.Nz > 1) w = w * g.tab[g.gtz + z];
     double acc = 0.0;
     for (int s = 0; s < nrhs; ++s) {
         const c128 t = lam[(size_t)s * N + p] * w * u[(size_t)s * N + p];
@@ -1117,7 +1118,7 @@ hipError_t launch_conj(const c128* src, c128* dst, size_t n, hipStream_t st) {
 
 hipError_t launch_mass_gradient(const c128* lam, const c128* u, int nrhs, const Geometry& g, double* grad,
                                 hipStream_t st) {
-    const size_t N = (size_t)g.Nx * g.Ny;
+    const size_t N = (size_t)g.Nx * g.Ny * g.Nz;
     k_mass_gradient<<<blocks_for(N, 256), 256, 0, st>>>(lam, u, nrhs, g, grad);
     return hipGetLastError();
 }

@@ -1,0 +1,547 @@
+// Device kernels of the 3D problem over a beam CDD.
+//
+//  k_f3_build   S_k = D_k - C G C (App. A 7-point operator restricted to one xy plane of a
+//               beam, minus the Schur terms of the planes already eliminated), batched
+//  k_f3_panel   Gauss-Jordan elimination of one column panel of every S_k (row pivoting)
+//  k_f3_prep    operands of the rank-b update of the other columns (a batched complex GEMM)
+//  k_f3_finish  column interchanges and the copy of G_k = S_k^-1 into the factor pool
+//  k_rhs3       right-hand sides of the local solves of a front (stage 1 or eq. DiscPol2)
+//  k_step3      one plane of the twisted block substitution of every solve of a front: each
+//               workgroup computes 64 rows of G_k v (v staged in LDS, G_k streamed)
+//  k_epi3       the solution on Omega_ij and the outgoing trace planes
+//  k_zsum3      z = sum of the per-sweep parts
+//  k_matvec3    y = A x with the 7-point operator (FP64)
+#include "launch3d.h"
+
+namespace lsw {
+namespace {
+
+constexpr uint32_t kOob3 = 0x80000000u;   // per-lane offset that reads nothing (past the range check)
+
+__device__ inline __amdgpu_buffer_rsrc_t rsrc3(const void* base, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, (int)bytes, 0x00020000);
+}
+template <typename T>
+__device__ inline cx<T> bload3(__amdgpu_buffer_rsrc_t r, uint32_t off);
+template <>
+__device__ inline cx<float> bload3<float>(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+    return __builtin_bit_cast(cx<float>, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+template <>
+__device__ inline cx<double> bload3<double>(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+    return __builtin_bit_cast(cx<double>, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+}
+
+// ------------------------------------------------------------------ 7-point coefficients
+// Tables (common.h layout): tab[t + a] = 1/alpha at integer point a, tab[t + P + a] = alpha at
+// the half point a - 1/2.  Symmetric form of App. A in 3D: s_x = alpha_x/(alpha_y alpha_z) at
+// x half points (and cyclically), mass term omega^2 m/(alpha_x alpha_y alpha_z).
+struct Box3 {
+    int tx, Px, ty, Py, tz, Pz;
+};
+__device__ inline c128 c3x(const c128* tab, const Box3& b, int x, int y, int z, double ih2) {
+    return -ih2 * (tab[b.tx + b.Px + x + 1] * tab[b.ty + y] * tab[b.tz + z]);   // (x,y,z)-(x+1,y,z)
+}
+__device__ inline c128 c3y(const c128* tab, const Box3& b, int x, int y, int z, double ih2) {
+    return -ih2 * (tab[b.ty + b.Py + y + 1] * tab[b.tx + x] * tab[b.tz + z]);   // (x,y,z)-(x,y+1,z)
+}
+__device__ inline c128 c3z(const c128* tab, const Box3& b, int x, int y, int z, double ih2) {
+    return -ih2 * (tab[b.tz + b.Pz + z + 1] * tab[b.tx + x] * tab[b.ty + y]);   // (x,y,z)-(x,y,z+1)
+}
+__device__ inline c128 d3(const c128* tab, const Box3& b, int x, int y, int z, double ih2, double om2m) {
+    const c128 ix = tab[b.tx + x], iy = tab[b.ty + y], iz = tab[b.tz + z];
+    const c128 sx = tab[b.tx + b.Px + x + 1] + tab[b.tx + b.Px + x];
+    const c128 sy = tab[b.ty + b.Py + y + 1] + tab[b.ty + b.Py + y];
+    const c128 sz = tab[b.tz + b.Pz + z + 1] + tab[b.tz + b.Pz + z];
+    return ih2 * (sx * iy * iz + sy * ix * iz + sz * ix * iy) - om2m * (ix * iy * iz);
+}
+__device__ inline Box3 window_box(const SubDesc& s, const Geometry& g) {
+    return Box3{s.tx, s.W, s.ty, s.H, g.gtz, g.Nz};
+}
+
+// ------------------------------------------------------------------ factorisation
+__global__ void k_f3_build(Fact3Args a) {
+    const Fact3Item it = a.items[blockIdx.y];
+    const SubDesc s = a.subs[it.sub];
+    const int n = a.n, W = s.W, S = s.W * s.H;
+    const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (size_t)n * n) return;
+    const int p = (int)(idx % n), q = (int)(idx / n);
+    c128* A = a.ws + (size_t)blockIdx.y * n * n;
+    if (p >= S || q >= S) {
+        A[idx] = mk(p == q ? 1.0 : 0.0, 0.0);
+        return;
+    }
+    const Geometry& g = a.geo;
+    const Box3 b = window_box(s, g);
+    const double ih2 = 1.0 / (g.h * g.h);
+    const int k = it.k;
+    const int yp = p / W, xp = p - yp * W, yq = q / W, xq = q - yq * W;
+    c128 v = mk(0.0, 0.0);
+    if (p == q) {
+        const double m = g.m[((size_t)k * g.Ny + s.wy0 + yp) * g.Nx + s.wx0 + xp];
+        v = d3(g.tab, b, xp, yp, k, ih2, g.omega * g.omega * m);
+    } else if (yp == yq && (xp - xq == 1 || xq - xp == 1)) {
+        v = c3x(g.tab, b, min(xp, xq), yp, k, ih2);
+    } else if (xp == xq && (yp - yq == 1 || yq - yp == 1)) {
+        v = c3y(g.tab, b, xp, min(yp, yq), k, ih2);
+    }
+    const size_t SS = (size_t)S * S;
+    if (it.below >= 0) {   // coupling of planes k-1 and k
+        const c128 cp = c3z(g.tab, b, xp, yp, k - 1, ih2), cq = c3z(g.tab, b, xq, yq, k - 1, ih2);
+        v = v - cp * a.G[s.g_off + (size_t)it.below * SS + (size_t)q * S + p] * cq;
+    }
+    if (it.above >= 0) {   // coupling of planes k and k+1
+        const c128 cp = c3z(g.tab, b, xp, yp, k, ih2), cq = c3z(g.tab, b, xq, yq, k, ih2);
+        v = v - cp * a.G[s.g_off + (size_t)it.above * SS + (size_t)q * S + p] * cq;
+    }
+    A[idx] = v;
+}
+
+// Gauss-Jordan on columns [p0, p0 + b) of every matrix: for each column j, choose the pivot in
+// rows >= j, swap full rows, scale the pivot row, eliminate the column from every other row.
+// Only the panel columns are updated here; the other columns receive the accumulated
+// transformation as a rank-b update.  One workgroup per matrix.
+__global__ __launch_bounds__(1024) void k_f3_panel(Fact3Args a, int p0, int b) {
+    constexpr int NT = 1024;
+    extern __shared__ __align__(16) unsigned char smem[];
+    c128* colj = reinterpret_cast<c128*>(smem);   // [n]
+    __shared__ c128 rowj[64];
+    __shared__ double wbest[NT / 64];
+    __shared__ int wbi[NT / 64];
+    __shared__ int sh_piv, sh_sing;
+    const int n = a.n, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    c128* A = a.ws + (size_t)blockIdx.x * n * n;
+    int* perm = a.perm + (size_t)blockIdx.x * n;
+    if (tid == 0) sh_sing = 0;
+    for (int jj = 0; jj < b; ++jj) {
+        const int j = p0 + jj;
+        double best = -1.0;
+        int bi = j;
+        for (int i = j + tid; i < n; i += NT) {
+            const double v = abs2(A[i + (size_t)j * n]);
+            if (v > best) {
+                best = v;
+                bi = i;
+            }
+        }
+        for (int off = 32; off > 0; off >>= 1) {
+            const double ob = __shfl_xor(best, off);
+            const int oi = __shfl_xor(bi, off);
+            if (ob > best || (ob == best && oi < bi)) {
+                best = ob;
+                bi = oi;
+            }
+        }
+        if (lane == 0) {
+            wbest[wv] = best;
+            wbi[wv] = bi;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            double bb = wbest[0];
+            int ii = wbi[0];
+            for (int w = 1; w < NT / 64; ++w)
+                if (wbest[w] > bb || (wbest[w] == bb && wbi[w] < ii)) {
+                    bb = wbest[w];
+                    ii = wbi[w];
+                }
+            sh_piv = ii;
+            perm[j] = ii;
+            if (!(bb > 0.0)) sh_sing = 1;
+        }
+        __syncthreads();
+        const int r = sh_piv;
+        if (r != j)
+            for (int c = tid; c < n; c += NT) {
+                const c128 t = A[j + (size_t)c * n];
+                A[j + (size_t)c * n] = A[r + (size_t)c * n];
+                A[r + (size_t)c * n] = t;
+            }
+        __syncthreads();
+        const c128 piv = A[j + (size_t)j * n];
+        const c128 inv = abs2(piv) > 0.0 ? cinv(piv) : mk(0.0, 0.0);
+        for (int i = tid; i < n; i += NT) colj[i] = A[i + (size_t)j * n];
+        if (tid < b) {
+            const int c = p0 + tid;
+            const c128 v = (c == j) ? inv : A[j + (size_t)c * n] * inv;
+            rowj[tid] = v;
+            A[j + (size_t)c * n] = v;
+        }
+        __syncthreads();
+        for (int i = tid; i < n; i += NT) {
+            if (i == j) continue;
+            const c128 f = colj[i];
+            for (int cc = 0; cc < b; ++cc) {
+                const int c = p0 + cc;
+                c128* e = A + i + (size_t)c * n;
+                *e = (c == j) ? -(f * inv) : *e - f * rowj[cc];
+            }
+        }
+        __syncthreads();
+    }
+    if (tid == 0 && sh_sing) a.status[a.items[blockIdx.x].sub] = 1;
+}
+
+__global__ void k_f3_prep(Fact3Args a, int p0, int b, c128* Pbar, c128* T) {
+    const int n = a.n;
+    const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (size_t)n * b) return;
+    const c128* A = a.ws + (size_t)blockIdx.y * n * n;
+    c128* P = Pbar + (size_t)blockIdx.y * n * b;
+    c128* Tb = T + (size_t)blockIdx.y * n * b;
+    {   // Pbar[i, cc] = A[i, p0 + cc] - (i == p0 + cc)
+        const int i = (int)(idx % n), cc = (int)(idx / n);
+        c128 v = A[i + (size_t)(p0 + cc) * n];
+        if (i == p0 + cc) v.re -= 1.0;
+        P[idx] = v;
+    }
+    {   // T[cc, c] = A[p0 + cc, c]
+        const int cc = (int)(idx % b), c = (int)(idx / b);
+        Tb[idx] = A[p0 + cc + (size_t)c * n];
+    }
+}
+
+__global__ __launch_bounds__(1024) void k_f3_finish(Fact3Args a) {
+    const Fact3Item it = a.items[blockIdx.x];
+    const SubDesc s = a.subs[it.sub];
+    const int n = a.n, S = s.W * s.H, tid = threadIdx.x;
+    c128* A = a.ws + (size_t)blockIdx.x * n * n;
+    const int* perm = a.perm + (size_t)blockIdx.x * n;
+    for (int j = n - 1; j >= 0; --j) {
+        const int r = perm[j];
+        if (r != j)
+            for (int i = tid; i < n; i += blockDim.x) {
+                const c128 t = A[i + (size_t)j * n];
+                A[i + (size_t)j * n] = A[i + (size_t)r * n];
+                A[i + (size_t)r * n] = t;
+            }
+        __syncthreads();
+    }
+    c128* G = a.G + s.g_off + (size_t)it.k * S * S;
+    for (size_t idx = tid; idx < (size_t)S * S; idx += blockDim.x) {
+        const int p = (int)(idx % S), q = (int)(idx / S);
+        G[idx] = A[p + (size_t)q * n];
+    }
+}
+
+// ------------------------------------------------------------------ sweeps
+template <typename T>
+__device__ inline bool chi3(int kind, const SubDesc& s, int y, int x) {
+    switch (kind) {
+        case KIND_B: return y >= s.r0;
+        case KIND_T: return y < s.r1;
+        case KIND_L: return x >= s.c0;
+        case KIND_R: return x < s.c1;
+        case KIND_BL: return y >= s.r0 && x >= s.c0;
+        case KIND_TR: return y < s.r1 && x < s.c1;
+        case KIND_BR: return y >= s.r0 && x < s.c1;
+        case KIND_TL: return y < s.r1 && x >= s.c0;
+        default: return false;
+    }
+}
+
+// incoming trace value at (x, y) of plane z: trace arrays are [line][z][along the side];
+// L legs are restricted to the receiving quadrant and the horizontal leg is used on the point
+// both legs share
+template <typename T>
+__device__ inline cx<T> utilde3(int kind, const SubDesc& s, int Nz, const cx<T>* in_h, const cx<T>* in_v, int y,
+                                int x, int z) {
+    const bool corner = kind >= KIND_BL;
+    const bool hB = (kind == KIND_B || kind == KIND_BL || kind == KIND_BR);
+    const bool hT = (kind == KIND_T || kind == KIND_TR || kind == KIND_TL);
+    const bool vL = (kind == KIND_L || kind == KIND_BL || kind == KIND_TL);
+    const bool vR = (kind == KIND_R || kind == KIND_TR || kind == KIND_BR);
+    if (hB || hT) {
+        const int l0 = hB ? s.r0 - 1 : s.r1 - 1;
+        const bool in_cols = !corner || (vL ? x >= s.c0 : x < s.c1);
+        if ((y == l0 || y == l0 + 1) && in_cols) return in_h[((size_t)(y - l0) * Nz + z) * s.W + x];
+    }
+    if (vL || vR) {
+        const int l0 = vL ? s.c0 - 1 : s.c1 - 1;
+        const bool in_rows = !corner || (hB ? y >= s.r0 : y < s.r1);
+        if ((x == l0 || x == l0 + 1) && in_rows) return in_v[((size_t)(x - l0) * Nz + z) * s.H + y];
+    }
+    return cx<T>{T(0), T(0)};
+}
+
+// eq. DiscPol2 at (x, y, z): sum over the in-plane neighbours q across the boundary of chi of
+// A_pq (chi_q - chi_p) u~_q (the z neighbours share chi)
+template <typename T>
+__device__ inline c128 polar3(int kind, const SubDesc& s, const Geometry& g, const Box3& b, const cx<T>* in_h,
+                              const cx<T>* in_v, int y, int x, int z) {
+    const bool cp = chi3<T>(kind, s, y, x);
+    const double ih2 = 1.0 / (g.h * g.h);
+    c128 acc = mk(0.0, 0.0);
+    auto add = [&](c128 A, cx<T> u) {
+        const c128 t = A * cvt<double>(u);
+        acc = cp ? acc - t : acc + t;
+    };
+    if (x > 0 && chi3<T>(kind, s, y, x - 1) != cp)
+        add(c3x(g.tab, b, x - 1, y, z, ih2), utilde3<T>(kind, s, g.Nz, in_h, in_v, y, x - 1, z));
+    if (x + 1 < s.W && chi3<T>(kind, s, y, x + 1) != cp)
+        add(c3x(g.tab, b, x, y, z, ih2), utilde3<T>(kind, s, g.Nz, in_h, in_v, y, x + 1, z));
+    if (y > 0 && chi3<T>(kind, s, y - 1, x) != cp)
+        add(c3y(g.tab, b, x, y - 1, z, ih2), utilde3<T>(kind, s, g.Nz, in_h, in_v, y - 1, x, z));
+    if (y + 1 < s.H && chi3<T>(kind, s, y + 1, x) != cp)
+        add(c3y(g.tab, b, x, y, z, ih2), utilde3<T>(kind, s, g.Nz, in_h, in_v, y + 1, x, z));
+    return acc;
+}
+
+template <typename T>
+__global__ void k_rhs3(Chain3Args a, int smax) {
+    const SolveDesc& d = a.descs[blockIdx.y];
+    const SubDesc s = a.subs[d.sub];
+    const Geometry& g = a.geo;
+    const int rhs = blockIdx.z, S = s.W * s.H;
+    const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (size_t)g.Nz * smax) return;
+    const int z = (int)(idx / smax), p = (int)(idx % smax);
+    cx<T>* out = reinterpret_cast<cx<T>*>(a.rhs) + ((size_t)rhs * a.nslots + blockIdx.y) * a.slot_stride;
+    c128 v = mk(0.0, 0.0);
+    if (p < S) {
+        const int y = p / s.W, x = p - y * s.W;
+        if (d.kind == KIND_STAGE1) {
+            if (y >= s.r0 && y < s.r1 && x >= s.c0 && x < s.c1) {
+                const size_t N = (size_t)g.Nx * g.Ny * g.Nz;
+                v = a.r[(size_t)rhs * N + ((size_t)z * g.Ny + s.wy0 + y) * g.Nx + s.wx0 + x];
+            }
+        } else {
+            const cx<T>* tr = reinterpret_cast<const cx<T>*>(a.traces) + (size_t)rhs * a.trace_stride;
+            v = polar3<T>(d.kind, s, g, window_box(s, g), d.in_h >= 0 ? tr + d.in_h : nullptr,
+                          d.in_v >= 0 ? tr + d.in_v : nullptr, y, x, z);
+        }
+    }
+    out[idx] = cvt<T>(v);
+}
+
+// One plane of the twisted substitution (planes k < m eliminated from below, k > m from
+// above, m last), for every (solve, half) of a front: workgroup (chunk, 2*slot + half) forms
+// v in LDS and computes rows [64*chunk, 64*chunk + 64) of G_k v, one row per lane, the 16
+// waves splitting the columns of the column-major block.
+//   phase 0, half 0: y_k = G_k (g_k - C_{k-1} y_{k-1}), k = t
+//   phase 0, half 1: y_k = G_k (g_k - C_k y_{k+1}),     k = Nz-1-t
+//   phase 1:         x_m = G_m (g_m - C_{m-1} y_{m-1} - C_m y_{m+1})
+//   phase 2, half 0: x_k = y_k - G_k C_k x_{k+1},       k = m-1-t
+//   phase 2, half 1: x_k = y_k - G_k C_{k-1} x_{k-1},   k = m+1+t
+template <typename T>
+__global__ __launch_bounds__(1024) void k_step3(Chain3Args a, int smax, int phase, int t) {
+    constexpr int NT = 1024, NW = NT / 64, KB = sizeof(T) == 4 ? 16 : 8;
+    extern __shared__ __align__(16) unsigned char smem[];
+    cx<T>* v = reinterpret_cast<cx<T>*>(smem);   // [S]
+    __shared__ cx<T> part[NW][64];
+    const int slot = blockIdx.y >> 1, half = blockIdx.y & 1, rhs = blockIdx.z;
+    const SolveDesc& d = a.descs[slot];
+    const SubDesc s = a.subs[d.sub];
+    const Geometry& g = a.geo;
+    const int S = s.W * s.H, Nz = g.Nz, m = s.mid;
+    const int row0 = blockIdx.x * 64;
+    if (row0 >= S) return;
+    int k, prev = -1, prev2 = -1, cpl = 0, cpl2 = 0;
+    if (phase == 0) {
+        if (half == 0) {
+            if (t >= m) return;
+            k = t;
+            if (t > 0) { prev = k - 1; cpl = k - 1; }
+        } else {
+            if (t >= Nz - 1 - m) return;
+            k = Nz - 1 - t;
+            if (t > 0) { prev = k + 1; cpl = k; }
+        }
+    } else if (phase == 1) {
+        if (half == 1) return;
+        k = m;
+        if (m >= 1) { prev = m - 1; cpl = m - 1; }
+        if (m + 1 <= Nz - 1) { prev2 = m + 1; cpl2 = m; }
+    } else {
+        if (half == 0) {
+            if (t >= m) return;
+            k = m - 1 - t;
+            prev = k + 1;
+            cpl = k;
+        } else {
+            if (t >= Nz - 1 - m) return;
+            k = m + 1 + t;
+            prev = k - 1;
+            cpl = k - 1;
+        }
+    }
+    const Box3 b = window_box(s, g);
+    const double ih2 = 1.0 / (g.h * g.h);
+    const cx<T>* R = reinterpret_cast<const cx<T>*>(a.rhs) + ((size_t)rhs * a.nslots + slot) * a.slot_stride;
+    cx<T>* Y = reinterpret_cast<cx<T>*>(a.Y) + ((size_t)rhs * a.nslots + slot) * a.slot_stride;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    for (int c = tid; c < S; c += NT) {
+        const int y = c / s.W, x = c - y * s.W;
+        cx<T> val{T(0), T(0)};
+        if (phase == 2) {
+            val = cvt<T>(c3z(g.tab, b, x, y, cpl, ih2)) * Y[(size_t)prev * smax + c];
+        } else {
+            val = R[(size_t)k * smax + c];
+            if (prev >= 0) val = val - cvt<T>(c3z(g.tab, b, x, y, cpl, ih2)) * Y[(size_t)prev * smax + c];
+            if (prev2 >= 0) val = val - cvt<T>(c3z(g.tab, b, x, y, cpl2, ih2)) * Y[(size_t)prev2 * smax + c];
+        }
+        v[c] = val;
+    }
+    __syncthreads();
+    const cx<T>* Gk = reinterpret_cast<const cx<T>*>(a.G) + s.g_off + (size_t)k * S * S;
+    const __amdgpu_buffer_rsrc_t gr = rsrc3(Gk, (uint32_t)((size_t)S * S * sizeof(cx<T>)));
+    const int row = row0 + lane;
+    const bool valid = row < S;
+    const int per = (S + NW - 1) / NW;
+    const int c0 = wv * per, c1 = min(S, c0 + per);
+    cx<T> acc{T(0), T(0)};
+    for (int base = c0; base < c1; base += KB) {
+        cx<T> q[KB];
+#pragma unroll
+        for (int u = 0; u < KB; ++u) {
+            const int c = base + u;
+            q[u] = bload3<T>(gr, (valid && c < c1) ? (uint32_t)((size_t)c * S + row) * (uint32_t)sizeof(cx<T>) : kOob3);
+        }
+#pragma unroll
+        for (int u = 0; u < KB; ++u)
+            if (base + u < c1) acc = acc + q[u] * v[base + u];
+    }
+    part[wv][lane] = acc;
+    __syncthreads();
+    if (wv == 0 && valid) {
+        cx<T> y = part[0][lane];
+#pragma unroll
+        for (int w = 1; w < NW; ++w) y = y + part[w][lane];
+        cx<T>* out = Y + (size_t)k * smax + row;
+        *out = (phase == 2) ? *out - y : y;
+    }
+}
+
+template <typename T>
+__global__ void k_epi3(Chain3Args a, int smax) {
+    const SolveDesc& d = a.descs[blockIdx.y];
+    const SubDesc s = a.subs[d.sub];
+    const Geometry& g = a.geo;
+    const int rhs = blockIdx.z, S = s.W * s.H, Nz = g.Nz;
+    const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (size_t)Nz * smax) return;
+    const int z = (int)(idx / smax), p = (int)(idx % smax);
+    if (p >= S) return;
+    const int y = p / s.W, x = p - y * s.W;
+    const cx<T> val = reinterpret_cast<const cx<T>*>(a.Y)[((size_t)rhs * a.nslots + blockIdx.y) * a.slot_stride + idx];
+    if (d.zpart >= 0 && y >= s.r0 && y < s.r1 && x >= s.c0 && x < s.c1) {
+        cx<T>* zp = reinterpret_cast<cx<T>*>(a.zpart) + (size_t)d.zpart * a.zpart_stride;
+        const size_t N = (size_t)g.Nx * g.Ny * Nz;
+        zp[(size_t)rhs * N + ((size_t)z * g.Ny + s.wy0 + y) * g.Nx + s.wx0 + x] = val;
+    }
+    cx<T>* tr = reinterpret_cast<cx<T>*>(a.traces) + (size_t)rhs * a.trace_stride;
+    for (int o = 0; o < d.nout; ++o) {
+        const int side = d.out_side[o];
+        long long e = -1;
+        if (side == SIDE_B || side == SIDE_T) {
+            const int l0 = side == SIDE_B ? s.r0 - 1 : s.r1 - 1;
+            if (y == l0 || y == l0 + 1) e = ((long long)(y - l0) * Nz + z) * s.W + x;
+        } else {
+            const int l0 = side == SIDE_L ? s.c0 - 1 : s.c1 - 1;
+            if (x == l0 || x == l0 + 1) e = ((long long)(x - l0) * Nz + z) * s.H + y;
+        }
+        if (e < 0) continue;
+        cx<T>* out = tr + d.out_off[o] + e;
+        *out = d.out_acc[o] ? *out + val : val;
+    }
+}
+
+template <typename T>
+__global__ void k_zsum3(const cx<T>* zpart, size_t stride, c128* z, size_t n) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    c128 acc = mk(0.0, 0.0);
+    for (int k = 0; k < 9; ++k) acc = acc + cvt<double>(zpart[(size_t)k * stride + i]);
+    z[i] = acc;
+}
+
+__global__ void k_matvec3(Geometry g, const c128* X, c128* Y, const c128* B) {
+    const size_t N = (size_t)g.Nx * g.Ny * g.Nz;
+    const size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= N) return;
+    const int rhs = blockIdx.y;
+    const int x = (int)(p % g.Nx), y = (int)((p / g.Nx) % g.Ny), z = (int)(p / ((size_t)g.Nx * g.Ny));
+    const double ih2 = 1.0 / (g.h * g.h);
+    const Box3 b{g.gtx, g.Nx, g.gty, g.Ny, g.gtz, g.Nz};
+    const c128* Xr = X + (size_t)rhs * N;
+    const size_t sy = g.Nx, sz = (size_t)g.Nx * g.Ny;
+    c128 acc = d3(g.tab, b, x, y, z, ih2, g.omega * g.omega * g.m[p]) * Xr[p];
+    if (x > 0) acc = acc + c3x(g.tab, b, x - 1, y, z, ih2) * Xr[p - 1];
+    if (x + 1 < g.Nx) acc = acc + c3x(g.tab, b, x, y, z, ih2) * Xr[p + 1];
+    if (y > 0) acc = acc + c3y(g.tab, b, x, y - 1, z, ih2) * Xr[p - sy];
+    if (y + 1 < g.Ny) acc = acc + c3y(g.tab, b, x, y, z, ih2) * Xr[p + sy];
+    if (z > 0) acc = acc + c3z(g.tab, b, x, y, z - 1, ih2) * Xr[p - sz];
+    if (z + 1 < g.Nz) acc = acc + c3z(g.tab, b, x, y, z, ih2) * Xr[p + sz];
+    Y[(size_t)rhs * N + p] = B ? B[(size_t)rhs * N + p] - acc : acc;
+}
+
+inline unsigned nblk(size_t n, unsigned b) { return (unsigned)((n + b - 1) / b); }
+
+}  // namespace
+
+hipError_t launch_fact3_build(const Fact3Args& a, int nbatch, hipStream_t st) {
+    k_f3_build<<<dim3(nblk((size_t)a.n * a.n, 256), nbatch), 256, 0, st>>>(a);
+    return hipGetLastError();
+}
+
+hipError_t launch_fact3_panel(const Fact3Args& a, int nbatch, int p0, int b, hipStream_t st) {
+    const size_t lds = sizeof(c128) * (size_t)a.n;
+    hipError_t e = hipFuncSetAttribute((const void*)k_f3_panel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    k_f3_panel<<<nbatch, 1024, lds, st>>>(a, p0, b);
+    return hipGetLastError();
+}
+
+hipError_t launch_fact3_prep(const Fact3Args& a, int nbatch, int p0, int b, c128* Pbar, c128* T, hipStream_t st) {
+    k_f3_prep<<<dim3(nblk((size_t)a.n * b, 256), nbatch), 256, 0, st>>>(a, p0, b, Pbar, T);
+    return hipGetLastError();
+}
+
+hipError_t launch_fact3_finish(const Fact3Args& a, int nbatch, hipStream_t st) {
+    k_f3_finish<<<nbatch, 1024, 0, st>>>(a);
+    return hipGetLastError();
+}
+
+hipError_t launch_rhs3(const Chain3Args& a, int smax, int nrhs, bool f32, hipStream_t st) {
+    dim3 grid(nblk((size_t)a.geo.Nz * smax, 256), a.nslots, nrhs);
+    if (f32) k_rhs3<float><<<grid, 256, 0, st>>>(a, smax);
+    else k_rhs3<double><<<grid, 256, 0, st>>>(a, smax);
+    return hipGetLastError();
+}
+
+hipError_t launch_step3(const Chain3Args& a, int smax, int nrhs, int phase, int t, bool f32, hipStream_t st) {
+    dim3 grid(nblk((size_t)smax, 64), 2 * a.nslots, nrhs);
+    const size_t lds = (f32 ? sizeof(c64) : sizeof(c128)) * (size_t)smax;
+    if (f32) {
+        hipError_t e = hipFuncSetAttribute((const void*)k_step3<float>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        k_step3<float><<<grid, 1024, lds, st>>>(a, smax, phase, t);
+    } else {
+        hipError_t e = hipFuncSetAttribute((const void*)k_step3<double>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        k_step3<double><<<grid, 1024, lds, st>>>(a, smax, phase, t);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_epi3(const Chain3Args& a, int smax, int nrhs, bool f32, hipStream_t st) {
+    dim3 grid(nblk((size_t)a.geo.Nz * smax, 256), a.nslots, nrhs);
+    if (f32) k_epi3<float><<<grid, 256, 0, st>>>(a, smax);
+    else k_epi3<double><<<grid, 256, 0, st>>>(a, smax);
+    return hipGetLastError();
+}
+
+hipError_t launch_zsum3(const void* zpart, size_t stride, c128* z, size_t n, bool f32, hipStream_t st) {
+    if (f32) k_zsum3<float><<<nblk(n, 256), 256, 0, st>>>(reinterpret_cast<const c64*>(zpart), stride, z, n);
+    else k_zsum3<double><<<nblk(n, 256), 256, 0, st>>>(reinterpret_cast<const c128*>(zpart), stride, z, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_matvec3(const Geometry& g, const c128* x, c128* y, const c128* b, int nrhs, hipStream_t st) {
+    const size_t N = (size_t)g.Nx * g.Ny * g.Nz;
+    k_matvec3<<<dim3(nblk(N, 256), nrhs), 256, 0, st>>>(g, x, y, b);
+    return hipGetLastError();
+}
+
+}  // namespace lsw

@@ -1,0 +1,69 @@
+// Argument blocks and launch wrappers of the 3D (beam CDD) device kernels (kernels3d.hip).
+//
+// A 3D local problem is a beam: the window W x H of its CDD cell times all Nz extended z
+// points.  Its unknowns are ordered plane by plane (z slowest, then y, then x), so the matrix
+// is block tridiagonal along z with dense-inverse blocks of size s = W*H (one xy plane) and
+// diagonal couplings between neighbouring planes.
+#pragma once
+
+#include "common.h"
+
+namespace lsw {
+
+// One matrix of a batched plane-block factorisation step.
+struct Fact3Item {
+    int sub;        // subdomain
+    int k;          // plane being factorised
+    int below;      // plane whose inverse enters the Schur complement from below (-1: none)
+    int above;      // ... from above (-1: none)
+};
+
+struct Fact3Args {
+    const Fact3Item* items;
+    const SubDesc* subs;
+    Geometry geo;
+    c128* ws;           // [batch][n][n] column-major matrices being inverted (n = padded size)
+    int n;              // padded matrix size (largest s)
+    c128* G;            // factor pool (complex128, column-major s x s blocks)
+    int* perm;          // [batch][n] pivot rows
+    int* status;        // per subdomain: 1 if a zero pivot was met
+};
+
+struct Chain3Args {
+    const SolveDesc* descs;   // the solves of one front
+    const SubDesc* subs;
+    Geometry geo;
+    const void* G;            // factor pool (complex64 or complex128)
+    void* traces;
+    size_t trace_stride;
+    void* rhs;                // [nrhs][front slot][Nz][s_max] right-hand sides of the front's solves
+    void* Y;                  // same layout: y, then x (in place)
+    size_t slot_stride;       // Nz * s_max
+    int nslots;               // solves in the front
+    void* zpart;              // [9][nrhs][N] per-sweep parts of z
+    size_t zpart_stride;      // nrhs * N
+    const c128* r;            // input vectors [nrhs][N]
+};
+
+// S = D_k - C G_below C - C G_above C into ws (identity padding), for every item
+hipError_t launch_fact3_build(const Fact3Args& a, int nbatch, hipStream_t st);
+// unblocked Gauss-Jordan on columns [p0, p0 + b) of every matrix (full-row pivoting swaps)
+hipError_t launch_fact3_panel(const Fact3Args& a, int nbatch, int p0, int b, hipStream_t st);
+// Pbar = panel with its diagonal block minus I (n x b), T = rows [p0, p0 + b) of all columns (b x n)
+hipError_t launch_fact3_prep(const Fact3Args& a, int nbatch, int p0, int b, c128* Pbar, c128* T, hipStream_t st);
+// undo the row interchanges as column interchanges, then copy the s x s inverse into the pool
+hipError_t launch_fact3_finish(const Fact3Args& a, int nbatch, hipStream_t st);
+
+// right-hand sides of a front's solves (stage 1: r on Omega; sweeps: polarized sources)
+hipError_t launch_rhs3(const Chain3Args& a, int smax, int nrhs, bool f32, hipStream_t st);
+// one step of the twisted block substitution of every solve of a front:
+// phase 0 forward (step t of each half), 1 middle plane, 2 backward (step t of each half)
+hipError_t launch_step3(const Chain3Args& a, int smax, int nrhs, int phase, int t, bool f32, hipStream_t st);
+// solution on Omega into the sweep's part of z, outgoing traces into the trace pool
+hipError_t launch_epi3(const Chain3Args& a, int smax, int nrhs, bool f32, hipStream_t st);
+// z = sum of the 9 per-sweep parts (n = nrhs * N entries, parts `stride` apart)
+hipError_t launch_zsum3(const void* zpart, size_t stride, c128* z, size_t n, bool f32, hipStream_t st);
+// y = A x (or b - A x) with the 7-point operator
+hipError_t launch_matvec3(const Geometry& g, const c128* x, c128* y, const c128* b, int nrhs, hipStream_t st);
+
+}  // namespace lsw

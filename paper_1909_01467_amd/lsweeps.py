@@ -115,12 +115,16 @@ class LswError(RuntimeError):
 
 def extend_medium(m_bulk: torch.Tensor, n_pml) -> torch.Tensor:
     """Normal (constant) extension of the squared slowness into the PML (Sec. 1.1), as a
-    differentiable gather: every PML point copies its nearest bulk point."""
-    ny, nx = m_bulk.shape
-    px, py = (n_pml, n_pml) if isinstance(n_pml, int) else n_pml
-    iy = torch.clamp(torch.arange(ny + 2 * py, device=m_bulk.device) - py, 0, ny - 1)
-    ix = torch.clamp(torch.arange(nx + 2 * px, device=m_bulk.device) - px, 0, nx - 1)
-    return m_bulk[iy][:, ix]
+    differentiable gather: every PML point copies its nearest bulk point.  m_bulk is [y, x]
+    or [z, y, x]; n_pml is one width or one per physical axis (x, y[, z])."""
+    d = m_bulk.dim()
+    ps = (n_pml,) * d if isinstance(n_pml, int) else tuple(n_pml)
+    out = m_bulk
+    for axis in range(d):                      # array axis; physical axis d - 1 - axis
+        n, p = m_bulk.shape[axis], ps[d - 1 - axis]
+        idx = torch.clamp(torch.arange(n + 2 * p, device=m_bulk.device) - p, 0, n - 1)
+        out = torch.index_select(out, axis, idx)
+    return out
 
 
 def _dptr(t: torch.Tensor) -> int:
@@ -143,19 +147,24 @@ class Solver:
         lib = load_library()
         if not torch.cuda.is_available():
             raise RuntimeError("the L-sweeps library needs a GPU")
-        nx, ny = (n, n) if isinstance(n, int) else n
-        px, py = (n_pml, n_pml) if isinstance(n_pml, int) else n_pml
+        dim = m_ext.dim()
+        if dim not in (2, 3):
+            raise ValueError("m must be a 2D [y, x] or 3D [z, y, x] array on the extended grid")
+        ns = (n,) * dim if isinstance(n, int) else tuple(n)
+        ps = (n_pml,) * dim if isinstance(n_pml, int) else tuple(n_pml)
         r = q if r is None else r
         m_ext = m_ext.to(device="cuda", dtype=torch.float64).contiguous()
-        if tuple(m_ext.shape) != (ny + 2 * py, nx + 2 * px):
-            raise ValueError(f"m must be on the extended grid {(ny + 2 * py, nx + 2 * px)}, got {tuple(m_ext.shape)}")
+        expect = tuple(ns[k] + 2 * ps[k] for k in reversed(range(dim)))
+        if tuple(m_ext.shape) != expect:
+            raise ValueError(f"m must be on the extended grid {expect}, got {tuple(m_ext.shape)}")
+        self.dim = dim
         self.shape = tuple(m_ext.shape)
         self.N = m_ext.numel()
-        self.omega, self.h, self.n, self.n_pml, self.q, self.r = omega, h, (nx, ny), (px, py), q, r
+        self.omega, self.h, self.n, self.n_pml, self.q, self.r = omega, h, ns, ps, q, r
         self.nrhs_max = nrhs_max
         self.C = 4.0 * math.log(omega) if C is None else C
         self.precision = precision
-        grid = lsw_grid_t(2, (ctypes.c_int * 3)(nx, ny, 0), (ctypes.c_int * 3)(px, py, 0))
+        grid = lsw_grid_t(dim, (ctypes.c_int * 3)(*ns, *([0] * (3 - dim))), (ctypes.c_int * 3)(*ps, *([0] * (3 - dim))))
         cdd = lsw_cdd_t(q, r)
         pml = lsw_pml_t(self.C, -1 if n_pml_local is None else n_pml_local)
         self.stream = torch.cuda.current_stream()
@@ -180,7 +189,7 @@ class Solver:
         raise LswError(rc, self._lib.lsw_last_error(self._h).decode())
 
     def _vec(self, x: torch.Tensor) -> tuple[torch.Tensor, int, bool]:
-        single = x.dim() == 1 or (x.dim() == 2 and tuple(x.shape) == self.shape)
+        single = x.dim() == 1 or tuple(x.shape) == self.shape
         x = x.to(device="cuda", dtype=torch.complex128).resolve_conj().resolve_neg()
         x = x.reshape(-1 if single else x.shape[0], self.N).contiguous()
         if single:

@@ -77,12 +77,22 @@ def test_argument_errors_need_no_gpu():
 def test_setup_rejects_bad_geometry_before_touching_memory():
     lib = lsweeps.load_library()
     h = ctypes.c_void_p()
-    grid = lsweeps.lsw_grid_t(3, (ctypes.c_int * 3)(8, 8, 8), (ctypes.c_int * 3)(2, 2, 2))
+    grid = lsweeps.lsw_grid_t(4, (ctypes.c_int * 3)(8, 8, 8), (ctypes.c_int * 3)(2, 2, 2))
     cdd = lsweeps.lsw_cdd_t(2, 2)
     rc = lib.lsw_setup(ctypes.byref(h), ctypes.c_void_p(1), 10.0, 0.1, ctypes.byref(grid), ctypes.byref(cdd),
                        None, None)
     assert rc == lsweeps.LSW_EINVAL and h.value is None
     assert b"dim" in lib.lsw_last_error(None)
+    grid = lsweeps.lsw_grid_t(3, (ctypes.c_int * 3)(20, 20, 20), (ctypes.c_int * 3)(5, 5, 5))
+    cdd = lsweeps.lsw_cdd_t(16, 16)   # 3D beams: groups of a single point
+    rc = lib.lsw_setup(ctypes.byref(h), ctypes.c_void_p(1), 10.0, 0.1, ctypes.byref(grid), ctypes.byref(cdd),
+                       None, None)
+    assert rc == lsweeps.LSW_EINVAL and b"window" in lib.lsw_last_error(None)
+    grid = lsweeps.lsw_grid_t(3, (ctypes.c_int * 3)(200, 200, 20), (ctypes.c_int * 3)(5, 5, 5))
+    cdd = lsweeps.lsw_cdd_t(2, 2)     # 3D beams: xy planes of more than 4096 points
+    rc = lib.lsw_setup(ctypes.byref(h), ctypes.c_void_p(1), 10.0, 0.1, ctypes.byref(grid), ctypes.byref(cdd),
+                       None, None)
+    assert rc == lsweeps.LSW_EINVAL and b"4096" in lib.lsw_last_error(None)
     grid = lsweeps.lsw_grid_t(2, (ctypes.c_int * 3)(20, 20, 0), (ctypes.c_int * 3)(5, 5, 0))
     cdd = lsweeps.lsw_cdd_t(16, 16)   # groups of a single point
     rc = lib.lsw_setup(ctypes.byref(h), ctypes.c_void_p(1), 10.0, 0.1, ctypes.byref(grid), ctypes.byref(cdd),

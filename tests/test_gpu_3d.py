@@ -1,0 +1,170 @@
+"""The 3D problem over a beam CDD through the C ABI.
+
+* y = A x with the 7-point operator against the oracle's assembled operator (1e-13);
+* one application against the oracle's Alg. Scenario3 over beams (FP64 1e-10, complex64 2e-4)
+  on cubes and ragged boxes with odd and even numbers of z planes; a single beam is the exact
+  inverse (1e-10 against the sparse direct solve);
+* solves against the sparse direct solve at tol 1e-8 (FP64 1e-6, mixed 1e-4);
+* the 95^3 lens workload (4x4 beams, 8-point PML, 8 points per wavelength, mixed precision) at
+  full size: the banded oracle does not fit, so the residual is recomputed in FP64 on the host
+  from the oracle's assembled 7-point operator.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from oracle.direct import SparseLU
+from oracle.discretization import GlobalProblem, extend_normal
+from oracle.lsweep3d import LSweep3D
+from paper_1909_01467_amd import inputs
+from paper_1909_01467_amd.lsweeps import Solver
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print("[case]", *a, file=sys.stderr, flush=True)
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a).ravel() - np.asarray(b).ravel()) / np.linalg.norm(np.asarray(b).ravel()))
+
+
+def medium3d(n, seed):
+    nx, ny, nz = n
+    rng = np.random.default_rng(seed)
+    h = 1.0 / (nx + 1)
+    z, y, x = np.meshgrid(np.arange(1, nz + 1) * h, np.arange(1, ny + 1) * h, np.arange(1, nx + 1) * h, indexing="ij")
+    a, b, c = rng.uniform(1, 3, 3)
+    return 1.0 + 0.3 * np.sin(a * x + b * y) * np.cos(c * z)
+
+
+class Case3:
+    def __init__(self, name, n, p, q, r, seed=41, ppw=8.0):
+        self.name, self.n, self.p, self.q, self.r = name, n, p, q, r
+        self.m = extend_normal(medium3d(n, seed), p)
+        self.h = 1.0 / (n[0] + 1)
+        self.omega = 2 * math.pi * n[0] / ppw
+        self.C = 4 * math.log(self.omega)
+        self._oracle = self._gp = None
+
+    @property
+    def oracle(self):
+        if self._oracle is None:
+            self._oracle = LSweep3D(self.m, self.omega, self.n, self.p, self.q, self.r, self.C, h=self.h)
+        return self._oracle
+
+    @property
+    def gp(self):
+        if self._gp is None:
+            self._gp = GlobalProblem(self.m, self.omega, self.n, self.p, self.C, h=self.h)
+        return self._gp
+
+    def solver(self, **kw):
+        say(self.name, kw)
+        return Solver(torch.from_numpy(self.m).cuda(), self.omega, self.h, self.n, self.p, self.q, self.r,
+                      C=self.C, **kw)
+
+
+CASES = {
+    "cube_2x2": Case3("cube_2x2", (11, 11, 11), (4, 4, 4), 2, 2),
+    "ragged_3x2": Case3("ragged_3x2", (13, 12, 9), (4, 4, 3), 3, 2),
+    "even_z_2x3": Case3("even_z_2x3", (15, 12, 10), (4, 4, 3), 2, 3),
+}
+
+
+def test_matvec3_matches_oracle():
+    c = CASES["ragged_3x2"]
+    x = inputs.complex_normal(c.m.size, 51)
+    s = c.solver()
+    y = s.matvec(torch.from_numpy(x).cuda()).cpu().numpy().ravel()
+    s.close()
+    assert rel(y, c.gp.A @ x) < 1e-13
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_apply3_fp64_matches_oracle(name):
+    c = CASES[name]
+    r = inputs.complex_normal(c.m.size, 52)
+    zo = c.oracle.apply(r)
+    s = c.solver()
+    z = s.apply(torch.from_numpy(r).cuda()).cpu().numpy().ravel()
+    st = s.stats()
+    s.close()
+    err = rel(z, zo)
+    say(name, "apply fp64 err", err, "factor ms", round(st["t_factor_ms"], 1))
+    assert err < 1e-10
+
+
+@pytest.mark.parametrize("name", ["cube_2x2", "even_z_2x3"])
+def test_apply3_mixed_matches_oracle(name):
+    c = CASES[name]
+    r = inputs.complex_normal(c.m.size, 53)
+    zo = c.oracle.apply(r)
+    s = c.solver(precision="mixed")
+    z = s.apply(torch.from_numpy(r).cuda()).cpu().numpy().ravel()
+    s.close()
+    err = rel(z, zo)
+    say(name, "apply mixed err", err)
+    assert err < 2e-4
+
+
+def test_apply3_single_beam_is_the_exact_inverse():
+    c = Case3("single", (10, 9, 8), (4, 4, 4), 1, 1)
+    r = inputs.complex_normal(c.m.size, 54)
+    u = SparseLU(c.gp.A).solve(r)
+    s = c.solver()
+    z = s.apply(torch.from_numpy(r).cuda()).cpu().numpy().ravel()
+    s.close()
+    assert rel(z, u) < 1e-10
+
+
+def test_apply3_batches_rhs_and_is_deterministic():
+    c = CASES["ragged_3x2"]
+    R = torch.from_numpy(np.stack([inputs.complex_normal(c.m.size, 60 + k) for k in range(3)])).cuda()
+    s = c.solver(nrhs_max=3)
+    Z = s.apply(R)
+    for k in range(3):
+        assert torch.equal(Z[k], s.apply(R[k:k + 1])[0])
+    assert torch.equal(Z, s.apply(R))
+    s.close()
+
+
+@pytest.mark.parametrize("precision,tol_err", [("fp64", 1e-6), ("mixed", 1e-4)])
+def test_solve3_matches_direct_solve(precision, tol_err):
+    c = CASES["cube_2x2"]
+    f = inputs.gaussian_source(c.n[0], (0.3, 0.6, 0.45))
+    b = c.gp.rhs(f)
+    u_ref = SparseLU(c.gp.A).solve(b)
+    s = c.solver(precision=precision, tol=1e-8)
+    u, info = s.solve(torch.from_numpy(b).cuda())
+    s.close()
+    un = u.cpu().numpy().ravel()
+    say("solve3", precision, info)
+    assert info["converged"] == [True]
+    assert np.linalg.norm(b - c.gp.A @ un) / np.linalg.norm(b) <= 1e-8
+    assert rel(un, u_ref) < tol_err
+
+
+def test_lens3d_full_size_solve():
+    wl = inputs.workload("lens3d")
+    m = extend_normal(wl.slowness2, wl.n_pml)
+    say("lens3d", wl.n, wl.q, "omega", round(wl.omega, 2))
+    s = Solver(torch.from_numpy(m).cuda(), wl.omega, wl.h, wl.n, wl.n_pml, wl.q, wl.r, C=wl.C,
+               precision="mixed", tol=1e-6)
+    st = s.stats()
+    say("lens3d setup ms", round(st["t_setup_ms"]), "factor ms", round(st["t_factor_ms"]), "S_max",
+        st["W_max"] * st["H_max"], "G GB", st["factor_elems"] * st["factor_elem_bytes"] / 1e9)
+    gp = GlobalProblem(m, wl.omega, wl.n, wl.n_pml, wl.C)
+    b = gp.rhs(wl.sources[0])
+    u, info = s.solve(torch.from_numpy(b).cuda())
+    s.apply(torch.from_numpy(b).cuda())
+    st = s.stats()
+    s.close()
+    say("lens3d solve", info, "apply ms", st["last_apply_ms"], "GB/apply", st["apply_chain_bytes"] / 1e9)
+    assert info["converged"] == [True]
+    un = u.cpu().numpy().ravel()
+    assert np.linalg.norm(b - gp.A @ un) / np.linalg.norm(b) <= 1.05e-6
