@@ -13,12 +13,14 @@
  * alpha = 1/(1 + i sigma/omega); symmetric 5-point form
  *   -div(Lambda grad u) - omega^2 m/(alpha_1 alpha_2) u = b,  Lambda = diag(s1, s2),
  *   s1 = alpha_1/alpha_2, s2 = alpha_2/alpha_1, coefficients at half points,
- * homogeneous Dirichlet data one point beyond the extended grid.  A is complex
- * symmetric (A = A^T), which the adjoint solve uses.
+ * homogeneous Dirichlet data one point beyond the extended grid; in 3D the 7-point form
+ * with s_k = alpha_k / (product of the other two alphas) and mass term
+ * omega^2 m/(alpha_1 alpha_2 alpha_3).  A is complex symmetric (A = A^T), which the adjoint
+ * solve uses.
  *
  * Conventions shared by every entry point:
- *  - Vectors live on the extended grid of N = N_x * N_y points (N_k = n_k + 2 n_pml_k),
- *    x fastest.  Complex values are interleaved (re, im) doubles, the layout of
+ *  - Vectors live on the extended grid of N = N_x * N_y (* N_z) points (N_k = n_k + 2 n_pml_k),
+ *    x fastest, then y, then z.  Complex values are interleaved (re, im) doubles, the layout of
  *    torch.complex128.  Several right-hand sides are stored one after the other:
  *    element (rhs, p) is at rhs * N + p.
  *  - Pointers named d_* are DEVICE pointers owned by the caller; they must stay valid
@@ -55,12 +57,12 @@ typedef enum {
 } lsw_precision;
 
 typedef enum {
-    LSW_SWEEP_COMPRESSED = 0,  /* sweeps as trace-to-trace products with Q = A_ij^-1 on the trace lines */
-    LSW_SWEEP_CHAIN = 1        /* every sweep solve as a full block forward/back substitution */
+    LSW_SWEEP_COMPRESSED = 0,  /* sweeps as trace-to-trace products with Q = A_ij^-1 on the trace lines (2D) */
+    LSW_SWEEP_CHAIN = 1        /* every sweep solve as a full block forward/back substitution (always in 3D) */
 } lsw_sweep_mode;
 
 typedef struct {
-    int dim;             /* 2 (the only dimension built so far) */
+    int dim;             /* 2, or 3: the CDD in (x, y) with beams over all z (7-point operator) */
     int n[3];            /* bulk points per axis (x, y, z) */
     int n_pml[3];        /* global PML points per side, per axis */
 } lsw_grid_t;
@@ -116,7 +118,7 @@ typedef struct {
     double t_setup_ms, t_factor_ms, t_q_ms;
     double last_apply_ms;        /* device time of the most recent lsw_apply (events) */
     double last_chain_ms;        /* ... spent in its block-substitution launches */
-    double last_gemv_ms;         /* ... spent in its trace-compressed launches */
+    double last_gemv_ms;         /* ... spent in its trace-compressed launches (3D: in the fronts after stage 1) */
     double apply_stage1_bytes;   /* part of apply_chain_bytes read by the stage-1 substitutions */
     double apply_final_bytes;    /* part of apply_chain_bytes read by the final z substitutions */
     double last_stage1_ms;       /* device time of the stage-1 substitutions (2 launches) */
@@ -136,8 +138,10 @@ typedef struct {
  * Builds the CDD (bulk points split as evenly as possible, the first n mod q groups
  * one larger, edge groups owning the global PML), the local problems (Omega_ij plus
  * 2 overlap lines and n_pml_local PML lines on every interior side, Sec. 2.2) and
- * factorises every local matrix by block-tridiagonal LU along y.
- * Errors: LSW_EINVAL (dim != 2, sizes, a window that does not fit the grid),
+ * factorises every local matrix by block-tridiagonal LU along y (2D: blocks are grid lines)
+ * or along z (3D: every subdomain is a beam over all z, blocks are its xy planes of at most
+ * 4096 points, and the global z PML is kept at both beam ends).
+ * Errors: LSW_EINVAL (dim not 2 or 3, sizes, a window that does not fit the grid),
  * LSW_ENAN (non-finite m), LSW_ENOMEM, LSW_EHIP, LSW_ESINGULAR.  On error *out is NULL
  * and nothing is leaked.
  */
@@ -171,14 +175,14 @@ int lsw_solve(lsw_handle_t handle, const double* d_f, double* d_u, int nrhs, lsw
 int lsw_adjoint(lsw_handle_t handle, const double* d_g, double* d_v, int nrhs, lsw_info_t* info);
 
 /*
- * lsw_matvec -- y = A x in FP64 (the global 5-point operator of App. A).
+ * lsw_matvec -- y = A x in FP64 (the global 5-point / 7-point operator of App. A).
  *   d_x, d_y : DEVICE, nrhs*N complex128; may not alias.
  */
 int lsw_matvec(lsw_handle_t handle, const double* d_x, double* d_y, int nrhs);
 
 /*
  * lsw_mass_gradient -- FWI gradient term  d_grad[p] += omega^2 Re( sum_s lam_s[p] w[p] u_s[p] ),
- * w = 1/(alpha_1 alpha_2) (the weight of m in the mass term of App. A), summed over nrhs
+ * w = 1/(alpha_1 alpha_2 [alpha_3]) (the weight of m in the mass term of App. A), summed over nrhs
  * right-hand sides.  d_lam, d_u : DEVICE nrhs*N complex128; d_grad : DEVICE N doubles (accumulated).
  */
 int lsw_mass_gradient(lsw_handle_t handle, const double* d_lam, const double* d_u, int nrhs,

@@ -1457,7 +1457,13 @@ int lsw_apply(lsw_handle_t p, const double* d_r, double* d_z, int nrhs) {
     HIPCK(p, hipEventElapsedTime(&t34, p->ev[3], p->ev[4]));
     HIPCK(p, hipEventElapsedTime(&t04, p->ev[0], p->ev[4]));
     p->last_apply_ms = t04;
-    if (p->sweep_mode == LSW_SWEEP_CHAIN) {
+    if (p->dim == 3) {   // [0,1] stage-1 front, [1,2] the other fronts, [3,4] the sum of the sweep parts
+        p->last_stage1_ms = t01;
+        p->last_gemv_ms = t12;
+        p->last_final_rhs_ms = 0;
+        p->last_final_ms = t34;
+        p->last_chain_ms = t01 + t12;
+    } else if (p->sweep_mode == LSW_SWEEP_CHAIN) {
         p->last_chain_ms = t01;
         p->last_gemv_ms = 0;
         p->last_stage1_ms = p->last_final_ms = p->last_final_rhs_ms = 0;
