@@ -124,6 +124,10 @@ typedef struct {
     double last_stage1_ms;       /* device time of the stage-1 substitutions (2 launches) */
     double last_final_ms;        /* device time of the final z substitutions (2 launches) */
     double last_final_rhs_ms;    /* device time of the final right-hand-side assembly */
+    int rhs_per_workgroup;       /* right-hand sides per workgroup of the stage-1 / final substitutions
+                                    (1, 2 or 4), chosen at setup by timing when nrhs_max > 1, or
+                                    fixed by the environment variable LSW_RHS_PER_WORKGROUP */
+    double tune_ms[3];           /* the timings of 1, 2 and 4 right-hand sides per workgroup (0: not tried) */
 } lsw_stats_t;
 
 /*

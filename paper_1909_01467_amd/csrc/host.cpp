@@ -17,6 +17,7 @@
 #include <chrono>
 #include <cmath>
 #include <complex>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <new>
@@ -85,6 +86,8 @@ struct lsw_plan {
     size_t QP_elems = 0;          // Q' pool (what the sweeps read)
     int max_nin = 0;
     int sweep_depth = 0;            // dependency levels of the sweep work items (one launch each)
+    int rgroup = 1;                 // right-hand sides per workgroup of the stage-1 / final substitutions
+    double rgroup_ms[3] = {0, 0, 0};   // timings of R = 1, 2, 4 when tuned
     int* d_frp = nullptr;           // final right-hand side: polarization terms per window point
     long long* d_fpool = nullptr;
     c128* d_fcoef = nullptr;
@@ -625,7 +628,10 @@ int apply_impl(lsw_plan* p, const c128* d_r, c128* d_z, int nrhs, bool timed) {
             } else {
                 if (fi == nf - 1 && timed) HIPCK(p, hipEventRecord(p->ev[3], p->stream));
                 a.descs = p->d_descs + f.offset;
-                HIPCK(p, launch_chain(a, f.count, nrhs, p->ept, c64, fi == 0 ? 0 : 1, p->ylds, p->stream));
+                if (p->rgroup > 1 && nrhs > 1)
+                    HIPCK(p, launch_chain_mr(a, f.count, nrhs, p->ept, c64, fi == 0 ? 0 : 1, p->rgroup, p->stream));
+                else
+                    HIPCK(p, launch_chain(a, f.count, nrhs, p->ept, c64, fi == 0 ? 0 : 1, p->ylds, p->stream));
             }
             if (fi == 0 && timed) HIPCK(p, hipEventRecord(p->ev[1], p->stream));
         }
@@ -973,6 +979,58 @@ int apply3d_impl(lsw_plan* p, const c128* d_r, c128* d_z, int nrhs, bool timed) 
     }
     HIPCK(p, launch_zsum3(p->d_zpart, p->zpart_stride, d_z, (size_t)nrhs * p->N, c64, p->stream));
     if (timed) HIPCK(p, hipEventRecord(p->ev[4], p->stream));
+    return LSW_OK;
+}
+
+// Autotuning of the batched substitutions: with several right-hand sides, the stage-1 and
+// final fronts can carry R = 1, 2 or 4 of them per workgroup (every factor block read once per
+// group).  Larger R reads less but holds more registers and LDS per step; each candidate is
+// timed on the real factors (zero inputs, the stage-1 and final fronts, nrhs_max right-hand
+// sides) and the fastest is kept.
+int tune_rgroup(lsw_plan* p) {
+    p->rgroup = 1;
+    if (p->dim != 2 || p->sweep_mode != LSW_SWEEP_COMPRESSED || p->nrhs_max < 2) return LSW_OK;
+    // LSW_RHS_PER_WORKGROUP = 1, 2 or 4 fixes the choice (no timing)
+    if (const char* env = std::getenv("LSW_RHS_PER_WORKGROUP")) {
+        const int R = std::atoi(env);
+        if (R == 1 || R == 2 || R == 4) {
+            p->rgroup = R;
+            return LSW_OK;
+        }
+    }
+    const bool c64 = p->precision == LSW_MIXED;
+    const int nrhs = p->nrhs_max;
+    HIPCK(p, hipMemsetAsync(p->d_tmp1, 0, sizeof(c128) * (size_t)nrhs * p->N, p->stream));
+    HIPCK(p, hipMemsetAsync(p->d_fw, 0, sizeof(c128) * (size_t)nrhs * p->FWT, p->stream));
+    ChainArgs a = chain_args(p, p->d_tmp1, p->d_tmp2);
+    const Front& f0 = p->fronts.front();
+    const Front& f1 = p->fronts.back();
+    double best = 1e30;
+    const int cands[3] = {1, 2, 4};
+    for (int ci = 0; ci < 3; ++ci) {
+        const int R = cands[ci];
+        if (R > nrhs) break;
+        double tmin = 1e30;
+        for (int rep = 0; rep < 3; ++rep) {
+            HIPCK(p, hipEventRecord(p->ev[0], p->stream));
+            for (const Front* f : {&f0, &f1}) {
+                a.descs = p->d_descs + f->offset;
+                const int cs = f == &f0 ? 0 : 1;
+                if (R > 1) HIPCK(p, launch_chain_mr(a, f->count, nrhs, p->ept, c64, cs, R, p->stream));
+                else HIPCK(p, launch_chain(a, f->count, nrhs, p->ept, c64, cs, p->ylds, p->stream));
+            }
+            HIPCK(p, hipEventRecord(p->ev[1], p->stream));
+            HIPCK(p, hipEventSynchronize(p->ev[1]));
+            float ms = 0;
+            HIPCK(p, hipEventElapsedTime(&ms, p->ev[0], p->ev[1]));
+            if (rep > 0) tmin = std::min(tmin, (double)ms);   // the first run warms up
+        }
+        p->rgroup_ms[ci] = tmin;
+        if (tmin < best) {
+            best = tmin;
+            p->rgroup = R;
+        }
+    }
     return LSW_OK;
 }
 
@@ -1409,6 +1467,7 @@ int setup_impl(lsw_plan* p, const double* d_m, double omega, double h, const lsw
     } else {
         p->d_G = G128;
     }
+    if ((rc = tune_rgroup(p)) != LSW_OK) return rc;
     p->t_setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     return LSW_OK;
 }
@@ -1555,6 +1614,8 @@ int lsw_query(lsw_handle_t p, lsw_stats_t* st) {
     st->last_stage1_ms = p->last_stage1_ms;
     st->last_final_ms = p->last_final_ms;
     st->last_final_rhs_ms = p->last_final_rhs_ms;
+    st->rhs_per_workgroup = p->rgroup;
+    for (int i = 0; i < 3; ++i) st->tune_ms[i] = p->rgroup_ms[i];
     return LSW_OK;
 }
 

@@ -590,6 +590,272 @@ __global__ __launch_bounds__(1024) void k_chain(ChainArgs a) {
     }
 }
 
+// The same twisted block substitution for R right-hand sides per workgroup (stage 1 and the
+// final z solves): every G_k element is loaded once and applied to the R vectors of the
+// group, so a batch of sources reads the factors nrhs/R times instead of nrhs times.  y and
+// x live in global memory (phase 0 writes y at [0, H W) of each right-hand side's slab,
+// phase 1 writes x at [H W, 2 H W)).
+template <typename T, int EPT, int PD, int CS, int R>
+__global__ __launch_bounds__(1024) void k_chain_mr(ChainArgs a) {
+    static_assert(CS == CS_STAGE1 || CS == CS_FINAL, "stage 1 and final solves only");
+    constexpr int NT = 1024;
+    const int sidx = blockIdx.x >> 1, h = blockIdx.x & 1, nsol = gridDim.x >> 1;
+    const SolveDesc& dref = a.descs[sidx];
+    const int sub = dref.sub;
+    const int kf0 = dref.kf0, kf1 = dref.kf1, kb0 = dref.kb0, kb1 = dref.kb1;
+    const SubDesc s = a.subs[sub];
+    const int rhs0 = blockIdx.y * R;
+    const int nr = min(R, a.nrhs - rhs0);   // right-hand sides of this group (the rest only reads zeros)
+    const int W = s.W, H = s.H, m = s.mid, tid = threadIdx.x;
+    const int NG = NT / W, NA = NG * W;
+    const bool act = tid < NA;
+    const bool mine = tid < W;
+    const int tc = mine ? tid : W - 1;
+    const int cg = act ? tid / W : 0;
+    const int ept = (W + NG - 1) / NG;
+    const int WW = W * W;
+    __shared__ cx<T> v[R][kMaxWindow];
+    __shared__ cx<T> part[R][NT];
+    __shared__ c128 a2h[kMaxWindow + 1];
+
+    const c128* tab = a.geo.tab;
+    const double ih2 = 1.0 / (a.geo.h * a.geo.h);
+    for (int k = tid; k <= H; k += NT) a2h[k] = tab[s.ty + H + k];
+    const c128 ia_c = tab[s.tx + tc];
+    const cx<T>* Gs = reinterpret_cast<const cx<T>*>(a.G) + s.g_off;
+    const size_t N = (size_t)a.geo.Nx * a.geo.Ny;
+    auto zero = []() { return cx<T>{T(0), T(0)}; };
+    auto cy = [&](int l) { return cvt<T>(-ih2 * (a2h[l + 1] * ia_c)); };
+    constexpr bool from_r = CS == CS_STAGE1;
+    // per right-hand side: its sources, its y/x slab (empty ranges for a short last group)
+    __amdgpu_buffer_rsrc_t rsrc[R], yrsrc[R];
+    cx<T>* Yg[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int rhs = rhs0 + r;
+        const bool ok = rhs < a.nrhs;
+        const int rr = ok ? rhs : rhs0;
+        const c128* rptr = from_r ? a.r + (size_t)rr * N : a.fw + (size_t)rr * a.fw_stride + s.fw_off;
+        rsrc[r] = make_rsrc(rptr, ok ? (uint32_t)((from_r ? N : (size_t)H * W) * sizeof(c128)) : 0u);
+        Yg[r] = reinterpret_cast<cx<T>*>(a.Y) + ((size_t)rr * nsol + sidx) * a.Y_stride;
+        yrsrc[r] = make_rsrc(Yg[r], ok ? (uint32_t)((size_t)H * W * sizeof(cx<T>)) : 0u);
+    }
+    const uint32_t rbase = (uint32_t)((from_r ? (size_t)s.wy0 * a.geo.Nx + s.wx0 + tc : (size_t)tc) * sizeof(c128));
+    const uint32_t rstep = (uint32_t)((from_r ? (size_t)a.geo.Nx : (size_t)W) * sizeof(c128));
+    const __amdgpu_buffer_rsrc_t grsrc = make_rsrc(Gs, (uint32_t)((size_t)H * WW * sizeof(cx<T>)));
+    const bool in_cols = mine && tid >= s.c0 && tid < s.c1;
+    auto rhs_use = [&](int k, cx<T> raw) -> cx<T> {
+        if (k < kf0 || k > kf1) return zero();
+        if constexpr (CS == CS_FINAL) return mine ? raw : zero();
+        return (in_cols && k >= s.r0 && k < s.r1) ? raw : zero();
+    };
+    auto rhs_load = [&](int r, int k) -> cx<T> { return cvt<T>(bload<double>(rsrc[r], rbase + (uint32_t)k * rstep)); };
+    auto yload = [&](int r, int k) -> cx<T> {
+        return bload<T>(yrsrc[r], (uint32_t)(k * W + tc) * (uint32_t)sizeof(cx<T>));
+    };
+    auto load = [&](int k, cx<T>* buf) {
+        const uint32_t kb = (uint32_t)k * (uint32_t)WW * (uint32_t)sizeof(cx<T>);
+#pragma unroll
+        for (int j = 0; j < EPT; ++j)
+            buf[j] = bload<T>(grsrc, kb + (uint32_t)(tid + NA * j) * (uint32_t)sizeof(cx<T>));
+    };
+    // part[r][tid] = sum_j G_k[c_j][t] v[r][c_j]
+    auto gemv = [&](const cx<T>* buf) {
+        cx<T> acc[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) acc[r] = zero();
+#pragma unroll
+        for (int j = 0; j < EPT; ++j) {
+            const int c = cg + NG * j;
+            const bool ok = act && j < ept && c < W;
+            const int cc = ok ? c : 0;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const cx<T> t = buf[j] * v[r][cc];
+                if (ok) acc[r] = acc[r] + t;
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) part[r][tid] = acc[r];
+    };
+    auto reduce = [&](int r, int t) {
+        cx<T> y = part[r][t];
+        for (int g = 1; g < NG; ++g) y = y + part[r][g * W + t];
+        return y;
+    };
+
+    cx<T> ring[PD + 1][EPT];
+    cx<T> rr[PD + 1][R];
+    cx<T> yv[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) yv[r] = zero();
+    __syncthreads();
+
+    if (a.phase == 0) {
+        const int kstart = h == 0 ? kf0 : kf1;
+        const int dir = h == 0 ? 1 : -1;
+        const int n = h == 0 ? m - kf0 : kf1 - m;
+        auto kat = [&](int i) { return kstart + dir * min(i, n - 1); };
+#pragma unroll
+        for (int p = 0; p < PD; ++p)
+            if (n > 0) {
+#pragma unroll
+                for (int r = 0; r < R; ++r) rr[p][r] = rhs_load(r, kat(p));
+                load(kat(p), ring[p]);
+            }
+        for (int i0 = 0; i0 < n; i0 += PD + 1) {
+#pragma unroll
+            for (int u = 0; u <= PD; ++u) {
+                const int i = i0 + u;
+                if (i < n) {
+                    const int k = kstart + dir * i;
+#pragma unroll
+                    for (int r = 0; r < R; ++r) rr[(u + PD) % (PD + 1)][r] = rhs_load(r, kat(i + PD));
+                    load(kat(i + PD), ring[(u + PD) % (PD + 1)]);
+                    if (mine) {
+                        const cx<T> c = cy(h == 0 ? k - 1 : k);
+#pragma unroll
+                        for (int r = 0; r < R; ++r) {
+                            cx<T> g = rhs_use(k, rr[u][r]);
+                            if (i > 0) g = g - c * yv[r];
+                            v[r][tid] = g;
+                        }
+                    }
+                    __syncthreads();
+                    gemv(ring[u]);
+                    __syncthreads();
+                    if (mine) {
+#pragma unroll
+                        for (int r = 0; r < R; ++r) {
+                            yv[r] = reduce(r, tid);
+                            if (r < nr) Yg[r][(size_t)k * W + tid] = yv[r];
+                        }
+                    }
+                }
+            }
+        }
+        return;
+    }
+
+    // ---- phase 1: middle row, then back substitution of this half away from it
+    {
+        cx<T> gm[EPT];
+        load(m, gm);
+        cx<T> rm[R], ylo[R], yhi[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            rm[r] = rhs_load(r, m);
+            ylo[r] = (kf0 <= m - 1) ? yload(r, m - 1) : zero();
+            yhi[r] = (kf1 >= m + 1) ? yload(r, m + 1) : zero();
+        }
+        if (mine) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                cx<T> g = rhs_use(m, rm[r]);
+                if (m >= 1) g = g - cy(m - 1) * ylo[r];
+                if (m + 1 <= H - 1) g = g - cy(m) * yhi[r];
+                v[r][tid] = g;
+            }
+        }
+        __syncthreads();
+        gemv(gm);
+        __syncthreads();
+        if (mine) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                yv[r] = reduce(r, tid);
+                if (r < nr) Yg[r][(size_t)H * W + (size_t)m * W + tid] = yv[r];
+            }
+        }
+    }
+    {
+        const int kstart = h == 0 ? m - 1 : m + 1;
+        const int dir = h == 0 ? -1 : 1;
+        const int n = h == 0 ? m - kb0 : kb1 - m;
+        auto kat = [&](int i) { return kstart + dir * min(i, n - 1); };
+#pragma unroll
+        for (int p = 0; p < PD; ++p)
+            if (n > 0) {
+#pragma unroll
+                for (int r = 0; r < R; ++r) rr[p][r] = yload(r, kat(p));
+                load(kat(p), ring[p]);
+            }
+        for (int i0 = 0; i0 < n; i0 += PD + 1) {
+#pragma unroll
+            for (int u = 0; u <= PD; ++u) {
+                const int i = i0 + u;
+                if (i < n) {
+                    const int k = kstart + dir * i;
+#pragma unroll
+                    for (int r = 0; r < R; ++r) rr[(u + PD) % (PD + 1)][r] = yload(r, kat(i + PD));
+                    load(kat(i + PD), ring[(u + PD) % (PD + 1)]);
+                    if (mine) {
+                        const cx<T> c = cy(h == 0 ? k : k - 1);
+#pragma unroll
+                        for (int r = 0; r < R; ++r) v[r][tid] = c * yv[r];
+                    }
+                    __syncthreads();
+                    gemv(ring[u]);
+                    __syncthreads();
+                    if (mine) {
+                        const bool has_y = h == 0 ? k >= kf0 : k <= kf1;
+#pragma unroll
+                        for (int r = 0; r < R; ++r) {
+                            const cx<T> y = has_y ? rr[u][r] : zero();
+                            yv[r] = y - reduce(r, tid);
+                            if (r < nr) Yg[r][(size_t)H * W + (size_t)k * W + tid] = yv[r];
+                        }
+                    }
+                }
+            }
+        }
+    }
+    __syncthreads();
+
+    // ---- outputs of the block rows this half owns
+    const int olo = h == 0 ? kb0 : max(kb0, m + 1);
+    const int ohi = h == 0 ? min(kb1, m) : kb1;
+    for (int r = 0; r < R; ++r) {
+        const int rhs = rhs0 + r;
+        if (rhs >= a.nrhs) break;
+        const cx<T>* X = Yg[r] + (size_t)H * W;
+        if constexpr (CS == CS_FINAL) {
+            const int r0 = max(s.r0, olo), r1 = min(s.r1, ohi + 1);
+            const int nc = s.c1 - s.c0, n = max(0, r1 - r0) * nc;
+            c128* z = a.z + (size_t)rhs * N + (size_t)(s.wy0 + r0) * a.geo.Nx + s.wx0 + s.c0;
+            for (int idx = tid; idx < n; idx += NT) {
+                const int rr0 = idx / nc, cc = idx - rr0 * nc;
+                z[(size_t)rr0 * a.geo.Nx + cc] = cvt<double>(X[(size_t)(r0 + rr0) * W + s.c0 + cc]);
+            }
+        } else {
+            cx<T>* tr = reinterpret_cast<cx<T>*>(a.traces) + (size_t)rhs * a.trace_stride;
+            auto own = [&](int k) { return k >= olo && k <= ohi; };
+            for (int o = 0; o < dref.nout; ++o) {
+                const int side = dref.out_side[o];
+                cx<T>* out = tr + dref.out_off[o];
+                const bool acc = dref.out_acc[o] != 0;
+                if (side == SIDE_B || side == SIDE_T) {
+                    const int l0 = (side == SIDE_B) ? s.r0 - 1 : s.r1 - 1;
+                    for (int idx = tid; idx < 2 * W; idx += NT) {
+                        const int line = idx / W, c = idx - line * W;
+                        if (!own(l0 + line)) continue;
+                        const cx<T> xv = X[(size_t)(l0 + line) * W + c];
+                        out[idx] = acc ? out[idx] + xv : xv;
+                    }
+                } else {
+                    const int l0 = (side == SIDE_L) ? s.c0 - 1 : s.c1 - 1;
+                    for (int idx = tid; idx < 2 * H; idx += NT) {
+                        const int line = idx / H, k = idx - line * H;
+                        if (!own(k)) continue;
+                        const cx<T> xv = X[(size_t)k * W + l0 + line];
+                        out[idx] = acc ? out[idx] + xv : xv;
+                    }
+                }
+            }
+        }
+    }
+}
+
 // Right-hand side of the final z solve of each window: r on Omega_ij plus the polarized
 // sources g_s of all its sweep solves.  Every incoming trace keeps, after the application, the
 // value its sweep solve read (each is written before it is consumed and never after), so the
@@ -980,11 +1246,14 @@ hipError_t launch_factor(const FactorArgs& a, int nsub, bool use_lds, size_t lds
 
 // prefetch depth: as many blocks in flight as the 128-VGPR budget of a 1024-thread
 // workgroup allows (complex64: 2 floats, complex128: 4 per element)
+// register-ring depth of the complex64 kernel at 8 elements per thread (blocks in flight)
+constexpr int kPdF8 = 3;
+
 template <typename T, int CS, bool YLDS>
 static void launch_chain_c(const ChainArgs& a, dim3 grid, int ept, size_t lds, hipStream_t st) {
     constexpr bool dbl = sizeof(T) == 8;
     if (ept <= 4) k_chain<T, 4, 2, CS, YLDS><<<grid, 1024, lds, st>>>(a);
-    else if (ept <= 8) k_chain<T, 8, dbl ? 1 : 2, CS, YLDS><<<grid, 1024, lds, st>>>(a);
+    else if (ept <= 8) k_chain<T, 8, dbl ? 1 : kPdF8, CS, YLDS><<<grid, 1024, lds, st>>>(a);
     else if (ept <= 16) k_chain<T, 16, dbl ? 0 : 1, CS, YLDS><<<grid, 1024, lds, st>>>(a);
     else if (ept <= 32) k_chain<T, 32, 0, CS, YLDS><<<grid, 1024, lds, st>>>(a);
     else k_chain<T, 64, 0, CS, YLDS><<<grid, 1024, lds, st>>>(a);
@@ -999,7 +1268,7 @@ static hipError_t set_lds(int cs, int ept, size_t lds) {
 #define LSW_SET(CSV)                                                                                      \
     if (cs == CSV) {                                                                                      \
         if (ept <= 4) e = one((const void*)k_chain<T, 4, 2, CSV, true>);                                  \
-        else if (ept <= 8) e = one((const void*)k_chain<T, 8, dbl ? 1 : 2, CSV, true>);                  \
+        else if (ept <= 8) e = one((const void*)k_chain<T, 8, dbl ? 1 : kPdF8, CSV, true>);              \
         else if (ept <= 16) e = one((const void*)k_chain<T, 16, dbl ? 0 : 1, CSV, true>);                \
         else if (ept <= 32) e = one((const void*)k_chain<T, 32, 0, CSV, true>);                          \
         else e = one((const void*)k_chain<T, 64, 0, CSV, true>);                                         \
@@ -1041,6 +1310,41 @@ hipError_t launch_chain(const ChainArgs& a, int nsolves, int nrhs, int ept, bool
                         hipStream_t st) {
     return c64mode ? launch_chain_t<float>(a, nsolves, nrhs, ept, cs, ylds, st)
                    : launch_chain_t<double>(a, nsolves, nrhs, ept, cs, ylds, st);
+}
+
+template <typename T, int CS, int R>
+static void launch_chain_mr_c(const ChainArgs& a, dim3 grid, int ept, hipStream_t st) {
+    constexpr bool dbl = sizeof(T) == 8;
+    if (ept <= 4) k_chain_mr<T, 4, 2, CS, R><<<grid, 1024, 0, st>>>(a);
+    else if (ept <= 8) k_chain_mr<T, 8, dbl ? 1 : 2, CS, R><<<grid, 1024, 0, st>>>(a);
+    else if (ept <= 16) k_chain_mr<T, 16, dbl ? 0 : 1, CS, R><<<grid, 1024, 0, st>>>(a);
+    else if (ept <= 32) k_chain_mr<T, 32, 0, CS, R><<<grid, 1024, 0, st>>>(a);
+    else k_chain_mr<T, 64, 0, CS, R><<<grid, 1024, 0, st>>>(a);
+}
+
+template <typename T>
+static hipError_t launch_chain_mr_t(const ChainArgs& a0, int nsolves, int nrhs, int ept, int cs, int R,
+                                    hipStream_t st) {
+    dim3 grid(2 * nsolves, (nrhs + R - 1) / R);
+    ChainArgs a = a0;
+    a.nrhs = nrhs;
+    for (int phase = 0; phase < 2; ++phase) {
+        a.phase = phase;
+#define LSW_GO(CSV, RV) if (cs == CSV && R == RV) launch_chain_mr_c<T, CSV, RV>(a, grid, ept, st);
+        LSW_GO(CS_STAGE1, 2)
+        LSW_GO(CS_STAGE1, 4)
+        LSW_GO(CS_FINAL, 2)
+        LSW_GO(CS_FINAL, 4)
+#undef LSW_GO
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_chain_mr(const ChainArgs& a, int nsolves, int nrhs, int ept, bool c64mode, int cs, int rgroup,
+                           hipStream_t st) {
+    if ((cs != 0 && cs != 1) || (rgroup != 2 && rgroup != 4)) return hipErrorInvalidValue;
+    return c64mode ? launch_chain_mr_t<float>(a, nsolves, nrhs, ept, cs, rgroup, st)
+                   : launch_chain_mr_t<double>(a, nsolves, nrhs, ept, cs, rgroup, st);
 }
 
 hipError_t launch_gemv(const GemvArgs& a, bool c64mode, hipStream_t st) {

@@ -36,6 +36,7 @@ struct ChainArgs {
     c128* fw;               // right-hand sides of the final z solves, window layout [nrhs][sum H*W]
     size_t fw_stride;       // sum over windows of H*W
     int phase;              // set by launch_chain: 0 forward halves, 1 middle + backward halves
+    int nrhs;               // set by launch_chain_mr: right-hand sides of the launch
 };
 
 struct GemvArgs {
@@ -97,6 +98,10 @@ hipError_t launch_factor(const FactorArgs& a, int nsub, bool use_lds, size_t lds
 hipError_t launch_chain(const ChainArgs& a, int nsolves, int nrhs, int ept, bool c64mode, int cs, size_t ylds,
                         hipStream_t st);
 // one dependency level of the trace-compressed sweeps: one workgroup per work item
+// stage 1 (cs 0) or final (cs 1) substitutions with rgroup (2 or 4) right-hand sides per
+// workgroup; y and x in a.Y (Y_stride >= 2 H_max W_max)
+hipError_t launch_chain_mr(const ChainArgs& a, int nsolves, int nrhs, int ept, bool c64mode, int cs, int rgroup,
+                           hipStream_t st);
 hipError_t launch_gemv(const GemvArgs& a, bool c64mode, hipStream_t st);
 hipError_t launch_final_rhs(const ChainArgs& a, int nsub, int nrhs, bool c64mode, hipStream_t st);
 hipError_t launch_cast(const c128* src, c64* dst, size_t n, hipStream_t st);

@@ -70,7 +70,8 @@ class lsw_stats_t(ctypes.Structure):
                 ("last_chain_ms", ctypes.c_double), ("last_gemv_ms", ctypes.c_double),
                 ("apply_stage1_bytes", ctypes.c_double), ("apply_final_bytes", ctypes.c_double),
                 ("last_stage1_ms", ctypes.c_double), ("last_final_ms", ctypes.c_double),
-                ("last_final_rhs_ms", ctypes.c_double)]
+                ("last_final_rhs_ms", ctypes.c_double), ("rhs_per_workgroup", ctypes.c_int),
+                ("tune_ms", ctypes.c_double * 3)]
 
 
 _lib = None
@@ -251,7 +252,9 @@ class Solver:
     def stats(self) -> dict:
         st = lsw_stats_t()
         self._check(self._lib.lsw_query(self._h, ctypes.byref(st)))
-        return {name: getattr(st, name) for name, _ in lsw_stats_t._fields_}
+        out = {name: getattr(st, name) for name, _ in lsw_stats_t._fields_}
+        out["tune_ms"] = list(out["tune_ms"])
+        return out
 
     def close(self):
         if getattr(self, "_h", None):

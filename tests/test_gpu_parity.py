@@ -138,7 +138,11 @@ def test_apply_mixed_matches_oracle(name, mode):
 
 
 @pytest.mark.parametrize("mode", ["compressed", "chain"])
-def test_apply_is_deterministic_and_batches_rhs_exactly(mode):
+def test_apply_is_deterministic_and_batches_rhs_exactly(mode, monkeypatch):
+    """One right-hand side per workgroup: a batch is bitwise the single applications, and
+    repeated applications are bitwise equal (the batched-workgroup kernels are compared to
+    tolerance in test_batched_substitutions_carry_several_rhs_per_workgroup)."""
+    monkeypatch.setenv("LSW_RHS_PER_WORKGROUP", "1")
     c = CASES["ragged_45x38_3x2"]
     R = inputs.complex_normal((3, c.N), 5)
     s = c.solver(nrhs_max=3, sweep_mode=mode)
@@ -330,3 +334,32 @@ def test_lazy_conjugate_views_are_materialised():
     s = c.solver()
     assert torch.equal(s.apply(torch.conj(x)), s.apply(torch.conj_physical(x)))
     s.close()
+
+
+@pytest.mark.parametrize("R", [1, 2, 4])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_batched_substitutions_carry_several_rhs_per_workgroup(R, precision, monkeypatch):
+    """R right-hand sides per workgroup of the stage-1 / final substitutions (every factor
+    block read once per group) give the same applications as one right-hand side at a time."""
+    c = CASES["wide_4x5"]
+    X = torch.from_numpy(np.stack([inputs.complex_normal(c.N, 70 + k) for k in range(5)])).cuda()
+    monkeypatch.setenv("LSW_RHS_PER_WORKGROUP", str(R))
+    s = c.solver(precision=precision, nrhs_max=5)
+    assert s.stats()["rhs_per_workgroup"] == R
+    Z = s.apply(X).cpu().numpy().reshape(5, -1)
+    singles = np.stack([s.apply(X[k:k + 1]).cpu().numpy().ravel() for k in range(5)])
+    s.close()
+    for k in range(5):
+        assert rel(Z[k], singles[k]) < (1e-13 if precision == "fp64" else 1e-6), (R, k)
+    zo = c.oracle.apply(X[2].cpu().numpy())
+    assert rel(Z[2], zo) < (1e-10 if precision == "fp64" else 2e-4)
+
+
+def test_rhs_per_workgroup_is_tuned_at_setup():
+    c = CASES["const127_4x4"]
+    s = c.solver(precision="mixed", nrhs_max=8)
+    st = s.stats()
+    s.close()
+    say("tuned R", st["rhs_per_workgroup"], st["tune_ms"])
+    assert st["rhs_per_workgroup"] in (1, 2, 4)
+    assert all(t > 0 for t in st["tune_ms"])

@@ -4,7 +4,8 @@
   against the oracle's Alg. Scenario3 (FP64 1e-10, complex64 2e-4); the batched 8-source
   solve at 255^2, 4x4 against the oracle's sparse direct solve (1e-6 / 1e-4 at tol 1e-8).
 * layered2d at full size (2047^2, 16x16 CDD, 32 sources batched in every launch, complex64):
-  one application against the oracle (the whole vector); batching is exact; the banded
+  one application against the oracle (the whole vector); a batch of 32 equals the single
+  applications; the banded
   oracle does not fit (430 GB), so the residuals of a short 32-source solve are recomputed in
   FP64 on the host from the oracle's assembled operator of App. A.
 * fwi2d at full size (1023^2, 8x8, 8 sources, 64 receivers): forward residuals by the
@@ -93,8 +94,12 @@ def test_layered2d_full_size_apply_and_32_source_batch():
     gp = GlobalProblem(m, wl.omega, wl.n, wl.n_pml, wl.C)
     B = torch.from_numpy(np.stack([gp.rhs(f) for f in wl.sources])).cuda()
     Z = s.apply(B)
+    say("layered2d full: right-hand sides per workgroup", st["rhs_per_workgroup"], "tuning ms", st["tune_ms"])
+    # a batch of 32 equals the single applications to complex64 rounding (the batch runs 4
+    # right-hand sides per workgroup, a different summation schedule: 2e-6 observed)
     for k in (0, 13, 31):
-        assert torch.equal(Z[k], s.apply(B[k:k + 1])[0])
+        zk = s.apply(B[k:k + 1])[0]
+        assert torch.linalg.norm(Z[k] - zk) <= 2e-5 * torch.linalg.norm(zk)
     U, info = s.solve(B)
     say("layered2d full 32-source solve", info["iterations"][:4], info["relres"][:4], "ms", info["t_solve_ms"])
     U = U.cpu().numpy().reshape(32, -1)
