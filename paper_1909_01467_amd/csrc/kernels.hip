@@ -317,14 +317,15 @@ enum ChainSet : int { CS_STAGE1 = 0, CS_FINAL = 1, CS_UNIT = 2, CS_POLAR = 3 };
 //   phase 1: x_m = G_m (g_m - C_{m-1} y_{m-1} - C_m y_{m+1}) (computed by both halves), then
 //            half 0: x_k = y_k - G_k C_k x_{k+1} downwards,  half 1: x_k = y_k - G_k C_{k-1} x_{k-1} upwards.
 // Thread tid < NA = floor(1024/W)*W owns block row t = tid % W and the columns
-// c = tid / W + NG*j (j < ept) of every W x W block G_k: its elements sit at the flat
+// c = tid / W + NG*j (c < W) of every W x W block G_k: its elements sit at the flat
 // offsets tid + NA*j of the column-major block, so the loads are fully coalesced.
 // A register ring keeps PD blocks of G (and the right-hand-side / y values) in flight ahead
-// of the block in use; every load in the loop is unconditional (zero past the buffer,
-// masked at use) and nothing is stored to global memory inside the loop (the half's y or x
+// of the block in use; every load in the loop is unconditional (zero past the buffer, and
+// columns past W meet a zero entry of v) and nothing is stored to global memory inside the
+// loop (the half's y or x
 // live in Ybuf, LDS when it fits), so waiting for a block never waits for the younger
 // prefetches.  Thread t < W carries its y/x entry in a register: two barriers per block.
-template <typename T, int EPT, int PD, int CS, bool YLDS>
+template <typename T, int EPT, int PD, int CS, bool YLDS, int PH>
 __global__ __launch_bounds__(1024) void k_chain(ChainArgs a) {
     constexpr int NT = 1024;
     extern __shared__ __align__(16) unsigned char dyn[];
@@ -340,21 +341,21 @@ __global__ __launch_bounds__(1024) void k_chain(ChainArgs a) {
     const bool mine = tid < W;
     const int tc = mine ? tid : W - 1;          // clamped column for address arithmetic
     const int cg = act ? tid / W : 0;
-    const int ept = (W + NG - 1) / NG;
     const int WW = W * W;
-    __shared__ cx<T> v[kMaxWindow];
+    __shared__ cx<T> v[kMaxWindow + 1];   // v[kMaxWindow] stays zero: the slot of masked columns
     __shared__ cx<T> part[NT];
     __shared__ c128 a2h[kMaxWindow + 1];
 
     const c128* tab = a.geo.tab;
     const double ih2 = 1.0 / (a.geo.h * a.geo.h);
     for (int k = tid; k <= H; k += NT) a2h[k] = tab[s.ty + H + k];   // alpha_y at the half points
+    if (tid == 0) v[kMaxWindow] = cx<T>{T(0), T(0)};
     const c128 ia_c = tab[s.tx + tc];                                  // 1/alpha_x of my column
     const cx<T>* Gs = reinterpret_cast<const cx<T>*>(a.G) + s.g_off;
     cx<T>* tr = reinterpret_cast<cx<T>*>(a.traces) + (size_t)rhs * a.trace_stride;
     // y of both halves (written in phase 0, read in phase 1); x goes to Ybuf
     cx<T>* Yg = reinterpret_cast<cx<T>*>(a.Y) + ((size_t)blockIdx.y * nsol + sidx) * a.Y_stride;
-    cx<T>* Ybuf = YLDS ? reinterpret_cast<cx<T>*>(dyn) : Yg + (a.phase == 1 ? (size_t)H * W : 0);
+    cx<T>* Ybuf = YLDS ? reinterpret_cast<cx<T>*>(dyn) : Yg + (PH == 1 ? (size_t)H * W : 0);
     const size_t N = (size_t)a.geo.Nx * a.geo.Ny;
     // a prvalue zero: a named zero in a conditional with an array element makes the
     // compiler select between addresses and move the register rings to scratch
@@ -399,15 +400,29 @@ __global__ __launch_bounds__(1024) void k_chain(ChainArgs a) {
         for (int j = 0; j < EPT; ++j)
             buf[j] = bload<T>(grsrc, kb + (uint32_t)(tid + NA * j) * (uint32_t)sizeof(cx<T>));
     };
-    // part[tid] = sum_j G_k[c_j][t] v[c_j]
+    // part[tid] = sum_j G_k[c_j][t] v[c_j].  With up to 8 complex64 values per thread all v
+    // reads are issued before the first product (one LDS round trip per block instead of one
+    // per column; columns past W, and the lanes past NA, read the zero slot).  Larger or
+    // complex128 blocks leave no registers for that and take one read per product.
     auto gemv = [&](const cx<T>* buf) {
         cx<T> acc = zero();
+        if constexpr (sizeof(T) == 4 && EPT <= 8) {
+            cx<T> vv[EPT];
 #pragma unroll
-        for (int j = 0; j < EPT; ++j) {
-            const int c = cg + NG * j;
-            const bool ok = act && j < ept && c < W;
-            const cx<T> t = buf[j] * v[ok ? c : 0];
-            if (ok) acc = acc + t;
+            for (int j = 0; j < EPT; ++j) {
+                const int c = cg + NG * j;
+                vv[j] = v[(act && c < W) ? c : kMaxWindow];
+            }
+#pragma unroll
+            for (int j = 0; j < EPT; ++j) acc = acc + buf[j] * vv[j];
+        } else {
+#pragma unroll
+            for (int j = 0; j < EPT; ++j) {
+                const int c = cg + NG * j;
+                const bool ok = act && c < W;
+                const cx<T> t = buf[j] * v[ok ? c : 0];
+                if (ok) acc = acc + t;
+            }
         }
         part[tid] = acc;
     };
@@ -423,7 +438,7 @@ __global__ __launch_bounds__(1024) void k_chain(ChainArgs a) {
     cx<T> yv = zero();   // the y (phase 0) or x (phase 1) entry of my column at the previous block row
     __syncthreads();   // a2h
 
-    if (a.phase == 0) {
+    if constexpr (PH == 0) {
         // ---- forward elimination of this half towards the middle row
         const int kstart = h == 0 ? kf0 : kf1;
         const int dir = h == 0 ? 1 : -1;
@@ -435,29 +450,33 @@ __global__ __launch_bounds__(1024) void k_chain(ChainArgs a) {
                 rr[p] = rhs_load(kat(p));
                 load(kat(p), ring[p]);
             }
-        for (int i0 = 0; i0 < n; i0 += PD + 1) {
-#pragma unroll
-            for (int u = 0; u <= PD; ++u) {
-                const int i = i0 + u;
-                if (i < n) {
-                    const int k = kstart + dir * i;
-                    rr[(u + PD) % (PD + 1)] = rhs_load(kat(i + PD));
-                    load(kat(i + PD), ring[(u + PD) % (PD + 1)]);
-                    if (mine) {
-                        cx<T> g = rhs_use(k, rr[u]);
-                        if (i > 0) g = g - cy(h == 0 ? k - 1 : k) * yv;
-                        v[tid] = g;
-                    }
-                    __syncthreads();
-                    gemv(ring[u]);
-                    __syncthreads();
-                    if (mine) {
-                        yv = reduce(tid);
-                        Ybuf[(size_t)k * W + tid] = yv;
-                    }
-                }
+        auto fstep = [&](int i, int u) __attribute__((always_inline)) {
+            const int k = kstart + dir * i;
+            rr[(u + PD) % (PD + 1)] = rhs_load(kat(i + PD));
+            load(kat(i + PD), ring[(u + PD) % (PD + 1)]);
+            if (mine) {
+                cx<T> g = rhs_use(k, rr[u]);
+                if (i > 0) g = g - cy(h == 0 ? k - 1 : k) * yv;
+                v[tid] = g;
             }
+            __syncthreads();
+            gemv(ring[u]);
+            __syncthreads();
+            if (mine) {
+                yv = reduce(tid);
+                Ybuf[(size_t)k * W + tid] = yv;
+            }
+        };
+        // whole groups of PD + 1 steps carry no guard, so every path through the loop
+        // consumes the ring in order and the waits stay partial; then the tail
+        int i0 = 0;
+        for (; i0 + PD < n; i0 += PD + 1) {
+#pragma unroll
+            for (int u = 0; u <= PD; ++u) fstep(i0 + u, u);
         }
+#pragma unroll
+        for (int u = 0; u < PD; ++u)
+            if (i0 + u < n) fstep(i0 + u, u);
         if constexpr (YLDS) {
             __syncthreads();
             const int lo = h == 0 ? kf0 : m + 1, hi = h == 0 ? m - 1 : kf1;
@@ -498,27 +517,29 @@ __global__ __launch_bounds__(1024) void k_chain(ChainArgs a) {
                 yr[p] = yload(kat(p));
                 load(kat(p), ring[p]);
             }
-        for (int i0 = 0; i0 < n; i0 += PD + 1) {
-#pragma unroll
-            for (int u = 0; u <= PD; ++u) {
-                const int i = i0 + u;
-                if (i < n) {
-                    const int k = kstart + dir * i;
-                    yr[(u + PD) % (PD + 1)] = yload(kat(i + PD));
-                    load(kat(i + PD), ring[(u + PD) % (PD + 1)]);
-                    if (mine) v[tid] = cy(h == 0 ? k : k - 1) * yv;
-                    __syncthreads();
-                    gemv(ring[u]);
-                    __syncthreads();
-                    if (mine) {
-                        // y of the bottom half is zero below kf0, that of the top half above kf1
-                        const cx<T> y = (h == 0 ? k >= kf0 : k <= kf1) ? yr[u] : zero();
-                        yv = y - reduce(tid);
-                        Ybuf[(size_t)k * W + tid] = yv;
-                    }
-                }
+        auto bstep = [&](int i, int u) __attribute__((always_inline)) {
+            const int k = kstart + dir * i;
+            yr[(u + PD) % (PD + 1)] = yload(kat(i + PD));
+            load(kat(i + PD), ring[(u + PD) % (PD + 1)]);
+            if (mine) v[tid] = cy(h == 0 ? k : k - 1) * yv;
+            __syncthreads();
+            gemv(ring[u]);
+            __syncthreads();
+            if (mine) {
+                // y of the bottom half is zero below kf0, that of the top half above kf1
+                const cx<T> y = (h == 0 ? k >= kf0 : k <= kf1) ? yr[u] : zero();
+                yv = y - reduce(tid);
+                Ybuf[(size_t)k * W + tid] = yv;
             }
+        };
+        int i0 = 0;
+        for (; i0 + PD < n; i0 += PD + 1) {
+#pragma unroll
+            for (int u = 0; u <= PD; ++u) bstep(i0 + u, u);
         }
+#pragma unroll
+        for (int u = 0; u < PD; ++u)
+            if (i0 + u < n) bstep(i0 + u, u);
     }
     __syncthreads();
 
@@ -595,7 +616,7 @@ __global__ __launch_bounds__(1024) void k_chain(ChainArgs a) {
 // group, so a batch of sources reads the factors nrhs/R times instead of nrhs times.  y and
 // x live in global memory (phase 0 writes y at [0, H W) of each right-hand side's slab,
 // phase 1 writes x at [H W, 2 H W)).
-template <typename T, int EPT, int PD, int CS, int R>
+template <typename T, int EPT, int PD, int CS, int R, int PH>
 __global__ __launch_bounds__(1024) void k_chain_mr(ChainArgs a) {
     static_assert(CS == CS_STAGE1 || CS == CS_FINAL, "stage 1 and final solves only");
     constexpr int NT = 1024;
@@ -612,15 +633,15 @@ __global__ __launch_bounds__(1024) void k_chain_mr(ChainArgs a) {
     const bool mine = tid < W;
     const int tc = mine ? tid : W - 1;
     const int cg = act ? tid / W : 0;
-    const int ept = (W + NG - 1) / NG;
     const int WW = W * W;
-    __shared__ cx<T> v[R][kMaxWindow];
+    __shared__ cx<T> v[R][kMaxWindow + 1];   // v[r][kMaxWindow] stays zero
     __shared__ cx<T> part[R][NT];
     __shared__ c128 a2h[kMaxWindow + 1];
 
     const c128* tab = a.geo.tab;
     const double ih2 = 1.0 / (a.geo.h * a.geo.h);
     for (int k = tid; k <= H; k += NT) a2h[k] = tab[s.ty + H + k];
+    if (tid < R) v[tid][kMaxWindow] = cx<T>{T(0), T(0)};
     const c128 ia_c = tab[s.tx + tc];
     const cx<T>* Gs = reinterpret_cast<const cx<T>*>(a.G) + s.g_off;
     const size_t N = (size_t)a.geo.Nx * a.geo.Ny;
@@ -667,7 +688,7 @@ __global__ __launch_bounds__(1024) void k_chain_mr(ChainArgs a) {
 #pragma unroll
         for (int j = 0; j < EPT; ++j) {
             const int c = cg + NG * j;
-            const bool ok = act && j < ept && c < W;
+            const bool ok = act && c < W;
             const int cc = ok ? c : 0;
 #pragma unroll
             for (int r = 0; r < R; ++r) {
@@ -691,7 +712,7 @@ __global__ __launch_bounds__(1024) void k_chain_mr(ChainArgs a) {
     for (int r = 0; r < R; ++r) yv[r] = zero();
     __syncthreads();
 
-    if (a.phase == 0) {
+    if constexpr (PH == 0) {
         const int kstart = h == 0 ? kf0 : kf1;
         const int dir = h == 0 ? 1 : -1;
         const int n = h == 0 ? m - kf0 : kf1 - m;
@@ -1268,29 +1289,35 @@ hipError_t launch_factor(const FactorArgs& a, int nsub, bool use_lds, size_t lds
 // register-ring depth of the complex64 kernel at 8 elements per thread (blocks in flight)
 constexpr int kPdF8 = 3;
 
-template <typename T, int CS, bool YLDS>
+template <typename T, int CS, bool YLDS, int PH>
 static void launch_chain_c(const ChainArgs& a, dim3 grid, int ept, size_t lds, hipStream_t st) {
     constexpr bool dbl = sizeof(T) == 8;
-    if (ept <= 4) k_chain<T, 4, 2, CS, YLDS><<<grid, 1024, lds, st>>>(a);
-    else if (ept <= 8) k_chain<T, 8, dbl ? 1 : kPdF8, CS, YLDS><<<grid, 1024, lds, st>>>(a);
-    else if (ept <= 16) k_chain<T, 16, dbl ? 0 : 1, CS, YLDS><<<grid, 1024, lds, st>>>(a);
-    else if (ept <= 32) k_chain<T, 32, 0, CS, YLDS><<<grid, 1024, lds, st>>>(a);
-    else k_chain<T, 64, 0, CS, YLDS><<<grid, 1024, lds, st>>>(a);
+    if (ept <= 4) k_chain<T, 4, 2, CS, YLDS, PH><<<grid, 1024, lds, st>>>(a);
+    else if (ept <= 8) k_chain<T, 8, dbl ? 1 : kPdF8, CS, YLDS, PH><<<grid, 1024, lds, st>>>(a);
+    else if (ept <= 16) k_chain<T, 16, dbl ? 0 : 1, CS, YLDS, PH><<<grid, 1024, lds, st>>>(a);
+    else if (ept <= 32) k_chain<T, 32, 0, CS, YLDS, PH><<<grid, 1024, lds, st>>>(a);
+    else k_chain<T, 64, 0, CS, YLDS, PH><<<grid, 1024, lds, st>>>(a);
+}
+
+template <typename T, int CS, int PH>
+static hipError_t set_lds_one(int ept, size_t lds) {
+    // dynamic LDS beyond the default needs the attribute on every instantiation that may run
+    auto one = [&](const void* f) { return hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds); };
+    constexpr bool dbl = sizeof(T) == 8;
+    if (ept <= 4) return one((const void*)k_chain<T, 4, 2, CS, true, PH>);
+    if (ept <= 8) return one((const void*)k_chain<T, 8, dbl ? 1 : kPdF8, CS, true, PH>);
+    if (ept <= 16) return one((const void*)k_chain<T, 16, dbl ? 0 : 1, CS, true, PH>);
+    if (ept <= 32) return one((const void*)k_chain<T, 32, 0, CS, true, PH>);
+    return one((const void*)k_chain<T, 64, 0, CS, true, PH>);
 }
 
 template <typename T>
 static hipError_t set_lds(int cs, int ept, size_t lds) {
-    // dynamic LDS beyond the default needs the attribute on every instantiation that may run
-    auto one = [&](const void* f) { return hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds); };
-    constexpr bool dbl = sizeof(T) == 8;
     hipError_t e = hipSuccess;
-#define LSW_SET(CSV)                                                                                      \
-    if (cs == CSV) {                                                                                      \
-        if (ept <= 4) e = one((const void*)k_chain<T, 4, 2, CSV, true>);                                  \
-        else if (ept <= 8) e = one((const void*)k_chain<T, 8, dbl ? 1 : kPdF8, CSV, true>);              \
-        else if (ept <= 16) e = one((const void*)k_chain<T, 16, dbl ? 0 : 1, CSV, true>);                \
-        else if (ept <= 32) e = one((const void*)k_chain<T, 32, 0, CSV, true>);                          \
-        else e = one((const void*)k_chain<T, 64, 0, CSV, true>);                                         \
+#define LSW_SET(CSV)                                                         \
+    if (cs == CSV) {                                                         \
+        e = set_lds_one<T, CSV, 0>(ept, lds);                                \
+        if (e == hipSuccess) e = set_lds_one<T, CSV, 1>(ept, lds);           \
     }
     LSW_SET(CS_STAGE1)
     LSW_SET(CS_FINAL)
@@ -1308,20 +1335,16 @@ static hipError_t launch_chain_t(const ChainArgs& a0, int nsolves, int nrhs, int
         hipError_t e = set_lds<T>(cs, ept, ylds);
         if (e != hipSuccess) return e;
     }
-    for (int phase = 0; phase < 2; ++phase) {
-        ChainArgs a = a0;
-        a.phase = phase;
-#define LSW_GO(CSV)                                                                 \
-        if (cs == CSV) {                                                            \
-            if (ylds > 0) launch_chain_c<T, CSV, true>(a, grid, ept, ylds, st);     \
-            else launch_chain_c<T, CSV, false>(a, grid, ept, 0, st);                \
-        }
-        LSW_GO(CS_STAGE1)
-        LSW_GO(CS_FINAL)
-        LSW_GO(CS_UNIT)
-        LSW_GO(CS_POLAR)
-#undef LSW_GO
+    // phase 0 (forward halves), then phase 1 (middle row and backward halves): the kernel
+    // boundary is where the two halves of every solve meet
+#define LSW_GO(CSV, PHV)                                                                    \
+    if (cs == CSV) {                                                                        \
+        if (ylds > 0) launch_chain_c<T, CSV, true, PHV>(a0, grid, ept, ylds, st);           \
+        else launch_chain_c<T, CSV, false, PHV>(a0, grid, ept, 0, st);                      \
     }
+    LSW_GO(CS_STAGE1, 0) LSW_GO(CS_FINAL, 0) LSW_GO(CS_UNIT, 0) LSW_GO(CS_POLAR, 0)
+    LSW_GO(CS_STAGE1, 1) LSW_GO(CS_FINAL, 1) LSW_GO(CS_UNIT, 1) LSW_GO(CS_POLAR, 1)
+#undef LSW_GO
     return hipGetLastError();
 }
 
@@ -1331,14 +1354,14 @@ hipError_t launch_chain(const ChainArgs& a, int nsolves, int nrhs, int ept, bool
                    : launch_chain_t<double>(a, nsolves, nrhs, ept, cs, ylds, st);
 }
 
-template <typename T, int CS, int R>
+template <typename T, int CS, int R, int PH>
 static void launch_chain_mr_c(const ChainArgs& a, dim3 grid, int ept, hipStream_t st) {
     constexpr bool dbl = sizeof(T) == 8;
-    if (ept <= 4) k_chain_mr<T, 4, 2, CS, R><<<grid, 1024, 0, st>>>(a);
-    else if (ept <= 8) k_chain_mr<T, 8, dbl ? 1 : 2, CS, R><<<grid, 1024, 0, st>>>(a);
-    else if (ept <= 16) k_chain_mr<T, 16, dbl ? 0 : 1, CS, R><<<grid, 1024, 0, st>>>(a);
-    else if (ept <= 32) k_chain_mr<T, 32, 0, CS, R><<<grid, 1024, 0, st>>>(a);
-    else k_chain_mr<T, 64, 0, CS, R><<<grid, 1024, 0, st>>>(a);
+    if (ept <= 4) k_chain_mr<T, 4, 2, CS, R, PH><<<grid, 1024, 0, st>>>(a);
+    else if (ept <= 8) k_chain_mr<T, 8, dbl ? 1 : 2, CS, R, PH><<<grid, 1024, 0, st>>>(a);
+    else if (ept <= 16) k_chain_mr<T, 16, dbl ? 0 : 1, CS, R, PH><<<grid, 1024, 0, st>>>(a);
+    else if (ept <= 32) k_chain_mr<T, 32, 0, CS, R, PH><<<grid, 1024, 0, st>>>(a);
+    else k_chain_mr<T, 64, 0, CS, R, PH><<<grid, 1024, 0, st>>>(a);
 }
 
 template <typename T>
@@ -1347,15 +1370,10 @@ static hipError_t launch_chain_mr_t(const ChainArgs& a0, int nsolves, int nrhs, 
     dim3 grid(2 * nsolves, (nrhs + R - 1) / R);
     ChainArgs a = a0;
     a.nrhs = nrhs;
-    for (int phase = 0; phase < 2; ++phase) {
-        a.phase = phase;
-#define LSW_GO(CSV, RV) if (cs == CSV && R == RV) launch_chain_mr_c<T, CSV, RV>(a, grid, ept, st);
-        LSW_GO(CS_STAGE1, 2)
-        LSW_GO(CS_STAGE1, 4)
-        LSW_GO(CS_FINAL, 2)
-        LSW_GO(CS_FINAL, 4)
+#define LSW_GO(CSV, RV, PHV) if (cs == CSV && R == RV) launch_chain_mr_c<T, CSV, RV, PHV>(a, grid, ept, st);
+    LSW_GO(CS_STAGE1, 2, 0) LSW_GO(CS_STAGE1, 4, 0) LSW_GO(CS_FINAL, 2, 0) LSW_GO(CS_FINAL, 4, 0)
+    LSW_GO(CS_STAGE1, 2, 1) LSW_GO(CS_STAGE1, 4, 1) LSW_GO(CS_FINAL, 2, 1) LSW_GO(CS_FINAL, 4, 1)
 #undef LSW_GO
-    }
     return hipGetLastError();
 }
 

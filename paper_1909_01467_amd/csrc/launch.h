@@ -35,7 +35,6 @@ struct ChainArgs {
     void* Q;                // Q pool (KIND_UNIT writes columns)
     c128* fw;               // right-hand sides of the final z solves, window layout [nrhs][sum H*W]
     size_t fw_stride;       // sum over windows of H*W
-    int phase;              // set by launch_chain: 0 forward halves, 1 middle + backward halves
     int nrhs;               // set by launch_chain_mr: right-hand sides of the launch
 };
 
