@@ -128,6 +128,9 @@ typedef struct {
                                     (1, 2 or 4), chosen at setup by timing when nrhs_max > 1, or
                                     fixed by the environment variable LSW_RHS_PER_WORKGROUP */
     double tune_ms[3];           /* the timings of 1, 2 and 4 right-hand sides per workgroup (0: not tried) */
+    int symmetric_factors;       /* 1 if the one-right-hand-side substitutions read the packed symmetric
+                                    blocks (G_k = G_k^T; about half the bytes of the full blocks) */
+    long long packed_factor_elems;  /* complex entries of the packed blocks (0 if not built) */
 } lsw_stats_t;
 
 /*

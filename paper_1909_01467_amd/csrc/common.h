@@ -92,9 +92,22 @@ struct SubDesc {
     int mid;             // middle block row of the twisted factorisation (H / 2)
     int L;               // number of trace-line slots, 4W + 4H
     long long g_off;     // offset (elements) of G_0 in the factor pool; G_k at g_off + k*W*W
+    long long gs_off;    // offset of G_0 in the packed symmetric pool; G_k at gs_off + k*sym_block(W)
     long long q_off;     // offset of Q = A_ij^-1[lines, lines] (L x L, column-major) in the Q pool
     long long fw_off;    // offset of this window (H x W, row-major) in the final right-hand-side array
 };
+
+// Packed storage of a complex symmetric W x W block G (G = G^T).  A = A^T makes every Schur
+// complement of the block elimination symmetric, and so every inverse G_k.  For d = 0..D,
+// D = floor(W/2), and t = 0..W-1 the entry P[d][t] = G[t][(t + d) mod W] sits at d*Ls + t:
+// every unordered pair {t, c} is stored once (the W/2 pairs at d = W/2 of an even W twice).
+// A row of Ls (even) entries ends with copies of its first Ls - W entries, so that two
+// consecutive entries are one load even across the wrap.  With all indices mod W,
+//   (G v)_t = sum_{d=0..D} P[d][t] v[t + d] + sum_{d in Dc} P[d][t - d] v[t - d],
+// Dc = {1..D} without W/2 for even W.
+__host__ __device__ inline int sym_D(int W) { return W / 2; }
+__host__ __device__ inline int sym_L(int W) { return W + 2 - (W & 1); }
+__host__ __device__ inline long long sym_block(int W) { return (long long)(sym_D(W) + 1) * sym_L(W); }
 
 // Layout of one axis table of a window with P points (offset t in the table pool):
 //   t + a        : 1/alpha at integer point a            (a = 0..P-1)

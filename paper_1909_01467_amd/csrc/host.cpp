@@ -95,6 +95,13 @@ struct lsw_plan {
     size_t FWT = 0;
     void* d_G = nullptr;
     size_t G_elems = 0;
+    // packed symmetric factors (2D): the stage-1 and final substitutions of one right-hand side
+    // per workgroup read these; d_G (full blocks) stays only where something else needs it
+    bool gsym = false;
+    int sym_ept = 0;                // packed rows per thread (max over the windows)
+    size_t sym_lds = 0;             // dynamic LDS of the packed substitutions: the largest packed block
+    void* d_Gs = nullptr;
+    size_t GS_elems = 0;
     void* d_traces = nullptr;
     size_t trace_stride = 0;
     void* d_zpart = nullptr;
@@ -588,6 +595,18 @@ ChainArgs chain_args(lsw_plan* p, const c128* d_r, c128* d_z) {
 
 int apply3d_impl(lsw_plan* p, const c128* d_r, c128* d_z, int nrhs, bool timed);
 
+// the stage-1 (cs 0) or final (cs 1) block substitutions of a 2D front: R right-hand sides per
+// workgroup on the full blocks, or one per workgroup on the packed symmetric blocks when present
+hipError_t launch_block_front(lsw_plan* p, ChainArgs a, const Front& f, int nrhs, int cs, int R) {
+    const bool c64 = p->precision == LSW_MIXED;
+    if (R > 1 && nrhs > 1) return launch_chain_mr(a, f.count, nrhs, p->ept, c64, cs, R, p->stream);
+    if (p->gsym) {
+        a.G = p->d_Gs;
+        return launch_chain_sym(a, f.count, nrhs, p->sym_ept, c64, cs, p->sym_lds, p->stream);
+    }
+    return launch_chain(a, f.count, nrhs, p->ept, c64, cs, p->ylds, p->stream);
+}
+
 int apply_impl(lsw_plan* p, const c128* d_r, c128* d_z, int nrhs, bool timed) {
     if (p->dim == 3) return apply3d_impl(p, d_r, d_z, nrhs, timed);
     const bool c64 = p->precision == LSW_MIXED;
@@ -628,10 +647,7 @@ int apply_impl(lsw_plan* p, const c128* d_r, c128* d_z, int nrhs, bool timed) {
             } else {
                 if (fi == nf - 1 && timed) HIPCK(p, hipEventRecord(p->ev[3], p->stream));
                 a.descs = p->d_descs + f.offset;
-                if (p->rgroup > 1 && nrhs > 1)
-                    HIPCK(p, launch_chain_mr(a, f.count, nrhs, p->ept, c64, fi == 0 ? 0 : 1, p->rgroup, p->stream));
-                else
-                    HIPCK(p, launch_chain(a, f.count, nrhs, p->ept, c64, fi == 0 ? 0 : 1, p->ylds, p->stream));
+                HIPCK(p, launch_block_front(p, a, f, nrhs, fi == 0 ? 0 : 1, p->rgroup));
             }
             if (fi == 0 && timed) HIPCK(p, hipEventRecord(p->ev[1], p->stream));
         }
@@ -998,7 +1014,6 @@ int tune_rgroup(lsw_plan* p) {
             return LSW_OK;
         }
     }
-    const bool c64 = p->precision == LSW_MIXED;
     const int nrhs = p->nrhs_max;
     HIPCK(p, hipMemsetAsync(p->d_tmp1, 0, sizeof(c128) * (size_t)nrhs * p->N, p->stream));
     HIPCK(p, hipMemsetAsync(p->d_fw, 0, sizeof(c128) * (size_t)nrhs * p->FWT, p->stream));
@@ -1016,8 +1031,7 @@ int tune_rgroup(lsw_plan* p) {
             for (const Front* f : {&f0, &f1}) {
                 a.descs = p->d_descs + f->offset;
                 const int cs = f == &f0 ? 0 : 1;
-                if (R > 1) HIPCK(p, launch_chain_mr(a, f->count, nrhs, p->ept, c64, cs, R, p->stream));
-                else HIPCK(p, launch_chain(a, f->count, nrhs, p->ept, c64, cs, p->ylds, p->stream));
+                HIPCK(p, launch_block_front(p, a, *f, nrhs, cs, R));
             }
             HIPCK(p, hipEventRecord(p->ev[1], p->stream));
             HIPCK(p, hipEventSynchronize(p->ev[1]));
@@ -1125,6 +1139,9 @@ int setup_impl(lsw_plan* p, const double* d_m, double omega, double h, const lsw
     // subdomains
     p->subs.clear();
     p->G_elems = 0;
+    p->GS_elems = 0;
+    p->sym_ept = 0;
+    p->sym_lds = 0;
     p->hbase.clear();
     p->vbase.clear();
     p->HT = p->VT = 0;
@@ -1149,6 +1166,10 @@ int setup_impl(lsw_plan* p, const double* d_m, double omega, double h, const lsw
                       (j > 0 ? 1 << SIDE_L : 0) | (j < p->r - 1 ? 1 << SIDE_R : 0);
             s.L = slot_count(s.W, s.H);
             s.g_off = (long long)p->G_elems;
+            s.gs_off = (long long)p->GS_elems;
+            p->GS_elems += (size_t)s.H * sym_block(s.W);
+            p->sym_ept = std::max(p->sym_ept, sym_ept(s.W));
+            p->sym_lds = std::max(p->sym_lds, (size_t)sym_block(s.W));
             const size_t S3 = (size_t)s.W * s.H;
             p->G_elems += p->dim == 3 ? (size_t)p->Nz * S3 * S3 : (size_t)s.H * s.W * s.W;
             p->Smax = std::max(p->Smax, (int)S3);
@@ -1176,6 +1197,23 @@ int setup_impl(lsw_plan* p, const double* d_m, double omega, double h, const lsw
         if (rc0 != LSW_OK) return rc0;
     }
     else p->Q_elems = 0;
+    // packed symmetric factors where the substitution kernel's registers allow (LSW_SYMMETRIC_FACTORS=0
+    // keeps the full blocks)
+    {
+        const char* env = std::getenv("LSW_SYMMETRIC_FACTORS");
+        const bool off = env && std::atoi(env) == 0;
+        const bool mixed = p->precision == LSW_MIXED;
+        const size_t eb = mixed ? sizeof(c64) : sizeof(c128);
+        p->sym_lds *= eb;
+        // static LDS of the kernel: v, part, the y and x coefficient tables
+        const size_t stat = eb * (kMaxWindow + 1 + 2048) + sizeof(c128) * (2 * kMaxWindow + 1) + 256;
+        int dev = 0, max_lds = 0;
+        HIPCK(p, hipGetDevice(&dev));
+        HIPCK(p, hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+        p->gsym = !off && p->dim == 2 && p->sweep_mode == LSW_SWEEP_COMPRESSED && p->sym_ept <= sym_max_ept(mixed) &&
+                  p->sym_lds + stat <= (size_t)max_lds;
+        if (p->gsym) HIPCK(p, prepare_chain_sym(p->sym_ept, mixed, p->sym_lds));
+    }
     const size_t eb = p->precision == LSW_MIXED ? sizeof(c64) : sizeof(c128);
     p->apply_chain_bytes = p->apply_gemv_bytes = p->apply_stage1_bytes = p->apply_final_bytes = 0;
     p->chain_launches = p->gemv_launches = 0;
@@ -1206,7 +1244,10 @@ int setup_impl(lsw_plan* p, const double* d_m, double omega, double h, const lsw
                 const int m = s.mid;
                 const double blocks = std::max(0, m - d.kf0) + std::max(0, d.kf1 - m) + 1 +
                                       std::max(0, m - d.kb0) + std::max(0, d.kb1 - m);
-                const double bytes = blocks * s.W * (double)s.W * eb;
+                // full blocks W^2 entries; packed blocks (floor(W/2) + 1) W (the wrap copies of a
+                // packed row are not counted)
+                const double per = p->gsym ? (sym_D(s.W) + 1.0) * s.W : s.W * (double)s.W;
+                const double bytes = blocks * per * eb;
                 p->apply_chain_bytes += bytes;
                 if (&f == &p->fronts.front()) p->apply_stage1_bytes += bytes;
                 else if (&f == &p->fronts.back()) p->apply_final_bytes += bytes;
@@ -1457,7 +1498,25 @@ int setup_impl(lsw_plan* p, const double* d_m, double omega, double h, const lsw
         }
         p->t_q_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tq).count();
     }
-    if (p->precision == LSW_MIXED) {
+    if (p->gsym) {
+        if (p->precision == LSW_MIXED) {
+            c64* GS = nullptr;
+            if ((rc = dalloc(p, &GS, p->GS_elems)) != LSW_OK) return rc;
+            p->d_Gs = GS;
+        } else {
+            c128* GS = nullptr;
+            if ((rc = dalloc(p, &GS, p->GS_elems)) != LSW_OK) return rc;
+            p->d_Gs = GS;
+        }
+        HIPCK(p, launch_pack_sym(p->d_subs, (int)p->subs.size(), G128, p->d_Gs, p->precision == LSW_MIXED, p->stream));
+        HIPCK(p, hipStreamSynchronize(p->stream));
+    }
+    // the full blocks stay for several right-hand sides per workgroup (and wherever no packed copy exists)
+    const bool keep_full = !p->gsym || p->nrhs_max > 1;
+    if (!keep_full) {
+        dfree(p, G128);
+        p->d_G = nullptr;
+    } else if (p->precision == LSW_MIXED) {
         c64* G64 = nullptr;
         if ((rc = dalloc(p, &G64, p->G_elems)) != LSW_OK) return rc;
         HIPCK(p, launch_cast(G128, G64, p->G_elems, p->stream));
@@ -1616,6 +1675,8 @@ int lsw_query(lsw_handle_t p, lsw_stats_t* st) {
     st->last_final_rhs_ms = p->last_final_rhs_ms;
     st->rhs_per_workgroup = p->rgroup;
     for (int i = 0; i < 3; ++i) st->tune_ms[i] = p->rgroup_ms[i];
+    st->symmetric_factors = p->gsym ? 1 : 0;
+    st->packed_factor_elems = p->gsym ? (long long)p->GS_elems : 0;
     return LSW_OK;
 }
 

@@ -877,6 +877,359 @@ __global__ __launch_bounds__(1024) void k_chain_mr(ChainArgs a) {
     }
 }
 
+// ------------------------------------------------------------------ K4 on packed symmetric factors
+// Two consecutive complex values (entries t and t+1 of a packed row) in one load.
+template <typename T>
+struct Pair {
+    cx<T> a, b;
+};
+template <typename T>
+__device__ inline Pair<T> bload2(__amdgpu_buffer_rsrc_t r, uint32_t off);
+template <>
+__device__ inline Pair<float> bload2<float>(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+    return __builtin_bit_cast(Pair<float>, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+}
+template <>
+__device__ inline Pair<double> bload2<double>(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+    return Pair<double>{bload<double>(r, off), bload<double>(r, off + 16u)};
+}
+
+// Sum over the 4 lanes of a quad (lanes 4i..4i+3), by DPP quad permutations.
+__device__ inline float quad_sum(float x) {
+    x += __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, x), 0xB1, 0xF, 0xF, false));
+    x += __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, x), 0x4E, 0xF, 0xF, false));
+    return x;
+}
+template <int CTRL>
+__device__ inline double dpp_f64(double v) {
+    const long long b = __builtin_bit_cast(long long, v);
+    const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffff), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ inline double quad_sum(double x) {
+    x += dpp_f64<0xB1>(x);   // quad_perm [1, 0, 3, 2]
+    x += dpp_f64<0x4E>(x);   // quad_perm [2, 3, 0, 1]
+    return x;
+}
+
+// The twisted block substitution of k_chain (stage 1 and final solves, one right-hand side per
+// workgroup) with the factors in the packed symmetric layout (sym_D / sym_L): half the bytes
+// per block.  Thread tid < NA = NG*P (P = ceil(W/2) row pairs) owns rows t0 = 2*(tid % P) and
+// t0 + 1 and the packed rows d = tid / P + NG*j (j < EPT, d <= D).  Per j it loads the pair
+//   A = P[d][t0], P[d][t0+1]   (G[t][t+d] of its own rows; one 16-byte load in complex64)
+// into a register ring that keeps PD blocks in flight, copies the block in use to LDS (Gl), and
+// after the barrier reads from there the pair
+//   B = P[d][t0-d], P[d][t0+1-d]   (G[t-d][t] = G[t][t-d], written by another thread).
+// Row t's partial sum goes to part[d-group][t]; RS = 4 lanes reduce one row (LDS, then DPP).
+// Scheduling barriers keep the issue order of the loads, so each wait covers the block in use.
+template <typename T, int EPT, int PD, int CS, int PH>
+__global__ __launch_bounds__(1024) void k_chain_sym(ChainArgs a) {
+    static_assert(CS == CS_STAGE1 || CS == CS_FINAL, "stage 1 and final solves only");
+    constexpr int NT = 1024, RS = 4;
+    extern __shared__ __align__(16) unsigned char dyn[];
+    cx<T>* Gl = reinterpret_cast<cx<T>*>(dyn);   // the packed block in use (sym_block(W) entries)
+    const int sidx = blockIdx.x >> 1, h = blockIdx.x & 1, nsol = gridDim.x >> 1;
+    const SolveDesc& dref = a.descs[sidx];
+    const int kf0 = dref.kf0, kf1 = dref.kf1, kb0 = dref.kb0, kb1 = dref.kb1;
+    const SubDesc s = a.subs[dref.sub];
+    const int rhs = blockIdx.y;
+    const int W = s.W, H = s.H, m = s.mid, tid = threadIdx.x;
+    const int D = sym_D(W), Ls = sym_L(W);
+    const uint32_t BSb = (uint32_t)sym_block(W) * (uint32_t)sizeof(cx<T>);   // bytes per block
+    const int P = (W + 1) >> 1, NG = NT / P, NA = NG * P;
+    const bool act = tid < NA;
+    const int dg = act ? tid / P : 0;
+    const int t0 = act ? 2 * (tid - dg * P) : 0;
+    const bool two = act && t0 + 1 < W;
+    // row t = tid / RS is reduced by threads RS*t .. RS*t + RS-1; the first of them owns it
+    const int tr = min(tid / RS, W - 1), rq = tid % RS;
+    const bool mine = rq == 0 && tid / RS < W;
+    __shared__ cx<T> v[kMaxWindow + 1];   // v[kMaxWindow] stays zero
+    __shared__ cx<T> part[2 * NT];        // part[g * W + t], g < NG (NG * W <= 2 NT)
+    __shared__ c128 a2h[kMaxWindow + 1];
+    __shared__ c128 iax[kMaxWindow];
+
+    const c128* tab = a.geo.tab;
+    const double ih2 = 1.0 / (a.geo.h * a.geo.h);
+    for (int k = tid; k <= H; k += NT) a2h[k] = tab[s.ty + H + k];   // alpha_y at the half points
+    for (int c = tid; c < W; c += NT) iax[c] = tab[s.tx + c];          // 1/alpha_x at the points
+    if (tid == 0) v[kMaxWindow] = cx<T>{T(0), T(0)};
+    const cx<T>* Gs = reinterpret_cast<const cx<T>*>(a.G) + s.gs_off;
+    cx<T>* Yg = reinterpret_cast<cx<T>*>(a.Y) + ((size_t)rhs * nsol + sidx) * a.Y_stride;
+    const size_t N = (size_t)a.geo.Nx * a.geo.Ny;
+    auto zero = []() { return cx<T>{T(0), T(0)}; };
+    // coupling of block rows l and l+1 at my row (from LDS: no global load older than the ring
+    // is left for the loop to wait on)
+    auto cy = [&](int l) { return cvt<T>(-ih2 * (a2h[l + 1] * iax[tr])); };
+
+    constexpr bool from_r = CS == CS_STAGE1;
+    const c128* rptr = from_r ? a.r + (size_t)rhs * N : a.fw + (size_t)rhs * a.fw_stride + s.fw_off;
+    const __amdgpu_buffer_rsrc_t rsrc = make_rsrc(rptr, (uint32_t)((from_r ? N : (size_t)H * W) * sizeof(c128)));
+    // only the row owners read right-hand sides and y (the other lanes read nothing)
+    const uint32_t rbase = mine ? (uint32_t)((from_r ? (size_t)s.wy0 * a.geo.Nx + s.wx0 + tr : (size_t)tr) * sizeof(c128))
+                                : kOob;
+    const uint32_t rstep = mine ? (uint32_t)((from_r ? (size_t)a.geo.Nx : (size_t)W) * sizeof(c128)) : 0u;
+    const __amdgpu_buffer_rsrc_t grsrc = make_rsrc(Gs, (uint32_t)H * BSb);
+    const __amdgpu_buffer_rsrc_t yrsrc = make_rsrc(Yg, (uint32_t)((size_t)H * W * sizeof(cx<T>)));
+    const bool in_cols = mine && tr >= s.c0 && tr < s.c1;
+    auto rhs_use = [&](int k, c128 raw) -> cx<T> {
+        if (k < kf0 || k > kf1) return zero();
+        if constexpr (CS == CS_FINAL) return mine ? cvt<T>(raw) : zero();
+        return (in_cols && k >= s.r0 && k < s.r1) ? cvt<T>(raw) : zero();
+    };
+    auto rhs_load = [&](int k) -> c128 { return bload<double>(rsrc, rbase + (uint32_t)k * rstep); };
+    auto yload = [&](int k) -> cx<T> {
+        return bload<T>(yrsrc, mine ? (uint32_t)(k * W + tr) * (uint32_t)sizeof(cx<T>) : kOob);
+    };
+
+    // per packed row of this thread: its entry in a block, the LDS slots of its B pair, and the
+    // v slots that multiply A.a, A.b, B.a, B.b (the zero slot where the term does not exist)
+    // (two 16-bit indices per register: entries < sym_block(256) < 2^16, v slots <= kMaxWindow)
+    int ae[EPT];
+    uint32_t be[EPT], va[EPT], vb[EPT];
+    auto lo16 = [](uint32_t x) { return (int)(x & 0xffffu); };
+    auto hi16 = [](uint32_t x) { return (int)(x >> 16); };
+#pragma unroll
+    for (int j = 0; j < EPT; ++j) {
+        const int d = dg + NG * j;
+        const bool ok = act && d <= D;
+        const bool col = ok && d >= 1 && !((W & 1) == 0 && d == D);
+        int tm = (t0 - d) % W;
+        if (tm < 0) tm += W;
+        const int tm1 = tm + 1 == W ? 0 : tm + 1;
+        ae[j] = ok ? d * Ls + t0 : -1;
+        be[j] = ok ? (uint32_t)(d * Ls + tm) | ((uint32_t)(d * Ls + tm1) << 16) : 0u;
+        va[j] = (uint32_t)(ok ? (t0 + d) % W : kMaxWindow) | ((uint32_t)(ok && two ? (t0 + 1 + d) % W : kMaxWindow) << 16);
+        vb[j] = (uint32_t)(col ? tm : kMaxWindow) | ((uint32_t)(col && two ? tm1 : kMaxWindow) << 16);
+    }
+    struct Slot {
+        Pair<T> A[EPT];
+    };
+    auto load = [&](int k, Slot& sl) {
+        const uint32_t kb = (uint32_t)k * BSb;
+#pragma unroll
+        for (int j = 0; j < EPT; ++j)
+            sl.A[j] = bload2<T>(grsrc, ae[j] >= 0 ? kb + (uint32_t)ae[j] * (uint32_t)sizeof(cx<T>) : kOob);
+    };
+    // the block in use to LDS (before the first barrier of a step)
+    auto stage = [&](const Slot& sl) {
+#pragma unroll
+        for (int j = 0; j < EPT; ++j)
+            if (ae[j] >= 0) {
+                Gl[ae[j]] = sl.A[j].a;
+                Gl[ae[j] + 1] = sl.A[j].b;
+            }
+    };
+    // part[dg][t] = this thread's terms of (G_k v)_t, t = t0, t0+1 (after the first barrier)
+    auto gemv = [&](const Slot& sl) {
+        cx<T> acc0 = zero(), acc1 = zero();
+#pragma unroll
+        for (int j = 0; j < EPT; ++j) {
+            const cx<T> B0 = Gl[lo16(be[j])], B1 = Gl[hi16(be[j])];
+            acc0 = acc0 + sl.A[j].a * v[lo16(va[j])] + B0 * v[lo16(vb[j])];
+            acc1 = acc1 + sl.A[j].b * v[hi16(va[j])] + B1 * v[hi16(vb[j])];
+        }
+        if (act) {
+            part[dg * W + t0] = acc0;
+            if (two) part[dg * W + t0 + 1] = acc1;
+        }
+    };
+    // (G_k v)_t for the row owners (every lane takes part: the quad sums are lane exchanges)
+    auto reduce = [&]() {
+        cx<T> y = zero();
+#pragma unroll 4
+        for (int g = rq; g < NG; g += RS) y = y + part[g * W + tr];
+        y.re = quad_sum(y.re);
+        y.im = quad_sum(y.im);
+        return y;
+    };
+
+    Slot ring[PD + 1];
+    c128 rr[PD + 1];
+    cx<T> yr[PD + 1];
+    cx<T> yv = zero();   // y (phase 0) or x (phase 1) of my row at the previous block row
+    __syncthreads();     // a2h, iax, zero slot
+
+    if constexpr (PH == 0) {
+        // ---- forward elimination of this half towards the middle row
+        const int kstart = h == 0 ? kf0 : kf1;
+        const int dir = h == 0 ? 1 : -1;
+        const int n = h == 0 ? m - kf0 : kf1 - m;
+        auto kat = [&](int i) { return kstart + dir * min(i, n - 1); };
+        if (n > 0) {
+#pragma unroll
+            for (int p = 0; p < PD; ++p) {
+                rr[p] = rhs_load(kat(p));
+                load(kat(p), ring[p]);
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        }
+        cx<T> gnext = zero();   // v of the next step (owners)
+        if (n > 0 && mine) gnext = rhs_use(kstart, rr[0]);
+        auto fstep = [&](int i, int u) __attribute__((always_inline)) {
+            const int k = kstart + dir * i;
+            rr[(u + PD) % (PD + 1)] = rhs_load(kat(i + PD));
+            load(kat(i + PD), ring[(u + PD) % (PD + 1)]);
+            __builtin_amdgcn_sched_barrier(0);
+            stage(ring[u]);
+            if (mine) v[tr] = gnext;
+            __syncthreads();
+            gemv(ring[u]);
+            // the next step's coupling and right-hand side while the others finish
+            const cx<T> cn = mine ? cy(h == 0 ? k : k - 1) : zero();
+            const cx<T> rn = (mine && i + 1 < n) ? rhs_use(k + dir, rr[(u + 1) % (PD + 1)]) : zero();
+            __syncthreads();
+            const cx<T> y = reduce();
+            if (mine) {
+                yv = y;
+                Yg[(size_t)k * W + tr] = y;
+                gnext = rn - cn * y;
+            }
+        };
+        int i0 = 0;
+        for (; i0 + PD < n; i0 += PD + 1) {
+#pragma unroll
+            for (int u = 0; u <= PD; ++u) fstep(i0 + u, u);
+        }
+#pragma unroll
+        for (int u = 0; u < PD; ++u)
+            if (i0 + u < n) fstep(i0 + u, u);
+        return;
+    }
+
+    // ---- phase 1: middle row, then back substitution of this half away from it
+    {
+        Slot gm;
+        load(m, gm);
+        const c128 rm = rhs_load(m);
+        const cx<T> ylo = (kf0 <= m - 1) ? yload(m - 1) : zero();
+        const cx<T> yhi = (kf1 >= m + 1) ? yload(m + 1) : zero();
+        stage(gm);
+        if (mine) {
+            cx<T> g = rhs_use(m, rm);
+            if (m >= 1) g = g - cy(m - 1) * ylo;
+            if (m + 1 <= H - 1) g = g - cy(m) * yhi;
+            v[tr] = g;
+        }
+        __syncthreads();
+        gemv(gm);
+        __syncthreads();
+        const cx<T> y = reduce();
+        if (mine) {
+            yv = y;
+            Yg[(size_t)H * W + (size_t)m * W + tr] = y;
+        }
+    }
+    {
+        const int kstart = h == 0 ? m - 1 : m + 1;
+        const int dir = h == 0 ? -1 : 1;
+        const int n = h == 0 ? m - kb0 : kb1 - m;
+        auto kat = [&](int i) { return kstart + dir * min(i, n - 1); };
+        __syncthreads();   // every gemv of the middle row has read Gl
+        __builtin_amdgcn_sched_barrier(0);
+        if (n > 0) {
+#pragma unroll
+            for (int p = 0; p < PD; ++p) {
+                yr[p] = yload(kat(p));
+                load(kat(p), ring[p]);
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        }
+        cx<T> vnext = zero();
+        if (n > 0 && mine) vnext = cy(h == 0 ? kstart : kstart - 1) * yv;
+        auto bstep = [&](int i, int u) __attribute__((always_inline)) {
+            const int k = kstart + dir * i;
+            yr[(u + PD) % (PD + 1)] = yload(kat(i + PD));
+            load(kat(i + PD), ring[(u + PD) % (PD + 1)]);
+            __builtin_amdgcn_sched_barrier(0);
+            stage(ring[u]);
+            if (mine) v[tr] = vnext;
+            __syncthreads();
+            gemv(ring[u]);
+            const int kn = k + dir;
+            const cx<T> cn = mine ? cy(h == 0 ? kn : kn - 1) : zero();
+            // y of the bottom half is zero below kf0, that of the top half above kf1
+            const cx<T> yk = (mine && (h == 0 ? k >= kf0 : k <= kf1)) ? yr[u] : zero();
+            __syncthreads();
+            const cx<T> x = reduce();
+            if (mine) {
+                yv = yk - x;
+                Yg[(size_t)H * W + (size_t)k * W + tr] = yv;
+                vnext = cn * yv;
+            }
+        };
+        int i0 = 0;
+        for (; i0 + PD < n; i0 += PD + 1) {
+#pragma unroll
+            for (int u = 0; u <= PD; ++u) bstep(i0 + u, u);
+        }
+#pragma unroll
+        for (int u = 0; u < PD; ++u)
+            if (i0 + u < n) bstep(i0 + u, u);
+    }
+    __syncthreads();
+
+    // ---- outputs of the block rows this half owns
+    const int olo = h == 0 ? kb0 : max(kb0, m + 1);
+    const int ohi = h == 0 ? min(kb1, m) : kb1;
+    const cx<T>* X = Yg + (size_t)H * W;
+    if constexpr (CS == CS_FINAL) {
+        const int r0 = max(s.r0, olo), r1 = min(s.r1, ohi + 1);
+        const int nc = s.c1 - s.c0, n = max(0, r1 - r0) * nc;
+        c128* z = a.z + (size_t)rhs * N + (size_t)(s.wy0 + r0) * a.geo.Nx + s.wx0 + s.c0;
+        for (int idx = tid; idx < n; idx += NT) {
+            const int rr0 = idx / nc, cc = idx - rr0 * nc;
+            z[(size_t)rr0 * a.geo.Nx + cc] = cvt<double>(X[(size_t)(r0 + rr0) * W + s.c0 + cc]);
+        }
+    } else {
+        cx<T>* trp = reinterpret_cast<cx<T>*>(a.traces) + (size_t)rhs * a.trace_stride;
+        auto own = [&](int k) { return k >= olo && k <= ohi; };
+        for (int o = 0; o < dref.nout; ++o) {
+            const int side = dref.out_side[o];
+            cx<T>* out = trp + dref.out_off[o];
+            const bool acc = dref.out_acc[o] != 0;
+            if (side == SIDE_B || side == SIDE_T) {
+                const int l0 = (side == SIDE_B) ? s.r0 - 1 : s.r1 - 1;
+                for (int idx = tid; idx < 2 * W; idx += NT) {
+                    const int line = idx / W, c = idx - line * W;
+                    if (!own(l0 + line)) continue;
+                    const cx<T> xv = X[(size_t)(l0 + line) * W + c];
+                    out[idx] = acc ? out[idx] + xv : xv;
+                }
+            } else {
+                const int l0 = (side == SIDE_L) ? s.c0 - 1 : s.c1 - 1;
+                for (int idx = tid; idx < 2 * H; idx += NT) {
+                    const int line = idx / H, k = idx - line * H;
+                    if (!own(k)) continue;
+                    const cx<T> xv = X[(size_t)k * W + l0 + line];
+                    out[idx] = acc ? out[idx] + xv : xv;
+                }
+            }
+        }
+    }
+}
+
+// Packed symmetric copy of the FP64 factor pool, rounded to T: P[d][i] of block k of window n
+// is the mean of G_k[t][c] and G_k[c][t], t = i mod W, c = (t + d) mod W (the computed inverse
+// is symmetric up to rounding; the mean is the nearest symmetric matrix).
+template <typename T>
+__global__ void k_pack_sym(const SubDesc* subs, const c128* G, cx<T>* Gp) {
+    const SubDesc s = subs[blockIdx.y];
+    const int W = s.W, H = s.H, Ls = sym_L(W);
+    const long long per = sym_block(W), total = per * H;
+    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (long long)gridDim.x * blockDim.x) {
+        const int k = (int)(e / per);
+        const int rem = (int)(e - (long long)k * per);
+        const int d = rem / Ls, i = rem - d * Ls;
+        const int t = i < W ? i : i - W;
+        const int c = (t + d) % W;
+        const c128* Gk = G + s.g_off + (size_t)k * W * W;   // column-major: (row t, col c) at c*W + t
+        const c128 g = 0.5 * (Gk[(size_t)c * W + t] + Gk[(size_t)t * W + c]);
+        Gp[s.gs_off + e] = cvt<T>(g);
+    }
+}
+
 // Right-hand side of the final z solve of each window: r on Omega_ij plus the polarized
 // sources g_s of all its sweep solves.  Every incoming trace keeps, after the application, the
 // value its sweep solve read (each is written before it is consumed and never after), so the
@@ -1382,6 +1735,63 @@ hipError_t launch_chain_mr(const ChainArgs& a, int nsolves, int nrhs, int ept, b
     if ((cs != 0 && cs != 1) || (rgroup != 2 && rgroup != 4)) return hipErrorInvalidValue;
     return c64mode ? launch_chain_mr_t<float>(a, nsolves, nrhs, ept, cs, rgroup, st)
                    : launch_chain_mr_t<double>(a, nsolves, nrhs, ept, cs, rgroup, st);
+}
+
+// register ring of k_chain_sym: 4 VGPRs per complex64 pair and 8 per complex128 pair, PD
+// blocks in flight within about 64 VGPRs
+template <typename T, int CS, int PH, typename F>
+static void sym_dispatch(int ept, F&& f) {
+    if constexpr (sizeof(T) == 4) {
+        if (ept <= 1) f(k_chain_sym<T, 1, 4, CS, PH>);
+        else if (ept <= 2) f(k_chain_sym<T, 2, 4, CS, PH>);
+        else f(k_chain_sym<T, 4, 2, CS, PH>);
+    } else {
+        if (ept <= 1) f(k_chain_sym<T, 1, 4, CS, PH>);
+        else f(k_chain_sym<T, 2, 2, CS, PH>);
+    }
+}
+
+int sym_max_ept(bool c64mode) { return c64mode ? 4 : 2; }
+
+hipError_t prepare_chain_sym(int ept, bool c64mode, size_t lds) {
+    hipError_t e = hipSuccess;
+    auto set = [&](auto kern) {
+        if (e == hipSuccess)
+            e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    };
+    if (c64mode) {
+        sym_dispatch<float, CS_STAGE1, 0>(ept, set); sym_dispatch<float, CS_STAGE1, 1>(ept, set);
+        sym_dispatch<float, CS_FINAL, 0>(ept, set); sym_dispatch<float, CS_FINAL, 1>(ept, set);
+    } else {
+        sym_dispatch<double, CS_STAGE1, 0>(ept, set); sym_dispatch<double, CS_STAGE1, 1>(ept, set);
+        sym_dispatch<double, CS_FINAL, 0>(ept, set); sym_dispatch<double, CS_FINAL, 1>(ept, set);
+    }
+    return e;
+}
+
+hipError_t launch_chain_sym(const ChainArgs& a, int nsolves, int nrhs, int ept, bool c64mode, int cs, size_t lds,
+                            hipStream_t st) {
+    if ((cs != CS_STAGE1 && cs != CS_FINAL) || ept < 1 || ept > sym_max_ept(c64mode)) return hipErrorInvalidValue;
+    dim3 grid(2 * nsolves, nrhs);
+    auto go = [&](auto kern) { kern<<<grid, 1024, lds, st>>>(a); };
+#define LSW_GO(T, CSV, PHV) if (cs == CSV) sym_dispatch<T, CSV, PHV>(ept, go);
+    if (c64mode) {
+        LSW_GO(float, CS_STAGE1, 0) LSW_GO(float, CS_FINAL, 0)
+        LSW_GO(float, CS_STAGE1, 1) LSW_GO(float, CS_FINAL, 1)
+    } else {
+        LSW_GO(double, CS_STAGE1, 0) LSW_GO(double, CS_FINAL, 0)
+        LSW_GO(double, CS_STAGE1, 1) LSW_GO(double, CS_FINAL, 1)
+    }
+#undef LSW_GO
+    return hipGetLastError();
+}
+
+hipError_t launch_pack_sym(const SubDesc* subs, int nsub, const c128* G, void* Gp, bool c64mode, hipStream_t st) {
+    if (nsub <= 0) return hipSuccess;
+    dim3 grid(256, nsub);
+    if (c64mode) k_pack_sym<float><<<grid, 256, 0, st>>>(subs, G, reinterpret_cast<c64*>(Gp));
+    else k_pack_sym<double><<<grid, 256, 0, st>>>(subs, G, reinterpret_cast<c128*>(Gp));
+    return hipGetLastError();
 }
 
 hipError_t launch_gemv(const GemvArgs& a, bool c64mode, hipStream_t st) {

@@ -71,7 +71,8 @@ class lsw_stats_t(ctypes.Structure):
                 ("apply_stage1_bytes", ctypes.c_double), ("apply_final_bytes", ctypes.c_double),
                 ("last_stage1_ms", ctypes.c_double), ("last_final_ms", ctypes.c_double),
                 ("last_final_rhs_ms", ctypes.c_double), ("rhs_per_workgroup", ctypes.c_int),
-                ("tune_ms", ctypes.c_double * 3)]
+                ("tune_ms", ctypes.c_double * 3), ("symmetric_factors", ctypes.c_int),
+                ("packed_factor_elems", ctypes.c_longlong)]
 
 
 _lib = None
