@@ -30,6 +30,22 @@ __host__ __device__ inline cx<T> operator*(cx<T> a, cx<T> b) {
 }
 template <typename T>
 __host__ __device__ inline cx<T> operator*(T s, cx<T> a) { return {s * a.re, s * a.im}; }
+// acc + a b as four fused multiply-adds
+template <typename T>
+__host__ __device__ inline cx<T> cmac(cx<T> acc, cx<T> a, cx<T> b) {
+    if constexpr (sizeof(T) == 4) {
+        acc.re = __builtin_fmaf(a.re, b.re, acc.re);
+        acc.re = __builtin_fmaf(-a.im, b.im, acc.re);
+        acc.im = __builtin_fmaf(a.re, b.im, acc.im);
+        acc.im = __builtin_fmaf(a.im, b.re, acc.im);
+    } else {
+        acc.re = __builtin_fma(a.re, b.re, acc.re);
+        acc.re = __builtin_fma(-a.im, b.im, acc.re);
+        acc.im = __builtin_fma(a.re, b.im, acc.im);
+        acc.im = __builtin_fma(a.im, b.re, acc.im);
+    }
+    return acc;
+}
 template <typename T>
 __host__ __device__ inline cx<T> conj(cx<T> a) { return {a.re, -a.im}; }
 template <typename T>
@@ -98,16 +114,18 @@ struct SubDesc {
 };
 
 // Packed storage of a complex symmetric W x W block G (G = G^T).  A = A^T makes every Schur
-// complement of the block elimination symmetric, and so every inverse G_k.  For d = 0..D,
-// D = floor(W/2), and t = 0..W-1 the entry P[d][t] = G[t][(t + d) mod W] sits at d*Ls + t:
-// every unordered pair {t, c} is stored once (the W/2 pairs at d = W/2 of an even W twice).
-// A row of Ls (even) entries ends with copies of its first Ls - W entries, so that two
-// consecutive entries are one load even across the wrap.  With all indices mod W,
-//   (G v)_t = sum_{d=0..D} P[d][t] v[t + d] + sum_{d in Dc} P[d][t - d] v[t - d],
-// Dc = {1..D} without W/2 for even W.
-__host__ __device__ inline int sym_D(int W) { return W / 2; }
-__host__ __device__ inline int sym_L(int W) { return W + 2 - (W & 1); }
-__host__ __device__ inline long long sym_block(int W) { return (long long)(sym_D(W) + 1) * sym_L(W); }
+// complement of the block elimination symmetric, and so every inverse G_k.  The upper triangle
+// is cut into 4x4 tiles: nt = ceil(W/4) tile rows, tiles (I, J) with I <= J numbered
+// tau = I nt - I (I - 1) / 2 + (J - I), NTL = nt (nt + 1) / 2 of them.  Tile tau holds
+// G[4I+i][4J+j] (zero outside the W x W block; diagonal tiles in full); its entry q = 4i + j
+// sits at (q / 2) * 2 NTL + 2 tau + q % 2, so that the entry pair u (q = 2u, 2u+1) of
+// consecutive tiles is contiguous.  With c[J][r] = sum over tile column J of G[r][.] v[.],
+//   (G v)_r = sum_J c[J][r],  c[J][4I+i] = (tile (I,J) v_J)_i  (I <= J),  (tile (J,I)^T v_J)_i  (I > J).
+__host__ __device__ inline int tile_nt(int W) { return (W + 3) / 4; }
+__host__ __device__ inline int tile_count(int W) { return tile_nt(W) * (tile_nt(W) + 1) / 2; }
+__host__ __device__ inline long long sym_block(int W) { return 16LL * tile_count(W); }
+// row stride of the per-tile-column partial sums in the substitution kernel (4 mod 16 entries)
+__host__ __device__ inline int sym_cstride(int W) { return 4 * tile_nt(W) + ((4 - 4 * tile_nt(W)) % 16 + 16) % 16; }
 
 // Layout of one axis table of a window with P points (offset t in the table pool):
 //   t + a        : 1/alpha at integer point a            (a = 0..P-1)

@@ -99,7 +99,7 @@ struct lsw_plan {
     // per workgroup read these; d_G (full blocks) stays only where something else needs it
     bool gsym = false;
     int sym_ept = 0;                // packed rows per thread (max over the windows)
-    size_t sym_lds = 0;             // dynamic LDS of the packed substitutions: the largest packed block
+    size_t sym_lds = 0;             // dynamic LDS of the packed substitutions: the widest window's column sums
     void* d_Gs = nullptr;
     size_t GS_elems = 0;
     void* d_traces = nullptr;
@@ -1169,7 +1169,7 @@ int setup_impl(lsw_plan* p, const double* d_m, double omega, double h, const lsw
             s.gs_off = (long long)p->GS_elems;
             p->GS_elems += (size_t)s.H * sym_block(s.W);
             p->sym_ept = std::max(p->sym_ept, sym_ept(s.W));
-            p->sym_lds = std::max(p->sym_lds, (size_t)sym_block(s.W));
+            p->sym_lds = std::max(p->sym_lds, (size_t)tile_nt(s.W) * sym_cstride(s.W));   // column sums c
             const size_t S3 = (size_t)s.W * s.H;
             p->G_elems += p->dim == 3 ? (size_t)p->Nz * S3 * S3 : (size_t)s.H * s.W * s.W;
             p->Smax = std::max(p->Smax, (int)S3);
@@ -1205,8 +1205,8 @@ int setup_impl(lsw_plan* p, const double* d_m, double omega, double h, const lsw
         const bool mixed = p->precision == LSW_MIXED;
         const size_t eb = mixed ? sizeof(c64) : sizeof(c128);
         p->sym_lds *= eb;
-        // static LDS of the kernel: v, part, the y and x coefficient tables
-        const size_t stat = eb * (kMaxWindow + 1 + 2048) + sizeof(c128) * (2 * kMaxWindow + 1) + 256;
+        // static LDS of the kernel: v and the y and x coefficient tables
+        const size_t stat = eb * (kMaxWindow + 4) + sizeof(c128) * (2 * kMaxWindow + 1) + 256;
         int dev = 0, max_lds = 0;
         HIPCK(p, hipGetDevice(&dev));
         HIPCK(p, hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
@@ -1244,9 +1244,8 @@ int setup_impl(lsw_plan* p, const double* d_m, double omega, double h, const lsw
                 const int m = s.mid;
                 const double blocks = std::max(0, m - d.kf0) + std::max(0, d.kf1 - m) + 1 +
                                       std::max(0, m - d.kb0) + std::max(0, d.kb1 - m);
-                // full blocks W^2 entries; packed blocks (floor(W/2) + 1) W (the wrap copies of a
-                // packed row are not counted)
-                const double per = p->gsym ? (sym_D(s.W) + 1.0) * s.W : s.W * (double)s.W;
+                // full blocks W^2 entries; packed blocks 16 per 4x4 tile of the upper triangle
+                const double per = p->gsym ? (double)sym_block(s.W) : s.W * (double)s.W;
                 const double bytes = blocks * per * eb;
                 p->apply_chain_bytes += bytes;
                 if (&f == &p->fronts.front()) p->apply_stage1_bytes += bytes;

@@ -893,11 +893,24 @@ template <>
 __device__ inline Pair<double> bload2<double>(__amdgpu_buffer_rsrc_t r, uint32_t off) {
     return Pair<double>{bload<double>(r, off), bload<double>(r, off + 16u)};
 }
+// the same with a uniform part of the offset in the scalar operand: voff alone past the buffer
+// size reads zeros whether or not the range check adds soff
+template <typename T>
+__device__ inline Pair<T> bload2s(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff);
+template <>
+__device__ inline Pair<float> bload2s<float>(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+    return __builtin_bit_cast(Pair<float>, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
+}
+template <>
+__device__ inline Pair<double> bload2s<double>(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+    return Pair<double>{__builtin_bit_cast(cx<double>, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0)),
+                        __builtin_bit_cast(cx<double>, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff + 16u, 0))};
+}
 
-// Sum over the 4 lanes of a quad (lanes 4i..4i+3), by DPP quad permutations.
-__device__ inline float quad_sum(float x) {
-    x += __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, x), 0xB1, 0xF, 0xF, false));
-    x += __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, x), 0x4E, 0xF, 0xF, false));
+// Sum over groups of RS = 1, 2 or 4 neighbouring lanes (RS uniform), by DPP quad permutations.
+__device__ inline float lane_sum(float x, int RS) {
+    if (RS >= 2) x += __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, x), 0xB1, 0xF, 0xF, false));
+    if (RS >= 4) x += __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, x), 0x4E, 0xF, 0xF, false));
     return x;
 }
 template <int CTRL>
@@ -907,61 +920,56 @@ __device__ inline double dpp_f64(double v) {
     const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xF, 0xF, false);
     return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
 }
-__device__ inline double quad_sum(double x) {
-    x += dpp_f64<0xB1>(x);   // quad_perm [1, 0, 3, 2]
-    x += dpp_f64<0x4E>(x);   // quad_perm [2, 3, 0, 1]
+__device__ inline double lane_sum(double x, int RS) {
+    if (RS >= 2) x += dpp_f64<0xB1>(x);   // quad_perm [1, 0, 3, 2]
+    if (RS >= 4) x += dpp_f64<0x4E>(x);   // quad_perm [2, 3, 0, 1]
     return x;
 }
 
 // The twisted block substitution of k_chain (stage 1 and final solves, one right-hand side per
-// workgroup) with the factors in the packed symmetric layout (sym_D / sym_L): half the bytes
-// per block.  Thread tid < NA = NG*P (P = ceil(W/2) row pairs) owns rows t0 = 2*(tid % P) and
-// t0 + 1 and the packed rows d = tid / P + NG*j (j < EPT, d <= D).  Per j it loads the pair
-//   A = P[d][t0], P[d][t0+1]   (G[t][t+d] of its own rows; one 16-byte load in complex64)
-// into a register ring that keeps PD blocks in flight, copies the block in use to LDS (Gl), and
-// after the barrier reads from there the pair
-//   B = P[d][t0-d], P[d][t0+1-d]   (G[t-d][t] = G[t][t-d], written by another thread).
-// Row t's partial sum goes to part[d-group][t]; RS = 4 lanes reduce one row (LDS, then DPP).
-// Scheduling barriers keep the issue order of the loads, so each wait covers the block in use.
-template <typename T, int EPT, int PD, int CS, int PH>
-__global__ __launch_bounds__(1024) void k_chain_sym(ChainArgs a) {
+// workgroup) on the factors in the packed symmetric tile layout (tile_nt / sym_block): about
+// half the bytes of the full blocks.  256 lanes; lane l holds the tiles tau = l + 256 m
+// (m < TPL).  For its tile (I, J) it forms the row sums A v_J (into c[J][4I..4I+3]) and, off the
+// diagonal, the column sums A^T v_I (into c[I][4J..4J+3]), so every entry read from HBM is used
+// twice from registers.  c (LDS, [nt][4 nt]) is then summed over J by RS lanes per row (LDS
+// reads, then DPP).  A register ring keeps PD blocks in flight; scheduling barriers keep the
+// issue order of the loads, so each wait covers only the block in use.
+template <typename T, int TPL, int PD, int CS, int PH>
+__global__ __launch_bounds__(256) void k_chain_sym(ChainArgs a) {
     static_assert(CS == CS_STAGE1 || CS == CS_FINAL, "stage 1 and final solves only");
-    constexpr int NT = 1024, RS = 4;
+    constexpr int NT = 256;
     extern __shared__ __align__(16) unsigned char dyn[];
-    cx<T>* Gl = reinterpret_cast<cx<T>*>(dyn);   // the packed block in use (sym_block(W) entries)
+    cx<T>* cs = reinterpret_cast<cx<T>*>(dyn);   // c[J][r] at J * Wp + r
     const int sidx = blockIdx.x >> 1, h = blockIdx.x & 1, nsol = gridDim.x >> 1;
     const SolveDesc& dref = a.descs[sidx];
     const int kf0 = dref.kf0, kf1 = dref.kf1, kb0 = dref.kb0, kb1 = dref.kb1;
     const SubDesc s = a.subs[dref.sub];
     const int rhs = blockIdx.y;
     const int W = s.W, H = s.H, m = s.mid, tid = threadIdx.x;
-    const int D = sym_D(W), Ls = sym_L(W);
+    // c rows are Wp apart, Wp = 4 (mod 16) entries: the 4 row sums of consecutive tiles (J, J+1,
+    // ...) land in different LDS banks
+    const int nt = tile_nt(W), Wp = sym_cstride(W), NTL = tile_count(W);
     const uint32_t BSb = (uint32_t)sym_block(W) * (uint32_t)sizeof(cx<T>);   // bytes per block
-    const int P = (W + 1) >> 1, NG = NT / P, NA = NG * P;
-    const bool act = tid < NA;
-    const int dg = act ? tid / P : 0;
-    const int t0 = act ? 2 * (tid - dg * P) : 0;
-    const bool two = act && t0 + 1 < W;
-    // row t = tid / RS is reduced by threads RS*t .. RS*t + RS-1; the first of them owns it
+    // the reduction of row t: lanes RS t .. RS t + RS-1; the first of them owns the row
+    const int RS = W <= 64 ? 4 : (W <= 128 ? 2 : 1);
     const int tr = min(tid / RS, W - 1), rq = tid % RS;
     const bool mine = rq == 0 && tid / RS < W;
-    __shared__ cx<T> v[kMaxWindow + 1];   // v[kMaxWindow] stays zero
-    __shared__ cx<T> part[2 * NT];        // part[g * W + t], g < NG (NG * W <= 2 NT)
-    __shared__ c128 a2h[kMaxWindow + 1];
-    __shared__ c128 iax[kMaxWindow];
+    __shared__ __align__(16) cx<T> v[kMaxWindow + 4];   // zero past W
+    __shared__ cx<T> ay[kMaxWindow];                      // -alpha_y(l + 1/2) / h^2, l < H - 1
+    __shared__ cx<T> ax[kMaxWindow];                      // 1/alpha_x at the points
 
     const c128* tab = a.geo.tab;
     const double ih2 = 1.0 / (a.geo.h * a.geo.h);
-    for (int k = tid; k <= H; k += NT) a2h[k] = tab[s.ty + H + k];   // alpha_y at the half points
-    for (int c = tid; c < W; c += NT) iax[c] = tab[s.tx + c];          // 1/alpha_x at the points
-    if (tid == 0) v[kMaxWindow] = cx<T>{T(0), T(0)};
+    for (int l = tid; l < H - 1; l += NT) ay[l] = cvt<T>(-ih2 * tab[s.ty + H + l + 1]);
+    for (int c = tid; c < W; c += NT) ax[c] = cvt<T>(tab[s.tx + c]);
+    for (int c = W + tid; c < 4 * nt; c += NT) v[c] = cx<T>{T(0), T(0)};
     const cx<T>* Gs = reinterpret_cast<const cx<T>*>(a.G) + s.gs_off;
     cx<T>* Yg = reinterpret_cast<cx<T>*>(a.Y) + ((size_t)rhs * nsol + sidx) * a.Y_stride;
     const size_t N = (size_t)a.geo.Nx * a.geo.Ny;
     auto zero = []() { return cx<T>{T(0), T(0)}; };
-    // coupling of block rows l and l+1 at my row (from LDS: no global load older than the ring
-    // is left for the loop to wait on)
-    auto cy = [&](int l) { return cvt<T>(-ih2 * (a2h[l + 1] * iax[tr])); };
+    // coupling of block rows l and l+1 at my row (iax: after the first barrier)
+    cx<T> iax = zero();
+    auto cy = [&](int l) { return ay[l] * iax; };
 
     constexpr bool from_r = CS == CS_STAGE1;
     const c128* rptr = from_r ? a.r + (size_t)rhs * N : a.fw + (size_t)rhs * a.fw_stride + s.fw_off;
@@ -983,65 +991,78 @@ __global__ __launch_bounds__(1024) void k_chain_sym(ChainArgs a) {
         return bload<T>(yrsrc, mine ? (uint32_t)(k * W + tr) * (uint32_t)sizeof(cx<T>) : kOob);
     };
 
-    // per packed row of this thread: its entry in a block, the LDS slots of its B pair, and the
-    // v slots that multiply A.a, A.b, B.a, B.b (the zero slot where the term does not exist)
-    // (two 16-bit indices per register: entries < sym_block(256) < 2^16, v slots <= kMaxWindow)
-    int ae[EPT];
-    uint32_t be[EPT], va[EPT], vb[EPT];
-    auto lo16 = [](uint32_t x) { return (int)(x & 0xffffu); };
-    auto hi16 = [](uint32_t x) { return (int)(x >> 16); };
+    // my tiles: (I, J) and the byte offset of entry pair 0 in a block (kOob past the last tile)
+    int tI[TPL], tJ[TPL];
+    uint32_t toff[TPL];
 #pragma unroll
-    for (int j = 0; j < EPT; ++j) {
-        const int d = dg + NG * j;
-        const bool ok = act && d <= D;
-        const bool col = ok && d >= 1 && !((W & 1) == 0 && d == D);
-        int tm = (t0 - d) % W;
-        if (tm < 0) tm += W;
-        const int tm1 = tm + 1 == W ? 0 : tm + 1;
-        ae[j] = ok ? d * Ls + t0 : -1;
-        be[j] = ok ? (uint32_t)(d * Ls + tm) | ((uint32_t)(d * Ls + tm1) << 16) : 0u;
-        va[j] = (uint32_t)(ok ? (t0 + d) % W : kMaxWindow) | ((uint32_t)(ok && two ? (t0 + 1 + d) % W : kMaxWindow) << 16);
-        vb[j] = (uint32_t)(col ? tm : kMaxWindow) | ((uint32_t)(col && two ? tm1 : kMaxWindow) << 16);
+    for (int q = 0; q < TPL; ++q) {
+        const int tau = tid + NT * q;
+        int I = 0, start = 0;
+        while (I < nt - 1 && start + (nt - I) <= tau) {
+            start += nt - I;
+            ++I;
+        }
+        tI[q] = I;
+        tJ[q] = I + (tau - start);
+        // an idle lane's offsets lie past the buffer (every block and pair), so its loads read zeros
+        toff[q] = tau < NTL ? (uint32_t)(2 * tau) * (uint32_t)sizeof(cx<T>) : (uint32_t)H * BSb;
     }
+    const uint32_t ustep = (uint32_t)(2 * NTL) * (uint32_t)sizeof(cx<T>);   // bytes between entry pairs
     struct Slot {
-        Pair<T> A[EPT];
+        Pair<T> A[TPL][8];
     };
     auto load = [&](int k, Slot& sl) {
         const uint32_t kb = (uint32_t)k * BSb;
 #pragma unroll
-        for (int j = 0; j < EPT; ++j)
-            sl.A[j] = bload2<T>(grsrc, ae[j] >= 0 ? kb + (uint32_t)ae[j] * (uint32_t)sizeof(cx<T>) : kOob);
-    };
-    // the block in use to LDS (before the first barrier of a step)
-    auto stage = [&](const Slot& sl) {
+        for (int q = 0; q < TPL; ++q)
 #pragma unroll
-        for (int j = 0; j < EPT; ++j)
-            if (ae[j] >= 0) {
-                Gl[ae[j]] = sl.A[j].a;
-                Gl[ae[j] + 1] = sl.A[j].b;
-            }
+            for (int u = 0; u < 8; ++u)
+                sl.A[q][u] = bload2s<T>(grsrc, toff[q], kb + (uint32_t)u * ustep);
     };
-    // part[dg][t] = this thread's terms of (G_k v)_t, t = t0, t0+1 (after the first barrier)
+    // c[J][4I+i] and c[I][4J+j] of my tiles (after the first barrier: v ready)
     auto gemv = [&](const Slot& sl) {
-        cx<T> acc0 = zero(), acc1 = zero();
 #pragma unroll
-        for (int j = 0; j < EPT; ++j) {
-            const cx<T> B0 = Gl[lo16(be[j])], B1 = Gl[hi16(be[j])];
-            acc0 = acc0 + sl.A[j].a * v[lo16(va[j])] + B0 * v[lo16(vb[j])];
-            acc1 = acc1 + sl.A[j].b * v[hi16(va[j])] + B1 * v[hi16(vb[j])];
-        }
-        if (act) {
-            part[dg * W + t0] = acc0;
-            if (two) part[dg * W + t0 + 1] = acc1;
+        for (int q = 0; q < TPL; ++q) {
+            if (tid + NT * q >= NTL) continue;
+            const int I = tI[q], J = tJ[q];
+            cx<T> vI[4], vJ[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                vI[i] = v[4 * I + i];
+                vJ[i] = v[4 * J + i];
+            }
+            // entry q = 4i + j is sl.A[q][q / 2].a (q even) or .b (q odd)
+            auto e = [&](int i, int j) -> cx<T> {
+                const Pair<T>& p = sl.A[q][(4 * i + j) >> 1];
+                return ((4 * i + j) & 1) ? p.b : p.a;
+            };
+            cx<T> row[4], col[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                row[i] = zero();
+                col[i] = zero();
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    row[i] = cmac(row[i], e(i, j), vJ[j]);
+                    col[j] = cmac(col[j], e(i, j), vI[i]);
+                }
+#pragma unroll
+            for (int i = 0; i < 4; ++i) cs[J * Wp + 4 * I + i] = row[i];
+            if (I < J)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) cs[I * Wp + 4 * J + j] = col[j];
         }
     };
-    // (G_k v)_t for the row owners (every lane takes part: the quad sums are lane exchanges)
+    // (G_k v)_t for the row owners (every lane takes part: the group sums are lane exchanges)
     auto reduce = [&]() {
         cx<T> y = zero();
 #pragma unroll 4
-        for (int g = rq; g < NG; g += RS) y = y + part[g * W + tr];
-        y.re = quad_sum(y.re);
-        y.im = quad_sum(y.im);
+        for (int J = rq; J < nt; J += RS) y = y + cs[J * Wp + tr];
+        y.re = lane_sum(y.re, RS);
+        y.im = lane_sum(y.im, RS);
         return y;
     };
 
@@ -1049,7 +1070,8 @@ __global__ __launch_bounds__(1024) void k_chain_sym(ChainArgs a) {
     c128 rr[PD + 1];
     cx<T> yr[PD + 1];
     cx<T> yv = zero();   // y (phase 0) or x (phase 1) of my row at the previous block row
-    __syncthreads();     // a2h, iax, zero slot
+    __syncthreads();     // ay, ax, zero tail of v
+    iax = ax[tr];        // from LDS: no global load older than the ring is left for the loop to wait on
 
     if constexpr (PH == 0) {
         // ---- forward elimination of this half towards the middle row
@@ -1072,7 +1094,6 @@ __global__ __launch_bounds__(1024) void k_chain_sym(ChainArgs a) {
             rr[(u + PD) % (PD + 1)] = rhs_load(kat(i + PD));
             load(kat(i + PD), ring[(u + PD) % (PD + 1)]);
             __builtin_amdgcn_sched_barrier(0);
-            stage(ring[u]);
             if (mine) v[tr] = gnext;
             __syncthreads();
             gemv(ring[u]);
@@ -1105,7 +1126,6 @@ __global__ __launch_bounds__(1024) void k_chain_sym(ChainArgs a) {
         const c128 rm = rhs_load(m);
         const cx<T> ylo = (kf0 <= m - 1) ? yload(m - 1) : zero();
         const cx<T> yhi = (kf1 >= m + 1) ? yload(m + 1) : zero();
-        stage(gm);
         if (mine) {
             cx<T> g = rhs_use(m, rm);
             if (m >= 1) g = g - cy(m - 1) * ylo;
@@ -1126,7 +1146,7 @@ __global__ __launch_bounds__(1024) void k_chain_sym(ChainArgs a) {
         const int dir = h == 0 ? -1 : 1;
         const int n = h == 0 ? m - kb0 : kb1 - m;
         auto kat = [&](int i) { return kstart + dir * min(i, n - 1); };
-        __syncthreads();   // every gemv of the middle row has read Gl
+        __syncthreads();   // every reduce of the middle row has read c
         __builtin_amdgcn_sched_barrier(0);
         if (n > 0) {
 #pragma unroll
@@ -1143,7 +1163,6 @@ __global__ __launch_bounds__(1024) void k_chain_sym(ChainArgs a) {
             yr[(u + PD) % (PD + 1)] = yload(kat(i + PD));
             load(kat(i + PD), ring[(u + PD) % (PD + 1)]);
             __builtin_amdgcn_sched_barrier(0);
-            stage(ring[u]);
             if (mine) v[tr] = vnext;
             __syncthreads();
             gemv(ring[u]);
@@ -1210,22 +1229,31 @@ __global__ __launch_bounds__(1024) void k_chain_sym(ChainArgs a) {
     }
 }
 
-// Packed symmetric copy of the FP64 factor pool, rounded to T: P[d][i] of block k of window n
-// is the mean of G_k[t][c] and G_k[c][t], t = i mod W, c = (t + d) mod W (the computed inverse
-// is symmetric up to rounding; the mean is the nearest symmetric matrix).
+// Packed symmetric copy of the FP64 factor pool, rounded to T (tile layout of tile_nt): entry
+// (r, c) is the mean of G_k[r][c] and G_k[c][r] (the computed inverse is symmetric up to
+// rounding; the mean is the nearest symmetric matrix).
 template <typename T>
 __global__ void k_pack_sym(const SubDesc* subs, const c128* G, cx<T>* Gp) {
     const SubDesc s = subs[blockIdx.y];
-    const int W = s.W, H = s.H, Ls = sym_L(W);
+    const int W = s.W, H = s.H, nt = tile_nt(W), NTL = tile_count(W);
     const long long per = sym_block(W), total = per * H;
     for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (long long)gridDim.x * blockDim.x) {
         const int k = (int)(e / per);
         const int rem = (int)(e - (long long)k * per);
-        const int d = rem / Ls, i = rem - d * Ls;
-        const int t = i < W ? i : i - W;
-        const int c = (t + d) % W;
-        const c128* Gk = G + s.g_off + (size_t)k * W * W;   // column-major: (row t, col c) at c*W + t
-        const c128 g = 0.5 * (Gk[(size_t)c * W + t] + Gk[(size_t)t * W + c]);
+        const int u = rem / (2 * NTL), w = rem - u * 2 * NTL;
+        const int tau = w >> 1, q = 2 * u + (w & 1);
+        int I = 0, start = 0;
+        while (I < nt - 1 && start + (nt - I) <= tau) {
+            start += nt - I;
+            ++I;
+        }
+        const int J = I + (tau - start);
+        const int r = 4 * I + (q >> 2), c = 4 * J + (q & 3);
+        c128 g = mk(0.0, 0.0);
+        if (r < W && c < W) {
+            const c128* Gk = G + s.g_off + (size_t)k * W * W;   // column-major: (row r, col c) at c*W + r
+            g = 0.5 * (Gk[(size_t)c * W + r] + Gk[(size_t)r * W + c]);
+        }
         Gp[s.gs_off + e] = cvt<T>(g);
     }
 }
@@ -1737,21 +1765,19 @@ hipError_t launch_chain_mr(const ChainArgs& a, int nsolves, int nrhs, int ept, b
                    : launch_chain_mr_t<double>(a, nsolves, nrhs, ept, cs, rgroup, st);
 }
 
-// register ring of k_chain_sym: 4 VGPRs per complex64 pair and 8 per complex128 pair, PD
-// blocks in flight within about 64 VGPRs
+// register ring of k_chain_sym: a tile is 32 VGPRs in complex64 and 64 in complex128; PD blocks
+// in flight within about 200 of the 256 VGPRs of a 256-lane workgroup
 template <typename T, int CS, int PH, typename F>
 static void sym_dispatch(int ept, F&& f) {
     if constexpr (sizeof(T) == 4) {
         if (ept <= 1) f(k_chain_sym<T, 1, 4, CS, PH>);
-        else if (ept <= 2) f(k_chain_sym<T, 2, 4, CS, PH>);
-        else f(k_chain_sym<T, 4, 2, CS, PH>);
-    } else {
-        if (ept <= 1) f(k_chain_sym<T, 1, 4, CS, PH>);
         else f(k_chain_sym<T, 2, 2, CS, PH>);
+    } else {
+        f(k_chain_sym<T, 1, 2, CS, PH>);
     }
 }
 
-int sym_max_ept(bool c64mode) { return c64mode ? 4 : 2; }
+int sym_max_ept(bool c64mode) { return c64mode ? 2 : 1; }
 
 hipError_t prepare_chain_sym(int ept, bool c64mode, size_t lds) {
     hipError_t e = hipSuccess;
@@ -1773,7 +1799,7 @@ hipError_t launch_chain_sym(const ChainArgs& a, int nsolves, int nrhs, int ept, 
                             hipStream_t st) {
     if ((cs != CS_STAGE1 && cs != CS_FINAL) || ept < 1 || ept > sym_max_ept(c64mode)) return hipErrorInvalidValue;
     dim3 grid(2 * nsolves, nrhs);
-    auto go = [&](auto kern) { kern<<<grid, 1024, lds, st>>>(a); };
+    auto go = [&](auto kern) { kern<<<grid, 256, lds, st>>>(a); };
 #define LSW_GO(T, CSV, PHV) if (cs == CSV) sym_dispatch<T, CSV, PHV>(ept, go);
     if (c64mode) {
         LSW_GO(float, CS_STAGE1, 0) LSW_GO(float, CS_FINAL, 0)

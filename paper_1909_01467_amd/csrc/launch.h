@@ -101,15 +101,13 @@ hipError_t launch_chain(const ChainArgs& a, int nsolves, int nrhs, int ept, bool
 // workgroup; y and x in a.Y (Y_stride >= 2 H_max W_max)
 hipError_t launch_chain_mr(const ChainArgs& a, int nsolves, int nrhs, int ept, bool c64mode, int cs, int rgroup,
                            hipStream_t st);
-// packed rows per thread of k_chain_sym for a window of width W (1024 threads, one row pair each)
-inline int sym_ept(int W) {
-    const int P = (W + 1) / 2, NG = 1024 / P;
-    return (sym_D(W) + NG) / NG;
-}
+// tiles per lane of k_chain_sym (256 lanes) for a window of width W
+inline int sym_ept(int W) { return (tile_count(W) + 255) / 256; }
 // stage 1 (cs 0) or final (cs 1) substitutions, one right-hand side per workgroup, on the packed
-// symmetric factors (a.G = packed pool, SubDesc::gs_off); ept = packed rows per thread (sym_ept,
-// at most sym_max_ept); lds = dynamic LDS bytes, >= sym_block(W_max) entries (set once with
-// prepare_chain_sym); y and x in a.Y (Y_stride >= 2 H_max W_max)
+// symmetric factors (a.G = packed pool, SubDesc::gs_off); ept = tiles per lane (sym_ept, at most
+// sym_max_ept); lds = dynamic LDS bytes, >= the column sums of the widest window,
+// tile_nt(W) sym_cstride(W) entries (set once with prepare_chain_sym); y and x in a.Y
+// (Y_stride >= 2 H_max W_max)
 int sym_max_ept(bool c64mode);
 hipError_t prepare_chain_sym(int ept, bool c64mode, size_t lds);
 hipError_t launch_chain_sym(const ChainArgs& a, int nsolves, int nrhs, int ept, bool c64mode, int cs, size_t lds,
