@@ -184,13 +184,19 @@ def main():
                             ms=med["last_stage1_ms"] + med["last_gemv_ms"]),
         }
     else:
+        # the one-right-hand-side substitutions read the packed symmetric factors when built
+        sym = bool(st.get("symmetric_factors"))
+        chain = "k_chain_sym" if sym else "k_chain"
+        layout = ("packed symmetric factors, 4x4 tiles of the upper triangle" if sym else "full factor blocks")
         kernels = {
-            "k_chain<CS_STAGE1>": dict(desc="stage-1 block substitutions, twisted (forward halves; middle + backward halves)",
-                                       launches=2, bytes=st["apply_stage1_bytes"], ms=med["last_stage1_ms"]),
+            f"{chain}<CS_STAGE1>": dict(desc=f"stage-1 block substitutions, twisted (forward halves; middle + backward "
+                                             f"halves), {layout}",
+                                        launches=2, bytes=st["apply_stage1_bytes"], ms=med["last_stage1_ms"]),
             "k_gemv": dict(desc="trace-compressed sweep fronts: out = Q' u~ per solve (batched GEMV)",
                            launches=st["gemv_launches"], bytes=st["apply_gemv_bytes"], ms=med["last_gemv_ms"]),
-            "k_chain<CS_FINAL>": dict(desc="final z block substitutions, twisted (forward halves; middle + backward halves)",
-                                      launches=2, bytes=st["apply_final_bytes"], ms=med["last_final_ms"]),
+            f"{chain}<CS_FINAL>": dict(desc=f"final z block substitutions, twisted (forward halves; middle + backward "
+                                            f"halves), {layout}",
+                                       launches=2, bytes=st["apply_final_bytes"], ms=med["last_final_ms"]),
         }
     for k in kernels.values():
         k["bytes_per_launch"] = k["bytes"] / max(1, k["launches"])
