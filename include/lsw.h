@@ -73,7 +73,7 @@ typedef struct {
 } lsw_cdd_t;
 
 typedef struct {
-    double C;            /* absorption constant of the cubic profile (App. A); <= 0 selects 4 ln(omega) */
+    double C;            /* absorption constant of the cubic profile (App. A); <= 0 selects 16 ln(omega) */
     int n_pml_local;     /* PML points of each interior side of a local problem; < 0 selects n_pml[x] */
 } lsw_pml_t;
 

@@ -1071,7 +1071,7 @@ int setup_impl(lsw_plan* p, const double* d_m, double omega, double h, const lsw
     if (p->q < 1 || p->r < 1) return fail(p, LSW_EINVAL, "q and r must be >= 1");
     p->omega = omega;
     p->h = h;
-    p->C = (pml && pml->C > 0) ? pml->C : 4.0 * std::log(omega);
+    p->C = (pml && pml->C > 0) ? pml->C : 16.0 * std::log(omega);
     p->pl = (pml && pml->n_pml_local >= 0) ? pml->n_pml_local : p->px;
     p->e = 2 + p->pl;
     if (opts) {

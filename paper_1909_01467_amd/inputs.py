@@ -65,6 +65,14 @@ def speed_lens_noise(n: int, seed: int = 2, amp: float = 0.05, corr: float = 0.0
     return speed_lens(n, 2) * (1.0 + p)
 
 
+def speed_random_smooth(n: int, seed: int = 5, amp: float = 0.3, corr: float = 0.1) -> np.ndarray:
+    """c = 1 + amp p, p = seeded white noise low-pass filtered to correlation length `corr` and
+    scaled to max|p| = 1 (stands in for the random smooth wave speed of Sec. 5.3)."""
+    rng = np.random.default_rng(seed)
+    p = ndimage.gaussian_filter(rng.standard_normal((n, n)), sigma=corr / bulk_h(n), mode="reflect")
+    return 1.0 + amp * p / np.max(np.abs(p))
+
+
 def speed_layered_faults(n: int, seed: int = 3, layers: int = 12, faults: int = 3,
                          cmin: float = 1.5, cmax: float = 4.5) -> np.ndarray:
     """Piecewise-constant dipping layers cut by vertical faults (reflective medium)."""
@@ -110,6 +118,13 @@ def gaussian_source(n: int, centre, width: float | None = None) -> np.ndarray:
     # mesh order is (.., y, x); centre is given as (x, y[, z])
     r2 = sum((X[dim - 1 - k] - centre[k]) ** 2 for k in range(dim))
     return np.exp(-r2 / w**2) / (math.pi * w**2) ** (dim / 2.0)
+
+
+def four_point_sources(n: int) -> np.ndarray:
+    """The sources of the standard setup of Sec. 5: narrow Gaussians of amplitude n^2/pi and
+    width 1/n at (0.125, 0.125), (0.125, 0.875), (0.875, 0.125) and (0.875, 0.875)."""
+    pts = ((0.125, 0.125), (0.125, 0.875), (0.875, 0.125), (0.875, 0.875))
+    return sum(gaussian_source(n, c, width=1.0 / n) for c in pts)
 
 
 def receiver_indices(n: int, xs, y: float) -> np.ndarray:
@@ -166,8 +181,9 @@ class Workload:
 
     @property
     def C(self) -> float:
-        """Default PML absorption constant: 4 ln(omega) (reading of App. A)."""
-        return 4.0 * math.log(self.omega)
+        """Default PML absorption constant: 16 ln(omega) (reading of App. A: the most accurate
+        truncation for PMLs of one wavelength, and the iteration counts of Tab. PMLeffect)."""
+        return 16.0 * math.log(self.omega)
 
     @property
     def slowness2(self) -> np.ndarray:

@@ -164,7 +164,7 @@ class Solver:
         self.N = m_ext.numel()
         self.omega, self.h, self.n, self.n_pml, self.q, self.r = omega, h, ns, ps, q, r
         self.nrhs_max = nrhs_max
-        self.C = 4.0 * math.log(omega) if C is None else C
+        self.C = 16.0 * math.log(omega) if C is None else C
         self.precision = precision
         grid = lsw_grid_t(dim, (ctypes.c_int * 3)(*ns, *([0] * (3 - dim))), (ctypes.c_int * 3)(*ps, *([0] * (3 - dim))))
         cdd = lsw_cdd_t(q, r)

@@ -1,0 +1,95 @@
+"""Iteration counts of the L-sweep preconditioned solve against the number of subdomains and the
+PML thickness, on the standard setup of the numerical section of the paper (Sec. 5).
+
+Setup (Sec. 5, with the readings of the grid and PML of App. A used everywhere in this package):
+  * q x q CDD with 101 bulk points per subdomain and direction, so n = 101 q;
+  * 10 points per wavelength at the slowest speed: omega = 2 pi c_min n / 10;
+  * PML of `wavelengths` wavelengths at the fastest speed: n_pml = ceil(10 w c_max / c_min) points,
+    the same width for the local PML of every subdomain; C = c_factor ln(omega) (default 16, the
+    package's reading of the PML constant of App. A);
+  * the four narrow Gaussian sources of the standard setup (inputs.four_point_sources);
+  * right-preconditioned FGMRES to a relative residual of 1e-6 from a zero initial guess.
+
+Tab. PMLeffect reports the constant medium for q = 2 ... 128 and PMLs of 1 ... 7 wavelengths,
+Tab. Complexity its q = p column N_it (2 wavelengths), Tab. RandomWavespeed a random smooth medium
+(2 wavelengths); the random smooth medium here is inputs.speed_random_smooth.
+
+usage: python -m paper_1909_01467_amd.trend --q 2 4 8 16 --wavelengths 1 2 3 [--medium const|smooth]
+       [--precision mixed|fp64] [--json out.json]
+Prints one line per case: q, n, n_pml, omega/2pi, iterations, relative residual, setup and solve
+times (ms).  Needs a GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import sys
+import time
+
+import numpy as np
+
+
+def case(q: int, wavelengths: float, medium: str = "const", precision: str = "mixed", tol: float = 1e-6,
+         points_per_subdomain: int = 101, c_factor: float = 16.0, maxit: int = 200) -> dict:
+    import torch
+
+    from . import inputs
+    from .lsweeps import Solver, extend_medium
+
+    n = points_per_subdomain * q
+    c = inputs.speed_constant(n) if medium == "const" else inputs.speed_random_smooth(n)
+    cmin, cmax = float(c.min()), float(c.max())
+    omega = 2.0 * math.pi * cmin * n / 10.0
+    n_pml = int(math.ceil(10.0 * wavelengths * cmax / cmin - 1e-9))
+    h = inputs.bulk_h(n)
+    m_ext = extend_medium(torch.from_numpy(1.0 / c**2).cuda(), n_pml).contiguous()
+    f = torch.from_numpy(inputs.four_point_sources(n)).to(torch.complex128).cuda()
+    b = torch.nn.functional.pad(f, (n_pml, n_pml, n_pml, n_pml)).contiguous()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s = Solver(m_ext, omega, h, n, n_pml, q, q, C=c_factor * math.log(omega), precision=precision, tol=tol,
+               maxit=maxit)
+    t_setup = (time.perf_counter() - t0) * 1e3
+    try:
+        s.solve(b)                                   # warm-up
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        _, info = s.solve(b)
+        torch.cuda.synchronize()
+        t_solve = (time.perf_counter() - t1) * 1e3
+    finally:
+        s.close()
+    return dict(q=q, n=n, n_pml=n_pml, wavelengths=wavelengths, medium=medium, precision=precision, c_factor=c_factor,
+                omega_over_2pi=omega / (2.0 * math.pi), iterations=int(info["iterations"][0]),
+                relres=float(info["relres"][0]), converged=bool(info["converged"][0]),
+                t_setup_ms=round(t_setup, 1), t_solve_ms=round(t_solve, 2))
+
+
+def main(argv=None) -> int:
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--q", type=int, nargs="+", default=[2, 4, 8, 16])
+    ap.add_argument("--wavelengths", type=float, nargs="+", default=[1, 2, 3])
+    ap.add_argument("--medium", choices=["const", "smooth"], default="const")
+    ap.add_argument("--precision", choices=["mixed", "fp64"], default="mixed")
+    ap.add_argument("--c-factor", type=float, nargs="+", default=[16.0], help="C = factor * ln(omega)")
+    ap.add_argument("--maxit", type=int, default=200)
+    ap.add_argument("--json", default=None)
+    args = ap.parse_args(argv)
+    rows = []
+    for cf in args.c_factor:
+        for w in args.wavelengths:
+            for q in args.q:
+                r = case(q, w, args.medium, args.precision, c_factor=cf, maxit=args.maxit)
+                rows.append(r)
+                print(f"q={r['q']:3d} n={r['n']:5d} n_pml={r['n_pml']:3d} omega/2pi={r['omega_over_2pi']:7.1f} "
+                      f"C/ln(omega)={cf:g} wavelengths={w:g} iterations={r['iterations']:3d} relres={r['relres']:.2e} "
+                      f"setup_ms={r['t_setup_ms']:.0f} solve_ms={r['t_solve_ms']:.1f}", flush=True)
+    if args.json:
+        with open(args.json, "w") as fh:
+            json.dump(rows, fh, indent=1)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

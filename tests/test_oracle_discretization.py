@@ -125,6 +125,23 @@ def test_converges_to_free_space_hankel_at_second_order():
     assert all(1.7 < o < 2.3 for o in orders), (errs, orders)
 
 
+def test_pml_constant_reading_truncates_one_wavelength_pml_best():
+    """App. A leaves the scale of C open.  For a PML of one wavelength (10 points at 10 points
+    per wavelength) the bulk solution with C = 16 ln(omega) agrees with a thick-PML reference
+    far better than with 4 ln(omega) or the literal ln(omega): the reading of the default C."""
+    n = 63
+    omega = 2 * math.pi * n / 10
+    f = inputs.four_point_sources(n)
+
+    def bulk(p, C):
+        gp = GlobalProblem(np.ones((n + 2 * p,) * 2), omega, n, p, C=C)
+        return SparseLU(gp.A).solve(gp.rhs(f)).reshape(gp.m.shape)[p:-p, p:-p]
+
+    ref = bulk(60, 8 * math.log(omega))
+    err = {cf: np.linalg.norm(bulk(10, cf * math.log(omega)) - ref) / np.linalg.norm(ref) for cf in (1, 4, 16)}
+    assert err[16] < err[4] / 20 < err[1] / 20, err
+
+
 def test_banded_sparse_and_dense_solvers_agree_2d():
     m = extend_normal(_rand_smooth((17, 20), 6), (6, 5))
     gp = GlobalProblem(m, 40.0, (20, 17), (6, 5), C=5.0)

@@ -145,8 +145,9 @@ def test_fgmres_const2d_matches_direct_solve():
     direct solution; 3 iterations to 1e-6 and 4 to 1e-8 with C = 4 ln(omega)."""
     wl = inputs.workload("const2d")
     m = extend_normal(wl.slowness2, wl.n_pml)
-    gp = GlobalProblem(m, wl.omega, wl.n, wl.n_pml, wl.C)
-    ls = LSweep2D(m, wl.omega, wl.n, wl.n_pml, wl.q, wl.r, wl.C)
+    C = 4 * math.log(wl.omega)
+    gp = GlobalProblem(m, wl.omega, wl.n, wl.n_pml, C)
+    ls = LSweep2D(m, wl.omega, wl.n, wl.n_pml, wl.q, wl.r, C)
     b = gp.rhs(wl.sources[0])
     u = solve_banded(gp.A, b)
     its = []
