@@ -166,7 +166,8 @@ def main():
         log(precision, "solve ms", round(ms, 3), "iterations", info["iterations"], "relres", info["relres"],
             "apply ms", round(med["last_apply_ms"], 4), "stage1 ms", round(med["last_stage1_ms"], 4),
             "gemv ms", round(med["last_gemv_ms"], 4), "final rhs ms", round(med["last_final_rhs_ms"], 4),
-            "final ms", round(med["last_final_ms"], 4), "Q setup ms", round(st["t_q_ms"], 1))
+            "final ms", round(med["last_final_ms"], 4), "Q setup ms", round(st["t_q_ms"], 1),
+            "sweep items", st["gemv_items"], "max inputs", st["gemv_max_inputs"])
         results[precision] = dict(ms=ms, info=info, med=med, stats=st)
         s.close()
         torch.cuda.synchronize()

@@ -131,6 +131,8 @@ typedef struct {
     int symmetric_factors;       /* 1 if the one-right-hand-side substitutions read the packed symmetric
                                     blocks (G_k = G_k^T; about half the bytes of the full blocks) */
     long long packed_factor_elems;  /* complex entries of the packed blocks (0 if not built) */
+    int gemv_items;              /* work items (<= 64 output rows of one sweep solve) per application */
+    int gemv_max_inputs;         /* largest input count (incoming trace values) of a sweep solve */
 } lsw_stats_t;
 
 /*

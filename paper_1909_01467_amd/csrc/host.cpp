@@ -1676,6 +1676,8 @@ int lsw_query(lsw_handle_t p, lsw_stats_t* st) {
     for (int i = 0; i < 3; ++i) st->tune_ms[i] = p->rgroup_ms[i];
     st->symmetric_factors = p->gsym ? 1 : 0;
     st->packed_factor_elems = p->gsym ? (long long)p->GS_elems : 0;
+    st->gemv_items = (int)p->gitems.size();
+    st->gemv_max_inputs = p->max_nin;
     return LSW_OK;
 }
 

@@ -72,7 +72,8 @@ class lsw_stats_t(ctypes.Structure):
                 ("last_stage1_ms", ctypes.c_double), ("last_final_ms", ctypes.c_double),
                 ("last_final_rhs_ms", ctypes.c_double), ("rhs_per_workgroup", ctypes.c_int),
                 ("tune_ms", ctypes.c_double * 3), ("symmetric_factors", ctypes.c_int),
-                ("packed_factor_elems", ctypes.c_longlong)]
+                ("packed_factor_elems", ctypes.c_longlong), ("gemv_items", ctypes.c_int),
+                ("gemv_max_inputs", ctypes.c_int)]
 
 
 _lib = None
