@@ -11,6 +11,7 @@ Modules
   direct          the exact solve u = A^-1 b (banded LU, SuperLU, dense)
   lsweep          Alg. Scenario3 of App. C, run literally and sequentially
   lsweep3d        the same over a beam CDD of a 3D box (7-point operator)
+  scenario4       Sec. 2.1 scenario 4: four shifted CDDs and a partition of unity
   fgmres          right-preconditioned flexible GMRES (Sec. 3, Phase 3)
   gradient        FWI misfit and its adjoint-state gradient (Sec. 1 motivation)
 

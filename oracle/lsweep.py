@@ -46,15 +46,15 @@ import scipy.sparse.linalg as spla
 from .discretization import alpha_of, assemble, axis_points, cubic_sigma
 
 
-def partition(n_bulk: int, n_pml: int, groups: int):
-    """[lo, hi) of each group along one axis (extended-grid indices)."""
+def partition(n_bulk: int, n_pml: int, groups: int, shift: int = 0):
+    """[lo, hi) of each group along one axis (extended-grid indices).
+
+    `shift` moves every interior group boundary by that many points towards larger indices
+    (the shifted CDDs of scenario 4, Sec. 2.1); the returned sizes are those of the even split."""
     sizes = [n_bulk // groups + (1 if g < n_bulk % groups else 0) for g in range(groups)]
-    lo, hi = [], []
-    start = n_pml
-    for g in range(groups):
-        lo.append(0 if g == 0 else start)
-        start += sizes[g]
-        hi.append(start + (n_pml if g == groups - 1 else 0))
+    bounds = [n_pml + sum(sizes[:g]) + shift for g in range(1, groups)]
+    lo = [0] + bounds
+    hi = bounds + [n_bulk + 2 * n_pml]
     return lo, hi, sizes
 
 
@@ -62,10 +62,11 @@ SIDES = ("B", "R", "T", "L")
 
 
 class LSweep2D:
-    """Alg. Scenario3 for a 2D q x r CDD."""
+    """Alg. Scenario3 for a 2D q x r CDD; `shift` = (sx, sy) moves the interior boundaries of
+    each axis (the shifted CDDs of scenario 4)."""
 
     def __init__(self, m_ext: np.ndarray, omega: float, n, n_pml, q: int, r: int, C: float,
-                 n_pml_local: int | None = None, h: float | None = None):
+                 n_pml_local: int | None = None, h: float | None = None, shift=(0, 0)):
         nx, ny = (n, n) if np.isscalar(n) else n
         px, py = (n_pml, n_pml) if np.isscalar(n_pml) else n_pml
         self.nx, self.ny, self.px, self.py = nx, ny, px, py
@@ -77,8 +78,9 @@ class LSweep2D:
         self.m = np.asarray(m_ext, dtype=np.float64)
         self.Nex, self.Ney = nx + 2 * px, ny + 2 * py
         assert self.m.shape == (self.Ney, self.Nex)
-        self.xlo, self.xhi, _ = partition(nx, px, r)
-        self.ylo, self.yhi, _ = partition(ny, py, q)
+        self.shift = tuple(shift)
+        self.xlo, self.xhi, _ = partition(nx, px, r, self.shift[0])
+        self.ylo, self.yhi, _ = partition(ny, py, q, self.shift[1])
         for lo, hi, N in ((self.xlo, self.xhi, self.Nex), (self.ylo, self.yhi, self.Ney)):
             for g in range(len(lo)):
                 if hi[g] - lo[g] < 2 or (g > 0 and lo[g] < self.e) or \

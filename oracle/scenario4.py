@@ -1,0 +1,90 @@
+"""Scenario 4 of Sec. 2.1: L-sweeps for arbitrary sources through four shifted CDDs and a
+partition of unity (oracle; test infrastructure only).
+
+The paper takes the CDD, three more CDDs obtained from it by a horizontal, a vertical and
+a combined shift, and four window functions phi_1..phi_4 that sum to one, each vanishing on
+the skeleton of one of the four CDDs.  Each windowed source phi_k f then avoids the
+skeleton of its own CDD, scenario 3 on that CDD handles it, and the approximate solution is
+the sum of the four results:  z = sum_k M_k^-1 (phi_k r).
+
+The paper fixes neither the shift nor the windows; the readings taken here:
+  * Shift: every interior group boundary of an axis moves by s points towards larger
+    indices (the edge groups keep the global PML); by default s is half of the smallest
+    bulk group of that axis.  The skeletons of the two CDDs of one axis are then disjoint
+    and interleaved.
+  * Windows: tensor products phi = a(x) b(y).  Along one axis, with interfaces at
+    P = lo - 1/2 (original CDD) and P' = lo' - 1/2 (shifted CDD), d and d' the distances
+    of a point to the nearest P and P', and w(t) = max(0, t - 1):
+        a = 0 to the left of the first P, a = 1 to the right of the last P',
+        a = w(d) / (w(d) + w(d')) in between.
+    a vanishes on the two trace lines of every original interface (d = 1/2) and equals 1 on
+    those of every shifted one; between them it is a linear ramp.  The CDD unshifted along
+    this axis takes a, the shifted one 1 - a, so the four products sum to one.
+
+Pins (tests/test_oracle_scenario4.py): the partition of unity and its vanishing on each
+CDD's skeleton; exact reconstruction of A^-1 f (up to the PML error) for sources that
+cross the original skeleton, where scenario 3 alone is visibly worse; reduction to
+scenario 3 when only one window is kept.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from .lsweep import LSweep2D, partition
+
+
+def default_shift(n_bulk: int, groups: int) -> int:
+    """Half of the smallest bulk group of the even split."""
+    return (n_bulk // groups) // 2
+
+
+def axis_window(N: int, lo: list[int], lo_shifted: list[int]) -> np.ndarray:
+    """The window a(x) of one axis on its N extended-grid points (see the module notes).
+    lo / lo_shifted are the group starts of the original and shifted CDD (lo[0] = 0)."""
+    P = np.asarray(lo[1:], dtype=np.float64) - 0.5
+    Ps = np.asarray(lo_shifted[1:], dtype=np.float64) - 0.5
+    a = np.empty(N)
+    for x in range(N):
+        if x < P.min():
+            a[x] = 0.0
+        elif x > Ps.max():
+            a[x] = 1.0
+        else:
+            w = max(0.0, np.abs(x - P).min() - 1.0)
+            ws = max(0.0, np.abs(x - Ps).min() - 1.0)
+            a[x] = w / (w + ws)
+    return a
+
+
+class Scenario4:
+    """z = sum over the four CDDs k of M_k^-1 (phi_k r)."""
+
+    def __init__(self, m_ext: np.ndarray, omega: float, n, n_pml, q: int, r: int, C: float,
+                 n_pml_local: int | None = None, h: float | None = None, shift=None):
+        nx, ny = (n, n) if np.isscalar(n) else n
+        px, py = (n_pml, n_pml) if np.isscalar(n_pml) else n_pml
+        if q < 2 or r < 2:
+            raise ValueError("scenario 4 needs at least two groups along each axis")
+        sx, sy = (default_shift(nx, r), default_shift(ny, q)) if shift is None else shift
+        self.shift = (sx, sy)
+        self.Nex, self.Ney = nx + 2 * px, ny + 2 * py
+        ax = axis_window(self.Nex, partition(nx, px, r)[0], partition(nx, px, r, sx)[0])
+        ay = axis_window(self.Ney, partition(ny, py, q)[0], partition(ny, py, q, sy)[0])
+        self.cdds, self.windows = [], []
+        for kx, ky in ((0, 0), (1, 0), (0, 1), (1, 1)):
+            self.cdds.append(LSweep2D(m_ext, omega, (nx, ny), (px, py), q, r, C, n_pml_local, h,
+                                      shift=(kx * sx, ky * sy)))
+            wx = 1.0 - ax if kx else ax
+            wy = 1.0 - ay if ky else ay
+            self.windows.append(np.outer(wy, wx))
+
+    def apply(self, rvec: np.ndarray) -> np.ndarray:
+        R = np.asarray(rvec, dtype=np.complex128).reshape(self.Ney, self.Nex)
+        z = np.zeros(R.size, dtype=np.complex128)
+        for ls, phi in zip(self.cdds, self.windows):
+            z += ls.apply((phi * R).ravel())
+        return z
+
+    @property
+    def solves(self) -> int:
+        return sum(ls.solves for ls in self.cdds)
