@@ -137,6 +137,15 @@ struct lsw_plan {
     hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
     double last_stage1_ms = 0, last_final_ms = 0, last_final_rhs_ms = 0;
     double apply_stage1_bytes = 0, apply_final_bytes = 0;
+    // scenario 4 (Sec. 2.1): this plan is the unshifted CDD; shifted[] holds the CDDs shifted along
+    // x, y and both, each a complete plan without a Krylov basis (member = true)
+    int windows = 0, shift_x = 0, shift_y = 0;
+    bool member = false;
+    lsw_plan* shifted[3] = {nullptr, nullptr, nullptr};
+    double* d_wx = nullptr;         // a(x) on the Nx extended points
+    double* d_wy = nullptr;         // b(y) on the Ny extended points
+    c128* d_wr = nullptr;           // windowed right-hand sides [nrhs][N]
+    c128* d_wz = nullptr;           // one shifted CDD's sweep result [nrhs][N]
 };
 
 namespace {
@@ -175,6 +184,10 @@ void dfree(lsw_plan* p, void* ptr) {
 
 void free_plan(lsw_plan* p) {
     if (!p) return;
+    for (lsw_plan*& c : p->shifted) {
+        free_plan(c);
+        c = nullptr;
+    }
     for (void* a : p->allocs) (void)hipFree(a);
     if (p->h_hbuf) (void)hipHostFree(p->h_hbuf);
     if (p->h_scale) (void)hipHostFree(p->h_scale);
@@ -187,16 +200,42 @@ void free_plan(lsw_plan* p) {
 }
 
 // ---------------------------------------------------------------- geometry
-void split(int n_bulk, int n_pml, int groups, std::vector<int>& lo, std::vector<int>& hi) {
+// groups of one axis; shift moves every interior boundary towards larger indices (the shifted
+// CDDs of scenario 4)
+void split(int n_bulk, int n_pml, int groups, std::vector<int>& lo, std::vector<int>& hi, int shift = 0) {
     lo.assign(groups, 0);
     hi.assign(groups, 0);
     int start = n_pml;
     for (int g = 0; g < groups; ++g) {
         const int size = n_bulk / groups + (g < n_bulk % groups ? 1 : 0);
-        lo[g] = (g == 0) ? 0 : start;
+        lo[g] = (g == 0) ? 0 : start + shift;
         start += size;
-        hi[g] = start + (g == groups - 1 ? n_pml : 0);
+        hi[g] = (g == groups - 1) ? n_bulk + 2 * n_pml : start + shift;
     }
+}
+
+// the window a of one axis (scenario 4): 0 on the trace lines of the interfaces at lo[g] - 1/2
+// (g >= 1), 1 on those of the shifted interfaces at los[g] - 1/2, a linear ramp w(d) / (w(d) + w(d'))
+// with w(t) = max(0, t - 1) between them, 0 before the first interface and 1 after the last
+std::vector<double> axis_window(int N, const std::vector<int>& lo, const std::vector<int>& los) {
+    std::vector<double> a(N);
+    const double first = lo[1] - 0.5, last = los.back() - 0.5;
+    for (int x = 0; x < N; ++x) {
+        if (x < first) {
+            a[x] = 0.0;
+        } else if (x > last) {
+            a[x] = 1.0;
+        } else {
+            double d = 1e300, ds = 1e300;
+            for (size_t g = 1; g < lo.size(); ++g) {
+                d = std::min(d, std::fabs(x - (lo[g] - 0.5)));
+                ds = std::min(ds, std::fabs(x - (los[g] - 0.5)));
+            }
+            const double w = std::max(0.0, d - 1.0), ws = std::max(0.0, ds - 1.0);
+            a[x] = w / (w + ws);
+        }
+    }
+    return a;
 }
 
 double sigma_cubic(double dist, double delta, double C) {
@@ -594,6 +633,10 @@ ChainArgs chain_args(lsw_plan* p, const c128* d_r, c128* d_z) {
 }
 
 int apply3d_impl(lsw_plan* p, const c128* d_r, c128* d_z, int nrhs, bool timed);
+int setup_impl(lsw_plan* p, const double* d_m, double omega, double h, const lsw_grid_t* grid,
+               const lsw_cdd_t* cdd, const lsw_pml_t* pml, const lsw_opts_t* opts);
+int setup_windows(lsw_plan* p, const double* d_m, double omega, double h, const lsw_grid_t* grid,
+                  const lsw_cdd_t* cdd, const lsw_pml_t* pml, const lsw_opts_t* opts);
 
 // the stage-1 (cs 0) or final (cs 1) block substitutions of a 2D front: R right-hand sides per
 // workgroup on the full blocks, or one per workgroup on the packed symmetric blocks when present
@@ -607,7 +650,8 @@ hipError_t launch_block_front(lsw_plan* p, ChainArgs a, const Front& f, int nrhs
     return launch_chain(a, f.count, nrhs, p->ept, c64, cs, p->ylds, p->stream);
 }
 
-int apply_impl(lsw_plan* p, const c128* d_r, c128* d_z, int nrhs, bool timed) {
+// z = M^-1 r on this plan's own CDD (Alg. Scenario3)
+int apply_cdd(lsw_plan* p, const c128* d_r, c128* d_z, int nrhs, bool timed) {
     if (p->dim == 3) return apply3d_impl(p, d_r, d_z, nrhs, timed);
     const bool c64 = p->precision == LSW_MIXED;
     ChainArgs a = chain_args(p, d_r, d_z);
@@ -651,6 +695,22 @@ int apply_impl(lsw_plan* p, const c128* d_r, c128* d_z, int nrhs, bool timed) {
             }
             if (fi == 0 && timed) HIPCK(p, hipEventRecord(p->ev[1], p->stream));
         }
+    }
+    if (timed) HIPCK(p, hipEventRecord(p->ev[4], p->stream));
+    return LSW_OK;
+}
+
+// z = M^-1 r: one CDD, or with windows the sum over the four CDDs of their sweeps of phi_k r
+// (scenario 4, Sec. 2.1); events [0] and [4] bracket the whole application
+int apply_impl(lsw_plan* p, const c128* d_r, c128* d_z, int nrhs, bool timed) {
+    if (!p->windows) return apply_cdd(p, d_r, d_z, nrhs, timed);
+    if (timed) HIPCK(p, hipEventRecord(p->ev[0], p->stream));
+    for (int k = 0; k < 4; ++k) {
+        lsw_plan* c = k == 0 ? p : p->shifted[k - 1];
+        HIPCK(p, launch_window(d_r, p->d_wr, p->d_wx, p->d_wy, k & 1, k >> 1, p->Nx, p->N, nrhs, p->stream));
+        const int rc = apply_cdd(c, p->d_wr, k == 0 ? d_z : p->d_wz, nrhs, false);
+        if (rc != LSW_OK) return c == p ? rc : fail(p, rc, c->err);
+        if (k > 0) HIPCK(p, launch_accumulate(d_z, p->d_wz, p->N * (size_t)nrhs, p->stream));
     }
     if (timed) HIPCK(p, hipEventRecord(p->ev[4], p->stream));
     return LSW_OK;
@@ -1069,6 +1129,23 @@ int setup_impl(lsw_plan* p, const double* d_m, double omega, double h, const lsw
     p->q = cdd->q;
     p->r = cdd->r;
     if (p->q < 1 || p->r < 1) return fail(p, LSW_EINVAL, "q and r must be >= 1");
+    if (cdd->windows != 0 && cdd->windows != 1) return fail(p, LSW_EINVAL, "cdd.windows must be 0 or 1");
+    int own_sx = 0, own_sy = 0;   // shift of this plan's own CDD
+    if (cdd->windows) {
+        if (p->dim != 2) return fail(p, LSW_EINVAL, "windows (scenario 4) are built for dim 2");
+        if (p->q < 2 || p->r < 2) return fail(p, LSW_EINVAL, "windows need q >= 2 and r >= 2");
+        const int gx = p->nx / p->r, gy = p->ny / p->q;   // smallest bulk group of each axis
+        p->shift_x = cdd->shift[0] > 0 ? cdd->shift[0] : gx / 2;
+        p->shift_y = cdd->shift[1] > 0 ? cdd->shift[1] : gy / 2;
+        if (p->shift_x < 3 || p->shift_x > gx - 3 || p->shift_y < 3 || p->shift_y > gy - 3)
+            return fail(p, LSW_EINVAL, "the window shift must lie in [3, smallest group - 3] along each axis");
+        p->windows = 1;
+    } else {
+        own_sx = cdd->shift[0];
+        own_sy = cdd->shift[1];
+        if (own_sx < 0 || own_sy < 0) return fail(p, LSW_EINVAL, "cdd.shift must be >= 0");
+        if ((own_sx || own_sy) && p->dim != 2) return fail(p, LSW_EINVAL, "a shifted CDD is built for dim 2");
+    }
     p->omega = omega;
     p->h = h;
     p->C = (pml && pml->C > 0) ? pml->C : 16.0 * std::log(omega);
@@ -1088,8 +1165,8 @@ int setup_impl(lsw_plan* p, const double* d_m, double omega, double h, const lsw
     p->Ny = p->ny + 2 * p->py;
     p->Nz = p->dim == 3 ? p->nz + 2 * p->pz : 1;
     p->N = (size_t)p->Nx * p->Ny * p->Nz;
-    split(p->nx, p->px, p->r, p->xlo, p->xhi);
-    split(p->ny, p->py, p->q, p->ylo, p->yhi);
+    split(p->nx, p->px, p->r, p->xlo, p->xhi, own_sx);
+    split(p->ny, p->py, p->q, p->ylo, p->yhi, own_sy);
     auto windows = [&](const std::vector<int>& lo, const std::vector<int>& hi, int Nax, std::vector<int>& w0,
                        std::vector<int>& w1) -> bool {
         const int G = (int)lo.size();
@@ -1310,8 +1387,10 @@ int setup_impl(lsw_plan* p, const double* d_m, double omega, double h, const lsw
     // Krylov
     const int m = p->restart, nr = p->nrhs_max;
     const int HS = 2 * (m + 1) + 1;
-    if ((rc = dalloc(p, &p->d_V, (size_t)(m + 1) * nr * p->N)) != LSW_OK) return rc;
-    if ((rc = dalloc(p, &p->d_Z, (size_t)m * nr * p->N)) != LSW_OK) return rc;
+    if (!p->member) {   // the shifted CDDs of scenario 4 only apply their sweeps
+        if ((rc = dalloc(p, &p->d_V, (size_t)(m + 1) * nr * p->N)) != LSW_OK) return rc;
+        if ((rc = dalloc(p, &p->d_Z, (size_t)m * nr * p->N)) != LSW_OK) return rc;
+    }
     if ((rc = dalloc(p, &p->d_w, (size_t)nr * p->N)) != LSW_OK) return rc;
     if ((rc = dalloc(p, &p->d_tmp1, (size_t)nr * p->N)) != LSW_OK) return rc;
     if ((rc = dalloc(p, &p->d_tmp2, (size_t)nr * p->N)) != LSW_OK) return rc;
@@ -1526,7 +1605,37 @@ int setup_impl(lsw_plan* p, const double* d_m, double omega, double h, const lsw
         p->d_G = G128;
     }
     if ((rc = tune_rgroup(p)) != LSW_OK) return rc;
+    if (p->windows && (rc = setup_windows(p, d_m, omega, h, grid, cdd, pml, opts)) != LSW_OK) return rc;
     p->t_setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    return LSW_OK;
+}
+
+// scenario 4 (Sec. 2.1): the three shifted CDDs, each set up and factorised as a plan of its own,
+// and the window tables of both axes
+int setup_windows(lsw_plan* p, const double* d_m, double omega, double h, const lsw_grid_t* grid,
+                  const lsw_cdd_t* cdd, const lsw_pml_t* pml, const lsw_opts_t* opts) {
+    const int kx[3] = {1, 0, 1}, ky[3] = {0, 1, 1};
+    for (int k = 0; k < 3; ++k) {
+        lsw_plan* c = new (std::nothrow) lsw_plan();
+        if (!c) return fail(p, LSW_ENOMEM, "host allocation failed");
+        p->shifted[k] = c;
+        c->member = true;
+        lsw_cdd_t ck{cdd->q, cdd->r, 0, {kx[k] * p->shift_x, ky[k] * p->shift_y}};
+        const int rc = setup_impl(c, d_m, omega, h, grid, &ck, pml, opts);
+        if (rc != LSW_OK) return fail(p, rc, "shifted CDD " + std::to_string(k + 1) + ": " + c->err);
+    }
+    std::vector<int> lo, hi;
+    split(p->nx, p->px, p->r, lo, hi, p->shift_x);
+    const std::vector<double> ax = axis_window(p->Nx, p->xlo, lo);
+    split(p->ny, p->py, p->q, lo, hi, p->shift_y);
+    const std::vector<double> ay = axis_window(p->Ny, p->ylo, lo);
+    int rc;
+    if ((rc = dalloc(p, &p->d_wx, ax.size())) != LSW_OK) return rc;
+    if ((rc = dalloc(p, &p->d_wy, ay.size())) != LSW_OK) return rc;
+    if ((rc = dalloc(p, &p->d_wr, (size_t)p->nrhs_max * p->N)) != LSW_OK) return rc;
+    if ((rc = dalloc(p, &p->d_wz, (size_t)p->nrhs_max * p->N)) != LSW_OK) return rc;
+    HIPCK(p, hipMemcpy(p->d_wx, ax.data(), sizeof(double) * ax.size(), hipMemcpyHostToDevice));
+    HIPCK(p, hipMemcpy(p->d_wy, ay.data(), sizeof(double) * ay.size(), hipMemcpyHostToDevice));
     return LSW_OK;
 }
 
@@ -1567,6 +1676,13 @@ int lsw_apply(lsw_handle_t p, const double* d_r, double* d_z, int nrhs) {
     rc = apply_impl(p, reinterpret_cast<const c128*>(d_r), reinterpret_cast<c128*>(d_z), nrhs, true);
     if (rc != LSW_OK) return rc;
     HIPCK(p, hipEventSynchronize(p->ev[4]));
+    if (p->windows) {   // only the whole application is timed
+        float t = 0;
+        HIPCK(p, hipEventElapsedTime(&t, p->ev[0], p->ev[4]));
+        p->last_apply_ms = t;
+        p->last_stage1_ms = p->last_gemv_ms = p->last_final_rhs_ms = p->last_final_ms = p->last_chain_ms = 0;
+        return LSW_OK;
+    }
     float t01 = 0, t12 = 0, t23 = 0, t34 = 0, t04 = 0;
     HIPCK(p, hipEventElapsedTime(&t01, p->ev[0], p->ev[1]));
     HIPCK(p, hipEventElapsedTime(&t12, p->ev[1], p->ev[2]));
@@ -1678,6 +1794,30 @@ int lsw_query(lsw_handle_t p, lsw_stats_t* st) {
     st->packed_factor_elems = p->gsym ? (long long)p->GS_elems : 0;
     st->gemv_items = (int)p->gitems.size();
     st->gemv_max_inputs = p->max_nin;
+    st->cdd_count = p->windows ? 4 : 1;
+    st->window_shift[0] = p->shift_x;
+    st->window_shift[1] = p->shift_y;
+    if (p->windows) {   // totals over the four CDDs (the setup time already covers all four)
+        for (const lsw_plan* c : p->shifted) {
+            st->n_subdomains += (int)c->subs.size();
+            st->factor_elems += (long long)c->G_elems;
+            st->solves_per_apply += (int)c->descs.size();
+            st->fronts_per_apply += (int)c->fronts.size();
+            st->apply_chain_bytes += c->apply_chain_bytes;
+            st->apply_gemv_bytes += c->apply_gemv_bytes;
+            st->chain_launches += c->chain_launches;
+            st->gemv_launches += c->gemv_launches;
+            st->q_elems += (long long)c->QP_elems;
+            st->factor_flops += c->factor_flops;
+            st->t_factor_ms += c->t_factor_ms;
+            st->t_q_ms += c->t_q_ms;
+            st->apply_stage1_bytes += c->apply_stage1_bytes;
+            st->apply_final_bytes += c->apply_final_bytes;
+            st->packed_factor_elems += c->gsym ? (long long)c->GS_elems : 0;
+            st->gemv_items += (int)c->gitems.size();
+            st->gemv_max_inputs = std::max(st->gemv_max_inputs, c->max_nin);
+        }
+    }
     return LSW_OK;
 }
 

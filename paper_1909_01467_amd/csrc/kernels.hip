@@ -1519,6 +1519,26 @@ __global__ void k_cast(const c128* src, c64* dst, size_t n) {
         dst[i] = c64{static_cast<float>(src[i].re), static_cast<float>(src[i].im)};
 }
 
+// ------------------------------------------------------------------ scenario 4 windows (Sec. 2.1)
+// out = phi (.) r over nrhs vectors of N = Nx*Ny points; phi = A(x) B(y) with A = a, or 1 - a for
+// the CDD shifted along x (kx = 1), and B = b, or 1 - b for the CDD shifted along y (ky = 1)
+__global__ void k_window(const c128* r, c128* out, const double* wx, const double* wy, int kx, int ky, int Nx,
+                         size_t N, size_t total) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (size_t)gridDim.x * blockDim.x) {
+        const size_t pnt = i % N;
+        const int x = (int)(pnt % Nx), y = (int)(pnt / Nx);
+        const double A = kx ? 1.0 - wx[x] : wx[x];
+        const double B = ky ? 1.0 - wy[y] : wy[y];
+        const double f = A * B;
+        out[i] = c128{f * r[i].re, f * r[i].im};
+    }
+}
+
+__global__ void k_accumulate(c128* z, const c128* add, size_t n) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        z[i] = c128{z[i].re + add[i].re, z[i].im + add[i].im};
+}
+
 // ------------------------------------------------------------------ z assembly
 template <typename T>
 __global__ void k_zsum(ZsumArgs a) {
@@ -1856,6 +1876,19 @@ hipError_t launch_pmap(const GemvSolve* gs, int ngs, int max_nin, const SubDesc*
 
 hipError_t launch_cast(const c128* src, c64* dst, size_t n, hipStream_t st) {
     k_cast<<<2048, 256, 0, st>>>(src, dst, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_window(const c128* r, c128* out, const double* wx, const double* wy, int kx, int ky, int Nx,
+                         size_t N, int nrhs, hipStream_t st) {
+    const size_t total = N * (size_t)nrhs;
+    k_window<<<(unsigned)std::min<size_t>(4096, blocks_for(total, 256)), 256, 0, st>>>(r, out, wx, wy, kx, ky, Nx,
+                                                                                      N, total);
+    return hipGetLastError();
+}
+
+hipError_t launch_accumulate(c128* z, const c128* add, size_t n, hipStream_t st) {
+    k_accumulate<<<(unsigned)std::min<size_t>(4096, blocks_for(n, 256)), 256, 0, st>>>(z, add, n);
     return hipGetLastError();
 }
 

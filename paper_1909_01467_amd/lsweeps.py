@@ -6,7 +6,7 @@ There is no CPU fallback: importing this module without the built library, or ca
 it without a GPU, raises.
 
     Solver(m_ext, omega, h, n, n_pml, q, r, ...)   lsw_setup  (Setup + Factorise, Sec. 3)
-    Solver.apply(r)                                 lsw_apply  (z = M^-1 r, Alg. Scenario3)
+    Solver.apply(r)                                 lsw_apply  (z = M^-1 r, Alg. Scenario3 / scenario 4)
     Solver.solve(f)                                 lsw_solve  (FGMRES, Sec. 3 Phase 3)
     Solver.adjoint(g)                               lsw_adjoint (A^H v = g via A = A^T)
     Solver.matvec(x)                                lsw_matvec (y = A x)
@@ -36,7 +36,7 @@ class lsw_grid_t(ctypes.Structure):
 
 
 class lsw_cdd_t(ctypes.Structure):
-    _fields_ = [("q", ctypes.c_int), ("r", ctypes.c_int)]
+    _fields_ = [("q", ctypes.c_int), ("r", ctypes.c_int), ("windows", ctypes.c_int), ("shift", ctypes.c_int * 2)]
 
 
 class lsw_pml_t(ctypes.Structure):
@@ -73,7 +73,7 @@ class lsw_stats_t(ctypes.Structure):
                 ("last_final_rhs_ms", ctypes.c_double), ("rhs_per_workgroup", ctypes.c_int),
                 ("tune_ms", ctypes.c_double * 3), ("symmetric_factors", ctypes.c_int),
                 ("packed_factor_elems", ctypes.c_longlong), ("gemv_items", ctypes.c_int),
-                ("gemv_max_inputs", ctypes.c_int)]
+                ("gemv_max_inputs", ctypes.c_int), ("cdd_count", ctypes.c_int), ("window_shift", ctypes.c_int * 2)]
 
 
 _lib = None
@@ -141,12 +141,17 @@ def _dptr(t: torch.Tensor) -> int:
 
 
 class Solver:
-    """A set-up and factorised L-sweeps preconditioner with its GMRES solver (one lsw handle)."""
+    """A set-up and factorised L-sweeps preconditioner with its GMRES solver (one lsw handle).
+
+    windows=True selects scenario 4 (Sec. 2.1): the CDD and three shifted copies, each sweeping
+    the right-hand side times its window of a partition of unity; `shift` is then the shift of
+    the copies along (x, y) ((0, 0): half of the smallest group).  Without windows `shift`
+    shifts this CDD's own interior boundaries."""
 
     def __init__(self, m_ext: torch.Tensor, omega: float, h: float, n, n_pml, q: int, r: int | None = None,
                  C: float | None = None, n_pml_local: int | None = None, precision: str = "fp64",
                  restart: int = 50, maxit: int = 500, tol: float = 1e-6, nrhs_max: int = 1,
-                 sweep_mode: str = "compressed"):
+                 sweep_mode: str = "compressed", windows: bool = False, shift=(0, 0)):
         lib = load_library()
         if not torch.cuda.is_available():
             raise RuntimeError("the L-sweeps library needs a GPU")
@@ -168,7 +173,7 @@ class Solver:
         self.C = 16.0 * math.log(omega) if C is None else C
         self.precision = precision
         grid = lsw_grid_t(dim, (ctypes.c_int * 3)(*ns, *([0] * (3 - dim))), (ctypes.c_int * 3)(*ps, *([0] * (3 - dim))))
-        cdd = lsw_cdd_t(q, r)
+        cdd = lsw_cdd_t(q, r, 1 if windows else 0, (ctypes.c_int * 2)(*shift))
         pml = lsw_pml_t(self.C, -1 if n_pml_local is None else n_pml_local)
         self.stream = torch.cuda.current_stream()
         if sweep_mode not in ("compressed", "chain"):
@@ -256,6 +261,7 @@ class Solver:
         self._check(self._lib.lsw_query(self._h, ctypes.byref(st)))
         out = {name: getattr(st, name) for name, _ in lsw_stats_t._fields_}
         out["tune_ms"] = list(out["tune_ms"])
+        out["window_shift"] = list(out["window_shift"])
         return out
 
     def close(self):
