@@ -98,15 +98,15 @@ def counter_traffic(kernel: str):
     return None
 
 
-def cpu_baseline(workload: str, budget_s: float = 60.0):
-    """The FP64 oracle (Alg. Scenario3 with SuperLU local solves inside FGMRES), timed on the
-    host on the same workload: setup and one solve to 1e-6."""
-    import numpy as np
+def cpu_baseline(workload: str, windows: bool = False):
+    """The FP64 oracle (Alg. Scenario3, or scenario 4 with windows, with SuperLU local solves
+    inside FGMRES), timed on the host on the same workload: setup and one solve to 1e-6."""
     from threadpoolctl import threadpool_limits
 
     from oracle.discretization import GlobalProblem, extend_normal
     from oracle.fgmres import fgmres
     from oracle.lsweep import LSweep2D
+    from oracle.scenario4 import Scenario4
     from paper_1909_01467_amd import inputs
 
     wl = inputs.workload(workload)
@@ -114,7 +114,7 @@ def cpu_baseline(workload: str, budget_s: float = 60.0):
         m = extend_normal(wl.slowness2, wl.n_pml)
         t0 = time.perf_counter()
         gp = GlobalProblem(m, wl.omega, wl.n, wl.n_pml, wl.C)
-        ls = LSweep2D(m, wl.omega, wl.n, wl.n_pml, wl.q, wl.r, wl.C)
+        ls = (Scenario4 if windows else LSweep2D)(m, wl.omega, wl.n, wl.n_pml, wl.q, wl.r, wl.C)
         t1 = time.perf_counter()
         b = gp.rhs(wl.sources[0])
         res = fgmres(lambda v: gp.A @ v, ls.apply, b, tol=1e-6)
@@ -133,6 +133,8 @@ def main():
     ap.add_argument("--workload", default="lens2d")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--windows", action="store_true",
+                    help="scenario 4 (Sec. 2.1): the CDD and three shifted copies with a partition of unity")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="first run one device copy of this many MiB (calibrates FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
@@ -158,7 +160,8 @@ def main():
     log("workload", wl.name, "n", wl.n, "q", wl.q, "omega", round(wl.omega, 2))
     results = {}
     for precision in (["mixed"] if args.no_fp64 else ["mixed", "fp64"]):
-        s = Solver(m_ext, wl.omega, wl.h, wl.n, wl.n_pml, wl.q, wl.r, C=wl.C, precision=precision, tol=1e-6)
+        s = Solver(m_ext, wl.omega, wl.h, wl.n, wl.n_pml, wl.q, wl.r, C=wl.C, precision=precision, tol=1e-6,
+                   windows=args.windows)
         st0 = s.stats()
         log(precision, "setup ms", round(st0["t_setup_ms"], 1), "factor ms", round(st0["t_factor_ms"], 1))
         u, info, ms = time_solves(s, b, args.steps, args.warmup)
@@ -185,19 +188,21 @@ def main():
                             ms=med["last_stage1_ms"] + med["last_gemv_ms"]),
         }
     else:
-        # the one-right-hand-side substitutions read the packed symmetric factors when built
+        # the one-right-hand-side substitutions read the packed symmetric factors when built;
+        # with windows every family runs once per CDD (four times)
         sym = bool(st.get("symmetric_factors"))
+        ncdd = st["cdd_count"]
         chain = "k_chain_sym" if sym else "k_chain"
         layout = ("packed symmetric factors, 4x4 tiles of the upper triangle" if sym else "full factor blocks")
         kernels = {
             f"{chain}<CS_STAGE1>": dict(desc=f"stage-1 block substitutions, twisted (forward halves; middle + backward "
                                              f"halves), {layout}",
-                                        launches=2, bytes=st["apply_stage1_bytes"], ms=med["last_stage1_ms"]),
+                                        launches=2 * ncdd, bytes=st["apply_stage1_bytes"], ms=med["last_stage1_ms"]),
             "k_gemv": dict(desc="trace-compressed sweep fronts: out = Q' u~ per solve (batched GEMV)",
                            launches=st["gemv_launches"], bytes=st["apply_gemv_bytes"], ms=med["last_gemv_ms"]),
             f"{chain}<CS_FINAL>": dict(desc=f"final z block substitutions, twisted (forward halves; middle + backward "
                                             f"halves), {layout}",
-                                       launches=2, bytes=st["apply_final_bytes"], ms=med["last_final_ms"]),
+                                       launches=2 * ncdd, bytes=st["apply_final_bytes"], ms=med["last_final_ms"]),
         }
     for k in kernels.values():
         k["bytes_per_launch"] = k["bytes"] / max(1, k["launches"])
@@ -225,6 +230,9 @@ def main():
                          f"noise, 10 ppw (omega={wl.omega:.2f}), 1 Gaussian source, GMRES tol 1e-6") if wl.dim == 2 else
                         (f"{wl.name}: {wl.n}^3 bulk + {wl.n_pml}-pt PML, {wl.q}x{wl.r} beam CDD (full z), Gaussian "
                          f"lens, 8 ppw (omega={wl.omega:.2f}), 1 Gaussian source, GMRES tol 1e-6"),
+            "preconditioner": ("scenario 4: the CDD and three copies shifted by (%d, %d) points, windowed "
+                               "right-hand sides (Sec. 2.1)" % tuple(st["window_shift"]) if args.windows else
+                               "scenario 3: one CDD (Alg. Scenario3)"),
             "precision": "complex64 factors and sweeps, FP64 FGMRES",
             "iterations": main_r["info"]["iterations"][0],
             "relres": main_r["info"]["relres"][0],
@@ -245,7 +253,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": (counter_traffic(dom_name) if args.workload == "lens2d" else None),
+            "traffic": (counter_traffic(dom_name) if args.workload == "lens2d" and not args.windows else None),
             "algorithmic_bytes_per_launch": round(dom["bytes_per_launch"]),
             "avg_launch_ms": round(dom["avg_launch_ms"], 5),
         },
@@ -258,7 +266,7 @@ def main():
         out["config"]["mixed_speedup_vs_fp64"] = round(f["ms"] / main_r["ms"], 3)
     if not args.no_cpu_baseline and wl.dim == 2:
         log("cpu baseline (oracle) ...")
-        out["cpu_baseline"] = cpu_baseline(args.workload)
+        out["cpu_baseline"] = cpu_baseline(args.workload, args.windows)
     print(json.dumps(out), flush=True)
 
 

@@ -75,9 +75,12 @@ typedef struct {
                             with the interior boundaries shifted by shift[0] along x, shift[1] along y
                             and both, each sweeping the right-hand side multiplied by its window of a
                             partition of unity; M^-1 r is the sum of the four sweeps */
-    int shift[2];        /* windows = 0: shift of this CDD's interior boundaries (points towards larger
-                            x / y; 0 = the even split).  windows = 1: the shift of the three shifted
-                            CDDs, <= 0 selecting half of the smallest bulk group; it must lie in
+    int shift[2];        /* windows = 0: s = shift[0] (x) or shift[1] (y) > 0 translates this CDD's
+                            interfaces along that axis: every group start of the even split, the
+                            first bulk point included, moves by s points towards larger indices, so
+                            the axis has one more group (the first holds the PML and s bulk points);
+                            0 = the even split.  windows = 1: the shift of the shifted CDDs, <= 0
+                            selecting half of the smallest bulk group; it must lie in
                             [3, smallest group - 3] so that the skeletons are disjoint */
 } lsw_cdd_t;
 
@@ -142,8 +145,9 @@ typedef struct {
     long long packed_factor_elems;  /* complex entries of the packed blocks (0 if not built) */
     int gemv_items;              /* work items (<= 64 output rows of one sweep solve) per application */
     int gemv_max_inputs;         /* largest input count (incoming trace values) of a sweep solve */
-    int cdd_count;               /* 1, or 4 with windows (sizes, work and setup times above are totals
-                                    over the four CDDs; W_max/H_max and the kernel timings are the first's) */
+    int cdd_count;               /* 1, or 4 with windows: then sizes, work, setup times and the kernel-family
+                                    times above are totals over the four CDDs (W_max/H_max: the first's),
+                                    and last_apply_ms also covers the window and accumulation kernels */
     int window_shift[2];         /* shift of the shifted CDDs along x / y (0 without windows) */
 } lsw_stats_t;
 
@@ -163,10 +167,10 @@ typedef struct {
  * or along z (3D: every subdomain is a beam over all z, blocks are its xy planes of at most
  * 4096 points, and the global z PML is kept at both beam ends).
  * With cdd->windows = 1 it builds and factorises the four CDDs of scenario 4 (Sec. 2.1) and the
- * window tables a(x), b(y): a = 0 on the two trace lines of every original interface, 1 on those
+ * window tables a(x), b(y): a = 0 on the two trace lines of every interface of the CDD, 1 on those
  * of every shifted one, a linear ramp in between (w(d) / (w(d) + w(d')), w(t) = max(0, t - 1), d
- * and d' the distances to the nearest original and shifted interface), 0 before the first
- * interface and 1 after the last; the four windows are a b, (1-a) b, a (1-b), (1-a)(1-b).
+ * and d' the distances to the nearest interface of either kind), and 1 beyond the outermost
+ * (shifted) interfaces; the four windows are a b, (1-a) b, a (1-b), (1-a)(1-b).
  * Errors: LSW_EINVAL (dim not 2 or 3, sizes, a window that does not fit the grid, windows
  * with dim 3, q or r below 2 or a shift outside its range),
  * LSW_ENAN (non-finite m), LSW_ENOMEM, LSW_EHIP, LSW_ESINGULAR.  On error *out is NULL

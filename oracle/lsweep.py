@@ -49,10 +49,13 @@ from .discretization import alpha_of, assemble, axis_points, cubic_sigma
 def partition(n_bulk: int, n_pml: int, groups: int, shift: int = 0):
     """[lo, hi) of each group along one axis (extended-grid indices).
 
-    `shift` moves every interior group boundary by that many points towards larger indices
-    (the shifted CDDs of scenario 4, Sec. 2.1); the returned sizes are those of the even split."""
+    shift > 0 gives the shifted CDD of scenario 4 (Sec. 2.1): every group start of the even split,
+    the first bulk point included, moves by `shift` points towards larger indices, so the axis has
+    one more group (the first holds the PML and `shift` bulk points).  The returned sizes are those
+    of the even split."""
     sizes = [n_bulk // groups + (1 if g < n_bulk % groups else 0) for g in range(groups)]
-    bounds = [n_pml + sum(sizes[:g]) + shift for g in range(1, groups)]
+    first = 1 if shift == 0 else 0
+    bounds = [n_pml + sum(sizes[:g]) + shift for g in range(first, groups)]
     lo = [0] + bounds
     hi = bounds + [n_bulk + 2 * n_pml]
     return lo, hi, sizes
@@ -62,8 +65,8 @@ SIDES = ("B", "R", "T", "L")
 
 
 class LSweep2D:
-    """Alg. Scenario3 for a 2D q x r CDD; `shift` = (sx, sy) moves the interior boundaries of
-    each axis (the shifted CDDs of scenario 4)."""
+    """Alg. Scenario3 for a 2D q x r CDD; `shift` = (sx, sy) shifts the group boundaries of each
+    axis (the shifted CDDs of scenario 4; a shifted axis has one more group)."""
 
     def __init__(self, m_ext: np.ndarray, omega: float, n, n_pml, q: int, r: int, C: float,
                  n_pml_local: int | None = None, h: float | None = None, shift=(0, 0)):
@@ -81,6 +84,7 @@ class LSweep2D:
         self.shift = tuple(shift)
         self.xlo, self.xhi, _ = partition(nx, px, r, self.shift[0])
         self.ylo, self.yhi, _ = partition(ny, py, q, self.shift[1])
+        q, r = self.q, self.r = len(self.ylo), len(self.xlo)
         for lo, hi, N in ((self.xlo, self.xhi, self.Nex), (self.ylo, self.yhi, self.Ney)):
             for g in range(len(lo)):
                 if hi[g] - lo[g] < 2 or (g > 0 and lo[g] < self.e) or \

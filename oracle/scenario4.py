@@ -8,23 +8,25 @@ skeleton of its own CDD, scenario 3 on that CDD handles it, and the approximate 
 the sum of the four results:  z = sum_k M_k^-1 (phi_k r).
 
 The paper fixes neither the shift nor the windows; the readings taken here:
-  * Shift: every interior group boundary of an axis moves by s points towards larger
-    indices (the edge groups keep the global PML); by default s is half of the smallest
-    bulk group of that axis.  The skeletons of the two CDDs of one axis are then disjoint
-    and interleaved.
+  * Shift: the CDD's grid of interfaces is translated by s points towards larger indices along
+    the shifted axis: every group start of the even split, the first bulk point included, moves
+    by s, so the shifted axis has one more group (the first holds the PML and s bulk points, the
+    last the remaining bulk points and the PML) and no group is larger than in the CDD.  By
+    default s is half of the smallest bulk group.  The skeletons of the two CDDs of one axis are
+    then disjoint and interleaved, the shifted one on both ends.
   * Windows: tensor products phi = a(x) b(y).  Along one axis, with interfaces at
-    P = lo - 1/2 (original CDD) and P' = lo' - 1/2 (shifted CDD), d and d' the distances
-    of a point to the nearest P and P', and w(t) = max(0, t - 1):
-        a = 0 to the left of the first P, a = 1 to the right of the last P',
-        a = w(d) / (w(d) + w(d')) in between.
-    a vanishes on the two trace lines of every original interface (d = 1/2) and equals 1 on
-    those of every shifted one; between them it is a linear ramp.  The CDD unshifted along
-    this axis takes a, the shifted one 1 - a, so the four products sum to one.
+    P = lo - 1/2 (CDD) and P' = lo' - 1/2 (shifted CDD), d and d' the distances of a point to the
+    nearest P and P', and w(t) = max(0, t - 1):
+        a = w(d) / (w(d) + w(d')) between the first and the last interface,
+        a = 1 beyond them (the nearest interface there is a shifted one).
+    a vanishes on the two trace lines of every interface of the CDD (d = 1/2) and equals 1 on those
+    of every shifted one; between them it is a linear ramp.  The CDD unshifted along this axis
+    takes a, the shifted one 1 - a, so the four products sum to one.
 
-Pins (tests/test_oracle_scenario4.py): the partition of unity and its vanishing on each
-CDD's skeleton; exact reconstruction of A^-1 f (up to the PML error) for sources that
-cross the original skeleton, where scenario 3 alone is visibly worse; reduction to
-scenario 3 when only one window is kept.
+Pins (tests/test_oracle_scenario4.py): the shifted partition; the window ramp; the partition of
+unity and its vanishing on each CDD's skeleton; reconstruction of A^-1 f up to the PML error for
+sources on the skeleton; each shifted CDD alone reconstructing its windowed source; a planted
+dropped window failing the reconstruction.
 """
 from __future__ import annotations
 
@@ -40,18 +42,17 @@ def default_shift(n_bulk: int, groups: int) -> int:
 
 def axis_window(N: int, lo: list[int], lo_shifted: list[int]) -> np.ndarray:
     """The window a(x) of one axis on its N extended-grid points (see the module notes).
-    lo / lo_shifted are the group starts of the original and shifted CDD (lo[0] = 0)."""
+    lo / lo_shifted are the group starts of the CDD and of the shifted CDD (lo[0] = 0)."""
     P = np.asarray(lo[1:], dtype=np.float64) - 0.5
     Ps = np.asarray(lo_shifted[1:], dtype=np.float64) - 0.5
+    first, last = min(P.min(), Ps.min()), max(P.max(), Ps.max())
     a = np.empty(N)
     for x in range(N):
-        if x < P.min():
-            a[x] = 0.0
-        elif x > Ps.max():
-            a[x] = 1.0
+        d, ds = np.abs(x - P).min(), np.abs(x - Ps).min()
+        if x < first or x > last:
+            a[x] = 1.0 if ds < d else 0.0
         else:
-            w = max(0.0, np.abs(x - P).min() - 1.0)
-            ws = max(0.0, np.abs(x - Ps).min() - 1.0)
+            w, ws = max(0.0, d - 1.0), max(0.0, ds - 1.0)
             a[x] = w / (w + ws)
     return a
 

@@ -146,6 +146,7 @@ struct lsw_plan {
     double* d_wy = nullptr;         // b(y) on the Ny extended points
     c128* d_wr = nullptr;           // windowed right-hand sides [nrhs][N]
     c128* d_wz = nullptr;           // one shifted CDD's sweep result [nrhs][N]
+    hipEvent_t evw[2] = {nullptr, nullptr};   // start and end of a windowed application
 };
 
 namespace {
@@ -195,42 +196,45 @@ void free_plan(lsw_plan* p) {
     if (p->h_coef) (void)hipHostFree(p->h_coef);
     for (hipEvent_t e : p->ev)
         if (e) (void)hipEventDestroy(e);
+    for (hipEvent_t e : p->evw)
+        if (e) (void)hipEventDestroy(e);
     if (p->rb) (void)rocblas_destroy_handle(p->rb);
     delete p;
 }
 
 // ---------------------------------------------------------------- geometry
-// groups of one axis; shift moves every interior boundary towards larger indices (the shifted
-// CDDs of scenario 4)
+// groups of one axis.  shift > 0 gives a shifted CDD of scenario 4: every group start of the even
+// split, the first bulk point included, moves by shift points towards larger indices, so the axis
+// has one more group (the first holds the PML and shift bulk points)
 void split(int n_bulk, int n_pml, int groups, std::vector<int>& lo, std::vector<int>& hi, int shift = 0) {
-    lo.assign(groups, 0);
-    hi.assign(groups, 0);
+    std::vector<int> bounds;
     int start = n_pml;
     for (int g = 0; g < groups; ++g) {
-        const int size = n_bulk / groups + (g < n_bulk % groups ? 1 : 0);
-        lo[g] = (g == 0) ? 0 : start + shift;
-        start += size;
-        hi[g] = (g == groups - 1) ? n_bulk + 2 * n_pml : start + shift;
+        if (g > 0 || shift > 0) bounds.push_back(start + shift);
+        start += n_bulk / groups + (g < n_bulk % groups ? 1 : 0);
     }
+    lo.assign(1, 0);
+    lo.insert(lo.end(), bounds.begin(), bounds.end());
+    hi = bounds;
+    hi.push_back(n_bulk + 2 * n_pml);
 }
 
 // the window a of one axis (scenario 4): 0 on the trace lines of the interfaces at lo[g] - 1/2
 // (g >= 1), 1 on those of the shifted interfaces at los[g] - 1/2, a linear ramp w(d) / (w(d) + w(d'))
-// with w(t) = max(0, t - 1) between them, 0 before the first interface and 1 after the last
+// with w(t) = max(0, t - 1) between them; beyond the first and the last interface it takes the
+// value of the nearest one's kind
 std::vector<double> axis_window(int N, const std::vector<int>& lo, const std::vector<int>& los) {
     std::vector<double> a(N);
-    const double first = lo[1] - 0.5, last = los.back() - 0.5;
+    double first = 1e300, last = -1e300;
+    for (size_t g = 1; g < lo.size(); ++g) first = std::min(first, lo[g] - 0.5), last = std::max(last, lo[g] - 0.5);
+    for (size_t g = 1; g < los.size(); ++g) first = std::min(first, los[g] - 0.5), last = std::max(last, los[g] - 0.5);
     for (int x = 0; x < N; ++x) {
-        if (x < first) {
-            a[x] = 0.0;
-        } else if (x > last) {
-            a[x] = 1.0;
+        double d = 1e300, ds = 1e300;
+        for (size_t g = 1; g < lo.size(); ++g) d = std::min(d, std::fabs(x - (lo[g] - 0.5)));
+        for (size_t g = 1; g < los.size(); ++g) ds = std::min(ds, std::fabs(x - (los[g] - 0.5)));
+        if (x < first || x > last) {
+            a[x] = ds < d ? 1.0 : 0.0;
         } else {
-            double d = 1e300, ds = 1e300;
-            for (size_t g = 1; g < lo.size(); ++g) {
-                d = std::min(d, std::fabs(x - (lo[g] - 0.5)));
-                ds = std::min(ds, std::fabs(x - (los[g] - 0.5)));
-            }
             const double w = std::max(0.0, d - 1.0), ws = std::max(0.0, ds - 1.0);
             a[x] = w / (w + ws);
         }
@@ -701,18 +705,19 @@ int apply_cdd(lsw_plan* p, const c128* d_r, c128* d_z, int nrhs, bool timed) {
 }
 
 // z = M^-1 r: one CDD, or with windows the sum over the four CDDs of their sweeps of phi_k r
-// (scenario 4, Sec. 2.1); events [0] and [4] bracket the whole application
+// (scenario 4, Sec. 2.1); with windows every CDD times its own kernel families and evw brackets
+// the whole application
 int apply_impl(lsw_plan* p, const c128* d_r, c128* d_z, int nrhs, bool timed) {
     if (!p->windows) return apply_cdd(p, d_r, d_z, nrhs, timed);
-    if (timed) HIPCK(p, hipEventRecord(p->ev[0], p->stream));
+    if (timed) HIPCK(p, hipEventRecord(p->evw[0], p->stream));
     for (int k = 0; k < 4; ++k) {
         lsw_plan* c = k == 0 ? p : p->shifted[k - 1];
         HIPCK(p, launch_window(d_r, p->d_wr, p->d_wx, p->d_wy, k & 1, k >> 1, p->Nx, p->N, nrhs, p->stream));
-        const int rc = apply_cdd(c, p->d_wr, k == 0 ? d_z : p->d_wz, nrhs, false);
+        const int rc = apply_cdd(c, p->d_wr, k == 0 ? d_z : p->d_wz, nrhs, timed);
         if (rc != LSW_OK) return c == p ? rc : fail(p, rc, c->err);
         if (k > 0) HIPCK(p, launch_accumulate(d_z, p->d_wz, p->N * (size_t)nrhs, p->stream));
     }
-    if (timed) HIPCK(p, hipEventRecord(p->ev[4], p->stream));
+    if (timed) HIPCK(p, hipEventRecord(p->evw[1], p->stream));
     return LSW_OK;
 }
 
@@ -1167,6 +1172,8 @@ int setup_impl(lsw_plan* p, const double* d_m, double omega, double h, const lsw
     p->N = (size_t)p->Nx * p->Ny * p->Nz;
     split(p->nx, p->px, p->r, p->xlo, p->xhi, own_sx);
     split(p->ny, p->py, p->q, p->ylo, p->yhi, own_sy);
+    p->r = (int)p->xlo.size();   // a shifted axis has one more group
+    p->q = (int)p->ylo.size();
     auto windows = [&](const std::vector<int>& lo, const std::vector<int>& hi, int Nax, std::vector<int>& w0,
                        std::vector<int>& w1) -> bool {
         const int G = (int)lo.size();
@@ -1636,6 +1643,36 @@ int setup_windows(lsw_plan* p, const double* d_m, double omega, double h, const 
     if ((rc = dalloc(p, &p->d_wz, (size_t)p->nrhs_max * p->N)) != LSW_OK) return rc;
     HIPCK(p, hipMemcpy(p->d_wx, ax.data(), sizeof(double) * ax.size(), hipMemcpyHostToDevice));
     HIPCK(p, hipMemcpy(p->d_wy, ay.data(), sizeof(double) * ay.size(), hipMemcpyHostToDevice));
+    for (hipEvent_t& e : p->evw) HIPCK(p, hipEventCreate(&e));
+    return LSW_OK;
+}
+
+// the kernel-family times of the last timed application of one CDD (its events are complete)
+int read_apply_times(lsw_plan* p) {
+    float t01 = 0, t12 = 0, t23 = 0, t34 = 0, t04 = 0;
+    HIPCK(p, hipEventElapsedTime(&t01, p->ev[0], p->ev[1]));
+    HIPCK(p, hipEventElapsedTime(&t12, p->ev[1], p->ev[2]));
+    HIPCK(p, hipEventElapsedTime(&t23, p->ev[2], p->ev[3]));
+    HIPCK(p, hipEventElapsedTime(&t34, p->ev[3], p->ev[4]));
+    HIPCK(p, hipEventElapsedTime(&t04, p->ev[0], p->ev[4]));
+    p->last_apply_ms = t04;
+    if (p->dim == 3) {   // [0,1] stage-1 front, [1,2] the other fronts, [3,4] the sum of the sweep parts
+        p->last_stage1_ms = t01;
+        p->last_gemv_ms = t12;
+        p->last_final_rhs_ms = 0;
+        p->last_final_ms = t34;
+        p->last_chain_ms = t01 + t12;
+    } else if (p->sweep_mode == LSW_SWEEP_CHAIN) {
+        p->last_chain_ms = t01;
+        p->last_gemv_ms = 0;
+        p->last_stage1_ms = p->last_final_ms = p->last_final_rhs_ms = 0;
+    } else {
+        p->last_stage1_ms = t01;
+        p->last_gemv_ms = t12;
+        p->last_final_rhs_ms = t23;
+        p->last_final_ms = t34;
+        p->last_chain_ms = t01 + t34;
+    }
     return LSW_OK;
 }
 
@@ -1675,39 +1712,31 @@ int lsw_apply(lsw_handle_t p, const double* d_r, double* d_z, int nrhs) {
     if (rc != LSW_OK) return rc;
     rc = apply_impl(p, reinterpret_cast<const c128*>(d_r), reinterpret_cast<c128*>(d_z), nrhs, true);
     if (rc != LSW_OK) return rc;
-    HIPCK(p, hipEventSynchronize(p->ev[4]));
-    if (p->windows) {   // only the whole application is timed
+    if (p->windows) {   // per-family times summed over the four CDDs, the total from the bracket
+        HIPCK(p, hipEventSynchronize(p->evw[1]));
+        if ((rc = read_apply_times(p)) != LSW_OK) return rc;
+        double s1 = p->last_stage1_ms, gv = p->last_gemv_ms, fr = p->last_final_rhs_ms, fi = p->last_final_ms,
+               ch = p->last_chain_ms;
+        for (lsw_plan* c : p->shifted) {
+            if ((rc = read_apply_times(c)) != LSW_OK) return fail(p, rc, c->err);
+            s1 += c->last_stage1_ms;
+            gv += c->last_gemv_ms;
+            fr += c->last_final_rhs_ms;
+            fi += c->last_final_ms;
+            ch += c->last_chain_ms;
+        }
         float t = 0;
-        HIPCK(p, hipEventElapsedTime(&t, p->ev[0], p->ev[4]));
+        HIPCK(p, hipEventElapsedTime(&t, p->evw[0], p->evw[1]));
         p->last_apply_ms = t;
-        p->last_stage1_ms = p->last_gemv_ms = p->last_final_rhs_ms = p->last_final_ms = p->last_chain_ms = 0;
+        p->last_stage1_ms = s1;
+        p->last_gemv_ms = gv;
+        p->last_final_rhs_ms = fr;
+        p->last_final_ms = fi;
+        p->last_chain_ms = ch;
         return LSW_OK;
     }
-    float t01 = 0, t12 = 0, t23 = 0, t34 = 0, t04 = 0;
-    HIPCK(p, hipEventElapsedTime(&t01, p->ev[0], p->ev[1]));
-    HIPCK(p, hipEventElapsedTime(&t12, p->ev[1], p->ev[2]));
-    HIPCK(p, hipEventElapsedTime(&t23, p->ev[2], p->ev[3]));
-    HIPCK(p, hipEventElapsedTime(&t34, p->ev[3], p->ev[4]));
-    HIPCK(p, hipEventElapsedTime(&t04, p->ev[0], p->ev[4]));
-    p->last_apply_ms = t04;
-    if (p->dim == 3) {   // [0,1] stage-1 front, [1,2] the other fronts, [3,4] the sum of the sweep parts
-        p->last_stage1_ms = t01;
-        p->last_gemv_ms = t12;
-        p->last_final_rhs_ms = 0;
-        p->last_final_ms = t34;
-        p->last_chain_ms = t01 + t12;
-    } else if (p->sweep_mode == LSW_SWEEP_CHAIN) {
-        p->last_chain_ms = t01;
-        p->last_gemv_ms = 0;
-        p->last_stage1_ms = p->last_final_ms = p->last_final_rhs_ms = 0;
-    } else {
-        p->last_stage1_ms = t01;
-        p->last_gemv_ms = t12;
-        p->last_final_rhs_ms = t23;
-        p->last_final_ms = t34;
-        p->last_chain_ms = t01 + t34;
-    }
-    return LSW_OK;
+    HIPCK(p, hipEventSynchronize(p->ev[4]));
+    return read_apply_times(p);
 }
 
 int lsw_solve(lsw_handle_t p, const double* d_f, double* d_u, int nrhs, lsw_info_t* info) {

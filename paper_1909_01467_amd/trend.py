@@ -15,7 +15,7 @@ Tab. Complexity its q = p column N_it (2 wavelengths), Tab. RandomWavespeed a ra
 (2 wavelengths); the random smooth medium here is inputs.speed_random_smooth.
 
 usage: python -m paper_1909_01467_amd.trend --q 2 4 8 16 --wavelengths 1 2 3 [--medium const|smooth]
-       [--precision mixed|fp64] [--json out.json]
+       [--precision mixed|fp64] [--windows] [--json out.json]
 Prints one line per case: q, n, n_pml, omega/2pi, iterations, relative residual, setup and solve
 times (ms).  Needs a GPU.
 """
@@ -31,7 +31,7 @@ import numpy as np
 
 
 def case(q: int, wavelengths: float, medium: str = "const", precision: str = "mixed", tol: float = 1e-6,
-         points_per_subdomain: int = 101, c_factor: float = 16.0, maxit: int = 200) -> dict:
+         points_per_subdomain: int = 101, c_factor: float = 16.0, maxit: int = 200, windows: bool = False) -> dict:
     import torch
 
     from . import inputs
@@ -49,7 +49,7 @@ def case(q: int, wavelengths: float, medium: str = "const", precision: str = "mi
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     s = Solver(m_ext, omega, h, n, n_pml, q, q, C=c_factor * math.log(omega), precision=precision, tol=tol,
-               maxit=maxit)
+               maxit=maxit, windows=windows)
     t_setup = (time.perf_counter() - t0) * 1e3
     try:
         s.solve(b)                                   # warm-up
@@ -61,6 +61,7 @@ def case(q: int, wavelengths: float, medium: str = "const", precision: str = "mi
     finally:
         s.close()
     return dict(q=q, n=n, n_pml=n_pml, wavelengths=wavelengths, medium=medium, precision=precision, c_factor=c_factor,
+                windows=windows,
                 omega_over_2pi=omega / (2.0 * math.pi), iterations=int(info["iterations"][0]),
                 relres=float(info["relres"][0]), converged=bool(info["converged"][0]),
                 t_setup_ms=round(t_setup, 1), t_solve_ms=round(t_solve, 2))
@@ -74,16 +75,17 @@ def main(argv=None) -> int:
     ap.add_argument("--precision", choices=["mixed", "fp64"], default="mixed")
     ap.add_argument("--c-factor", type=float, nargs="+", default=[16.0], help="C = factor * ln(omega)")
     ap.add_argument("--maxit", type=int, default=200)
+    ap.add_argument("--windows", action="store_true", help="scenario 4 (four shifted CDDs with windows)")
     ap.add_argument("--json", default=None)
     args = ap.parse_args(argv)
     rows = []
     for cf in args.c_factor:
         for w in args.wavelengths:
             for q in args.q:
-                r = case(q, w, args.medium, args.precision, c_factor=cf, maxit=args.maxit)
+                r = case(q, w, args.medium, args.precision, c_factor=cf, maxit=args.maxit, windows=args.windows)
                 rows.append(r)
                 print(f"q={r['q']:3d} n={r['n']:5d} n_pml={r['n_pml']:3d} omega/2pi={r['omega_over_2pi']:7.1f} "
-                      f"C/ln(omega)={cf:g} wavelengths={w:g} iterations={r['iterations']:3d} relres={r['relres']:.2e} "
+                      f"C/ln(omega)={cf:g} wavelengths={w:g} windows={int(args.windows)} iterations={r['iterations']:3d} relres={r['relres']:.2e} "
                       f"setup_ms={r['t_setup_ms']:.0f} solve_ms={r['t_solve_ms']:.1f}", flush=True)
     if args.json:
         with open(args.json, "w") as fh:

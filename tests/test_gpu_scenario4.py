@@ -102,8 +102,8 @@ def test_windowed_apply_mixed_matches_oracle(name):
 
 
 def test_shifted_cdd_alone_matches_oracle():
-    """A single CDD with shifted interior boundaries (windows off) against the oracle's sweep on
-    the same shifted CDD."""
+    """A single shifted CDD (windows off; one more group along each shifted axis) against the
+    oracle's sweep on the same shifted CDD."""
     c = CASES["ragged_45x38_3x2"]
     ls = LSweep2D(c.m, c.omega, (c.nx, c.ny), (c.px, c.py), c.q, c.r, c.C, h=c.h, shift=(7, 4))
     s = Solver(torch.from_numpy(c.m).cuda(), c.omega, c.h, (c.nx, c.ny), (c.px, c.py), c.q, c.r, C=c.C,
@@ -123,9 +123,14 @@ def test_windowed_apply_batches_rhs():
     Z = s.apply(Rt)
     for k in range(3):
         assert rel(to_np(Z[k]), to_np(s.apply(Rt[k]))) < 1e-13
-    assert s.stats()["solves_per_apply"] == 4 * Solver(
-        torch.from_numpy(c.m).cuda(), c.omega, c.h, (c.nx, c.ny), (c.px, c.py), c.q, c.r, C=c.C).stats()[
-        "solves_per_apply"]
+    # the work of the windowed plan is that of its four CDDs built alone
+    st = s.stats()
+    sx, sy = st["window_shift"]
+    alone = [Solver(torch.from_numpy(c.m).cuda(), c.omega, c.h, (c.nx, c.ny), (c.px, c.py), c.q, c.r, C=c.C,
+                    shift=sh).stats() for sh in ((0, 0), (sx, 0), (0, sy), (sx, sy))]
+    assert [(a["q"], a["r"]) for a in alone] == [(c.q, c.r), (c.q, c.r + 1), (c.q + 1, c.r), (c.q + 1, c.r + 1)]
+    for key in ("n_subdomains", "solves_per_apply", "factor_elems", "gemv_items"):
+        assert st[key] == sum(a[key] for a in alone), key
     s.close()
 
 

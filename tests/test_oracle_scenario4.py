@@ -14,26 +14,27 @@ from oracle.scenario4 import Scenario4, axis_window, default_shift
 from paper_1909_01467_amd import inputs
 
 
-def test_shifted_partition_moves_interior_boundaries_only():
+def test_shifted_partition_translates_every_group_start():
     lo, hi, sizes = partition(127, 10, 4, 16)
     assert sizes == [32, 32, 32, 31]
-    assert lo == [0, 58, 90, 122] and hi == [58, 90, 122, 147]
+    assert lo == [0, 26, 58, 90, 122] and hi == [26, 58, 90, 122, 147]
+    assert partition(127, 10, 4, 0)[0] == [0, 42, 74, 106]
     assert default_shift(127, 4) == 15 and default_shift(511, 8) == 31
 
 
 def test_axis_window_ramps_between_the_two_skeletons():
     lo = [0, 20, 40]
-    los = [0, 30, 50]
+    los = [0, 10, 30, 50]
     a = axis_window(70, lo, los)
-    assert np.all(a[:20] == 0) and np.all(a[50:] == 1)
-    for b in (20, 40):                    # trace lines of an original interface
+    assert np.all(a[:11] == 1) and np.all(a[49:] == 1)
+    for b in (20, 40):                    # trace lines of an interface of the CDD
         assert a[b - 1] == 0 and a[b] == 0
-    for b in (30, 50):                    # trace lines of a shifted interface
+    for b in (10, 30, 50):                # trace lines of a shifted interface
         assert a[b - 1] == 1 and a[b] == 1
     # linear ramp from d = 1 to d' = 1: at x = 25, d = 5.5 and d' = 4.5
     assert a[25] == pytest.approx(4.5 / (4.5 + 3.5), abs=1e-15)
     assert np.all(np.diff(a[20:30]) >= 0) and np.all(np.diff(a[40:50]) >= 0)
-    assert np.all(np.diff(a[30:40]) <= 0)
+    assert np.all(np.diff(a[10:20]) <= 0) and np.all(np.diff(a[30:40]) <= 0)
 
 
 @pytest.fixture(scope="module")
