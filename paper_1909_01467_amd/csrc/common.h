@@ -109,6 +109,7 @@ struct SubDesc {
     int L;               // number of trace-line slots, 4W + 4H
     long long g_off;     // offset (elements) of G_0 in the factor pool; G_k at g_off + k*W*W
     long long gs_off;    // offset of G_0 in the packed symmetric pool; G_k at gs_off + k*sym_block(W)
+                         // (3D: at gs_off + k*4096*plane3_tiles(W*H))
     long long q_off;     // offset of Q = A_ij^-1[lines, lines] (L x L, column-major) in the Q pool
     long long fw_off;    // offset of this window (H x W, row-major) in the final right-hand-side array
 };
@@ -126,6 +127,15 @@ __host__ __device__ inline int tile_count(int W) { return tile_nt(W) * (tile_nt(
 __host__ __device__ inline long long sym_block(int W) { return 16LL * tile_count(W); }
 // row stride of the per-tile-column partial sums in the substitution kernel (4 mod 16 entries)
 __host__ __device__ inline int sym_cstride(int W) { return 4 * tile_nt(W) + ((4 - 4 * tile_nt(W)) % 16 + 16) % 16; }
+
+// Packed storage of a complex symmetric plane block of a 3D beam (s = W*H unknowns, G = G^T):
+// the upper triangle in 64 x 64 tiles, nb = ceil(s/64) tile rows, tiles (I, J) with I <= J numbered
+// tau = I nb - I (I - 1) / 2 + (J - I) (entries past s zero, diagonal tiles in full), 4096 entries
+// per tile and plane3_tiles(s) tiles per plane.  Inside a tile, lane l = 16 i4 + j4 of a
+// 256-lane workgroup owns rows 4 i4 + a and columns 4 j4 + b (a, b < 4); its entry q = 4a + b sits
+// at (q / 2) * 512 + 2 l + q % 2, so that chunk u = q / 2 of all lanes is one contiguous run.
+__host__ __device__ inline int plane3_nb(int S) { return (S + 63) / 64; }
+__host__ __device__ inline int plane3_tiles(int S) { return plane3_nb(S) * (plane3_nb(S) + 1) / 2; }
 
 // Layout of one axis table of a window with P points (offset t in the table pool):
 //   t + a        : 1/alpha at integer point a            (a = 0..P-1)

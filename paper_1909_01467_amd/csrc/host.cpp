@@ -102,6 +102,9 @@ struct lsw_plan {
     size_t sym_lds = 0;             // dynamic LDS of the packed substitutions: the widest window's column sums
     void* d_Gs = nullptr;
     size_t GS_elems = 0;
+    int ptiles3 = 0;                // 3D packed: tiles per plane of the largest block
+    size_t pack3_max = 0;           // 3D packed: largest packed pool of one beam (entries)
+    void* d_P3 = nullptr;           // 3D packed: partial products of a step
     void* d_traces = nullptr;
     size_t trace_stride = 0;
     void* d_zpart = nullptr;
@@ -1005,7 +1008,20 @@ int setup3d_factor(lsw_plan* p) {
         if (status[sidx])
             return fail(p, LSW_ESINGULAR, "zero pivot in the block factorisation of beam (" +
                                               std::to_string(p->subs[sidx].i) + "," + std::to_string(p->subs[sidx].j) + ")");
-    if (p->precision == LSW_MIXED) {
+    const size_t eb = p->precision == LSW_MIXED ? sizeof(c64) : sizeof(c128);
+    if (p->gsym) {   // the steps read only the packed blocks
+        HIPCK(p, hipMemcpy(p->d_subs, p->subs.data(), sizeof(SubDesc) * p->subs.size(), hipMemcpyHostToDevice));
+        char* GS = nullptr;
+        if ((rc = dalloc(p, &GS, p->GS_elems * eb)) != LSW_OK) return rc;
+        HIPCK(p, launch_pack3(p->d_subs, nsub, Nz, G128, GS, p->pack3_max, p->precision == LSW_MIXED, p->stream));
+        HIPCK(p, hipStreamSynchronize(p->stream));
+        dfree(p, G128);
+        p->d_Gs = GS;
+        p->d_G = nullptr;
+        char* P3 = nullptr;
+        if ((rc = dalloc(p, &P3, (size_t)p->nrhs_max * p->max_front * 2 * p->ptiles3 * 128 * eb)) != LSW_OK) return rc;
+        p->d_P3 = P3;
+    } else if (p->precision == LSW_MIXED) {
         c64* G64 = nullptr;
         if ((rc = dalloc(p, &G64, p->G_elems)) != LSW_OK) return rc;
         HIPCK(p, launch_cast(G128, G64, p->G_elems, p->stream));
@@ -1015,7 +1031,6 @@ int setup3d_factor(lsw_plan* p) {
     } else {
         p->d_G = G128;
     }
-    const size_t eb = p->precision == LSW_MIXED ? sizeof(c64) : sizeof(c128);
     const size_t slots = (size_t)p->nrhs_max * p->max_front * Nz * p->Smax;
     char *r3 = nullptr, *y3 = nullptr;
     if ((rc = dalloc(p, &r3, slots * eb)) != LSW_OK) return rc;
@@ -1042,15 +1057,22 @@ int apply3d_impl(lsw_plan* p, const c128* d_r, c128* d_z, int nrhs, bool timed) 
     a.zpart = p->d_zpart;
     a.zpart_stride = p->zpart_stride;
     a.r = d_r;
+    a.P3 = p->d_P3;
+    a.ptiles = p->ptiles3;
+    if (p->gsym) a.G = p->d_Gs;
+    auto step = [&](int phase, int t) {
+        return p->gsym ? launch_step3_packed(a, p->Smax, nrhs, phase, t, c64, p->stream)
+                       : launch_step3(a, p->Smax, nrhs, phase, t, c64, p->stream);
+    };
     if (timed) HIPCK(p, hipEventRecord(p->ev[0], p->stream));
     for (size_t fi = 0; fi < p->fronts.size(); ++fi) {
         const Front& f = p->fronts[fi];
         a.descs = p->d_descs + f.offset;
         a.nslots = f.count;
         HIPCK(p, launch_rhs3(a, p->Smax, nrhs, c64, p->stream));
-        for (int t = 0; t < mh; ++t) HIPCK(p, launch_step3(a, p->Smax, nrhs, 0, t, c64, p->stream));
-        HIPCK(p, launch_step3(a, p->Smax, nrhs, 1, 0, c64, p->stream));
-        for (int t = 0; t < mh; ++t) HIPCK(p, launch_step3(a, p->Smax, nrhs, 2, t, c64, p->stream));
+        for (int t = 0; t < mh; ++t) HIPCK(p, step(0, t));
+        HIPCK(p, step(1, 0));
+        for (int t = 0; t < mh; ++t) HIPCK(p, step(2, t));
         HIPCK(p, launch_epi3(a, p->Smax, nrhs, c64, p->stream));
         if (fi == 0 && timed) HIPCK(p, hipEventRecord(p->ev[1], p->stream));
     }
@@ -1297,6 +1319,18 @@ int setup_impl(lsw_plan* p, const double* d_m, double omega, double h, const lsw
         p->gsym = !off && p->dim == 2 && p->sweep_mode == LSW_SWEEP_COMPRESSED && p->sym_ept <= sym_max_ept(mixed) &&
                   p->sym_lds + stat <= (size_t)max_lds;
         if (p->gsym) HIPCK(p, prepare_chain_sym(p->sym_ept, mixed, p->sym_lds));
+        if (p->dim == 3) {   // packed 64 x 64 tiles of every plane block (k_tile3 / k_red3)
+            p->gsym = !off;
+            p->GS_elems = 0;
+            p->ptiles3 = 0;
+            for (SubDesc& s : p->subs) {
+                const int S3 = s.W * s.H;
+                s.gs_off = (long long)p->GS_elems;
+                p->GS_elems += (size_t)p->Nz * plane3_tiles(S3) * 4096;
+                p->ptiles3 = std::max(p->ptiles3, plane3_tiles(S3));
+                p->pack3_max = std::max(p->pack3_max, (size_t)p->Nz * plane3_tiles(S3) * 4096);
+            }
+        }
     }
     const size_t eb = p->precision == LSW_MIXED ? sizeof(c64) : sizeof(c128);
     p->apply_chain_bytes = p->apply_gemv_bytes = p->apply_stage1_bytes = p->apply_final_bytes = 0;
@@ -1315,7 +1349,8 @@ int setup_impl(lsw_plan* p, const double* d_m, double omega, double h, const lsw
             for (int n = 0; n < f.count; ++n) {
                 const SubDesc& s = p->subs[p->descs[f.offset + n].sub];
                 const double S3 = (double)s.W * s.H;
-                const double bytes = (2.0 * p->Nz - 1.0) * S3 * S3 * eb;
+                const double block = p->gsym ? 4096.0 * plane3_tiles(s.W * s.H) : S3 * S3;
+                const double bytes = (2.0 * p->Nz - 1.0) * block * eb;
                 p->apply_chain_bytes += bytes;
                 if (&f == &p->fronts.front()) p->apply_stage1_bytes += bytes;
             }

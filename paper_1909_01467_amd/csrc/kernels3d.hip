@@ -8,6 +8,9 @@
 //  k_rhs3       right-hand sides of the local solves of a front (stage 1 or eq. DiscPol2)
 //  k_step3      one plane of the twisted block substitution of every solve of a front: each
 //               workgroup computes 64 rows of G_k v (v staged in LDS, G_k streamed)
+//  k_tile3      the same step on packed symmetric plane blocks: one 64 x 64 tile of the upper
+//  k_red3       triangle per workgroup (tile v_J and tile^T v_I), then a fixed-order sum per row
+//  k_pack3      packing of the plane blocks into that tile layout
 //  k_epi3       the solution on Omega_ij and the outgoing trace planes
 //  k_zsum3      z = sum of the per-sweep parts
 //  k_matvec3    y = A x with the 7-point operator (FP64)
@@ -315,15 +318,66 @@ __global__ void k_rhs3(Chain3Args a, int smax) {
     out[idx] = cvt<T>(v);
 }
 
-// One plane of the twisted substitution (planes k < m eliminated from below, k > m from
-// above, m last), for every (solve, half) of a front: workgroup (chunk, 2*slot + half) forms
-// v in LDS and computes rows [64*chunk, 64*chunk + 64) of G_k v, one row per lane, the 16
-// waves splitting the columns of the column-major block.
+// The plane of one half at step (phase, t) of the twisted substitution (planes k < m eliminated
+// from below, k > m from above, m last) and the planes whose results enter its input:
 //   phase 0, half 0: y_k = G_k (g_k - C_{k-1} y_{k-1}), k = t
 //   phase 0, half 1: y_k = G_k (g_k - C_k y_{k+1}),     k = Nz-1-t
 //   phase 1:         x_m = G_m (g_m - C_{m-1} y_{m-1} - C_m y_{m+1})
 //   phase 2, half 0: x_k = y_k - G_k C_k x_{k+1},       k = m-1-t
 //   phase 2, half 1: x_k = y_k - G_k C_{k-1} x_{k-1},   k = m+1+t
+// prev/prev2 are the planes read (-1: none), cpl/cpl2 the coupling planes.  False: no plane.
+struct StepPlane {
+    int k, prev, prev2, cpl, cpl2;
+};
+__device__ inline bool step_plane(int phase, int t, int half, int Nz, int m, StepPlane& sp) {
+    sp.prev = sp.prev2 = -1;
+    sp.cpl = sp.cpl2 = 0;
+    if (phase == 0) {
+        if (half == 0) {
+            if (t >= m) return false;
+            sp.k = t;
+            if (t > 0) sp.prev = sp.cpl = sp.k - 1;
+        } else {
+            if (t >= Nz - 1 - m) return false;
+            sp.k = Nz - 1 - t;
+            if (t > 0) { sp.prev = sp.k + 1; sp.cpl = sp.k; }
+        }
+    } else if (phase == 1) {
+        if (half == 1) return false;
+        sp.k = m;
+        if (m >= 1) sp.prev = sp.cpl = m - 1;
+        if (m + 1 <= Nz - 1) { sp.prev2 = m + 1; sp.cpl2 = m; }
+    } else {
+        if (half == 0) {
+            if (t >= m) return false;
+            sp.k = m - 1 - t;
+            sp.prev = sp.k + 1;
+            sp.cpl = sp.k;
+        } else {
+            if (t >= Nz - 1 - m) return false;
+            sp.k = m + 1 + t;
+            sp.prev = sp.cpl = sp.k - 1;
+        }
+    }
+    return true;
+}
+
+// entry c of the vector the plane block multiplies: g_k - couplings * neighbours (phases 0, 1),
+// or C x_prev (phase 2)
+template <typename T>
+__device__ inline cx<T> step_input(int phase, const StepPlane& sp, const SubDesc& s, const Geometry& g, const Box3& b,
+                                   double ih2, const cx<T>* R, const cx<T>* Y, int smax, int c) {
+    const int y = c / s.W, x = c - y * s.W;
+    if (phase == 2) return cvt<T>(c3z(g.tab, b, x, y, sp.cpl, ih2)) * Y[(size_t)sp.prev * smax + c];
+    cx<T> val = R[(size_t)sp.k * smax + c];
+    if (sp.prev >= 0) val = val - cvt<T>(c3z(g.tab, b, x, y, sp.cpl, ih2)) * Y[(size_t)sp.prev * smax + c];
+    if (sp.prev2 >= 0) val = val - cvt<T>(c3z(g.tab, b, x, y, sp.cpl2, ih2)) * Y[(size_t)sp.prev2 * smax + c];
+    return val;
+}
+
+// One step of the twisted substitution on the full plane blocks, for every (solve, half) of a
+// front: workgroup (chunk, 2*slot + half) forms v in LDS and computes rows [64*chunk, 64*chunk + 64)
+// of G_k v, one row per lane, the 16 waves splitting the columns of the column-major block.
 template <typename T>
 __global__ __launch_bounds__(1024) void k_step3(Chain3Args a, int smax, int phase, int t) {
     constexpr int NT = 1024, NW = NT / 64, KB = sizeof(T) == 4 ? 16 : 8;
@@ -334,55 +388,18 @@ __global__ __launch_bounds__(1024) void k_step3(Chain3Args a, int smax, int phas
     const SolveDesc& d = a.descs[slot];
     const SubDesc s = a.subs[d.sub];
     const Geometry& g = a.geo;
-    const int S = s.W * s.H, Nz = g.Nz, m = s.mid;
+    const int S = s.W * s.H;
     const int row0 = blockIdx.x * 64;
     if (row0 >= S) return;
-    int k, prev = -1, prev2 = -1, cpl = 0, cpl2 = 0;
-    if (phase == 0) {
-        if (half == 0) {
-            if (t >= m) return;
-            k = t;
-            if (t > 0) { prev = k - 1; cpl = k - 1; }
-        } else {
-            if (t >= Nz - 1 - m) return;
-            k = Nz - 1 - t;
-            if (t > 0) { prev = k + 1; cpl = k; }
-        }
-    } else if (phase == 1) {
-        if (half == 1) return;
-        k = m;
-        if (m >= 1) { prev = m - 1; cpl = m - 1; }
-        if (m + 1 <= Nz - 1) { prev2 = m + 1; cpl2 = m; }
-    } else {
-        if (half == 0) {
-            if (t >= m) return;
-            k = m - 1 - t;
-            prev = k + 1;
-            cpl = k;
-        } else {
-            if (t >= Nz - 1 - m) return;
-            k = m + 1 + t;
-            prev = k - 1;
-            cpl = k - 1;
-        }
-    }
+    StepPlane sp;
+    if (!step_plane(phase, t, half, g.Nz, s.mid, sp)) return;
+    const int k = sp.k;
     const Box3 b = window_box(s, g);
     const double ih2 = 1.0 / (g.h * g.h);
     const cx<T>* R = reinterpret_cast<const cx<T>*>(a.rhs) + ((size_t)rhs * a.nslots + slot) * a.slot_stride;
     cx<T>* Y = reinterpret_cast<cx<T>*>(a.Y) + ((size_t)rhs * a.nslots + slot) * a.slot_stride;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    for (int c = tid; c < S; c += NT) {
-        const int y = c / s.W, x = c - y * s.W;
-        cx<T> val{T(0), T(0)};
-        if (phase == 2) {
-            val = cvt<T>(c3z(g.tab, b, x, y, cpl, ih2)) * Y[(size_t)prev * smax + c];
-        } else {
-            val = R[(size_t)k * smax + c];
-            if (prev >= 0) val = val - cvt<T>(c3z(g.tab, b, x, y, cpl, ih2)) * Y[(size_t)prev * smax + c];
-            if (prev2 >= 0) val = val - cvt<T>(c3z(g.tab, b, x, y, cpl2, ih2)) * Y[(size_t)prev2 * smax + c];
-        }
-        v[c] = val;
-    }
+    for (int c = tid; c < S; c += NT) v[c] = step_input<T>(phase, sp, s, g, b, ih2, R, Y, smax, c);
     __syncthreads();
     const cx<T>* Gk = reinterpret_cast<const cx<T>*>(a.G) + s.g_off + (size_t)k * S * S;
     const __amdgpu_buffer_rsrc_t gr = rsrc3(Gk, (uint32_t)((size_t)S * S * sizeof(cx<T>)));
@@ -411,6 +428,166 @@ __global__ __launch_bounds__(1024) void k_step3(Chain3Args a, int smax, int phas
         cx<T>* out = Y + (size_t)k * smax + row;
         *out = (phase == 2) ? *out - y : y;
     }
+}
+
+// ------------------------------------------------------------------ packed symmetric plane blocks
+// lane-to-lane moves inside rows of 16 lanes (DPP): quad_perm [1,0,3,2], quad_perm [2,3,0,1],
+// row_half_mirror, row_mirror; every lane of a row ends with the row's sum
+template <int CTRL>
+__device__ inline float dpp3(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ inline double dpp3(double v) {
+    const long long bits = __builtin_bit_cast(long long, v);
+    const int lo = __builtin_amdgcn_mov_dpp((int)(bits & 0xffffffff), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(bits >> 32), CTRL, 0xF, 0xF, false);
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
+template <typename T>
+__device__ inline T row16_sum(T x) {
+    x += dpp3<0xB1>(x);
+    x += dpp3<0x4E>(x);
+    x += dpp3<0x141>(x);
+    x += dpp3<0x140>(x);
+    return x;
+}
+
+__device__ inline void tile3_ij(int tau, int nb, int& I, int& J) {
+    int i = 0, rem = tau;
+    while (rem >= nb - i) {
+        rem -= nb - i;
+        ++i;
+    }
+    I = i;
+    J = i + rem;
+}
+
+// Tile part of a packed step: workgroup (tau, 2*slot + half) multiplies tile (I, J) of G_k by v_J
+// (rows of block I) and, off the diagonal, its transpose by v_I (rows of block J).  Lane l owns a
+// 4 x 4 sub-block: row sums over the 16 lanes of a tile row by DPP, column sums through LDS.
+template <typename T>
+__global__ __launch_bounds__(256) void k_tile3(Chain3Args a, int smax, int phase, int t) {
+    __shared__ cx<T> vJ[64], vI[64];
+    __shared__ cx<T> cs[16][68];
+    const int slot = blockIdx.y >> 1, half = blockIdx.y & 1, rhs = blockIdx.z;
+    const SolveDesc& d = a.descs[slot];
+    const SubDesc s = a.subs[d.sub];
+    const Geometry& g = a.geo;
+    const int S = s.W * s.H, nb = plane3_nb(S), ntl = nb * (nb + 1) / 2;
+    const int tau = blockIdx.x;
+    if (tau >= ntl) return;
+    StepPlane sp;
+    if (!step_plane(phase, t, half, g.Nz, s.mid, sp)) return;
+    int I, J;
+    tile3_ij(tau, nb, I, J);
+    const int tid = threadIdx.x;
+    // the tile: 8 contiguous runs of 512 entries, two per lane in each
+    const cx<T>* Gt = reinterpret_cast<const cx<T>*>(a.G) + s.gs_off + ((size_t)sp.k * ntl + tau) * 4096 + 2 * tid;
+    cx<T> e[16];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+        e[2 * u] = Gt[u * 512];
+        e[2 * u + 1] = Gt[u * 512 + 1];
+    }
+    if (tid < 128) {
+        const int blk = tid < 64 ? J : I, c = blk * 64 + (tid & 63);
+        cx<T> val{T(0), T(0)};
+        if (c < S) {
+            const Box3 b = window_box(s, g);
+            const double ih2 = 1.0 / (g.h * g.h);
+            const cx<T>* R = reinterpret_cast<const cx<T>*>(a.rhs) + ((size_t)rhs * a.nslots + slot) * a.slot_stride;
+            const cx<T>* Y = reinterpret_cast<const cx<T>*>(a.Y) + ((size_t)rhs * a.nslots + slot) * a.slot_stride;
+            val = step_input<T>(phase, sp, s, g, b, ih2, R, Y, smax, c);
+        }
+        if (tid < 64) vJ[tid] = val;
+        else vI[tid - 64] = val;
+    }
+    __syncthreads();
+    const int i4 = tid >> 4, j4 = tid & 15;
+    cx<T>* P = reinterpret_cast<cx<T>*>(a.P3) +
+               ((((size_t)rhs * a.nslots + slot) * 2 + half) * a.ptiles + tau) * 128;
+    cx<T> rp[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        cx<T> acc{T(0), T(0)};
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc = acc + e[4 * r + c] * vJ[4 * j4 + c];
+        acc.re = row16_sum(acc.re);
+        acc.im = row16_sum(acc.im);
+        rp[r] = acc;
+    }
+    if (j4 == 0) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) P[4 * i4 + r] = rp[r];
+    }
+    if (I != J) {   // uniform over the workgroup
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            cx<T> acc{T(0), T(0)};
+#pragma unroll
+            for (int r = 0; r < 4; ++r) acc = acc + e[4 * r + c] * vI[4 * i4 + r];
+            cs[i4][4 * j4 + c] = acc;
+        }
+        __syncthreads();
+        if (tid < 64) {
+            cx<T> acc = cs[0][tid];
+#pragma unroll
+            for (int r = 1; r < 16; ++r) acc = acc + cs[r][tid];
+            P[64 + tid] = acc;
+        }
+    }
+}
+
+// Reduction part of a packed step: wave (block b, 2*slot + half) adds, for the 64 rows of block b,
+// the row partials of tiles (b, J >= b) and the column partials of tiles (I < b, b), in that order.
+template <typename T>
+__global__ __launch_bounds__(64) void k_red3(Chain3Args a, int smax, int phase, int t) {
+    const int slot = blockIdx.y >> 1, half = blockIdx.y & 1, rhs = blockIdx.z;
+    const SolveDesc& d = a.descs[slot];
+    const SubDesc s = a.subs[d.sub];
+    const Geometry& g = a.geo;
+    const int S = s.W * s.H, nb = plane3_nb(S), bI = blockIdx.x;
+    if (bI >= nb) return;
+    StepPlane sp;
+    if (!step_plane(phase, t, half, g.Nz, s.mid, sp)) return;
+    const int lane = threadIdx.x, row = bI * 64 + lane;
+    const cx<T>* P = reinterpret_cast<const cx<T>*>(a.P3) + (((size_t)rhs * a.nslots + slot) * 2 + half) * a.ptiles * 128;
+    cx<T> y{T(0), T(0)};
+    const int base = bI * nb - bI * (bI - 1) / 2;   // tau of tile (b, b)
+    for (int J = bI; J < nb; ++J) y = y + P[(size_t)(base + J - bI) * 128 + lane];
+    for (int I = 0; I < bI; ++I) {
+        const int tau = I * nb - I * (I - 1) / 2 + (bI - I);
+        y = y + P[(size_t)tau * 128 + 64 + lane];
+    }
+    if (row < S) {
+        cx<T>* out = reinterpret_cast<cx<T>*>(a.Y) + ((size_t)rhs * a.nslots + slot) * a.slot_stride +
+                     (size_t)sp.k * smax + row;
+        *out = (phase == 2) ? *out - y : y;
+    }
+}
+
+// Packing: entry o of subdomain blockIdx.y's packed pool from its full FP64 plane blocks.
+template <typename T>
+__global__ void k_pack3(const SubDesc* subs, int Nz, const c128* G, cx<T>* Gs) {
+    const SubDesc s = subs[blockIdx.y];
+    const int S = s.W * s.H, nb = plane3_nb(S), ntl = nb * (nb + 1) / 2;
+    const size_t per_plane = (size_t)ntl * 4096;
+    const size_t o = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (o >= per_plane * Nz) return;
+    const size_t k = o / per_plane, rem = o - k * per_plane;
+    const int tau = (int)(rem >> 12), e = (int)(rem & 4095);
+    const int u = e >> 9, w = e & 511, l = w >> 1, q = 2 * u + (w & 1);
+    int I, J;
+    tile3_ij(tau, nb, I, J);
+    const int row = I * 64 + 4 * (l >> 4) + (q >> 2), col = J * 64 + 4 * (l & 15) + (q & 3);
+    c128 v = mk(0.0, 0.0);
+    if (row < S && col < S) {
+        const c128* Gk = G + s.g_off + k * (size_t)S * S;   // column-major
+        const c128 x = Gk[(size_t)col * S + row], y = Gk[(size_t)row * S + col];
+        v = mk(0.5 * (x.re + y.re), 0.5 * (x.im + y.im));
+    }
+    Gs[s.gs_off + o] = cvt<T>(v);
 }
 
 template <typename T>
@@ -522,6 +699,26 @@ hipError_t launch_step3(const Chain3Args& a, int smax, int nrhs, int phase, int 
         if (e != hipSuccess) return e;
         k_step3<double><<<grid, 1024, lds, st>>>(a, smax, phase, t);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_step3_packed(const Chain3Args& a, int smax, int nrhs, int phase, int t, bool f32, hipStream_t st) {
+    const dim3 tg(a.ptiles, 2 * a.nslots, nrhs), rg(plane3_nb(smax), 2 * a.nslots, nrhs);
+    if (f32) {
+        k_tile3<float><<<tg, 256, 0, st>>>(a, smax, phase, t);
+        k_red3<float><<<rg, 64, 0, st>>>(a, smax, phase, t);
+    } else {
+        k_tile3<double><<<tg, 256, 0, st>>>(a, smax, phase, t);
+        k_red3<double><<<rg, 64, 0, st>>>(a, smax, phase, t);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_pack3(const SubDesc* subs, int nsub, int Nz, const c128* G, void* Gs, size_t maxper, bool f32,
+                        hipStream_t st) {
+    const dim3 grid(nblk(maxper, 256), nsub);
+    if (f32) k_pack3<float><<<grid, 256, 0, st>>>(subs, Nz, G, reinterpret_cast<c64*>(Gs));
+    else k_pack3<double><<<grid, 256, 0, st>>>(subs, Nz, G, reinterpret_cast<c128*>(Gs));
     return hipGetLastError();
 }
 

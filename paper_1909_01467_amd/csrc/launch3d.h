@@ -43,6 +43,8 @@ struct Chain3Args {
     void* zpart;              // [9][nrhs][N] per-sweep parts of z
     size_t zpart_stride;      // nrhs * N
     const c128* r;            // input vectors [nrhs][N]
+    void* P3;                 // packed steps: [nrhs][front slot][half][tile][2][64] partial products
+    int ptiles;               // tiles per plane of the largest block (partial stride)
 };
 
 // S = D_k - C G_below C - C G_above C into ws (identity padding), for every item
@@ -59,6 +61,14 @@ hipError_t launch_rhs3(const Chain3Args& a, int smax, int nrhs, bool f32, hipStr
 // one step of the twisted block substitution of every solve of a front:
 // phase 0 forward (step t of each half), 1 middle plane, 2 backward (step t of each half)
 hipError_t launch_step3(const Chain3Args& a, int smax, int nrhs, int phase, int t, bool f32, hipStream_t st);
+// the same step on the packed symmetric plane blocks (a.G = packed pool, SubDesc::gs_off): one
+// workgroup per 64 x 64 tile forms tile v_J and tile^T v_I (a.P3), then one wave per 64-row block
+// adds its row and column partials in a fixed order into y (phase 2: x = y - sum)
+hipError_t launch_step3_packed(const Chain3Args& a, int smax, int nrhs, int phase, int t, bool f32, hipStream_t st);
+// packs the symmetrised mean (G + G^T)/2 of every plane block of the full FP64 pool into the
+// tile layout of plane3_tiles (complex64 when f32); maxper = the largest Nz*plane3_tiles*4096
+hipError_t launch_pack3(const SubDesc* subs, int nsub, int Nz, const c128* G, void* Gs, size_t maxper, bool f32,
+                        hipStream_t st);
 // solution on Omega into the sweep's part of z, outgoing traces into the trace pool
 hipError_t launch_epi3(const Chain3Args& a, int smax, int nrhs, bool f32, hipStream_t st);
 // z = sum of the 9 per-sweep parts (n = nrhs * N entries, parts `stride` apart)

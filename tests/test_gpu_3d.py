@@ -133,6 +133,29 @@ def test_apply3_batches_rhs_and_is_deterministic():
     s.close()
 
 
+@pytest.mark.parametrize("name", ["ragged_3x2", "even_z_2x3"])
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("mixed", 2e-5)])
+def test_packed_plane_blocks_match_full_blocks(name, precision, tol, monkeypatch):
+    """The steps on the packed upper triangles of the plane blocks (64 x 64 tiles, G_k = G_k^T)
+    against the steps on the full blocks (LSW_SYMMETRIC_FACTORS=0), on ragged plane sizes."""
+    c = CASES[name]
+    r = torch.from_numpy(inputs.complex_normal(c.m.size, 55)).cuda()
+    s = c.solver(precision=precision)
+    st = s.stats()
+    assert st["symmetric_factors"] == 1 and st["packed_factor_elems"] > 0
+    zp = s.apply(r).cpu().numpy().ravel()
+    s.close()
+    monkeypatch.setenv("LSW_SYMMETRIC_FACTORS", "0")
+    s = c.solver(precision=precision)
+    assert s.stats()["symmetric_factors"] == 0
+    zf = s.apply(r).cpu().numpy().ravel()
+    s.close()
+    err = rel(zp, zf)
+    say(name, precision, "packed vs full plane blocks", err, "packed/full entries",
+        st["packed_factor_elems"] / st["factor_elems"])
+    assert err < tol
+
+
 @pytest.mark.parametrize("precision,tol_err", [("fp64", 1e-6), ("mixed", 1e-4)])
 def test_solve3_matches_direct_solve(precision, tol_err):
     c = CASES["cube_2x2"]
