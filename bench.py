@@ -182,11 +182,20 @@ def main():
     if wl.dim == 3:
         # every front: k_rhs3, 2*ceil(Nz/2) k_step3 plane steps, k_epi3; the event time of the
         # fronts includes the small k_rhs3/k_epi3 launches, so the rate is a lower bound
-        kernels = {
-            "k_step3": dict(desc="3D twisted plane-block substitutions of every front (64 rows of G_k per workgroup)",
-                            launches=st["chain_launches"], bytes=st["apply_chain_bytes"],
-                            ms=med["last_stage1_ms"] + med["last_gemv_ms"]),
-        }
+        if st.get("symmetric_factors"):
+            kernels = {
+                "k_tile3+k_red3": dict(desc="3D twisted substitution plane steps on the packed symmetric plane blocks "
+                                            "(one 64x64 tile of the upper triangle per workgroup, then a fixed-order "
+                                            "sum per 64-row block)",
+                                       launches=st["chain_launches"], bytes=st["apply_chain_bytes"],
+                                       ms=med["last_stage1_ms"] + med["last_gemv_ms"]),
+            }
+        else:
+            kernels = {
+                "k_step3": dict(desc="3D twisted plane-block substitutions of every front (64 rows of G_k per "
+                                     "workgroup)", launches=st["chain_launches"], bytes=st["apply_chain_bytes"],
+                                ms=med["last_stage1_ms"] + med["last_gemv_ms"]),
+            }
     else:
         # the one-right-hand-side substitutions read the packed symmetric factors when built;
         # with windows every family runs once per CDD (four times)

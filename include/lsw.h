@@ -117,7 +117,7 @@ typedef struct {
     int q, r, n_subdomains;
     int W_max, H_max;            /* largest local window (points along x / y) */
     long long N;                 /* extended-grid points */
-    long long factor_elems;      /* complex entries of all stored block inverses G_k */
+    long long factor_elems;      /* complex entries of all block inverses G_k in full (built at setup) */
     int factor_elem_bytes;       /* 8 (complex64) or 16 (complex128) */
     int solves_per_apply;        /* (3q-2)(3r-2)-type count of local solves per application */
     int fronts_per_apply;        /* dependent launch steps per application */
@@ -140,8 +140,9 @@ typedef struct {
                                     (1, 2 or 4), chosen at setup by timing when nrhs_max > 1, or
                                     fixed by the environment variable LSW_RHS_PER_WORKGROUP */
     double tune_ms[3];           /* the timings of 1, 2 and 4 right-hand sides per workgroup (0: not tried) */
-    int symmetric_factors;       /* 1 if the one-right-hand-side substitutions read the packed symmetric
-                                    blocks (G_k = G_k^T; about half the bytes of the full blocks) */
+    int symmetric_factors;       /* 1 if the substitutions read packed symmetric blocks (G_k = G_k^T; about
+                                    half the bytes of the full blocks): in 2D those with one right-hand
+                                    side per workgroup, in 3D every plane step (64 x 64 tiles) */
     long long packed_factor_elems;  /* complex entries of the packed blocks (0 if not built) */
     int gemv_items;              /* work items (<= 64 output rows of one sweep solve) per application */
     int gemv_max_inputs;         /* largest input count (incoming trace values) of a sweep solve */

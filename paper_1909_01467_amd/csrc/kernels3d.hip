@@ -539,10 +539,14 @@ __global__ __launch_bounds__(256) void k_tile3(Chain3Args a, int smax, int phase
     }
 }
 
-// Reduction part of a packed step: wave (block b, 2*slot + half) adds, for the 64 rows of block b,
-// the row partials of tiles (b, J >= b) and the column partials of tiles (I < b, b), in that order.
+// Reduction part of a packed step: workgroup (block b, 2*slot + half) adds, for the 64 rows of
+// block b, its nb partials: entry e < nb - b is the row partial of tile (b, b + e), entry
+// e >= nb - b the column partial of tile (e - (nb - b), b).  Wave w takes the entries e = w mod 4
+// (loads issued together), then wave 0 adds the four sums in order.
 template <typename T>
-__global__ __launch_bounds__(64) void k_red3(Chain3Args a, int smax, int phase, int t) {
+__global__ __launch_bounds__(256) void k_red3(Chain3Args a, int smax, int phase, int t) {
+    constexpr int EPW = 8;   // entries per wave and pass
+    __shared__ cx<T> part[4][64];
     const int slot = blockIdx.y >> 1, half = blockIdx.y & 1, rhs = blockIdx.z;
     const SolveDesc& d = a.descs[slot];
     const SubDesc s = a.subs[d.sub];
@@ -551,16 +555,31 @@ __global__ __launch_bounds__(64) void k_red3(Chain3Args a, int smax, int phase, 
     if (bI >= nb) return;
     StepPlane sp;
     if (!step_plane(phase, t, half, g.Nz, s.mid, sp)) return;
-    const int lane = threadIdx.x, row = bI * 64 + lane;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const cx<T>* P = reinterpret_cast<const cx<T>*>(a.P3) + (((size_t)rhs * a.nslots + slot) * 2 + half) * a.ptiles * 128;
-    cx<T> y{T(0), T(0)};
-    const int base = bI * nb - bI * (bI - 1) / 2;   // tau of tile (b, b)
-    for (int J = bI; J < nb; ++J) y = y + P[(size_t)(base + J - bI) * 128 + lane];
-    for (int I = 0; I < bI; ++I) {
-        const int tau = I * nb - I * (I - 1) / 2 + (bI - I);
-        y = y + P[(size_t)tau * 128 + 64 + lane];
+    const int nrow = nb - bI, diag = bI * nb - bI * (bI - 1) / 2;   // tau of tile (b, b)
+    cx<T> acc{T(0), T(0)};
+    for (int e0 = w; e0 < nb; e0 += 4 * EPW) {
+        cx<T> v[EPW];
+#pragma unroll
+        for (int u = 0; u < EPW; ++u) {
+            const int e = e0 + 4 * u;
+            v[u] = cx<T>{T(0), T(0)};
+            if (e < nrow) {
+                v[u] = P[(size_t)(diag + e) * 128 + lane];
+            } else if (e < nb) {
+                const int I = e - nrow;
+                v[u] = P[(size_t)(I * nb - I * (I - 1) / 2 + (bI - I)) * 128 + 64 + lane];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < EPW; ++u) acc = acc + v[u];
     }
-    if (row < S) {
+    part[w][lane] = acc;
+    __syncthreads();
+    const int row = bI * 64 + lane;
+    if (w == 0 && row < S) {
+        const cx<T> y = ((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane];
         cx<T>* out = reinterpret_cast<cx<T>*>(a.Y) + ((size_t)rhs * a.nslots + slot) * a.slot_stride +
                      (size_t)sp.k * smax + row;
         *out = (phase == 2) ? *out - y : y;
@@ -706,10 +725,10 @@ hipError_t launch_step3_packed(const Chain3Args& a, int smax, int nrhs, int phas
     const dim3 tg(a.ptiles, 2 * a.nslots, nrhs), rg(plane3_nb(smax), 2 * a.nslots, nrhs);
     if (f32) {
         k_tile3<float><<<tg, 256, 0, st>>>(a, smax, phase, t);
-        k_red3<float><<<rg, 64, 0, st>>>(a, smax, phase, t);
+        k_red3<float><<<rg, 256, 0, st>>>(a, smax, phase, t);
     } else {
         k_tile3<double><<<tg, 256, 0, st>>>(a, smax, phase, t);
-        k_red3<double><<<rg, 64, 0, st>>>(a, smax, phase, t);
+        k_red3<double><<<rg, 256, 0, st>>>(a, smax, phase, t);
     }
     return hipGetLastError();
 }

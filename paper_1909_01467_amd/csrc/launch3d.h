@@ -62,8 +62,8 @@ hipError_t launch_rhs3(const Chain3Args& a, int smax, int nrhs, bool f32, hipStr
 // phase 0 forward (step t of each half), 1 middle plane, 2 backward (step t of each half)
 hipError_t launch_step3(const Chain3Args& a, int smax, int nrhs, int phase, int t, bool f32, hipStream_t st);
 // the same step on the packed symmetric plane blocks (a.G = packed pool, SubDesc::gs_off): one
-// workgroup per 64 x 64 tile forms tile v_J and tile^T v_I (a.P3), then one wave per 64-row block
-// adds its row and column partials in a fixed order into y (phase 2: x = y - sum)
+// workgroup per 64 x 64 tile forms tile v_J and tile^T v_I (a.P3), then one workgroup per 64-row
+// block adds its row and column partials in a fixed order into y (phase 2: x = y - sum)
 hipError_t launch_step3_packed(const Chain3Args& a, int smax, int nrhs, int phase, int t, bool f32, hipStream_t st);
 // packs the symmetrised mean (G + G^T)/2 of every plane block of the full FP64 pool into the
 // tile layout of plane3_tiles (complex64 when f32); maxper = the largest Nz*plane3_tiles*4096
