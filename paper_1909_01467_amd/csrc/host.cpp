@@ -124,13 +124,13 @@ struct lsw_plan {
     c128* d_coef = nullptr;
     c128* d_tmp1 = nullptr;
     c128* d_tmp2 = nullptr;
-    double* d_scale = nullptr;
     int* d_active = nullptr;
+    std::vector<int> dev_active;    // what d_active holds
     c128* h_hbuf = nullptr;   // pinned
-    double* h_scale = nullptr;
     int* h_active = nullptr;
     c128* h_coef = nullptr;
-    int nblk = 256;
+    int nblk = 256;                 // workgroups per (column, rhs) of the Krylov dot products
+    int gsblk = 256;                // workgroups per rhs of the Gram-Schmidt updates (grid-stride)
     // bookkeeping
     std::vector<void*> allocs;
     std::string err;
@@ -150,6 +150,7 @@ struct lsw_plan {
     c128* d_wr = nullptr;           // windowed right-hand sides [nrhs][N]
     c128* d_wz = nullptr;           // one shifted CDD's sweep result [nrhs][N]
     hipEvent_t evw[2] = {nullptr, nullptr};   // start and end of a windowed application
+    hipEvent_t ev_spin = nullptr;   // polled by the Krylov loop's waits
 };
 
 namespace {
@@ -194,13 +195,13 @@ void free_plan(lsw_plan* p) {
     }
     for (void* a : p->allocs) (void)hipFree(a);
     if (p->h_hbuf) (void)hipHostFree(p->h_hbuf);
-    if (p->h_scale) (void)hipHostFree(p->h_scale);
     if (p->h_active) (void)hipHostFree(p->h_active);
     if (p->h_coef) (void)hipHostFree(p->h_coef);
     for (hipEvent_t e : p->ev)
         if (e) (void)hipEventDestroy(e);
     for (hipEvent_t e : p->evw)
         if (e) (void)hipEventDestroy(e);
+    if (p->ev_spin) (void)hipEventDestroy(p->ev_spin);
     if (p->rb) (void)rocblas_destroy_handle(p->rb);
     delete p;
 }
@@ -737,8 +738,36 @@ int matvec_impl(lsw_plan* p, const c128* x, c128* y, const c128* b, int nrhs) {
 // out[rhs*ostride + l] = <V_l, w>  for l < nv
 int dots_impl(lsw_plan* p, const c128* V, size_t vl, size_t vr, const c128* w, size_t ws, int nv, int nrhs,
               c128* out, int ostride) {
-    DotsArgs a{V, vl, vr, w, ws, p->N, nv, p->nblk, p->d_partial};
-    HIPCK(p, launch_dots(a, nrhs, out, ostride, 0, p->stream));
+    DotsArgs a{V, vl, vr, w, ws, p->N, nv, p->nblk, p->d_partial, out, ostride, 0};
+    HIPCK(p, launch_dots(a, nrhs, p->stream));
+    return LSW_OK;
+}
+
+// w -= V c (sign -1) or += (sign +1) for nv columns; with norm, ||w||^2 after it into norm[rhs * nstride]
+int gs_impl(lsw_plan* p, const c128* V, size_t vl, const c128* coef, int cstride, c128* w, int nv, int sign,
+            int nrhs, c128* norm, int nstride) {
+    GsArgs a{V, vl, p->N, coef, cstride, w, p->N, p->N, nv, sign, p->d_active, p->gsblk, norm, nstride,
+             norm ? p->d_partial : nullptr};
+    HIPCK(p, launch_gs_update(a, nrhs, p->stream));
+    return LSW_OK;
+}
+
+// the per-rhs mask on the device follows h_active (copied only when it changed)
+int sync_active(lsw_plan* p, int nrhs) {
+    if (std::equal(p->h_active, p->h_active + nrhs, p->dev_active.begin())) return LSW_OK;
+    std::copy(p->h_active, p->h_active + nrhs, p->dev_active.begin());
+    HIPCK(p, hipMemcpyAsync(p->d_active, p->h_active, sizeof(int) * nrhs, hipMemcpyHostToDevice, p->stream));
+    return LSW_OK;
+}
+
+// waits for the stream by polling an event: the Krylov loop waits once per iteration, and a
+// blocking wait adds its wake-up latency to every iteration
+int spin_wait(lsw_plan* p) {
+    HIPCK(p, hipEventRecord(p->ev_spin, p->stream));
+    hipError_t e;
+    while ((e = hipEventQuery(p->ev_spin)) == hipErrorNotReady) {
+    }
+    HIPCK(p, e);
     return LSW_OK;
 }
 
@@ -753,7 +782,7 @@ int solve_impl(lsw_plan* p, const c128* d_b, c128* d_x, int nrhs, lsw_info_t* in
     // ||b||
     if ((rc = dots_impl(p, d_b, 0, N, d_b, N, 1, nrhs, p->d_hbuf, HS)) != LSW_OK) return rc;
     HIPCK(p, hipMemcpyAsync(p->h_hbuf, p->d_hbuf, sizeof(c128) * HS * nrhs, hipMemcpyDeviceToHost, p->stream));
-    HIPCK(p, hipStreamSynchronize(p->stream));
+    if ((rc = spin_wait(p)) != LSW_OK) return rc;
     std::vector<double> bnorm(nrhs), relres(nrhs, 1.0);
     for (int s = 0; s < nrhs; ++s) bnorm[s] = std::sqrt(std::max(0.0, p->h_hbuf[(size_t)s * HS].re));
     std::vector<int> its(nrhs, 0), conv(nrhs, 0);
@@ -769,7 +798,7 @@ int solve_impl(lsw_plan* p, const c128* d_b, c128* d_x, int nrhs, lsw_info_t* in
         if ((rc = matvec_impl(p, d_x, V, d_b, nrhs)) != LSW_OK) return rc;
         if ((rc = dots_impl(p, V, 0, N, V, N, 1, nrhs, p->d_hbuf, HS)) != LSW_OK) return rc;
         HIPCK(p, hipMemcpyAsync(p->h_hbuf, p->d_hbuf, sizeof(c128) * HS * nrhs, hipMemcpyDeviceToHost, p->stream));
-        HIPCK(p, hipStreamSynchronize(p->stream));
+        if ((rc = spin_wait(p)) != LSW_OK) return rc;
         int nlive = 0;
         for (int s = 0; s < nrhs; ++s) {
             const double beta = std::sqrt(std::max(0.0, p->h_hbuf[(size_t)s * HS].re));
@@ -778,39 +807,37 @@ int solve_impl(lsw_plan* p, const c128* d_b, c128* d_x, int nrhs, lsw_info_t* in
             live[s] = !conv[s] && its[s] < p->maxit;
             kend[s] = 0;
             p->h_active[s] = live[s];
-            p->h_scale[s] = (live[s] && beta > 0) ? 1.0 / beta : 0.0;
             std::fill(g.begin() + (size_t)s * (m + 1), g.begin() + (size_t)(s + 1) * (m + 1), cd(0));
             g[(size_t)s * (m + 1)] = beta;
             nlive += live[s];
         }
         if (nlive == 0) break;
-        HIPCK(p, hipMemcpyAsync(p->d_active, p->h_active, sizeof(int) * nrhs, hipMemcpyHostToDevice, p->stream));
-        HIPCK(p, hipMemcpyAsync(p->d_scale, p->h_scale, sizeof(double) * nrhs, hipMemcpyHostToDevice, p->stream));
-        HIPCK(p, launch_scale(V, V, p->d_scale, p->d_active, N, N, N, nrhs, p->stream));
+        if ((rc = sync_active(p, nrhs)) != LSW_OK) return rc;
+        HIPCK(p, launch_scale(V, V, p->d_hbuf, HS, p->d_active, N, N, N, nrhs, p->stream));
         for (int k = 0; k < m; ++k) {
             c128* Vk = V + (size_t)k * vl;
             c128* Zk = Z + (size_t)k * vl;
             if ((rc = apply_impl(p, Vk, Zk, nrhs, false)) != LSW_OK) return rc;
             applies++;
             if ((rc = matvec_impl(p, Zk, p->d_w, nullptr, nrhs)) != LSW_OK) return rc;
-            // classical Gram-Schmidt, twice
+            // classical Gram-Schmidt, twice; the second update also forms ||w||^2
             for (int pass = 0; pass < 2; ++pass) {
                 c128* hcoef = p->d_hbuf + pass * (m + 1);
                 if ((rc = dots_impl(p, V, vl, N, p->d_w, N, k + 1, nrhs, hcoef, HS)) != LSW_OK) return rc;
-                GsArgs ga{V, vl, N, hcoef, HS, p->d_w, N, N, k + 1, -1, p->d_active};
-                HIPCK(p, launch_gs_update(ga, nrhs, p->stream));
+                if ((rc = gs_impl(p, V, vl, hcoef, HS, p->d_w, k + 1, -1, nrhs, pass == 1 ? p->d_hbuf + 2 * (m + 1) : nullptr,
+                                  HS)) != LSW_OK)
+                    return rc;
             }
-            if ((rc = dots_impl(p, p->d_w, 0, N, p->d_w, N, 1, nrhs, p->d_hbuf + 2 * (m + 1), HS)) != LSW_OK)
-                return rc;
+            // V_{k+1} = w / ||w|| needs no host decision: it is formed before the host reads the column
+            // (unused if this right-hand side stops here; V has room for m + 1 vectors)
+            HIPCK(p, launch_scale(p->d_w, V + (size_t)(k + 1) * vl, p->d_hbuf + 2 * (m + 1), HS, p->d_active, N, N,
+                                  N, nrhs, p->stream));
             HIPCK(p, hipMemcpyAsync(p->h_hbuf, p->d_hbuf, sizeof(c128) * HS * nrhs, hipMemcpyDeviceToHost,
                                     p->stream));
-            HIPCK(p, hipStreamSynchronize(p->stream));
+            if ((rc = spin_wait(p)) != LSW_OK) return rc;
             int still = 0;
             for (int s = 0; s < nrhs; ++s) {
-                if (!live[s]) {
-                    p->h_scale[s] = 0.0;
-                    continue;
-                }
+                if (!live[s]) continue;
                 const c128* hb = p->h_hbuf + (size_t)s * HS;
                 std::vector<cd> h(k + 2);
                 for (int l = 0; l <= k; ++l) h[l] = cd(hb[l].re + hb[m + 1 + l].re, hb[l].im + hb[m + 1 + l].im);
@@ -841,16 +868,12 @@ int solve_impl(lsw_plan* p, const c128* d_b, c128* d_x, int nrhs, lsw_info_t* in
                 kend[s] = k + 1;
                 const double est = bnorm[s] > 0 ? std::abs(gg[k + 1]) / bnorm[s] : 0.0;
                 hist[s].push_back(est);
-                p->h_scale[s] = nrm > 0 ? 1.0 / nrm : 0.0;
                 if (est <= p->tol || its[s] >= p->maxit || nrm == 0.0) live[s] = 0;
                 p->h_active[s] = live[s];
                 still += live[s];
             }
             if (still == 0 || k == m - 1) break;
-            HIPCK(p, hipMemcpyAsync(p->d_active, p->h_active, sizeof(int) * nrhs, hipMemcpyHostToDevice, p->stream));
-            HIPCK(p, hipMemcpyAsync(p->d_scale, p->h_scale, sizeof(double) * nrhs, hipMemcpyHostToDevice, p->stream));
-            HIPCK(p, launch_scale(p->d_w, V + (size_t)(k + 1) * vl, p->d_scale, p->d_active, N, N, N, nrhs,
-                                  p->stream));
+            if ((rc = sync_active(p, nrhs)) != LSW_OK) return rc;
         }
         // x += Z y with y = H^-1 g (upper triangular back substitution on the host)
         int kmax = 0;
@@ -868,9 +891,8 @@ int solve_impl(lsw_plan* p, const c128* d_b, c128* d_x, int nrhs, lsw_info_t* in
         }
         if (kmax > 0) {
             HIPCK(p, hipMemcpyAsync(p->d_coef, p->h_coef, sizeof(c128) * m * nrhs, hipMemcpyHostToDevice, p->stream));
-            HIPCK(p, hipMemcpyAsync(p->d_active, p->h_active, sizeof(int) * nrhs, hipMemcpyHostToDevice, p->stream));
-            GsArgs ga{Z, vl, N, p->d_coef, m, d_x, N, N, kmax, +1, p->d_active};
-            HIPCK(p, launch_gs_update(ga, nrhs, p->stream));
+            if ((rc = sync_active(p, nrhs)) != LSW_OK) return rc;
+            if ((rc = gs_impl(p, Z, vl, p->d_coef, m, d_x, kmax, +1, nrhs, nullptr, 0)) != LSW_OK) return rc;
         }
         bool any_left = false;
         for (int s = 0; s < nrhs; ++s) any_left |= (!conv[s] && its[s] < p->maxit);
@@ -880,7 +902,7 @@ int solve_impl(lsw_plan* p, const c128* d_b, c128* d_x, int nrhs, lsw_info_t* in
             if ((rc = dots_impl(p, V, 0, N, V, N, 1, nrhs, p->d_hbuf, HS)) != LSW_OK) return rc;
             HIPCK(p, hipMemcpyAsync(p->h_hbuf, p->d_hbuf, sizeof(c128) * HS * nrhs, hipMemcpyDeviceToHost,
                                     p->stream));
-            HIPCK(p, hipStreamSynchronize(p->stream));
+            if ((rc = spin_wait(p)) != LSW_OK) return rc;
             for (int s = 0; s < nrhs; ++s) {
                 const double beta = std::sqrt(std::max(0.0, p->h_hbuf[(size_t)s * HS].re));
                 relres[s] = bnorm[s] > 0 ? beta / bnorm[s] : 0.0;
@@ -889,7 +911,7 @@ int solve_impl(lsw_plan* p, const c128* d_b, c128* d_x, int nrhs, lsw_info_t* in
             break;
         }
     }
-    HIPCK(p, hipStreamSynchronize(p->stream));
+    if ((rc = spin_wait(p)) != LSW_OK) return rc;
     const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     bool all = true;
     for (int s = 0; s < nrhs; ++s) all &= conv[s] != 0;
@@ -1436,16 +1458,19 @@ int setup_impl(lsw_plan* p, const double* d_m, double omega, double h, const lsw
     if ((rc = dalloc(p, &p->d_w, (size_t)nr * p->N)) != LSW_OK) return rc;
     if ((rc = dalloc(p, &p->d_tmp1, (size_t)nr * p->N)) != LSW_OK) return rc;
     if ((rc = dalloc(p, &p->d_tmp2, (size_t)nr * p->N)) != LSW_OK) return rc;
-    if ((rc = dalloc(p, &p->d_partial, (size_t)nr * (m + 1) * p->nblk)) != LSW_OK) return rc;
+    p->gsblk = (int)std::min<size_t>(1024, (p->N + 255) / 256);
+    if ((rc = dalloc(p, &p->d_partial, (size_t)nr * std::max<size_t>((size_t)(m + 1) * p->nblk, p->gsblk))) != LSW_OK)
+        return rc;
     if ((rc = dalloc(p, &p->d_hbuf, (size_t)nr * HS)) != LSW_OK) return rc;
     if ((rc = dalloc(p, &p->d_coef, (size_t)nr * m)) != LSW_OK) return rc;
-    if ((rc = dalloc(p, &p->d_scale, (size_t)nr)) != LSW_OK) return rc;
     if ((rc = dalloc(p, &p->d_active, (size_t)nr)) != LSW_OK) return rc;
+    HIPCK(p, hipMemset(p->d_active, 0, sizeof(int) * (size_t)nr));
+    p->dev_active.assign(nr, 0);
     HIPCK(p, hipHostMalloc((void**)&p->h_hbuf, sizeof(c128) * nr * HS, hipHostMallocDefault));
-    HIPCK(p, hipHostMalloc((void**)&p->h_scale, sizeof(double) * nr, hipHostMallocDefault));
     HIPCK(p, hipHostMalloc((void**)&p->h_active, sizeof(int) * nr, hipHostMallocDefault));
     HIPCK(p, hipHostMalloc((void**)&p->h_coef, sizeof(c128) * nr * m, hipHostMallocDefault));
     for (hipEvent_t& e : p->ev) HIPCK(p, hipEventCreate(&e));
+    HIPCK(p, hipEventCreateWithFlags(&p->ev_spin, hipEventDisableTiming));
     p->geo.tab = p->d_tab;
     p->geo.m = p->d_m;
     p->geo.Nx = p->Nx;

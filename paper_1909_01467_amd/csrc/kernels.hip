@@ -1582,7 +1582,19 @@ __global__ void k_matvec(MatvecArgs a) {
 }
 
 // ------------------------------------------------------------------ K7: Krylov BLAS (FP64)
-// partial[(rhs * nv + l) * nblk + blk] = sum over the block's points of conj(V_l) w
+// Reductions are two launches: workgroup partials, then one workgroup per sum adds them in a fixed
+// order (a device-wide completion count would need an L2 write-back per workgroup on this chip).
+__device__ inline c128 block_sum(c128 acc, c128* red) {
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int off = blockDim.x / 2; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) red[threadIdx.x] = red[threadIdx.x] + red[threadIdx.x + off];
+        __syncthreads();
+    }
+    return red[0];
+}
+
+// partial[(rhs * nv + l) * nblk + blk] = sum over the points blk*256 + t + k*nblk*256 of conj(V_l) w
 __global__ void k_dots_partial(DotsArgs a) {
     __shared__ c128 red[256];
     const int blk = blockIdx.x, l = blockIdx.y, rhs = blockIdx.z;
@@ -1591,55 +1603,58 @@ __global__ void k_dots_partial(DotsArgs a) {
     c128 acc = mk(0.0, 0.0);
     for (size_t p = (size_t)blk * blockDim.x + threadIdx.x; p < a.N; p += (size_t)gridDim.x * blockDim.x)
         acc = acc + conj(V[p]) * w[p];
-    red[threadIdx.x] = acc;
-    __syncthreads();
-    for (int off = blockDim.x / 2; off > 0; off >>= 1) {
-        if ((int)threadIdx.x < off) red[threadIdx.x] = red[threadIdx.x] + red[threadIdx.x + off];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) a.partial[((size_t)rhs * a.nv + l) * gridDim.x + blk] = red[0];
+    const c128 part = block_sum(acc, red);
+    if (threadIdx.x == 0) a.partial[((size_t)rhs * a.nv + l) * gridDim.x + blk] = part;
 }
 
 // out[rhs * ostride + l] (+)= sum_blk partial ; one workgroup per (l, rhs), fixed order
-__global__ void k_dots_finish(const c128* partial, int nblk, int nv, int nrhs, c128* out, int ostride,
-                              int accumulate) {
+__global__ void k_dots_finish(const c128* partial, int nblk, int nv, c128* out, int ostride, int accumulate) {
     __shared__ c128 red[256];
     const int l = blockIdx.x, rhs = blockIdx.y;
     const c128* pp = partial + ((size_t)rhs * nv + l) * nblk;
     c128 acc = mk(0.0, 0.0);
     for (int b = threadIdx.x; b < nblk; b += blockDim.x) acc = acc + pp[b];
-    red[threadIdx.x] = acc;
-    __syncthreads();
-    for (int off = blockDim.x / 2; off > 0; off >>= 1) {
-        if ((int)threadIdx.x < off) red[threadIdx.x] = red[threadIdx.x] + red[threadIdx.x + off];
-        __syncthreads();
-    }
+    const c128 sum = block_sum(acc, red);
     if (threadIdx.x == 0) {
         c128* o = out + (size_t)rhs * ostride + l;
-        *o = accumulate ? *o + red[0] : red[0];
+        *o = accumulate ? *o + sum : sum;
     }
 }
 
-// w -= sum_l V_l c_l   (c = coefficients on the device, [rhs * cstride + l]); masked rhs skipped
+// w -= sum_l V_l c_l (c = coefficients on the device, [rhs * cstride + l]; masked rhs skipped); with
+// partial, also the workgroup partials of ||w||^2 after the update, partial[rhs * nblk + blk]
 __global__ void k_gs_update(GsArgs a) {
-    const size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    __shared__ c128 red[256];
     const int rhs = blockIdx.y;
-    if (p >= a.N || (a.active && !a.active[rhs])) return;
+    const bool on = !(a.active && !a.active[rhs]);
+    if (!on && !a.partial) return;
     const c128* cf = a.coef + (size_t)rhs * a.cstride;
-    c128 acc = mk(0.0, 0.0);
-    for (int l = 0; l < a.nv; ++l)
-        acc = acc + a.V[(size_t)l * a.vstride_l + (size_t)rhs * a.vstride_rhs + p] * cf[l];
-    c128* w = a.w + (size_t)rhs * a.wstride + p;
-    *w = a.sign > 0 ? *w + acc : *w - acc;
+    c128* w = a.w + (size_t)rhs * a.wstride;
+    c128 nacc = mk(0.0, 0.0);
+    for (size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x; p < a.N; p += (size_t)gridDim.x * blockDim.x) {
+        c128 v = w[p];
+        if (on) {
+            c128 acc = mk(0.0, 0.0);
+            for (int l = 0; l < a.nv; ++l)
+                acc = acc + a.V[(size_t)l * a.vstride_l + (size_t)rhs * a.vstride_rhs + p] * cf[l];
+            v = a.sign > 0 ? v + acc : v - acc;
+            w[p] = v;
+        }
+        nacc = nacc + conj(v) * v;
+    }
+    if (!a.partial) return;
+    const c128 part = block_sum(nacc, red);
+    if (threadIdx.x == 0) a.partial[(size_t)rhs * gridDim.x + blockIdx.x] = part;
 }
 
-// dst = src * scale[rhs]  (scale = 1/norm, computed on the host), masked rhs skipped
-__global__ void k_scale(const c128* src, c128* dst, const double* scale, const int* active, size_t N,
+// dst = src / sqrt(nrm2[rhs * nstride].re) (0 if the norm is 0), masked rhs skipped
+__global__ void k_scale(const c128* src, c128* dst, const c128* nrm2, int nstride, const int* active, size_t N,
                         size_t sstride, size_t dstride) {
     const size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int rhs = blockIdx.y;
     if (p >= N || (active && !active[rhs])) return;
-    const double s = scale[rhs];
+    const double nr = sqrt(fmax(0.0, nrm2[(size_t)rhs * nstride].re));
+    const double s = nr > 0 ? 1.0 / nr : 0.0;
     const c128 v = src[(size_t)rhs * sstride + p];
     dst[(size_t)rhs * dstride + p] = mk(s * v.re, s * v.im);
 }
@@ -1907,23 +1922,22 @@ hipError_t launch_matvec(const MatvecArgs& a, int nrhs, hipStream_t st) {
     return hipGetLastError();
 }
 
-hipError_t launch_dots(const DotsArgs& a, int nrhs, c128* out, int ostride, int accumulate, hipStream_t st) {
-    dim3 grid(a.nblk, a.nv, nrhs);
-    k_dots_partial<<<grid, 256, 0, st>>>(a);
-    k_dots_finish<<<dim3(a.nv, nrhs), 256, 0, st>>>(a.partial, a.nblk, a.nv, nrhs, out, ostride, accumulate);
+hipError_t launch_dots(const DotsArgs& a, int nrhs, hipStream_t st) {
+    k_dots_partial<<<dim3(a.nblk, a.nv, nrhs), 256, 0, st>>>(a);
+    k_dots_finish<<<dim3(a.nv, nrhs), 256, 0, st>>>(a.partial, a.nblk, a.nv, a.out, a.ostride, a.accumulate);
     return hipGetLastError();
 }
 
 hipError_t launch_gs_update(const GsArgs& a, int nrhs, hipStream_t st) {
-    dim3 grid(blocks_for(a.N, 256), nrhs);
-    k_gs_update<<<grid, 256, 0, st>>>(a);
+    k_gs_update<<<dim3(a.nblk, nrhs), 256, 0, st>>>(a);
+    if (a.partial) k_dots_finish<<<dim3(1, nrhs), 256, 0, st>>>(a.partial, a.nblk, 1, a.norm_out, a.nstride, 0);
     return hipGetLastError();
 }
 
-hipError_t launch_scale(const c128* src, c128* dst, const double* scale, const int* active, size_t N,
+hipError_t launch_scale(const c128* src, c128* dst, const c128* nrm2, int nstride, const int* active, size_t N,
                         size_t sstride, size_t dstride, int nrhs, hipStream_t st) {
     dim3 grid(blocks_for(N, 256), nrhs);
-    k_scale<<<grid, 256, 0, st>>>(src, dst, scale, active, N, sstride, dstride);
+    k_scale<<<grid, 256, 0, st>>>(src, dst, nrm2, nstride, active, N, sstride, dstride);
     return hipGetLastError();
 }
 

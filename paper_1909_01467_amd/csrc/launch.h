@@ -70,8 +70,11 @@ struct DotsArgs {
     size_t wstride;
     size_t N;
     int nv;
-    int nblk;
-    c128* partial;   // [nrhs][nv][nblk]
+    int nblk;          // workgroups per (l, rhs)
+    c128* partial;     // [nrhs][nv][nblk]
+    c128* out;         // out[rhs * ostride + l]
+    int ostride;
+    int accumulate;    // 1: out += sum
 };
 
 struct GsArgs {
@@ -85,6 +88,10 @@ struct GsArgs {
     int nv;
     int sign;          // -1: w -= V c ; +1: w += V c
     const int* active; // optional per-rhs mask
+    int nblk;          // workgroups per rhs (grid-stride over the points)
+    c128* norm_out;    // with partial: ||w||^2 after the update into norm_out[rhs * nstride]
+    int nstride;
+    c128* partial;     // optional [nrhs][nblk] workgroup partials of the norm
 };
 
 // twisted block factorisation (complex128 factors); work: 2 blocks per subdomain when not in LDS
@@ -128,9 +135,12 @@ hipError_t launch_qprime(const GemvSolve* gs, int ngs, int max_nin, const SubDes
                          const c128* Q, c128* Qp, hipStream_t st);
 hipError_t launch_zsum(const ZsumArgs& a, int nrhs, bool c64mode, hipStream_t st);
 hipError_t launch_matvec(const MatvecArgs& a, int nrhs, hipStream_t st);
-hipError_t launch_dots(const DotsArgs& a, int nrhs, c128* out, int ostride, int accumulate, hipStream_t st);
+// out[rhs * ostride + l] (+)= <V_l, w> for l < nv (workgroup partials, then a fixed-order sum)
+hipError_t launch_dots(const DotsArgs& a, int nrhs, hipStream_t st);
+// w -= V c (or +=), optionally followed by ||w||^2 (same point order as launch_dots)
 hipError_t launch_gs_update(const GsArgs& a, int nrhs, hipStream_t st);
-hipError_t launch_scale(const c128* src, c128* dst, const double* scale, const int* active, size_t N,
+// dst = src / ||.|| with the squared norm read from nrm2[rhs * nstride] on the device
+hipError_t launch_scale(const c128* src, c128* dst, const c128* nrm2, int nstride, const int* active, size_t N,
                         size_t sstride, size_t dstride, int nrhs, hipStream_t st);
 hipError_t launch_conj(const c128* src, c128* dst, size_t n, hipStream_t st);
 hipError_t launch_mass_gradient(const c128* lam, const c128* u, int nrhs, const Geometry& g, double* grad,
