@@ -73,6 +73,13 @@ def speed_random_smooth(n: int, seed: int = 5, amp: float = 0.3, corr: float = 0
     return 1.0 + amp * p / np.max(np.abs(p))
 
 
+def speed_waveguide(n: int, contrast: float = 2.0, width: float = 0.1) -> np.ndarray:
+    """A straight horizontal wave-guide (stand-in for the wave-guide of Sec. 5): c = 1 in the
+    channel |y - 1/2| < width/2, c = contrast elsewhere."""
+    Y, X = _mesh(n, 2)
+    return np.where(np.abs(Y - 0.5) < width / 2, 1.0, float(contrast)) + 0.0 * X
+
+
 def speed_layered_faults(n: int, seed: int = 3, layers: int = 12, faults: int = 3,
                          cmin: float = 1.5, cmax: float = 4.5) -> np.ndarray:
     """Piecewise-constant dipping layers cut by vertical faults (reflective medium)."""
@@ -125,6 +132,12 @@ def four_point_sources(n: int) -> np.ndarray:
     width 1/n at (0.125, 0.125), (0.125, 0.875), (0.875, 0.125) and (0.875, 0.875)."""
     pts = ((0.125, 0.125), (0.125, 0.875), (0.875, 0.125), (0.875, 0.875))
     return sum(gaussian_source(n, c, width=1.0 / n) for c in pts)
+
+
+def entrance_source(n: int) -> np.ndarray:
+    """One narrow Gaussian (amplitude n^2/pi, width 1/n) at the entrance (0.125, 0.5) of the
+    wave-guide."""
+    return gaussian_source(n, (0.125, 0.5), width=1.0 / n)
 
 
 def receiver_indices(n: int, xs, y: float) -> np.ndarray:

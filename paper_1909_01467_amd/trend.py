@@ -12,7 +12,8 @@ Setup (Sec. 5, with the readings of the grid and PML of App. A used everywhere i
 
 Tab. PMLeffect reports the constant medium for q = 2 ... 128 and PMLs of 1 ... 7 wavelengths,
 Tab. Complexity its q = p column N_it (2 wavelengths), Tab. RandomWavespeed a random smooth medium
-(2 wavelengths); the random smooth medium here is inputs.speed_random_smooth.
+(2 wavelengths; here inputs.speed_random_smooth), Tab. Waveguide a wave-guide with a source at its
+entrance for contrasts 2 ... 6 (here inputs.speed_waveguide and inputs.entrance_source).
 
 usage: python -m paper_1909_01467_amd.trend --q 2 4 8 16 --wavelengths 1 2 3 [--medium const|smooth]
        [--precision mixed|fp64] [--windows] [--json out.json]
@@ -31,25 +32,34 @@ import numpy as np
 
 
 def case(q: int, wavelengths: float, medium: str = "const", precision: str = "mixed", tol: float = 1e-6,
-         points_per_subdomain: int = 101, c_factor: float = 16.0, maxit: int = 200, windows: bool = False) -> dict:
+         points_per_subdomain: int = 101, c_factor: float = 16.0, maxit: int = 200, windows: bool = False,
+         restart: int = 50) -> dict:
     import torch
 
     from . import inputs
     from .lsweeps import Solver, extend_medium
 
     n = points_per_subdomain * q
-    c = inputs.speed_constant(n) if medium == "const" else inputs.speed_random_smooth(n)
+    if medium == "const":
+        c = inputs.speed_constant(n)
+    elif medium == "smooth":
+        c = inputs.speed_random_smooth(n)
+    elif medium.startswith("waveguide"):   # waveguide<contrast>, e.g. waveguide2
+        c = inputs.speed_waveguide(n, float(medium[len("waveguide"):] or 2))
+    else:
+        raise ValueError(medium)
     cmin, cmax = float(c.min()), float(c.max())
     omega = 2.0 * math.pi * cmin * n / 10.0
     n_pml = int(math.ceil(10.0 * wavelengths * cmax / cmin - 1e-9))
     h = inputs.bulk_h(n)
     m_ext = extend_medium(torch.from_numpy(1.0 / c**2).cuda(), n_pml).contiguous()
-    f = torch.from_numpy(inputs.four_point_sources(n)).to(torch.complex128).cuda()
+    src = inputs.entrance_source(n) if medium.startswith("waveguide") else inputs.four_point_sources(n)
+    f = torch.from_numpy(src).to(torch.complex128).cuda()
     b = torch.nn.functional.pad(f, (n_pml, n_pml, n_pml, n_pml)).contiguous()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     s = Solver(m_ext, omega, h, n, n_pml, q, q, C=c_factor * math.log(omega), precision=precision, tol=tol,
-               maxit=maxit, windows=windows)
+               maxit=maxit, windows=windows, restart=restart)
     t_setup = (time.perf_counter() - t0) * 1e3
     try:
         s.solve(b)                                   # warm-up
@@ -61,7 +71,7 @@ def case(q: int, wavelengths: float, medium: str = "const", precision: str = "mi
     finally:
         s.close()
     return dict(q=q, n=n, n_pml=n_pml, wavelengths=wavelengths, medium=medium, precision=precision, c_factor=c_factor,
-                windows=windows,
+                windows=windows, restart=restart,
                 omega_over_2pi=omega / (2.0 * math.pi), iterations=int(info["iterations"][0]),
                 relres=float(info["relres"][0]), converged=bool(info["converged"][0]),
                 t_setup_ms=round(t_setup, 1), t_solve_ms=round(t_solve, 2))
@@ -71,10 +81,12 @@ def main(argv=None) -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--q", type=int, nargs="+", default=[2, 4, 8, 16])
     ap.add_argument("--wavelengths", type=float, nargs="+", default=[1, 2, 3])
-    ap.add_argument("--medium", choices=["const", "smooth"], default="const")
+    ap.add_argument("--medium", default="const",
+                    help="const, smooth, or waveguide<contrast> (e.g. waveguide2: c = 1 in the channel, 2 outside)")
     ap.add_argument("--precision", choices=["mixed", "fp64"], default="mixed")
     ap.add_argument("--c-factor", type=float, nargs="+", default=[16.0], help="C = factor * ln(omega)")
     ap.add_argument("--maxit", type=int, default=200)
+    ap.add_argument("--restart", type=int, default=50, help="FGMRES restart length")
     ap.add_argument("--windows", action="store_true", help="scenario 4 (four shifted CDDs with windows)")
     ap.add_argument("--json", default=None)
     args = ap.parse_args(argv)
@@ -82,7 +94,8 @@ def main(argv=None) -> int:
     for cf in args.c_factor:
         for w in args.wavelengths:
             for q in args.q:
-                r = case(q, w, args.medium, args.precision, c_factor=cf, maxit=args.maxit, windows=args.windows)
+                r = case(q, w, args.medium, args.precision, c_factor=cf, maxit=args.maxit, windows=args.windows,
+                         restart=args.restart)
                 rows.append(r)
                 print(f"q={r['q']:3d} n={r['n']:5d} n_pml={r['n_pml']:3d} omega/2pi={r['omega_over_2pi']:7.1f} "
                       f"C/ln(omega)={cf:g} wavelengths={w:g} windows={int(args.windows)} iterations={r['iterations']:3d} relres={r['relres']:.2e} "
