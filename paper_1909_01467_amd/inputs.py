@@ -80,6 +80,27 @@ def speed_waveguide(n: int, contrast: float = 2.0, width: float = 0.1) -> np.nda
     return np.where(np.abs(Y - 0.5) < width / 2, 1.0, float(contrast)) + 0.0 * X
 
 
+def speed_depth_gradient(n: int, top: float = 1.5, bottom: float = 3.0) -> np.ndarray:
+    """Smooth background whose speed grows linearly with depth (1 - y), from `top` at y = 1 to
+    `bottom` at y = 0 (stand-in for the smooth background BG1 of Sec. 5)."""
+    Y, X = _mesh(n, 2)
+    return top + (bottom - top) * (1.0 - Y) + 0.0 * X
+
+
+def speed_salt(n: int, seed: int = 6, salt: float = 4.5, blobs: int = 3) -> np.ndarray:
+    """The depth-gradient background with a salt body of speed `salt`: the region where a sum of
+    `blobs` seeded Gaussian bumps (centres in [0.3, 0.7] x [0.35, 0.6], radii 0.08-0.15) exceeds
+    1/2 (stand-in for BG1 with the salt body of Sec. 5)."""
+    rng = np.random.default_rng(seed)
+    Y, X = _mesh(n, 2)
+    bump = np.zeros_like(X)
+    for _ in range(blobs):
+        cx, cy = rng.uniform(0.3, 0.7), rng.uniform(0.35, 0.6)
+        r = rng.uniform(0.08, 0.15)
+        bump += np.exp(-((X - cx) ** 2 + (Y - cy) ** 2) / r**2)
+    return np.where(bump > 0.5, float(salt), speed_depth_gradient(n))
+
+
 def speed_layered_faults(n: int, seed: int = 3, layers: int = 12, faults: int = 3,
                          cmin: float = 1.5, cmax: float = 4.5) -> np.ndarray:
     """Piecewise-constant dipping layers cut by vertical faults (reflective medium)."""

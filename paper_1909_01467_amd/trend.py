@@ -13,7 +13,8 @@ Setup (Sec. 5, with the readings of the grid and PML of App. A used everywhere i
 Tab. PMLeffect reports the constant medium for q = 2 ... 128 and PMLs of 1 ... 7 wavelengths,
 Tab. Complexity its q = p column N_it (2 wavelengths), Tab. RandomWavespeed a random smooth medium
 (2 wavelengths; here inputs.speed_random_smooth), Tab. Waveguide a wave-guide with a source at its
-entrance for contrasts 2 ... 6 (here inputs.speed_waveguide and inputs.entrance_source).
+entrance for contrasts 2 ... 6 (here inputs.speed_waveguide and inputs.entrance_source), Tab. BP a
+smooth background with and without a salt body (here inputs.speed_depth_gradient and inputs.speed_salt).
 
 usage: python -m paper_1909_01467_amd.trend --q 2 4 8 16 --wavelengths 1 2 3 [--medium const|smooth]
        [--precision mixed|fp64] [--windows] [--json out.json]
@@ -44,6 +45,10 @@ def case(q: int, wavelengths: float, medium: str = "const", precision: str = "mi
         c = inputs.speed_constant(n)
     elif medium == "smooth":
         c = inputs.speed_random_smooth(n)
+    elif medium == "background":
+        c = inputs.speed_depth_gradient(n)
+    elif medium == "salt":
+        c = inputs.speed_salt(n)
     elif medium.startswith("waveguide"):   # waveguide<contrast>, e.g. waveguide2
         c = inputs.speed_waveguide(n, float(medium[len("waveguide"):] or 2))
     else:
@@ -82,7 +87,8 @@ def main(argv=None) -> int:
     ap.add_argument("--q", type=int, nargs="+", default=[2, 4, 8, 16])
     ap.add_argument("--wavelengths", type=float, nargs="+", default=[1, 2, 3])
     ap.add_argument("--medium", default="const",
-                    help="const, smooth, or waveguide<contrast> (e.g. waveguide2: c = 1 in the channel, 2 outside)")
+                    help="const, smooth, background (speed growing with depth), salt (that background with a "
+                         "salt body), or waveguide<contrast> (e.g. waveguide2: c = 1 in the channel, 2 outside)")
     ap.add_argument("--precision", choices=["mixed", "fp64"], default="mixed")
     ap.add_argument("--c-factor", type=float, nargs="+", default=[16.0], help="C = factor * ln(omega)")
     ap.add_argument("--maxit", type=int, default=200)
