@@ -141,6 +141,7 @@ def main():
     ap.add_argument("--all-sources", action="store_true",
                     help="solve for all of the workload's sources in one batch (nrhs = number of sources)")
     ap.add_argument("--maxit", type=int, default=500)
+    ap.add_argument("--restart", type=int, default=50, help="FGMRES restart (the basis holds restart+1 vectors per rhs)")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="first run one device copy of this many MiB (calibrates FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
@@ -168,7 +169,7 @@ def main():
     results = {}
     for precision in (["mixed"] if args.no_fp64 else ["mixed", "fp64"]):
         s = Solver(m_ext, wl.omega, wl.h, wl.n, wl.n_pml, wl.q, wl.r, C=wl.C, precision=precision, tol=1e-6,
-                   windows=args.windows, nrhs_max=nrhs, maxit=args.maxit)
+                   windows=args.windows, nrhs_max=nrhs, maxit=args.maxit, restart=args.restart)
         st0 = s.stats()
         log(precision, "setup ms", round(st0["t_setup_ms"], 1), "factor ms", round(st0["t_factor_ms"], 1))
         u, info, ms = time_solves(s, b, args.steps, args.warmup)
