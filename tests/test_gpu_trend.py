@@ -1,6 +1,8 @@
-"""Iteration counts of the GPU solve on the standard setup of Sec. 5 (constant medium, 101 points
-per subdomain and direction, 10 points per wavelength, four narrow sources, tolerance 1e-6)
-against Tab. PMLeffect, with the package's default PML constant (16 ln omega)."""
+"""Iteration counts of the GPU solve on the standard setup of Sec. 5 (101 points per subdomain and
+direction, 10 points per wavelength, tolerance 1e-6) against the paper's tables, with the package's
+default PML constant (16 ln omega): Tab. PMLeffect (constant medium), Tab. BP (smooth background,
+with and without a salt body) and Tab. Waveguide (contrast 2).  The media of the last two are
+synthetic stand-ins (inputs.speed_depth_gradient, speed_salt, speed_waveguide)."""
 import json
 import os
 import sys
@@ -34,3 +36,27 @@ def test_standard_setup_iterations_follow_paper_table():
             its[w] = r["iterations"]
         assert its[1] <= row["iterations_pml_1_wavelength"] + 1, (row, its)
         assert its[2] <= its[1], (row, its)
+
+
+def test_reflective_media_follow_paper_tables_with_windows():
+    """PML of two wavelengths at the fastest speed (the paper's rule), restart 300.  The smooth
+    background needs at most two iterations more than BG1; with the salt body, scenario 4 (four
+    shifted CDDs) stays within one iteration of Tab. BP and needs fewer iterations than one CDD;
+    on the wave-guide scenario 4 needs no more iterations than Tab. Waveguide."""
+    with open(os.path.join(GOLDEN, "reflective_media_iterations.json")) as fh:
+        table = json.load(fh)
+    for row in table["bp"][:2]:
+        r = trend.case(row["q"], 2, medium="background", restart=300, maxit=300)
+        say("background q", row["q"], "iterations", r["iterations"], "paper", row["bg1"])
+        assert r["converged"] and r["iterations"] <= row["bg1"] + 2
+        rw = trend.case(row["q"], 2, medium="salt", restart=300, maxit=300, windows=True)
+        r3 = trend.case(row["q"], 2, medium="salt", restart=300, maxit=300)
+        say("salt q", row["q"], "scenario 4", rw["iterations"], "scenario 3", r3["iterations"], "paper",
+            row["bg1_with_salt"])
+        assert rw["converged"] and r3["converged"]
+        assert rw["iterations"] <= row["bg1_with_salt"] + 1
+        assert rw["iterations"] < r3["iterations"]
+    row = table["waveguide_contrast_2"][1]
+    rw = trend.case(row["q"], 2, medium="waveguide2", restart=300, maxit=300, windows=True)
+    say("wave-guide q", row["q"], "scenario 4", rw["iterations"], "paper", row["iterations"])
+    assert rw["converged"] and rw["iterations"] <= row["iterations"]
