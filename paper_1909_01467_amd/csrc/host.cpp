@@ -147,9 +147,14 @@ struct lsw_plan {
     lsw_plan* shifted[3] = {nullptr, nullptr, nullptr};
     double* d_wx = nullptr;         // a(x) on the Nx extended points
     double* d_wy = nullptr;         // b(y) on the Ny extended points
-    c128* d_wr = nullptr;           // windowed right-hand sides [nrhs][N]
-    c128* d_wz = nullptr;           // one shifted CDD's sweep result [nrhs][N]
+    c128* d_wr[4] = {nullptr, nullptr, nullptr, nullptr};   // windowed right-hand sides of each CDD [nrhs][N]
+    c128* d_wz[3] = {nullptr, nullptr, nullptr};            // the shifted CDDs' sweep results [nrhs][N]
     hipEvent_t evw[2] = {nullptr, nullptr};   // start and end of a windowed application
+    // the shifted CDDs run on streams of their own (default priority), forked from and joined to
+    // the caller's stream by events, so that their latency-bound launches overlap
+    hipStream_t own_stream = nullptr;         // a member's stream (created by the windowed plan)
+    hipEvent_t ev_fork = nullptr;
+    hipEvent_t ev_join[3] = {nullptr, nullptr, nullptr};
     hipEvent_t ev_spin = nullptr;   // polled by the Krylov loop's waits
 };
 
@@ -201,6 +206,10 @@ void free_plan(lsw_plan* p) {
         if (e) (void)hipEventDestroy(e);
     for (hipEvent_t e : p->evw)
         if (e) (void)hipEventDestroy(e);
+    for (hipEvent_t e : p->ev_join)
+        if (e) (void)hipEventDestroy(e);
+    if (p->ev_fork) (void)hipEventDestroy(p->ev_fork);
+    if (p->own_stream) (void)hipStreamDestroy(p->own_stream);
     if (p->ev_spin) (void)hipEventDestroy(p->ev_spin);
     if (p->rb) (void)rocblas_destroy_handle(p->rb);
     delete p;
@@ -714,13 +723,20 @@ int apply_cdd(lsw_plan* p, const c128* d_r, c128* d_z, int nrhs, bool timed) {
 int apply_impl(lsw_plan* p, const c128* d_r, c128* d_z, int nrhs, bool timed) {
     if (!p->windows) return apply_cdd(p, d_r, d_z, nrhs, timed);
     if (timed) HIPCK(p, hipEventRecord(p->evw[0], p->stream));
-    for (int k = 0; k < 4; ++k) {
-        lsw_plan* c = k == 0 ? p : p->shifted[k - 1];
-        HIPCK(p, launch_window(d_r, p->d_wr, p->d_wx, p->d_wy, k & 1, k >> 1, p->Nx, p->N, nrhs, p->stream));
-        const int rc = apply_cdd(c, p->d_wr, k == 0 ? d_z : p->d_wz, nrhs, timed);
-        if (rc != LSW_OK) return c == p ? rc : fail(p, rc, c->err);
-        if (k > 0) HIPCK(p, launch_accumulate(d_z, p->d_wz, p->N * (size_t)nrhs, p->stream));
+    HIPCK(p, hipEventRecord(p->ev_fork, p->stream));
+    for (int k = 1; k < 4; ++k) {   // the shifted CDDs, each on its own stream
+        lsw_plan* c = p->shifted[k - 1];
+        HIPCK(p, hipStreamWaitEvent(c->stream, p->ev_fork, 0));
+        HIPCK(p, launch_window(d_r, p->d_wr[k], p->d_wx, p->d_wy, k & 1, k >> 1, p->Nx, p->N, nrhs, c->stream));
+        const int rc = apply_cdd(c, p->d_wr[k], p->d_wz[k - 1], nrhs, timed);
+        if (rc != LSW_OK) return fail(p, rc, c->err);
+        HIPCK(p, hipEventRecord(p->ev_join[k - 1], c->stream));
     }
+    HIPCK(p, launch_window(d_r, p->d_wr[0], p->d_wx, p->d_wy, 0, 0, p->Nx, p->N, nrhs, p->stream));
+    const int rc = apply_cdd(p, p->d_wr[0], d_z, nrhs, timed);
+    if (rc != LSW_OK) return rc;
+    for (hipEvent_t e : p->ev_join) HIPCK(p, hipStreamWaitEvent(p->stream, e, 0));
+    HIPCK(p, launch_accumulate(d_z, p->d_wz[0], p->d_wz[1], p->d_wz[2], p->N * (size_t)nrhs, p->stream));
     if (timed) HIPCK(p, hipEventRecord(p->evw[1], p->stream));
     return LSW_OK;
 }
@@ -1699,8 +1715,16 @@ int setup_windows(lsw_plan* p, const double* d_m, double omega, double h, const 
     int rc;
     if ((rc = dalloc(p, &p->d_wx, ax.size())) != LSW_OK) return rc;
     if ((rc = dalloc(p, &p->d_wy, ay.size())) != LSW_OK) return rc;
-    if ((rc = dalloc(p, &p->d_wr, (size_t)p->nrhs_max * p->N)) != LSW_OK) return rc;
-    if ((rc = dalloc(p, &p->d_wz, (size_t)p->nrhs_max * p->N)) != LSW_OK) return rc;
+    for (c128*& b : p->d_wr)
+        if ((rc = dalloc(p, &b, (size_t)p->nrhs_max * p->N)) != LSW_OK) return rc;
+    for (c128*& b : p->d_wz)
+        if ((rc = dalloc(p, &b, (size_t)p->nrhs_max * p->N)) != LSW_OK) return rc;
+    HIPCK(p, hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming));
+    for (hipEvent_t& e : p->ev_join) HIPCK(p, hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    for (lsw_plan* c : p->shifted) {   // set up on the caller's stream; applied on their own
+        HIPCK(p, hipStreamCreateWithFlags(&c->own_stream, hipStreamNonBlocking));
+        c->stream = c->own_stream;
+    }
     HIPCK(p, hipMemcpy(p->d_wx, ax.data(), sizeof(double) * ax.size(), hipMemcpyHostToDevice));
     HIPCK(p, hipMemcpy(p->d_wy, ay.data(), sizeof(double) * ay.size(), hipMemcpyHostToDevice));
     for (hipEvent_t& e : p->evw) HIPCK(p, hipEventCreate(&e));

@@ -1534,9 +1534,10 @@ __global__ void k_window(const c128* r, c128* out, const double* wx, const doubl
     }
 }
 
-__global__ void k_accumulate(c128* z, const c128* add, size_t n) {
+// z = ((z + a) + b) + c, entry by entry
+__global__ void k_accumulate(c128* z, const c128* a, const c128* b, const c128* c, size_t n) {
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
-        z[i] = c128{z[i].re + add[i].re, z[i].im + add[i].im};
+        z[i] = ((z[i] + a[i]) + b[i]) + c[i];
 }
 
 // ------------------------------------------------------------------ z assembly
@@ -1902,8 +1903,8 @@ hipError_t launch_window(const c128* r, c128* out, const double* wx, const doubl
     return hipGetLastError();
 }
 
-hipError_t launch_accumulate(c128* z, const c128* add, size_t n, hipStream_t st) {
-    k_accumulate<<<(unsigned)std::min<size_t>(4096, blocks_for(n, 256)), 256, 0, st>>>(z, add, n);
+hipError_t launch_accumulate(c128* z, const c128* a, const c128* b, const c128* c, size_t n, hipStream_t st) {
+    k_accumulate<<<(unsigned)std::min<size_t>(4096, blocks_for(n, 256)), 256, 0, st>>>(z, a, b, c, n);
     return hipGetLastError();
 }
 

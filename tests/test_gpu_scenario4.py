@@ -121,6 +121,7 @@ def test_windowed_apply_batches_rhs():
     s = c.solver(nrhs_max=3)
     Rt = torch.from_numpy(R).cuda()
     Z = s.apply(Rt)
+    assert torch.equal(Z, s.apply(Rt))   # the four CDDs run concurrently; the sum order is fixed
     for k in range(3):
         assert rel(to_np(Z[k]), to_np(s.apply(Rt[k]))) < 1e-13
     # the work of the windowed plan is that of its four CDDs built alone
