@@ -35,6 +35,8 @@
 #ifndef LSW_H
 #define LSW_H
 
+#include <stddef.h>
+
 #ifdef __cplusplus
 extern "C" {
 #endif
@@ -97,6 +99,14 @@ typedef struct {
     int nrhs_max;        /* largest nrhs any later call will pass (default 1 when <= 0) */
     void* stream;        /* hipStream_t for all device work (NULL = default stream) */
     int sweep_mode;      /* lsw_sweep_mode; both compute the same M^-1 r up to rounding */
+    /* Optional device allocator for every workspace buffer of the handle (factors, traces, Krylov
+     * basis, ...), e.g. a framework's caching allocator; NULL selects hipMalloc / hipFree.  alloc
+     * returns a device pointer of at least `bytes` bytes aligned to 256 bytes, or NULL on failure
+     * (lsw_setup then fails with LSW_ENOMEM); release frees it.  Both or neither must be given.
+     * The handle calls release only after waiting for its own streams.  ctx is passed through. */
+    void* (*alloc)(size_t bytes, void* ctx);
+    void (*release)(void* ptr, void* ctx);
+    void* alloc_ctx;
 } lsw_opts_t;
 
 typedef struct {
@@ -172,7 +182,8 @@ typedef struct {
  * of every shifted one, a linear ramp in between (w(d) / (w(d) + w(d')), w(t) = max(0, t - 1), d
  * and d' the distances to the nearest interface of either kind), and 1 beyond the outermost
  * (shifted) interfaces; the four windows are a b, (1-a) b, a (1-b), (1-a)(1-b).
- * Errors: LSW_EINVAL (dim not 2 or 3, sizes, a window that does not fit the grid, windows
+ * Errors: LSW_EINVAL (dim not 2 or 3, sizes, a window that does not fit the grid, only one of
+ * opts->alloc and opts->release, windows
  * with dim 3, q or r below 2 or a shift outside its range),
  * LSW_ENAN (non-finite m), LSW_ENOMEM, LSW_EHIP, LSW_ESINGULAR.  On error *out is NULL
  * and nothing is leaked.

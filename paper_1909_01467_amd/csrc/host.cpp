@@ -156,6 +156,9 @@ struct lsw_plan {
     hipEvent_t ev_fork = nullptr;
     hipEvent_t ev_join[3] = {nullptr, nullptr, nullptr};
     hipEvent_t ev_spin = nullptr;   // polled by the Krylov loop's waits
+    void* (*ualloc)(size_t, void*) = nullptr;   // the caller's device allocator (optional)
+    void (*ufree)(void*, void*) = nullptr;
+    void* uctx = nullptr;
 };
 
 namespace {
@@ -171,25 +174,43 @@ std::string g_setup_error;
         }                                                                        \
     } while (0)
 
+// device workspace: the caller's allocator when given, else hipMalloc
 template <typename T>
 int dalloc(lsw_plan* p, T** out, size_t count) {
     void* ptr = nullptr;
     if (count == 0) count = 1;
-    hipError_t e = hipMalloc(&ptr, count * sizeof(T));
-    if (e != hipSuccess) {
-        p->err = "hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes failed: " + hipGetErrorString(e);
-        return LSW_ENOMEM;
+    const size_t bytes = count * sizeof(T);
+    if (p->ualloc) {
+        ptr = p->ualloc(bytes, p->uctx);
+        if (!ptr) {
+            p->err = "the caller's allocator returned no memory for " + std::to_string(bytes) + " bytes";
+            return LSW_ENOMEM;
+        }
+    } else {
+        hipError_t e = hipMalloc(&ptr, bytes);
+        if (e != hipSuccess) {
+            p->err = "hipMalloc of " + std::to_string(bytes) + " bytes failed: " + hipGetErrorString(e);
+            return LSW_ENOMEM;
+        }
     }
     p->allocs.push_back(ptr);
     *out = static_cast<T*>(ptr);
     return LSW_OK;
 }
 
+void release_mem(lsw_plan* p, void* ptr) {
+    if (p->ufree) p->ufree(ptr, p->uctx);
+    else (void)hipFree(ptr);
+}
+
+// frees one buffer once the plan's stream has finished with it (hipFree waits by itself; a
+// caller's allocator may hand the memory out again at once)
 void dfree(lsw_plan* p, void* ptr) {
     if (!ptr) return;
     auto it = std::find(p->allocs.begin(), p->allocs.end(), ptr);
     if (it != p->allocs.end()) p->allocs.erase(it);
-    (void)hipFree(ptr);
+    if (p->ufree) (void)hipStreamSynchronize(p->stream);
+    release_mem(p, ptr);
 }
 
 void free_plan(lsw_plan* p) {
@@ -198,7 +219,8 @@ void free_plan(lsw_plan* p) {
         free_plan(c);
         c = nullptr;
     }
-    for (void* a : p->allocs) (void)hipFree(a);
+    if (p->ufree) (void)hipStreamSynchronize(p->stream);   // own_stream for a member
+    for (void* a : p->allocs) release_mem(p, a);
     if (p->h_hbuf) (void)hipHostFree(p->h_hbuf);
     if (p->h_active) (void)hipHostFree(p->h_active);
     if (p->h_coef) (void)hipHostFree(p->h_coef);
@@ -1217,6 +1239,11 @@ int setup_impl(lsw_plan* p, const double* d_m, double omega, double h, const lsw
     p->pl = (pml && pml->n_pml_local >= 0) ? pml->n_pml_local : p->px;
     p->e = 2 + p->pl;
     if (opts) {
+        if ((opts->alloc == nullptr) != (opts->release == nullptr))
+            return fail(p, LSW_EINVAL, "opts.alloc and opts.release must be given together");
+        p->ualloc = opts->alloc;
+        p->ufree = opts->release;
+        p->uctx = opts->alloc_ctx;
         p->precision = opts->precision == LSW_MIXED ? LSW_MIXED : LSW_FP64;
         if (opts->restart > 0) p->restart = opts->restart;
         if (opts->maxit > 0) p->maxit = opts->maxit;

@@ -43,10 +43,15 @@ class lsw_pml_t(ctypes.Structure):
     _fields_ = [("C", ctypes.c_double), ("n_pml_local", ctypes.c_int)]
 
 
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+RELEASE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
+
 class lsw_opts_t(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("restart", ctypes.c_int), ("maxit", ctypes.c_int),
                 ("tol", ctypes.c_double), ("nrhs_max", ctypes.c_int), ("stream", ctypes.c_void_p),
-                ("sweep_mode", ctypes.c_int)]
+                ("sweep_mode", ctypes.c_int), ("alloc", ALLOC_FN), ("release", RELEASE_FN),
+                ("alloc_ctx", ctypes.c_void_p)]
 
 
 class lsw_rhs_info_t(ctypes.Structure):
@@ -146,12 +151,16 @@ class Solver:
     windows=True selects scenario 4 (Sec. 2.1): the CDD and three shifted copies, each sweeping
     the right-hand side times its window of a partition of unity; `shift` is then the shift of
     the copies along (x, y) ((0, 0): half of the smallest group).  Without windows `shift`
-    shifts this CDD's own interior boundaries."""
+    shifts this CDD's own interior boundaries.
+
+    torch_allocator=True places the handle's whole device workspace in PyTorch's caching
+    allocator (on the solver's stream) instead of hipMalloc."""
 
     def __init__(self, m_ext: torch.Tensor, omega: float, h: float, n, n_pml, q: int, r: int | None = None,
                  C: float | None = None, n_pml_local: int | None = None, precision: str = "fp64",
                  restart: int = 50, maxit: int = 500, tol: float = 1e-6, nrhs_max: int = 1,
-                 sweep_mode: str = "compressed", windows: bool = False, shift=(0, 0)):
+                 sweep_mode: str = "compressed", windows: bool = False, shift=(0, 0),
+                 torch_allocator: bool = False):
         lib = load_library()
         if not torch.cuda.is_available():
             raise RuntimeError("the L-sweeps library needs a GPU")
@@ -181,6 +190,24 @@ class Solver:
         opts = lsw_opts_t(LSW_MIXED if precision == "mixed" else LSW_FP64, restart, maxit, tol, nrhs_max,
                           ctypes.c_void_p(self.stream.cuda_stream),
                           LSW_SWEEP_CHAIN if sweep_mode == "chain" else LSW_SWEEP_COMPRESSED)
+        if torch_allocator:
+            stream = self.stream
+
+            def _alloc(nbytes, _ctx):
+                try:
+                    return torch.cuda.caching_allocator_alloc(nbytes, stream=stream)
+                except Exception:   # out of memory: the library reports LSW_ENOMEM
+                    return None
+
+            def _release(ptr, _ctx):
+                try:
+                    torch.cuda.caching_allocator_delete(ptr)
+                except Exception:
+                    pass
+
+            # the callbacks must outlive the handle (lsw_destroy calls release)
+            self._callbacks = (ALLOC_FN(_alloc), RELEASE_FN(_release))
+            opts.alloc, opts.release = self._callbacks
         handle = ctypes.c_void_p()
         torch.cuda.synchronize()
         rc = lib.lsw_setup(ctypes.byref(handle), ctypes.c_void_p(_dptr(m_ext)), omega, h, ctypes.byref(grid),

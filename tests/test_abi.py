@@ -134,6 +134,20 @@ def test_setup_rejects_bad_windows_before_touching_memory():
         assert msg in lib.lsw_last_error(None), (msg, lib.lsw_last_error(None))
 
 
+def test_setup_rejects_an_allocator_without_its_release():
+    lib = lsweeps.load_library()
+    h = ctypes.c_void_p()
+    grid = lsweeps.lsw_grid_t(2, (ctypes.c_int * 3)(40, 40, 0), (ctypes.c_int * 3)(5, 5, 0))
+    cdd = lsweeps.lsw_cdd_t(2, 2)
+    opts = lsweeps.lsw_opts_t()
+    keep = lsweeps.ALLOC_FN(lambda n, ctx: None)
+    opts.alloc = keep
+    rc = lib.lsw_setup(ctypes.byref(h), ctypes.c_void_p(1), 10.0, 0.1, ctypes.byref(grid), ctypes.byref(cdd),
+                       None, ctypes.byref(opts))
+    assert rc == lsweeps.LSW_EINVAL and h.value is None
+    assert b"release" in lib.lsw_last_error(None)
+
+
 def test_solver_refuses_to_run_without_a_gpu():
     import torch
     if torch.cuda.is_available():

@@ -388,3 +388,31 @@ def test_rhs_per_workgroup_is_tuned_at_setup():
     say("tuned R", st["rhs_per_workgroup"], st["tune_ms"])
     assert st["rhs_per_workgroup"] in (1, 2, 4)
     assert all(t > 0 for t in st["tune_ms"])
+
+
+@pytest.mark.parametrize("windows", [False, True])
+def test_workspace_in_the_torch_caching_allocator(windows):
+    """torch_allocator=True: every workspace buffer comes from PyTorch's caching allocator (the
+    allocated bytes grow by at least the Krylov basis and return to where they were after close),
+    and the results are bitwise those of the hipMalloc workspace."""
+    c = CASES["ragged_45x38_3x2"]
+    r = torch.from_numpy(inputs.complex_normal(c.N, 61)).cuda()
+    b = torch.from_numpy(inputs.complex_normal(c.N, 62)).cuda()
+    torch.cuda.synchronize()
+    before = torch.cuda.memory_allocated()
+    s = c.solver(torch_allocator=True, windows=windows, tol=1e-8)
+    grown = torch.cuda.memory_allocated() - before
+    assert grown >= 51 * c.N * 16   # the Krylov basis V alone (restart 50)
+    z1 = s.apply(r).cpu()
+    u1, i1 = s.solve(b)
+    u1 = u1.cpu()
+    s.close()
+    torch.cuda.synchronize()
+    assert torch.cuda.memory_allocated() == before
+    s2 = c.solver(windows=windows, tol=1e-8)
+    z2 = s2.apply(r).cpu()
+    u2, i2 = s2.solve(b)
+    u2 = u2.cpu()
+    s2.close()
+    say("torch allocator", windows, "workspace MB", grown / 1e6, "iterations", i1["iterations"], i2["iterations"])
+    assert torch.equal(z1, z2) and torch.equal(u1, u2) and i1["iterations"] == i2["iterations"]
