@@ -558,7 +558,8 @@ int compress_schedule(lsw_plan* p) {
             ld = (ld + 15) & ~15;
             gs.ld = ld;
             gs.qp_off = (long long)p->QP_elems;
-            p->QP_elems += (size_t)ld * nin;
+            const int ninp = nin + (nin & 1);   // column pairs (k_qprime / k_gemv layout)
+            p->QP_elems += (size_t)ld * ninp;
             p->max_nin = std::max(p->max_nin, nin);
             p->gsolves.push_back(gs);
             // trace-pool ranges of u~, in the order of the in-slot ranges
@@ -580,8 +581,8 @@ int compress_schedule(lsw_plan* p) {
                 for (int c = 0; c * 64 < len; ++c) {
                     GemvItem it = base;
                     const long long row = gs.row_base[o] + 64LL * c;
-                    it.qoff = gs.qp_off + row;
-                    it.qlen = (long long)nin * ld - row;
+                    it.qoff = gs.qp_off + 2 * row;
+                    it.qlen = (long long)ninp * ld - 2 * row;
                     it.nrow = std::min(64, len - 64 * c);
                     it.out_off = d.out_off[o] + 64LL * c;
                     it.out_acc = d.out_acc[o];
@@ -1670,6 +1671,7 @@ int setup_impl(lsw_plan* p, const double* d_m, double omega, double h, const lsw
         // fold the polarization map of every sweep solve into its trace-to-trace operator
         c128* QP128 = nullptr;
         if ((rc = dalloc(p, &QP128, std::max<size_t>(1, p->QP_elems))) != LSW_OK) return rc;
+        HIPCK(p, hipMemsetAsync(QP128, 0, sizeof(c128) * std::max<size_t>(1, p->QP_elems), p->stream));   // odd-column pads
         HIPCK(p, launch_qprime(p->d_gsolves, (int)p->gsolves.size(), p->max_nin, p->d_subs, p->geo, Q128, QP128,
                                p->stream));
         HIPCK(p, hipStreamSynchronize(p->stream));

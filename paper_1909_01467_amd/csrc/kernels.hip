@@ -1382,10 +1382,12 @@ __global__ void k_qprime(const GemvSolve* gsv, const SubDesc* subs, Geometry geo
     if (e >= total) return;
     const PolColumn col = pol_column(d, s, geo, e);
     const c128* Qs = Q + s.q_off;
-    c128* out = Qp + d.qp_off + (size_t)e * d.ld;
+    // column pairs: entry (t, e) at (e / 2) * 2 ld + 2 t + e % 2, so that a lane loads the entries
+    // of two columns at its row in one 16-byte access (complex64)
+    c128* out = Qp + d.qp_off + (size_t)(e >> 1) * 2 * d.ld + (e & 1);
     for (int t = threadIdx.x; t < d.ld; t += blockDim.x) {
         if (t >= d.rows) {   // alignment padding
-            out[t] = mk(0.0, 0.0);
+            out[2 * t] = mk(0.0, 0.0);
             continue;
         }
         int o = 0;
@@ -1395,7 +1397,7 @@ __global__ void k_qprime(const GemvSolve* gsv, const SubDesc* subs, Geometry geo
         const int os = sb + t - d.row_base[o];
         c128 v = mk(0.0, 0.0);
         for (int j = 0; j < col.np; ++j) v = v + Qs[(size_t)col.slot[j] * s.L + os] * col.coef[j];
-        out[t] = v;
+        out[2 * t] = v;
     }
 }
 
@@ -1437,7 +1439,7 @@ __global__ void k_pmap(const GemvSolve* gsv, int max_nin, const SubDesc* subs, G
 // fits, so a batch of sources reads Q' about nrhs/4 times.
 template <typename T, int RC>   // RC: right-hand sides per pass over Q'
 __global__ __launch_bounds__(512) void k_gemv(GemvArgs a) {
-    constexpr int NT = 512, NW = NT / 64, KB = sizeof(T) == 4 ? 16 : 8;
+    constexpr int NT = 512, NW = NT / 64, KB = sizeof(T) == 4 ? 16 : 8, KP = KB / 2;
     __shared__ cx<T> gv[RC][4 * kMaxWindow + KB * NW];
     __shared__ cx<T> part[NW][64];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -1446,17 +1448,18 @@ __global__ __launch_bounds__(512) void k_gemv(GemvArgs a) {
     const bool valid = lane < it.nrow;
     const cx<T>* Qb = reinterpret_cast<const cx<T>*>(a.Q) + it.qoff;
     const __amdgpu_buffer_rsrc_t qr = make_rsrc(Qb, (uint32_t)((size_t)it.qlen * sizeof(cx<T>)));
-    const int per = (nin + NW - 1) / NW;
+    // the waves split the input entries in even-sized shares (column pairs of Q')
+    const int per = (((nin + NW - 1) / NW) + 1) & ~1;
     const int i0 = wv * per, i1 = min(nin, i0 + per);
     const bool resident = per <= KB;   // the whole share of Q' stays in registers across rhs chunks
-    const uint32_t lo = (uint32_t)lane * (uint32_t)sizeof(cx<T>);
-    const uint32_t cs = (uint32_t)ld * (uint32_t)sizeof(cx<T>);
-    // column c of this wave's share at my row, or nothing (no overlap with the next wave's
-    // share, no rows past the chunk): every byte fetched is used
-    auto qoff = [&](int c) { return (valid && c < i1) ? lo + (uint32_t)c * cs : kOob; };
-    cx<T> q[KB];
+    const uint32_t lo = (uint32_t)lane * 2u * (uint32_t)sizeof(cx<T>);
+    const uint32_t cs = (uint32_t)ld * 2u * (uint32_t)sizeof(cx<T>);
+    // columns c, c + 1 (c even) of this wave's share at my row, or nothing (no overlap with the
+    // next wave's share, no rows past the chunk)
+    auto qoff = [&](int c) { return (valid && c < i1) ? lo + (uint32_t)(c >> 1) * cs : kOob; };
+    Pair<T> q[KP];
 #pragma unroll
-    for (int u = 0; u < KB; ++u) q[u] = bload<T>(qr, qoff(i0 + u));
+    for (int u = 0; u < KP; ++u) q[u] = bload2<T>(qr, qoff(i0 + 2 * u));
     for (int rc0 = 0; rc0 < a.nrhs; rc0 += RC) {
         const int nrc = min(RC, a.nrhs - rc0);
         cx<T> old[RC];
@@ -1485,14 +1488,17 @@ __global__ __launch_bounds__(512) void k_gemv(GemvArgs a) {
         for (int base = i0;;) {
             if (base != i0 || (rc0 > 0 && !resident)) {
 #pragma unroll
-                for (int u = 0; u < KB; ++u) q[u] = bload<T>(qr, qoff(base + u));
+                for (int u = 0; u < KP; ++u) q[u] = bload2<T>(qr, qoff(base + 2 * u));
             }
 #pragma unroll
-            for (int u = 0; u < KB; ++u)
-                if (base + u < i0 + per) {
+            for (int u = 0; u < KP; ++u)
+                if (base + 2 * u < i0 + per) {
 #pragma unroll
                     for (int r = 0; r < RC; ++r)
-                        if (r < nrc) acc[r] = fma(acc[r], q[u], gv[r][base + u]);
+                        if (r < nrc) {
+                            acc[r] = fma(acc[r], q[u].a, gv[r][base + 2 * u]);
+                            acc[r] = fma(acc[r], q[u].b, gv[r][base + 2 * u + 1]);
+                        }
                 }
             base += KB;
             if (base >= i1) break;
