@@ -195,7 +195,8 @@ int lsw_setup(lsw_handle_t* out, const double* d_m, double omega, double h,
 /*
  * lsw_apply -- one application z = M^-1 r of the L-sweeps preconditioner
  * (Alg. Scenario3: stage 1, four cardinal sweeps, four diagonal sweeps; with windows, the sum
- * of the four windowed sweeps of scenario 4).
+ * of the four windowed sweeps of scenario 4, the three shifted CDDs on streams of the handle's
+ * own that are forked from and joined to opts.stream).
  *   d_r : DEVICE, nrhs*N complex128 (read only).   d_z : DEVICE, nrhs*N complex128 (written).
  *   1 <= nrhs <= nrhs_max.  In LSW_MIXED the sweeps run in complex64.
  */
@@ -208,7 +209,9 @@ int lsw_apply(lsw_handle_t handle, const double* d_r, double* d_z, int nrhs);
  *         setting), out: solution.  Stops when ||b - A u||_2 <= tol ||b||_2 (true
  *         residual, FP64) or after maxit applications (then LSW_ENOCONV, u = last iterate).
  *   info: HOST, optional (may be NULL).
- * Each right-hand side runs its own Krylov process; applications are batched.
+ * Each right-hand side runs its own Krylov process; applications are batched.  Once per
+ * iteration the calling thread waits for the Hessenberg column by polling the stream (it
+ * stays busy for the duration of the call).
  */
 int lsw_solve(lsw_handle_t handle, const double* d_f, double* d_u, int nrhs, lsw_info_t* info);
 
