@@ -1813,13 +1813,14 @@ template <typename T, int CS, int PH, typename F>
 static void sym_dispatch(int ept, F&& f) {
     if constexpr (sizeof(T) == 4) {
         if (ept <= 1) f(k_chain_sym<T, 1, 4, CS, PH>);
-        else f(k_chain_sym<T, 2, 2, CS, PH>);
+        else if (ept <= 2) f(k_chain_sym<T, 2, 2, CS, PH>);
+        else f(k_chain_sym<T, 3, 1, CS, PH>);
     } else {
         f(k_chain_sym<T, 1, 2, CS, PH>);
     }
 }
 
-int sym_max_ept(bool c64mode) { return c64mode ? 2 : 1; }
+int sym_max_ept(bool c64mode) { return c64mode ? 3 : 1; }
 
 hipError_t prepare_chain_sym(int ept, bool c64mode, size_t lds) {
     hipError_t e = hipSuccess;

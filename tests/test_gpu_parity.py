@@ -80,6 +80,7 @@ CASES = {
     "thin_local_pml": Case("thin_local_pml", 64, 64, 8, 8, 3, 3, pl=3),
     "no_pml": Case("no_pml", 33, 29, 0, 0, 2, 2, C=1.0),
     "wide_4x5": Case("wide_4x5", 150, 131, 10, 10, 4, 5),
+    "wide_windows_2x2": Case("wide_windows_2x2", 250, 180, 10, 10, 2, 2),   # windows 147 x 112
 }
 
 
@@ -378,6 +379,29 @@ def test_packed_symmetric_factors_match_full_blocks(name, precision, tol, monkey
         err = rel(Z[k], Z0[k])
         say(name, precision, "packed vs full", err)
         assert err < tol
+
+
+def test_packed_factors_of_wide_windows(monkeypatch):
+    """Windows 147 points wide (three packed tiles per lane in complex64) against the oracle and
+    against the full blocks."""
+    c = CASES["wide_windows_2x2"]
+    X = torch.from_numpy(inputs.complex_normal((2, c.N), 7)).cuda()
+    monkeypatch.setenv("LSW_RHS_PER_WORKGROUP", "1")
+    s = c.solver(precision="mixed", nrhs_max=2)
+    st = s.stats()
+    assert st["symmetric_factors"] == 1 and st["W_max"] == 147
+    Z = s.apply(X).cpu().numpy().reshape(2, -1)
+    s.close()
+    monkeypatch.setenv("LSW_SYMMETRIC_FACTORS", "0")
+    s = c.solver(precision="mixed", nrhs_max=2)
+    Z0 = s.apply(X).cpu().numpy().reshape(2, -1)
+    s.close()
+    zo = c.oracle.apply(X[0].cpu().numpy())
+    for k in range(2):
+        say("wide windows packed vs full", rel(Z[k], Z0[k]))
+        assert rel(Z[k], Z0[k]) < 2e-5
+    say("wide windows packed vs oracle", rel(Z[0], zo))
+    assert rel(Z[0], zo) < 2e-4
 
 
 def test_rhs_per_workgroup_is_tuned_at_setup():
