@@ -156,6 +156,9 @@ struct lsw_plan {
     hipEvent_t ev_fork = nullptr;
     hipEvent_t ev_join[3] = {nullptr, nullptr, nullptr};
     hipEvent_t ev_spin = nullptr;   // polled by the Krylov loop's waits
+    hipEvent_t ev_step[2] = {nullptr, nullptr};   // end of the column copy of Arnoldi step k (slot k % 2)
+    int* h_act_stage = nullptr;     // pinned [2][nrhs_max] staging of the mask copies
+    int act_slot = 0;
     void* (*ualloc)(size_t, void*) = nullptr;   // the caller's device allocator (optional)
     void (*ufree)(void*, void*) = nullptr;
     void* uctx = nullptr;
@@ -233,6 +236,9 @@ void free_plan(lsw_plan* p) {
     if (p->ev_fork) (void)hipEventDestroy(p->ev_fork);
     if (p->own_stream) (void)hipStreamDestroy(p->own_stream);
     if (p->ev_spin) (void)hipEventDestroy(p->ev_spin);
+    for (hipEvent_t e : p->ev_step)
+        if (e) (void)hipEventDestroy(e);
+    if (p->h_act_stage) (void)hipHostFree(p->h_act_stage);
     if (p->rb) (void)rocblas_destroy_handle(p->rb);
     delete p;
 }
@@ -792,10 +798,15 @@ int gs_impl(lsw_plan* p, const c128* V, size_t vl, const c128* coef, int cstride
 }
 
 // the per-rhs mask on the device follows h_active (copied only when it changed)
+// (the copy reads one of two pinned staging slots: a copy queued behind a step that was queued
+// ahead may run after the host has moved on, so its source must not change before the next wait)
 int sync_active(lsw_plan* p, int nrhs) {
     if (std::equal(p->h_active, p->h_active + nrhs, p->dev_active.begin())) return LSW_OK;
     std::copy(p->h_active, p->h_active + nrhs, p->dev_active.begin());
-    HIPCK(p, hipMemcpyAsync(p->d_active, p->h_active, sizeof(int) * nrhs, hipMemcpyHostToDevice, p->stream));
+    p->act_slot ^= 1;
+    int* stage = p->h_act_stage + (size_t)p->act_slot * p->nrhs_max;
+    std::copy(p->h_active, p->h_active + nrhs, stage);
+    HIPCK(p, hipMemcpyAsync(p->d_active, stage, sizeof(int) * nrhs, hipMemcpyHostToDevice, p->stream));
     return LSW_OK;
 }
 
@@ -807,6 +818,14 @@ int spin_wait(lsw_plan* p) {
     while ((e = hipEventQuery(p->ev_spin)) == hipErrorNotReady) {
     }
     HIPCK(p, e);
+    return LSW_OK;
+}
+
+int wait_event(lsw_plan* p, hipEvent_t e) {
+    hipError_t r;
+    while ((r = hipEventQuery(e)) == hipErrorNotReady) {
+    }
+    HIPCK(p, r);
     return LSW_OK;
 }
 
@@ -853,31 +872,55 @@ int solve_impl(lsw_plan* p, const c128* d_b, c128* d_x, int nrhs, lsw_info_t* in
         if (nlive == 0) break;
         if ((rc = sync_active(p, nrhs)) != LSW_OK) return rc;
         HIPCK(p, launch_scale(V, V, p->d_hbuf, HS, p->d_active, N, N, N, nrhs, p->stream));
-        for (int k = 0; k < m; ++k) {
+        // One Arnoldi step on the device: z_k = M^-1 v_k, w = A z_k, two Gram-Schmidt passes (the second
+        // also forms ||w||^2), v_{k+1} = w / ||w||, and the column copied to host slot k % 2.  Nothing in
+        // it waits for the host, so step k+1 may be queued before the host has read column k.
+        auto enqueue_step = [&](int k) -> int {
             c128* Vk = V + (size_t)k * vl;
             c128* Zk = Z + (size_t)k * vl;
-            if ((rc = apply_impl(p, Vk, Zk, nrhs, false)) != LSW_OK) return rc;
+            int rc2;
+            if ((rc2 = apply_impl(p, Vk, Zk, nrhs, false)) != LSW_OK) return rc2;
             applies++;
-            if ((rc = matvec_impl(p, Zk, p->d_w, nullptr, nrhs)) != LSW_OK) return rc;
-            // classical Gram-Schmidt, twice; the second update also forms ||w||^2
+            if ((rc2 = matvec_impl(p, Zk, p->d_w, nullptr, nrhs)) != LSW_OK) return rc2;
             for (int pass = 0; pass < 2; ++pass) {
                 c128* hcoef = p->d_hbuf + pass * (m + 1);
-                if ((rc = dots_impl(p, V, vl, N, p->d_w, N, k + 1, nrhs, hcoef, HS)) != LSW_OK) return rc;
-                if ((rc = gs_impl(p, V, vl, hcoef, HS, p->d_w, k + 1, -1, nrhs, pass == 1 ? p->d_hbuf + 2 * (m + 1) : nullptr,
-                                  HS)) != LSW_OK)
-                    return rc;
+                if ((rc2 = dots_impl(p, V, vl, N, p->d_w, N, k + 1, nrhs, hcoef, HS)) != LSW_OK) return rc2;
+                if ((rc2 = gs_impl(p, V, vl, hcoef, HS, p->d_w, k + 1, -1, nrhs,
+                                   pass == 1 ? p->d_hbuf + 2 * (m + 1) : nullptr, HS)) != LSW_OK)
+                    return rc2;
             }
-            // V_{k+1} = w / ||w|| needs no host decision: it is formed before the host reads the column
-            // (unused if this right-hand side stops here; V has room for m + 1 vectors)
+            // (v_{k+1} is unused if every right-hand side stops here; V has room for m + 1 vectors)
             HIPCK(p, launch_scale(p->d_w, V + (size_t)(k + 1) * vl, p->d_hbuf + 2 * (m + 1), HS, p->d_active, N, N,
                                   N, nrhs, p->stream));
-            HIPCK(p, hipMemcpyAsync(p->h_hbuf, p->d_hbuf, sizeof(c128) * HS * nrhs, hipMemcpyDeviceToHost,
-                                    p->stream));
-            if ((rc = spin_wait(p)) != LSW_OK) return rc;
+            HIPCK(p, hipMemcpyAsync(p->h_hbuf + (size_t)(k & 1) * nrhs * HS, p->d_hbuf, sizeof(c128) * HS * nrhs,
+                                    hipMemcpyDeviceToHost, p->stream));
+            HIPCK(p, hipEventRecord(p->ev_step[k & 1], p->stream));
+            return LSW_OK;
+        };
+        bool queued = false;   // step k was queued ahead, while the host read column k - 1
+        for (int k = 0; k < m; ++k) {
+            if (!queued && (rc = enqueue_step(k)) != LSW_OK) return rc;
+            // queue step k + 1 now unless every live right-hand side is expected to stop at step k
+            // (geometric extrapolation of its residual estimates); a step queued in vain costs one
+            // application, a step queued late the host's round trip
+            bool ahead = false;
+            if (k + 1 < m) {
+                for (int s = 0; s < nrhs && !ahead; ++s) {
+                    if (!live[s] || its[s] + 1 >= p->maxit) continue;
+                    const std::vector<double>& hs = hist[s];
+                    const size_t nh = hs.size();
+                    const double pred = nh == 0 ? 1.0 : nh == 1 ? 0.5 * hs[0] : hs[nh - 1] * (hs[nh - 1] / hs[nh - 2]);
+                    ahead = pred > p->tol;
+                }
+                if (ahead && (rc = enqueue_step(k + 1)) != LSW_OK) return rc;
+            }
+            if ((rc = wait_event(p, p->ev_step[k & 1])) != LSW_OK) return rc;
+            queued = ahead;
+            const c128* hslot = p->h_hbuf + (size_t)(k & 1) * nrhs * HS;
             int still = 0;
             for (int s = 0; s < nrhs; ++s) {
                 if (!live[s]) continue;
-                const c128* hb = p->h_hbuf + (size_t)s * HS;
+                const c128* hb = hslot + (size_t)s * HS;
                 std::vector<cd> h(k + 2);
                 for (int l = 0; l <= k; ++l) h[l] = cd(hb[l].re + hb[m + 1 + l].re, hb[l].im + hb[m + 1 + l].im);
                 const double nrm = std::sqrt(std::max(0.0, hb[2 * (m + 1)].re));
@@ -911,7 +954,7 @@ int solve_impl(lsw_plan* p, const c128* d_b, c128* d_x, int nrhs, lsw_info_t* in
                 p->h_active[s] = live[s];
                 still += live[s];
             }
-            if (still == 0 || k == m - 1) break;
+            if (still == 0 || k == m - 1) break;   // a step queued ahead only wrote unused slots
             if ((rc = sync_active(p, nrhs)) != LSW_OK) return rc;
         }
         // x += Z y with y = H^-1 g (upper triangular back substitution on the host)
@@ -1510,11 +1553,13 @@ int setup_impl(lsw_plan* p, const double* d_m, double omega, double h, const lsw
     if ((rc = dalloc(p, &p->d_active, (size_t)nr)) != LSW_OK) return rc;
     HIPCK(p, hipMemset(p->d_active, 0, sizeof(int) * (size_t)nr));
     p->dev_active.assign(nr, 0);
-    HIPCK(p, hipHostMalloc((void**)&p->h_hbuf, sizeof(c128) * nr * HS, hipHostMallocDefault));
+    HIPCK(p, hipHostMalloc((void**)&p->h_hbuf, sizeof(c128) * 2 * nr * HS, hipHostMallocDefault));   // 2 slots
     HIPCK(p, hipHostMalloc((void**)&p->h_active, sizeof(int) * nr, hipHostMallocDefault));
     HIPCK(p, hipHostMalloc((void**)&p->h_coef, sizeof(c128) * nr * m, hipHostMallocDefault));
     for (hipEvent_t& e : p->ev) HIPCK(p, hipEventCreate(&e));
     HIPCK(p, hipEventCreateWithFlags(&p->ev_spin, hipEventDisableTiming));
+    for (hipEvent_t& e : p->ev_step) HIPCK(p, hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    HIPCK(p, hipHostMalloc((void**)&p->h_act_stage, sizeof(int) * 2 * nr, hipHostMallocDefault));
     p->geo.tab = p->d_tab;
     p->geo.m = p->d_m;
     p->geo.Nx = p->Nx;
