@@ -440,3 +440,29 @@ def test_workspace_in_the_torch_caching_allocator(windows):
     s2.close()
     say("torch allocator", windows, "workspace MB", grown / 1e6, "iterations", i1["iterations"], i2["iterations"])
     assert torch.equal(z1, z2) and torch.equal(u1, u2) and i1["iterations"] == i2["iterations"]
+
+
+def test_random_geometries_match_oracle():
+    """Seeded random grids, PML widths, local PML widths and CDD shapes (ragged splits, thin
+    groups, single rows or columns): one FP64 application against the oracle's, 1e-10."""
+    rng = np.random.default_rng(2024)
+    done = 0
+    while done < 10:
+        nx, ny = (int(v) for v in rng.integers(16, 80, 2))
+        px, py = (int(v) for v in rng.integers(0, 9, 2))
+        q, r = (int(v) for v in rng.integers(1, 5, 2))
+        pl = None if rng.random() < 0.5 else int(rng.integers(1, max(2, px + 1)))
+        c = Case(f"random_{done}", nx, ny, px, py, q, r, pl=pl, C=None if px and py else 1.0)
+        try:
+            oracle = c.oracle
+        except ValueError:   # a group or window that does not fit: the library must refuse it too
+            with pytest.raises(LswError):
+                c.solver()
+            continue
+        x = inputs.complex_normal(c.N, 70 + done)
+        s = c.solver()
+        err = rel(to_np(s.apply(torch.from_numpy(x).cuda())), oracle.apply(x))
+        s.close()
+        say("random geometry", (nx, ny, px, py, q, r, pl), "apply fp64 rel err", err)
+        assert err < 1e-10
+        done += 1
