@@ -19,6 +19,7 @@ from oracle.discretization import GlobalProblem, extend_normal
 from oracle.fgmres import fgmres
 from oracle.gradient import FWIProblem
 from oracle.lsweep import LSweep2D
+from oracle.scenario4 import Scenario4
 from paper_1909_01467_amd import inputs
 from paper_1909_01467_amd.lsweeps import LSW_EINVAL, LSW_ENAN, HelmholtzSolve, LswError, Solver, extend_medium
 
@@ -465,4 +466,11 @@ def test_random_geometries_match_oracle():
         s.close()
         say("random geometry", (nx, ny, px, py, q, r, pl), "apply fp64 rel err", err)
         assert err < 1e-10
+        if q >= 2 and r >= 2 and min(nx // r, ny // q) >= 6:   # scenario 4 with the default shifts
+            s4 = Scenario4(c.m, c.omega, (nx, ny), (px, py), q, r, c.C, n_pml_local=pl, h=c.h)
+            s = c.solver(windows=True)
+            err = rel(to_np(s.apply(torch.from_numpy(x).cuda())), s4.apply(x))
+            s.close()
+            say("random geometry, windows", s4.shift, "apply fp64 rel err", err)
+            assert err < 1e-10
         done += 1
