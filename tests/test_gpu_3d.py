@@ -191,3 +191,28 @@ def test_lens3d_full_size_solve():
     assert info["converged"] == [True]
     un = u.cpu().numpy().ravel()
     assert np.linalg.norm(b - gp.A @ un) / np.linalg.norm(b) <= 1.05e-6
+
+
+def test_random_3d_geometries_match_oracle():
+    """Seeded random boxes, PML widths and beam CDDs (plane blocks of ragged sizes, odd and even
+    numbers of z planes): one FP64 and one complex64 application against the oracle's."""
+    rng = np.random.default_rng(3033)
+    done = 0
+    while done < 5:
+        n = tuple(int(v) for v in rng.integers(7, 15, 3))
+        p = tuple(int(v) for v in rng.integers(2, 5, 3))
+        q, r = (int(v) for v in rng.integers(1, 4, 2))
+        c = Case3(f"random3d_{done}", n, p, q, r, seed=50 + done)
+        try:
+            oracle = c.oracle
+        except ValueError:
+            continue
+        x = inputs.complex_normal(c.m.size, 80 + done)
+        zo = oracle.apply(x)
+        for precision, tol in (("fp64", 1e-10), ("mixed", 2e-4)):
+            s = c.solver(precision=precision)
+            err = rel(s.apply(torch.from_numpy(x).cuda()).cpu().numpy().ravel(), zo)
+            s.close()
+            say("random 3D", n, p, q, r, precision, "apply rel err", err)
+            assert err < tol
+        done += 1
