@@ -23,10 +23,11 @@ from .lsweep import SIDES, LSweep2D, partition
 
 
 class LSweep3D(LSweep2D):
-    """Alg. Scenario3 for a q x r beam CDD of a 3D box (n_x, n_y, n_z bulk points)."""
+    """Alg. Scenario3 for a q x r beam CDD of a 3D box (n_x, n_y, n_z bulk points); `shift` as for
+    LSweep2D (the shifted CDDs of scenario 4, in x and y)."""
 
     def __init__(self, m_ext: np.ndarray, omega: float, n, n_pml, q: int, r: int, C: float,
-                 n_pml_local: int | None = None, h: float | None = None):
+                 n_pml_local: int | None = None, h: float | None = None, shift=(0, 0)):
         nx, ny, nz = (n, n, n) if np.isscalar(n) else n
         px, py, pz = (n_pml, n_pml, n_pml) if np.isscalar(n_pml) else n_pml
         self.nx, self.ny, self.nz, self.px, self.py, self.pz = nx, ny, nz, px, py, pz
@@ -38,8 +39,10 @@ class LSweep3D(LSweep2D):
         self.m = np.asarray(m_ext, dtype=np.float64)
         self.Nex, self.Ney, self.Nez = nx + 2 * px, ny + 2 * py, nz + 2 * pz
         assert self.m.shape == (self.Nez, self.Ney, self.Nex)
-        self.xlo, self.xhi, _ = partition(nx, px, r)
-        self.ylo, self.yhi, _ = partition(ny, py, q)
+        self.shift = tuple(shift)
+        self.xlo, self.xhi, _ = partition(nx, px, r, self.shift[0])
+        self.ylo, self.yhi, _ = partition(ny, py, q, self.shift[1])
+        q, r = self.q, self.r = len(self.ylo), len(self.xlo)   # a shifted axis has one more group
         for lo, hi, N in ((self.xlo, self.xhi, self.Nex), (self.ylo, self.yhi, self.Ney)):
             for g in range(len(lo)):
                 if hi[g] - lo[g] < 2 or (g > 0 and lo[g] < self.e) or \

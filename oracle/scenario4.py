@@ -33,6 +33,7 @@ from __future__ import annotations
 import numpy as np
 
 from .lsweep import LSweep2D, partition
+from .lsweep3d import LSweep3D
 
 
 def default_shift(n_bulk: int, groups: int) -> int:
@@ -58,29 +59,35 @@ def axis_window(N: int, lo: list[int], lo_shifted: list[int]) -> np.ndarray:
 
 
 class Scenario4:
-    """z = sum over the four CDDs k of M_k^-1 (phi_k r)."""
+    """z = sum over the four CDDs k of M_k^-1 (phi_k r).  In 3D (m_ext of shape [z, y, x], beams
+    over all z) the CDDs and windows are those of the (x, y) cross-section, the same on every plane."""
 
     def __init__(self, m_ext: np.ndarray, omega: float, n, n_pml, q: int, r: int, C: float,
                  n_pml_local: int | None = None, h: float | None = None, shift=None):
-        nx, ny = (n, n) if np.isscalar(n) else n
-        px, py = (n_pml, n_pml) if np.isscalar(n_pml) else n_pml
+        dim = np.asarray(m_ext).ndim
+        ns = (n,) * dim if np.isscalar(n) else tuple(n)
+        ps = (n_pml,) * dim if np.isscalar(n_pml) else tuple(n_pml)
+        nx, ny, px, py = ns[0], ns[1], ps[0], ps[1]
         if q < 2 or r < 2:
             raise ValueError("scenario 4 needs at least two groups along each axis")
         sx, sy = (default_shift(nx, r), default_shift(ny, q)) if shift is None else shift
+        if not (3 <= sx <= nx // r - 3 and 3 <= sy <= ny // q - 3):
+            raise ValueError("the shift must lie in [3, smallest group - 3] so that the skeletons are disjoint")
         self.shift = (sx, sy)
+        self.shape = np.asarray(m_ext).shape
         self.Nex, self.Ney = nx + 2 * px, ny + 2 * py
         ax = axis_window(self.Nex, partition(nx, px, r)[0], partition(nx, px, r, sx)[0])
         ay = axis_window(self.Ney, partition(ny, py, q)[0], partition(ny, py, q, sy)[0])
+        cls = LSweep2D if dim == 2 else LSweep3D
         self.cdds, self.windows = [], []
         for kx, ky in ((0, 0), (1, 0), (0, 1), (1, 1)):
-            self.cdds.append(LSweep2D(m_ext, omega, (nx, ny), (px, py), q, r, C, n_pml_local, h,
-                                      shift=(kx * sx, ky * sy)))
+            self.cdds.append(cls(m_ext, omega, ns, ps, q, r, C, n_pml_local, h, shift=(kx * sx, ky * sy)))
             wx = 1.0 - ax if kx else ax
             wy = 1.0 - ay if ky else ay
-            self.windows.append(np.outer(wy, wx))
+            self.windows.append(np.outer(wy, wx))   # [y, x]; broadcast over z in 3D
 
     def apply(self, rvec: np.ndarray) -> np.ndarray:
-        R = np.asarray(rvec, dtype=np.complex128).reshape(self.Ney, self.Nex)
+        R = np.asarray(rvec, dtype=np.complex128).reshape(self.shape)
         z = np.zeros(R.size, dtype=np.complex128)
         for ls, phi in zip(self.cdds, self.windows):
             z += ls.apply((phi * R).ravel())

@@ -111,3 +111,27 @@ def test_needs_two_groups_per_axis():
     m = np.ones((30, 30))
     with pytest.raises(ValueError):
         Scenario4(m, 10.0, 20, 5, 1, 3, 4.0)
+
+
+def test_shift_must_keep_the_skeletons_apart():
+    m = np.ones((40, 40))
+    with pytest.raises(ValueError):
+        Scenario4(m, 10.0, 30, 5, 2, 2, 4.0, shift=(2, 5))
+    with pytest.raises(ValueError):
+        Scenario4(m, 10.0, 30, 5, 2, 2, 4.0, shift=(5, 13))
+
+
+def test_3d_beams_reconstruct_a_random_source():
+    """Scenario 4 over beams (windows of the (x, y) cross-section on every z plane): constant
+    medium, strong PML, a random source (nonzero on every skeleton) is reconstructed up to the PML
+    error, as the 3D scenario-3 pins require of sources inside beams."""
+    n, q, p, C = 13, 2, 6, 30.0
+    omega = 2 * math.pi * n / 8
+    m = np.ones((n + 2 * p,) * 3)
+    gp = GlobalProblem(m, omega, n, p, C)
+    s4 = Scenario4(m, omega, n, p, q, q, C)
+    assert s4.shift == (3, 3)
+    assert np.max(np.abs(sum(s4.windows) - 1.0)) < 1e-15
+    b = inputs.complex_normal(gp.size, 34)
+    u = SparseLU(gp.A).solve(b)
+    assert np.linalg.norm(s4.apply(b) - u) / np.linalg.norm(u) < 1e-3   # PML error 2.6e-4 at this width
