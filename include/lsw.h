@@ -73,7 +73,8 @@ typedef struct {
     int q;               /* CDD rows (groups along y, row 0 at the bottom) */
     int r;               /* CDD columns (groups along x, column 0 at the left) */
     int windows;         /* 0: one CDD (scenario 3 applied to any right-hand side);
-                            1: scenario 4 of Sec. 2.1 (2D only, q, r >= 2): the CDD and three copies
+                            1: scenario 4 of Sec. 2.1 (q, r >= 2; in 3D over the beams' (x, y)
+                            cross-section): the CDD and three copies
                             with the interior boundaries shifted by shift[0] along x, shift[1] along y
                             and both, each sweeping the right-hand side multiplied by its window of a
                             partition of unity; M^-1 r is the sum of the four sweeps */
@@ -183,8 +184,7 @@ typedef struct {
  * and d' the distances to the nearest interface of either kind), and 1 beyond the outermost
  * (shifted) interfaces; the four windows are a b, (1-a) b, a (1-b), (1-a)(1-b).
  * Errors: LSW_EINVAL (dim not 2 or 3, sizes, a window that does not fit the grid, only one of
- * opts->alloc and opts->release, windows
- * with dim 3, q or r below 2 or a shift outside its range),
+ * opts->alloc and opts->release, windows with q or r below 2 or a shift outside its range),
  * LSW_ENAN (non-finite m), LSW_ENOMEM, LSW_EHIP, LSW_ESINGULAR.  On error *out is NULL
  * and nothing is leaked.
  */

@@ -751,17 +751,20 @@ int apply_cdd(lsw_plan* p, const c128* d_r, c128* d_z, int nrhs, bool timed) {
 // the whole application
 int apply_impl(lsw_plan* p, const c128* d_r, c128* d_z, int nrhs, bool timed) {
     if (!p->windows) return apply_cdd(p, d_r, d_z, nrhs, timed);
+    for (const lsw_plan* c : p->shifted)
+        if (!c) return fail(p, LSW_EINVAL, "windowed plan without its shifted CDDs");
     if (timed) HIPCK(p, hipEventRecord(p->evw[0], p->stream));
     HIPCK(p, hipEventRecord(p->ev_fork, p->stream));
     for (int k = 1; k < 4; ++k) {   // the shifted CDDs, each on its own stream
         lsw_plan* c = p->shifted[k - 1];
         HIPCK(p, hipStreamWaitEvent(c->stream, p->ev_fork, 0));
-        HIPCK(p, launch_window(d_r, p->d_wr[k], p->d_wx, p->d_wy, k & 1, k >> 1, p->Nx, p->N, nrhs, c->stream));
+        HIPCK(p, launch_window(d_r, p->d_wr[k], p->d_wx, p->d_wy, k & 1, k >> 1, p->Nx, p->Ny, p->N, nrhs,
+                               c->stream));
         const int rc = apply_cdd(c, p->d_wr[k], p->d_wz[k - 1], nrhs, timed);
         if (rc != LSW_OK) return fail(p, rc, c->err);
         HIPCK(p, hipEventRecord(p->ev_join[k - 1], c->stream));
     }
-    HIPCK(p, launch_window(d_r, p->d_wr[0], p->d_wx, p->d_wy, 0, 0, p->Nx, p->N, nrhs, p->stream));
+    HIPCK(p, launch_window(d_r, p->d_wr[0], p->d_wx, p->d_wy, 0, 0, p->Nx, p->Ny, p->N, nrhs, p->stream));
     const int rc = apply_cdd(p, p->d_wr[0], d_z, nrhs, timed);
     if (rc != LSW_OK) return rc;
     for (hipEvent_t e : p->ev_join) HIPCK(p, hipStreamWaitEvent(p->stream, e, 0));
@@ -1263,7 +1266,6 @@ int setup_impl(lsw_plan* p, const double* d_m, double omega, double h, const lsw
     if (cdd->windows != 0 && cdd->windows != 1) return fail(p, LSW_EINVAL, "cdd.windows must be 0 or 1");
     int own_sx = 0, own_sy = 0;   // shift of this plan's own CDD
     if (cdd->windows) {
-        if (p->dim != 2) return fail(p, LSW_EINVAL, "windows (scenario 4) are built for dim 2");
         if (p->q < 2 || p->r < 2) return fail(p, LSW_EINVAL, "windows need q >= 2 and r >= 2");
         const int gx = p->nx / p->r, gy = p->ny / p->q;   // smallest bulk group of each axis
         p->shift_x = cdd->shift[0] > 0 ? cdd->shift[0] : gx / 2;
@@ -1275,7 +1277,6 @@ int setup_impl(lsw_plan* p, const double* d_m, double omega, double h, const lsw
         own_sx = cdd->shift[0];
         own_sy = cdd->shift[1];
         if (own_sx < 0 || own_sy < 0) return fail(p, LSW_EINVAL, "cdd.shift must be >= 0");
-        if ((own_sx || own_sy) && p->dim != 2) return fail(p, LSW_EINVAL, "a shifted CDD is built for dim 2");
     }
     p->omega = omega;
     p->h = h;
@@ -1568,6 +1569,7 @@ int setup_impl(lsw_plan* p, const double* d_m, double omega, double h, const lsw
     p->geo.omega = omega;
     if (p->dim == 3) {
         if ((rc = setup3d_factor(p)) != LSW_OK) return rc;
+        if (p->windows && (rc = setup_windows(p, d_m, omega, h, grid, cdd, pml, opts)) != LSW_OK) return rc;
         p->t_setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
         return LSW_OK;
     }
@@ -1986,6 +1988,7 @@ int lsw_query(lsw_handle_t p, lsw_stats_t* st) {
     st->window_shift[1] = p->shift_y;
     if (p->windows) {   // totals over the four CDDs (the setup time already covers all four)
         for (const lsw_plan* c : p->shifted) {
+            if (!c) continue;
             st->n_subdomains += (int)c->subs.size();
             st->factor_elems += (long long)c->G_elems;
             st->solves_per_apply += (int)c->descs.size();

@@ -1526,13 +1526,14 @@ __global__ void k_cast(const c128* src, c64* dst, size_t n) {
 }
 
 // ------------------------------------------------------------------ scenario 4 windows (Sec. 2.1)
-// out = phi (.) r over nrhs vectors of N = Nx*Ny points; phi = A(x) B(y) with A = a, or 1 - a for
-// the CDD shifted along x (kx = 1), and B = b, or 1 - b for the CDD shifted along y (ky = 1)
+// out = phi (.) r over nrhs vectors of N points (x fastest, then y, then z in 3D); phi = A(x) B(y)
+// with A = a, or 1 - a for the CDD shifted along x (kx = 1), and B = b, or 1 - b for the CDD
+// shifted along y (ky = 1), the same on every z plane
 __global__ void k_window(const c128* r, c128* out, const double* wx, const double* wy, int kx, int ky, int Nx,
-                         size_t N, size_t total) {
+                         int Ny, size_t N, size_t total) {
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (size_t)gridDim.x * blockDim.x) {
         const size_t pnt = i % N;
-        const int x = (int)(pnt % Nx), y = (int)(pnt / Nx);
+        const int x = (int)(pnt % Nx), y = (int)((pnt / Nx) % Ny);
         const double A = kx ? 1.0 - wx[x] : wx[x];
         const double B = ky ? 1.0 - wy[y] : wy[y];
         const double f = A * B;
@@ -1903,10 +1904,10 @@ hipError_t launch_cast(const c128* src, c64* dst, size_t n, hipStream_t st) {
 }
 
 hipError_t launch_window(const c128* r, c128* out, const double* wx, const double* wy, int kx, int ky, int Nx,
-                         size_t N, int nrhs, hipStream_t st) {
+                         int Ny, size_t N, int nrhs, hipStream_t st) {
     const size_t total = N * (size_t)nrhs;
     k_window<<<(unsigned)std::min<size_t>(4096, blocks_for(total, 256)), 256, 0, st>>>(r, out, wx, wy, kx, ky, Nx,
-                                                                                      N, total);
+                                                                                      Ny, N, total);
     return hipGetLastError();
 }
 

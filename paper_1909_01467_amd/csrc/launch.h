@@ -125,7 +125,7 @@ hipError_t launch_gemv(const GemvArgs& a, bool c64mode, hipStream_t st);
 hipError_t launch_final_rhs(const ChainArgs& a, int nsub, int nrhs, bool c64mode, hipStream_t st);
 hipError_t launch_cast(const c128* src, c64* dst, size_t n, hipStream_t st);
 hipError_t launch_window(const c128* r, c128* out, const double* wx, const double* wy, int kx, int ky, int Nx,
-                         size_t N, int nrhs, hipStream_t st);
+                         int Ny, size_t N, int nrhs, hipStream_t st);
 // z = ((z + a) + b) + c over n entries (the sum of the four CDDs of scenario 4, in a fixed order)
 hipError_t launch_accumulate(c128* z, const c128* a, const c128* b, const c128* c, size_t n, hipStream_t st);
 // the polarization maps of all sweep solves as PEntry terms, 4 per (solve, entry) slot (sub = -1: none)

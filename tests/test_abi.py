@@ -107,13 +107,13 @@ def test_setup_rejects_bad_geometry_before_touching_memory():
 
 
 def test_setup_rejects_bad_windows_before_touching_memory():
-    """Scenario 4 needs dim 2, two groups per axis and a shift in [3, smallest group - 3]."""
+    """Scenario 4 needs two groups per axis and a shift in [3, smallest group - 3] (2D and 3D)."""
     lib = lsweeps.load_library()
     h = ctypes.c_void_p()
     shift = ctypes.c_int * 2
     cases = [
         (lsweeps.lsw_grid_t(3, (ctypes.c_int * 3)(20, 20, 20), (ctypes.c_int * 3)(5, 5, 5)),
-         lsweeps.lsw_cdd_t(2, 2, 1, shift(0, 0)), b"dim 2"),
+         lsweeps.lsw_cdd_t(2, 2, 1, shift(8, 0)), b"shift"),
         (lsweeps.lsw_grid_t(2, (ctypes.c_int * 3)(40, 40, 0), (ctypes.c_int * 3)(5, 5, 0)),
          lsweeps.lsw_cdd_t(1, 2, 1, shift(0, 0)), b"q >= 2"),
         (lsweeps.lsw_grid_t(2, (ctypes.c_int * 3)(40, 40, 0), (ctypes.c_int * 3)(5, 5, 0)),
@@ -124,8 +124,6 @@ def test_setup_rejects_bad_windows_before_touching_memory():
          lsweeps.lsw_cdd_t(2, 2, 2, shift(0, 0)), b"windows"),
         (lsweeps.lsw_grid_t(2, (ctypes.c_int * 3)(40, 40, 0), (ctypes.c_int * 3)(5, 5, 0)),
          lsweeps.lsw_cdd_t(2, 2, 0, shift(-1, 0)), b"shift"),
-        (lsweeps.lsw_grid_t(3, (ctypes.c_int * 3)(20, 20, 20), (ctypes.c_int * 3)(5, 5, 5)),
-         lsweeps.lsw_cdd_t(2, 2, 0, shift(4, 0)), b"dim 2"),
     ]
     for grid, cdd, msg in cases:
         rc = lib.lsw_setup(ctypes.byref(h), ctypes.c_void_p(1), 10.0, 0.1, ctypes.byref(grid), ctypes.byref(cdd),
