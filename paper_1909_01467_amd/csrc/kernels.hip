@@ -1878,7 +1878,7 @@ hipError_t launch_gemv(const GemvArgs& a, bool c64mode, hipStream_t st) {
 }
 
 hipError_t launch_final_rhs(const ChainArgs& a, int nsub, int nrhs, bool c64mode, hipStream_t st) {
-    dim3 grid(nsub, nrhs, 8);
+    dim3 grid(nsub, nrhs, 32);   // about one window point per lane at W = H = 88
     if (c64mode) k_final_rhs<float><<<grid, 256, 0, st>>>(a);
     else k_final_rhs<double><<<grid, 256, 0, st>>>(a);
     return hipGetLastError();
