@@ -146,8 +146,8 @@ def main():
                     help="first run one device copy of this many MiB (calibrates FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding is designed, not built "
-                                   "(see the design notes). Use --gpus 1."}))
+        print(json.dumps({"error": "this implementation runs on one GPU; sharding over several GPUs is "
+                                   "not implemented. Use --gpus 1."}))
         sys.exit(2)
 
     import torch

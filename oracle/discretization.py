@@ -8,7 +8,7 @@ Follows App. A of the paper:
   * second-order differences with the coefficient taken at half points.
 The medium is extended into the PML by its normal (constant) extension (Sec. 1.1).
 
-Readings (the paper is silent or garbled; see the design notes):
+Readings (where the paper is silent or garbled):
   * grid: n bulk points per axis at x = h..n h, h = 1/(n+1) by default; n_pml extra
     points per side at x = 0, -h, ..., -(n_pml-1)h (and mirrored), Dirichlet ghosts at
     x = -n_pml h and 1 + n_pml h, so delta = n_pml h and the bulk interval is [0, (n+1)h];

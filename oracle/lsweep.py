@@ -13,7 +13,7 @@ where Gamma_2 are the points of the receiving region chi adjacent to its outside
 Gamma_1 the outside points adjacent to chi (Sec. 1.3).  They are found from the
 sparsity of A_ij itself, so g = A_ij(chi u~) - chi (A_ij u~) exactly.
 
-Discrete conventions (Sec. 2.2; readings listed in the design notes):
+Discrete conventions (Sec. 2.2; where the paper leaves them open, the readings below):
   * CDD: the bulk points of each axis are split into q (rows, along y) or r (columns,
     along x) contiguous groups, the first (n mod q) one point larger; the first and last
     groups also own the global PML points.  Row i = 0 is at the bottom, column j = 0 at
