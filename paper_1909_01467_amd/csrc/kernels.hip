@@ -1808,12 +1808,13 @@ hipError_t launch_chain_mr(const ChainArgs& a, int nsolves, int nrhs, int ept, b
                    : launch_chain_mr_t<double>(a, nsolves, nrhs, ept, cs, rgroup, st);
 }
 
-// register ring of k_chain_sym: a tile is 32 VGPRs in complex64 and 64 in complex128; PD blocks
-// in flight within about 200 of the 256 VGPRs of a 256-lane workgroup
+// register ring of k_chain_sym: a tile is 32 VGPRs in complex64 and 64 in complex128.  Measured at
+// W = 88 (one tile per lane): 2 or 3 blocks in flight are equal, 4 is 2% and 6 is 11% slower (the
+// loads of later blocks then compete with the step in use)
 template <typename T, int CS, int PH, typename F>
 static void sym_dispatch(int ept, F&& f) {
     if constexpr (sizeof(T) == 4) {
-        if (ept <= 1) f(k_chain_sym<T, 1, 4, CS, PH>);
+        if (ept <= 1) f(k_chain_sym<T, 1, 3, CS, PH>);
         else if (ept <= 2) f(k_chain_sym<T, 2, 2, CS, PH>);
         else f(k_chain_sym<T, 3, 1, CS, PH>);
     } else {
