@@ -840,12 +840,10 @@ int solve_impl(lsw_plan* p, const c128* d_b, c128* d_x, int nrhs, lsw_info_t* in
     const int HS = 2 * (m + 1) + 1;           // host buffer stride per rhs: h1 | h2 | norm
     const size_t vl = (size_t)nrhs * N;       // basis stride between Krylov vectors
     int rc;
-    // ||b||
-    if ((rc = dots_impl(p, d_b, 0, N, d_b, N, 1, nrhs, p->d_hbuf, HS)) != LSW_OK) return rc;
-    HIPCK(p, hipMemcpyAsync(p->h_hbuf, p->d_hbuf, sizeof(c128) * HS * nrhs, hipMemcpyDeviceToHost, p->stream));
-    if ((rc = spin_wait(p)) != LSW_OK) return rc;
+    // ||b||^2 into entry 1 of every column; the host reads it with the first residual norm
+    if ((rc = dots_impl(p, d_b, 0, N, d_b, N, 1, nrhs, p->d_hbuf + 1, HS)) != LSW_OK) return rc;
+    bool first_cycle = true;
     std::vector<double> bnorm(nrhs), relres(nrhs, 1.0);
-    for (int s = 0; s < nrhs; ++s) bnorm[s] = std::sqrt(std::max(0.0, p->h_hbuf[(size_t)s * HS].re));
     std::vector<int> its(nrhs, 0), conv(nrhs, 0);
     std::vector<std::vector<double>> hist(nrhs);
     std::vector<cd> H((size_t)nrhs * (m + 1) * m), cs((size_t)nrhs * m), sn((size_t)nrhs * m),
@@ -860,6 +858,10 @@ int solve_impl(lsw_plan* p, const c128* d_b, c128* d_x, int nrhs, lsw_info_t* in
         if ((rc = dots_impl(p, V, 0, N, V, N, 1, nrhs, p->d_hbuf, HS)) != LSW_OK) return rc;
         HIPCK(p, hipMemcpyAsync(p->h_hbuf, p->d_hbuf, sizeof(c128) * HS * nrhs, hipMemcpyDeviceToHost, p->stream));
         if ((rc = spin_wait(p)) != LSW_OK) return rc;
+        if (first_cycle) {
+            for (int s = 0; s < nrhs; ++s) bnorm[s] = std::sqrt(std::max(0.0, p->h_hbuf[(size_t)s * HS + 1].re));
+            first_cycle = false;
+        }
         int nlive = 0;
         for (int s = 0; s < nrhs; ++s) {
             const double beta = std::sqrt(std::max(0.0, p->h_hbuf[(size_t)s * HS].re));
