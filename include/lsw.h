@@ -161,6 +161,12 @@ typedef struct {
                                     times above are totals over the four CDDs (W_max/H_max: the first's),
                                     and last_apply_ms also covers the window and accumulation kernels */
     int window_shift[2];         /* shift of the shifted CDDs along x / y (0 without windows) */
+    /* the dominant kernel of the most recent lsw_apply, timed launch by launch with events on the
+     * handle's stream: 2D the final z substitutions (k_chain_sym / k_chain, 2 launches per CDD),
+     * 3D the plane-step kernel reading the factors (k_tile3 on packed blocks, else k_step3) */
+    double last_dom_ms;          /* summed device time of its launches */
+    int dom_launches;            /* its launches */
+    double dom_bytes;            /* algorithmic bytes those launches read (factor blocks) */
 } lsw_stats_t;
 
 /*

@@ -139,6 +139,12 @@ struct lsw_plan {
     int chain_launches = 0, gemv_launches = 0;
     hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
     double last_stage1_ms = 0, last_final_ms = 0, last_final_rhs_ms = 0;
+    // the dominant kernel of a timed application (2D: the final substitutions; 3D: the plane
+    // steps' k_tile3 / k_step3 launches, bracketed one by one by the event pairs kev[2i], kev[2i+1])
+    std::vector<hipEvent_t> kev;
+    size_t kev_used = 0;
+    double last_dom_ms = 0, dom_bytes = 0;
+    int dom_launches = 0;
     double apply_stage1_bytes = 0, apply_final_bytes = 0;
     // scenario 4 (Sec. 2.1): this plan is the unshifted CDD; shifted[] holds the CDDs shifted along
     // x, y and both, each a complete plan without a Krylov basis (member = true)
@@ -237,6 +243,8 @@ void free_plan(lsw_plan* p) {
     if (p->own_stream) (void)hipStreamDestroy(p->own_stream);
     if (p->ev_spin) (void)hipEventDestroy(p->ev_spin);
     for (hipEvent_t e : p->ev_step)
+        if (e) (void)hipEventDestroy(e);
+    for (hipEvent_t e : p->kev)
         if (e) (void)hipEventDestroy(e);
     if (p->h_act_stage) (void)hipHostFree(p->h_act_stage);
     if (p->rb) (void)rocblas_destroy_handle(p->rb);
@@ -1169,9 +1177,15 @@ int apply3d_impl(lsw_plan* p, const c128* d_r, c128* d_z, int nrhs, bool timed) 
     a.P3 = p->d_P3;
     a.ptiles = p->ptiles3;
     if (p->gsym) a.G = p->d_Gs;
+    p->kev_used = 0;
     auto step = [&](int phase, int t) {
-        return p->gsym ? launch_step3_packed(a, p->Smax, nrhs, phase, t, c64, p->stream)
-                       : launch_step3(a, p->Smax, nrhs, phase, t, c64, p->stream);
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (timed && p->kev_used + 2 <= p->kev.size()) {
+            e0 = p->kev[p->kev_used++];
+            e1 = p->kev[p->kev_used++];
+        }
+        return p->gsym ? launch_step3_packed(a, p->Smax, nrhs, phase, t, c64, p->stream, e0, e1)
+                       : launch_step3(a, p->Smax, nrhs, phase, t, c64, p->stream, e0, e1);
     };
     if (timed) HIPCK(p, hipEventRecord(p->ev[0], p->stream));
     for (size_t fi = 0; fi < p->fronts.size(); ++fi) {
@@ -1570,6 +1584,10 @@ int setup_impl(lsw_plan* p, const double* d_m, double omega, double h, const lsw
     p->geo.h = h;
     p->geo.omega = omega;
     if (p->dim == 3) {
+        // one event pair per plane step of a timed application (the dominant kernel's launches)
+        const int mz = p->Nz / 2, mhz = std::max(mz, p->Nz - 1 - mz);
+        p->kev.assign(2 * p->fronts.size() * (size_t)(2 * mhz + 1), nullptr);
+        for (hipEvent_t& e : p->kev) HIPCK(p, hipEventCreate(&e));
         if ((rc = setup3d_factor(p)) != LSW_OK) return rc;
         if (p->windows && (rc = setup_windows(p, d_m, omega, h, grid, cdd, pml, opts)) != LSW_OK) return rc;
         p->t_setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
@@ -1824,6 +1842,15 @@ int read_apply_times(lsw_plan* p) {
         p->last_final_rhs_ms = 0;
         p->last_final_ms = t34;
         p->last_chain_ms = t01 + t12;
+        double dom = 0;
+        for (size_t i = 0; i + 1 < p->kev_used; i += 2) {
+            float t = 0;
+            HIPCK(p, hipEventElapsedTime(&t, p->kev[i], p->kev[i + 1]));
+            dom += t;
+        }
+        p->last_dom_ms = dom;
+        p->dom_launches = (int)(p->kev_used / 2);
+        p->dom_bytes = p->apply_chain_bytes;
     } else if (p->sweep_mode == LSW_SWEEP_CHAIN) {
         p->last_chain_ms = t01;
         p->last_gemv_ms = 0;
@@ -1834,6 +1861,9 @@ int read_apply_times(lsw_plan* p) {
         p->last_final_rhs_ms = t23;
         p->last_final_ms = t34;
         p->last_chain_ms = t01 + t34;
+        p->last_dom_ms = t34;     // the two launches of the final z substitutions
+        p->dom_launches = 2;
+        p->dom_bytes = p->apply_final_bytes;
     }
     return LSW_OK;
 }
@@ -1878,7 +1908,8 @@ int lsw_apply(lsw_handle_t p, const double* d_r, double* d_z, int nrhs) {
         HIPCK(p, hipEventSynchronize(p->evw[1]));
         if ((rc = read_apply_times(p)) != LSW_OK) return rc;
         double s1 = p->last_stage1_ms, gv = p->last_gemv_ms, fr = p->last_final_rhs_ms, fi = p->last_final_ms,
-               ch = p->last_chain_ms;
+               ch = p->last_chain_ms, dm = p->last_dom_ms, db = p->dom_bytes;
+        int dl = p->dom_launches;
         for (lsw_plan* c : p->shifted) {
             if ((rc = read_apply_times(c)) != LSW_OK) return fail(p, rc, c->err);
             s1 += c->last_stage1_ms;
@@ -1886,6 +1917,9 @@ int lsw_apply(lsw_handle_t p, const double* d_r, double* d_z, int nrhs) {
             fr += c->last_final_rhs_ms;
             fi += c->last_final_ms;
             ch += c->last_chain_ms;
+            dm += c->last_dom_ms;
+            db += c->dom_bytes;
+            dl += c->dom_launches;
         }
         float t = 0;
         HIPCK(p, hipEventElapsedTime(&t, p->evw[0], p->evw[1]));
@@ -1895,6 +1929,9 @@ int lsw_apply(lsw_handle_t p, const double* d_r, double* d_z, int nrhs) {
         p->last_final_rhs_ms = fr;
         p->last_final_ms = fi;
         p->last_chain_ms = ch;
+        p->last_dom_ms = dm;
+        p->dom_bytes = db;
+        p->dom_launches = dl;
         return LSW_OK;
     }
     HIPCK(p, hipEventSynchronize(p->ev[4]));
@@ -1988,6 +2025,9 @@ int lsw_query(lsw_handle_t p, lsw_stats_t* st) {
     st->cdd_count = p->windows ? 4 : 1;
     st->window_shift[0] = p->shift_x;
     st->window_shift[1] = p->shift_y;
+    st->last_dom_ms = p->last_dom_ms;
+    st->dom_launches = p->dom_launches;
+    st->dom_bytes = p->dom_bytes;
     if (p->windows) {   // totals over the four CDDs (the setup time already covers all four)
         for (const lsw_plan* c : p->shifted) {
             if (!c) continue;

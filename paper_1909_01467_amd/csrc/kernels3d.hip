@@ -706,30 +706,32 @@ hipError_t launch_rhs3(const Chain3Args& a, int smax, int nrhs, bool f32, hipStr
     return hipGetLastError();
 }
 
-hipError_t launch_step3(const Chain3Args& a, int smax, int nrhs, int phase, int t, bool f32, hipStream_t st) {
+hipError_t launch_step3(const Chain3Args& a, int smax, int nrhs, int phase, int t, bool f32, hipStream_t st,
+                        hipEvent_t e0, hipEvent_t e1) {
     dim3 grid(nblk((size_t)smax, 64), 2 * a.nslots, nrhs);
     const size_t lds = (f32 ? sizeof(c64) : sizeof(c128)) * (size_t)smax;
-    if (f32) {
-        hipError_t e = hipFuncSetAttribute((const void*)k_step3<float>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
-        k_step3<float><<<grid, 1024, lds, st>>>(a, smax, phase, t);
-    } else {
-        hipError_t e = hipFuncSetAttribute((const void*)k_step3<double>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
-        k_step3<double><<<grid, 1024, lds, st>>>(a, smax, phase, t);
-    }
-    return hipGetLastError();
+    hipError_t e = hipFuncSetAttribute(f32 ? (const void*)k_step3<float> : (const void*)k_step3<double>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    if (e0 && (e = hipEventRecord(e0, st)) != hipSuccess) return e;
+    if (f32) k_step3<float><<<grid, 1024, lds, st>>>(a, smax, phase, t);
+    else k_step3<double><<<grid, 1024, lds, st>>>(a, smax, phase, t);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (e1 && (e = hipEventRecord(e1, st)) != hipSuccess) return e;
+    return hipSuccess;
 }
 
-hipError_t launch_step3_packed(const Chain3Args& a, int smax, int nrhs, int phase, int t, bool f32, hipStream_t st) {
+hipError_t launch_step3_packed(const Chain3Args& a, int smax, int nrhs, int phase, int t, bool f32, hipStream_t st,
+                               hipEvent_t e0, hipEvent_t e1) {
     const dim3 tg(a.ptiles, 2 * a.nslots, nrhs), rg(plane3_nb(smax), 2 * a.nslots, nrhs);
-    if (f32) {
-        k_tile3<float><<<tg, 256, 0, st>>>(a, smax, phase, t);
-        k_red3<float><<<rg, 256, 0, st>>>(a, smax, phase, t);
-    } else {
-        k_tile3<double><<<tg, 256, 0, st>>>(a, smax, phase, t);
-        k_red3<double><<<rg, 256, 0, st>>>(a, smax, phase, t);
-    }
+    hipError_t e;
+    if (e0 && (e = hipEventRecord(e0, st)) != hipSuccess) return e;
+    if (f32) k_tile3<float><<<tg, 256, 0, st>>>(a, smax, phase, t);
+    else k_tile3<double><<<tg, 256, 0, st>>>(a, smax, phase, t);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (e1 && (e = hipEventRecord(e1, st)) != hipSuccess) return e;
+    if (f32) k_red3<float><<<rg, 256, 0, st>>>(a, smax, phase, t);
+    else k_red3<double><<<rg, 256, 0, st>>>(a, smax, phase, t);
     return hipGetLastError();
 }
 

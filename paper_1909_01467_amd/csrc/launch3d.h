@@ -60,11 +60,14 @@ hipError_t launch_fact3_finish(const Fact3Args& a, int nbatch, hipStream_t st);
 hipError_t launch_rhs3(const Chain3Args& a, int smax, int nrhs, bool f32, hipStream_t st);
 // one step of the twisted block substitution of every solve of a front:
 // phase 0 forward (step t of each half), 1 middle plane, 2 backward (step t of each half)
-hipError_t launch_step3(const Chain3Args& a, int smax, int nrhs, int phase, int t, bool f32, hipStream_t st);
+// (e0, e1: optional events recorded before and after the step's main kernel)
+hipError_t launch_step3(const Chain3Args& a, int smax, int nrhs, int phase, int t, bool f32, hipStream_t st,
+                        hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 // the same step on the packed symmetric plane blocks (a.G = packed pool, SubDesc::gs_off): one
 // workgroup per 64 x 64 tile forms tile v_J and tile^T v_I (a.P3), then one workgroup per 64-row
 // block adds its row and column partials in a fixed order into y (phase 2: x = y - sum)
-hipError_t launch_step3_packed(const Chain3Args& a, int smax, int nrhs, int phase, int t, bool f32, hipStream_t st);
+hipError_t launch_step3_packed(const Chain3Args& a, int smax, int nrhs, int phase, int t, bool f32, hipStream_t st,
+                               hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 // packs the symmetrised mean (G + G^T)/2 of every plane block of the full FP64 pool into the
 // tile layout of plane3_tiles (complex64 when f32); maxper = the largest Nz*plane3_tiles*4096
 hipError_t launch_pack3(const SubDesc* subs, int nsub, int Nz, const c128* G, void* Gs, size_t maxper, bool f32,

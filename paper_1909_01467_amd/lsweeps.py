@@ -78,7 +78,8 @@ class lsw_stats_t(ctypes.Structure):
                 ("last_final_rhs_ms", ctypes.c_double), ("rhs_per_workgroup", ctypes.c_int),
                 ("tune_ms", ctypes.c_double * 3), ("symmetric_factors", ctypes.c_int),
                 ("packed_factor_elems", ctypes.c_longlong), ("gemv_items", ctypes.c_int),
-                ("gemv_max_inputs", ctypes.c_int), ("cdd_count", ctypes.c_int), ("window_shift", ctypes.c_int * 2)]
+                ("gemv_max_inputs", ctypes.c_int), ("cdd_count", ctypes.c_int), ("window_shift", ctypes.c_int * 2),
+                ("last_dom_ms", ctypes.c_double), ("dom_launches", ctypes.c_int), ("dom_bytes", ctypes.c_double)]
 
 
 _lib = None
@@ -303,6 +304,16 @@ class Solver:
             pass
 
 
+def _require_converged(solver: Solver, info: dict, what: str) -> None:
+    """A gradient built from an unconverged state or adjoint field is wrong without any sign of it,
+    so the autograd path refuses it (the plain Solver API reports LSW_ENOCONV through `info`)."""
+    bad = [k for k, ok in enumerate(info["converged"]) if not ok]
+    if bad:
+        solver.close()
+        raise LswError(LSW_ENOCONV, f"{what} did not reach tol for right-hand sides {bad} "
+                                    f"(relative residuals {[info['relres'][k] for k in bad]})")
+
+
 class HelmholtzSolve(torch.autograd.Function):
     """u = A(m)^-1 f on the extended grid, differentiable in the bulk squared slowness m
     and in f.  Backward (adjoint state, A = A^T): lam = A^-H g_u solved with the same
@@ -314,6 +325,7 @@ class HelmholtzSolve(torch.autograd.Function):
         kw = dict(solver_kwargs)
         solver = Solver(m_ext.detach(), **kw)
         u, info = solver.solve(f.detach())
+        _require_converged(solver, info, "forward solve")
         ctx.solver = solver
         ctx.f_shape = f.shape
         ctx.save_for_backward(u)
@@ -324,7 +336,8 @@ class HelmholtzSolve(torch.autograd.Function):
     def backward(ctx, g_u):
         (u,) = ctx.saved_tensors
         solver = ctx.solver
-        lam, _ = solver.adjoint(g_u.contiguous())
+        lam, info = solver.adjoint(g_u.contiguous())
+        _require_converged(solver, info, "adjoint solve")
         grad_m = solver.mass_gradient(torch.conj_physical(lam), u) if ctx.needs_input_grad[0] else None
         grad_f = lam.reshape(ctx.f_shape) if ctx.needs_input_grad[1] else None
         solver.close()

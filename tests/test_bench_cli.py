@@ -34,6 +34,6 @@ def test_counter_summary_is_read_for_the_current_kernels():
     if f"sha256[:16] = {sha}" not in text:
         pytest.skip("the counters predate the current kernels (bench.py reports traffic null)")
     for kernel in ("k_chain_sym<CS_STAGE1>", "k_chain_sym<CS_FINAL>"):
-        t = bench.counter_traffic(kernel)
+        t = bench.counter_traffic(kernel, "lens2d")
         assert t is not None and 1.0 <= t / 158292992 <= 1.5, (kernel, t)
 

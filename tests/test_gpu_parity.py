@@ -1,9 +1,10 @@
 """Parity of the HIP path (through the C ABI) with the FP64 oracle.
 
-Tolerances (relative L2):
+Tolerances (relative L2 over the whole vector, and on every subdomain Omega_ij at 10x the bar):
   * y = A x (FP64 stencil)                               1e-13
-  * z = M^-1 r, FP64 sweeps (block LU vs SuperLU)        1e-10
-  * z = M^-1 r, complex64 sweeps                         2e-4
+  * z = M^-1 r, FP64 sweeps (block LU vs SuperLU)        1e-12 (largest measured 1.2e-13)
+  * z = M^-1 r, complex64 sweeps                         1e-6 (small cases, largest measured 3.5e-7),
+                                                         2e-6 (lens2d and 147-point windows, 6.8e-7)
   * GMRES solve vs the exact solve: 1e-6 (FP64) and 1e-4 (mixed) at tol 1e-8,
     and the true residual computed by the oracle's own matrix <= tol.
 """
@@ -22,6 +23,7 @@ from oracle.lsweep import LSweep2D
 from oracle.scenario4 import Scenario4
 from paper_1909_01467_amd import inputs
 from paper_1909_01467_amd.lsweeps import LSW_EINVAL, LSW_ENAN, HelmholtzSolve, LswError, Solver, extend_medium
+from tests.parity_check import check
 
 pytestmark = pytest.mark.gpu
 
@@ -111,9 +113,7 @@ def test_apply_fp64_matches_oracle(name, mode):
     s = c.solver(sweep_mode=mode)
     z = to_np(s.apply(torch.from_numpy(r).cuda()))
     zo = c.oracle.apply(r)
-    err = rel(z, zo)
-    say(name, mode, "apply fp64 rel err", err)
-    assert err < 1e-10
+    check(f"{name} {mode} apply fp64", z, zo, 1e-12, cdd=c.oracle, shape=c.m.shape)
     s.close()
 
 
@@ -122,7 +122,7 @@ def test_apply_single_subdomain_is_exact_inverse():
     b = inputs.complex_normal(c.N, 3)
     s = c.solver()
     z = to_np(s.apply(torch.from_numpy(b).cuda()))
-    assert rel(z, solve_banded(c.gp.A, b)) < 1e-10
+    check("single_1x1 apply = A^-1", z, solve_banded(c.gp.A, b), 1e-12)
     s.close()
 
 
@@ -133,9 +133,7 @@ def test_apply_mixed_matches_oracle(name, mode):
     r = inputs.complex_normal(c.N, 4)
     s = c.solver(precision="mixed", sweep_mode=mode)
     z = to_np(s.apply(torch.from_numpy(r).cuda()))
-    err = rel(z, c.oracle.apply(r))
-    say(name, "apply mixed rel err", err)
-    assert err < 2e-4
+    check(f"{name} {mode} apply mixed", z, c.oracle.apply(r), 1e-6, cdd=c.oracle, shape=c.m.shape)
     s.close()
 
 
@@ -282,6 +280,27 @@ def test_fwi_gradient_matches_oracle_and_finite_differences():
     assert err < 1e-7
 
 
+def test_helmholtz_solve_passes_gradcheck_on_a_tiny_grid():
+    """torch.autograd.gradcheck of a real misfit through HelmholtzSolve, with respect to the bulk
+    squared slowness (real) and the right-hand side (complex): checks the adjoint backward and
+    PyTorch's conjugate-Wirtinger convention for the complex input against finite differences."""
+    n, p, q = 10, 4, 2
+    omega = 2 * math.pi * n / 10
+    kw = dict(omega=omega, h=1.0 / (n + 1), n=n, n_pml=p, q=q, r=q, C=16 * math.log(omega), tol=1e-13,
+              precision="fp64")
+    N = n + 2 * p
+    rec = torch.tensor([[p + 2, p + 1], [p + 5, p + 7], [p + 8, p + 3]], device="cuda")
+    d = torch.from_numpy(inputs.complex_normal(3, 31)).cuda()
+
+    def misfit(mb, f):
+        U = HelmholtzSolve.apply(extend_medium(mb, p), f, kw).reshape(N, N)
+        return 0.5 * ((U[rec[:, 0], rec[:, 1]] - d).abs() ** 2).sum()
+
+    mb = torch.from_numpy(1.0 / inputs.speed_lens(n, 2) ** 2).cuda().requires_grad_(True)
+    f = torch.from_numpy(inputs.complex_normal((N, N), 32)).cuda().requires_grad_(True)
+    assert torch.autograd.gradcheck(misfit, (mb, f), eps=1e-6, atol=1e-7, rtol=1e-5, fast_mode=True)
+
+
 @pytest.mark.parametrize("precision,tol_err", [("fp64", 1e-6), ("mixed", 1e-4)])
 def test_lens2d_full_size_solve(precision, tol_err):
     """511^2, 8x8 CDD, lens + 5% smooth noise (the benchmark workload) at tol 1e-8."""
@@ -309,12 +328,11 @@ def test_lens2d_full_size_apply_matches_oracle():
     ls = LSweep2D(m, wl.omega, wl.n, wl.n_pml, wl.q, wl.r, wl.C)
     zo = ls.apply(r)
     for mode in ("compressed", "chain"):
-        for precision, tol in (("fp64", 1e-10), ("mixed", 2e-4)):
+        for precision, tol in (("fp64", 1e-12), ("mixed", 2e-6)):
             s = Solver(torch.from_numpy(m).cuda(), wl.omega, wl.h, wl.n, wl.n_pml, wl.q, wl.r, C=wl.C,
                        precision=precision, sweep_mode=mode)
-            err = rel(to_np(s.apply(torch.from_numpy(r).cuda())), zo)
-            say("lens2d apply", mode, precision, err)
-            assert err < tol
+            check(f"lens2d apply {mode} {precision}", to_np(s.apply(torch.from_numpy(r).cuda())), zo, tol,
+                  cdd=ls, shape=m.shape)
             s.close()
 
 
@@ -355,10 +373,11 @@ def test_batched_substitutions_carry_several_rhs_per_workgroup(R, precision, mon
     for k in range(5):
         assert rel(Z[k], singles[k]) < (1e-12 if precision == "fp64" else 2e-6), (R, k)
     zo = c.oracle.apply(X[2].cpu().numpy())
-    assert rel(Z[2], zo) < (1e-10 if precision == "fp64" else 2e-4)
+    check(f"wide_4x5 R={R} batched apply {precision}", Z[2], zo, 1e-12 if precision == "fp64" else 1e-6,
+          cdd=c.oracle, shape=c.m.shape)
 
 
-@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("mixed", 2e-5)])
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("mixed", 2e-6)])
 @pytest.mark.parametrize("name", ["ragged_45x38_3x2", "wide_4x5", "thin_local_pml", "row_1x3"])
 def test_packed_symmetric_factors_match_full_blocks(name, precision, tol, monkeypatch):
     """The substitutions on the packed symmetric blocks (odd and even window widths, several
@@ -377,9 +396,7 @@ def test_packed_symmetric_factors_match_full_blocks(name, precision, tol, monkey
     Z0 = s.apply(X).cpu().numpy().reshape(2, -1)
     s.close()
     for k in range(2):
-        err = rel(Z[k], Z0[k])
-        say(name, precision, "packed vs full", err)
-        assert err < tol
+        check(f"{name} {precision} packed vs full blocks", Z[k], Z0[k], tol, cdd=c.oracle, shape=c.m.shape)
 
 
 def test_packed_factors_of_wide_windows(monkeypatch):
@@ -399,10 +416,8 @@ def test_packed_factors_of_wide_windows(monkeypatch):
     s.close()
     zo = c.oracle.apply(X[0].cpu().numpy())
     for k in range(2):
-        say("wide windows packed vs full", rel(Z[k], Z0[k]))
-        assert rel(Z[k], Z0[k]) < 2e-5
-    say("wide windows packed vs oracle", rel(Z[0], zo))
-    assert rel(Z[0], zo) < 2e-4
+        check("wide windows packed vs full blocks", Z[k], Z0[k], 2e-6, cdd=c.oracle, shape=c.m.shape)
+    check("wide windows packed vs oracle", Z[0], zo, 2e-6, cdd=c.oracle, shape=c.m.shape)
 
 
 def test_rhs_per_workgroup_is_tuned_at_setup():
@@ -445,7 +460,7 @@ def test_workspace_in_the_torch_caching_allocator(windows):
 
 def test_random_geometries_match_oracle():
     """Seeded random grids, PML widths, local PML widths and CDD shapes (ragged splits, thin
-    groups, single rows or columns): one FP64 application against the oracle's, 1e-10."""
+    groups, single rows or columns): one FP64 application against the oracle's, 1e-12."""
     rng = np.random.default_rng(2024)
     done = 0
     while done < 10:
@@ -462,15 +477,15 @@ def test_random_geometries_match_oracle():
             continue
         x = inputs.complex_normal(c.N, 70 + done)
         s = c.solver()
-        err = rel(to_np(s.apply(torch.from_numpy(x).cuda())), oracle.apply(x))
+        z = to_np(s.apply(torch.from_numpy(x).cuda()))
         s.close()
-        say("random geometry", (nx, ny, px, py, q, r, pl), "apply fp64 rel err", err)
-        assert err < 1e-10
+        check(f"random geometry {(nx, ny, px, py, q, r, pl)} apply fp64", z, oracle.apply(x), 1e-12,
+              cdd=oracle, shape=c.m.shape)
         if q >= 2 and r >= 2 and min(nx // r, ny // q) >= 6:   # scenario 4 with the default shifts
             s4 = Scenario4(c.m, c.omega, (nx, ny), (px, py), q, r, c.C, n_pml_local=pl, h=c.h)
             s = c.solver(windows=True)
-            err = rel(to_np(s.apply(torch.from_numpy(x).cuda())), s4.apply(x))
+            z = to_np(s.apply(torch.from_numpy(x).cuda()))
             s.close()
-            say("random geometry, windows", s4.shift, "apply fp64 rel err", err)
-            assert err < 1e-10
+            check(f"random geometry {(nx, ny, px, py, q, r, pl)}, windows {s4.shift} apply fp64", z, s4.apply(x),
+                  1e-12, cdd=oracle, shape=c.m.shape)
         done += 1

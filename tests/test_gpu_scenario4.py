@@ -1,7 +1,8 @@
 """Scenario 4 (Sec. 2.1) on the HIP path through the C ABI, against the FP64 oracle.
 
-Tolerances (relative L2) as for scenario 3: 1e-10 for the FP64 sweeps, 2e-4 for the
-complex64 sweeps; the windowed solve reaches the exact solve to 1e-6 at tol 1e-8.
+Tolerances (relative L2, whole vector and 10x on every subdomain of the unshifted CDD) as for
+scenario 3: 1e-12 for the FP64 sweeps, 1e-6 for the complex64 sweeps (largest measured 7.4e-15 and
+2.1e-7); the windowed solve reaches the exact solve to 1e-6 at tol 1e-8.
 """
 import math
 import sys
@@ -16,6 +17,7 @@ from oracle.lsweep import LSweep2D
 from oracle.scenario4 import Scenario4
 from paper_1909_01467_amd import inputs
 from paper_1909_01467_amd.lsweeps import Solver
+from tests.parity_check import check
 
 pytestmark = pytest.mark.gpu
 
@@ -84,9 +86,8 @@ def test_windowed_apply_fp64_matches_oracle(name, mode):
     st = s.stats()
     assert st["cdd_count"] == 4 and tuple(st["window_shift"]) == c.oracle.shift
     z = to_np(s.apply(torch.from_numpy(r).cuda()))
-    err = rel(z, c.oracle.apply(r))
-    say(name, mode, "windowed apply fp64 rel err", err)
-    assert err < 1e-10
+    check(f"{name} {mode} windowed apply fp64", z, c.oracle.apply(r), 1e-12, cdd=c.oracle.cdds[0],
+          shape=c.m.shape)
     s.close()
 
 
@@ -95,9 +96,8 @@ def test_windowed_apply_mixed_matches_oracle(name):
     c = CASES[name]
     r = inputs.complex_normal(c.N, 42)
     s = c.solver(precision="mixed")
-    err = rel(to_np(s.apply(torch.from_numpy(r).cuda())), c.oracle.apply(r))
-    say(name, "windowed apply mixed rel err", err)
-    assert err < 2e-4
+    check(f"{name} windowed apply mixed", to_np(s.apply(torch.from_numpy(r).cuda())), c.oracle.apply(r), 1e-6,
+          cdd=c.oracle.cdds[0], shape=c.m.shape)
     s.close()
 
 
@@ -109,9 +109,8 @@ def test_shifted_cdd_alone_matches_oracle():
     s = Solver(torch.from_numpy(c.m).cuda(), c.omega, c.h, (c.nx, c.ny), (c.px, c.py), c.q, c.r, C=c.C,
                shift=(7, 4))
     r = inputs.complex_normal(c.N, 43)
-    err = rel(to_np(s.apply(torch.from_numpy(r).cuda())), ls.apply(r))
-    say("shifted CDD alone rel err", err)
-    assert err < 1e-10
+    check("shifted CDD alone apply fp64", to_np(s.apply(torch.from_numpy(r).cuda())), ls.apply(r), 1e-12,
+          cdd=ls, shape=c.m.shape)
     s.close()
 
 

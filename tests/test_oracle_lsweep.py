@@ -177,3 +177,29 @@ def test_iteration_counts_follow_paper_table():
         res = fgmres(lambda v: gp.A @ v, ls.apply, gp.rhs(f), tol=1e-6)
         assert res.converged
         assert abs(res.iterations - row["iterations_pml_1_wavelength"]) <= 1, (n, q, res.iterations)
+
+
+def test_iteration_counts_at_the_default_pml_constant():
+    """The library's default PML constant C = 16 ln(omega) (reading of App. A): on the standard
+    setup of Sec. 5 with PMLs of one and two wavelengths the oracle's FGMRES stays in the two-sided
+    band paper - 2 <= count <= paper + 1 of Tab. PMLeffect at q = 2 and 4 (N = 202^2 and 404^2),
+    and the thicker PML never needs more iterations."""
+    with open(os.path.join(GOLDEN, "pml_effect_iterations.json")) as fh:
+        table = json.load(fh)
+    for row in table["rows"][:2]:
+        n, q = row["n"], row["q"]
+        omega = 2 * math.pi * n / 10
+        its = {}
+        for w in (1, 2):
+            p = 10 * w
+            m = np.ones((n + 2 * p,) * 2)
+            C = 16 * math.log(omega)
+            gp = GlobalProblem(m, omega, n, p, C)
+            ls = LSweep2D(m, omega, n, p, q, q, C)
+            f = sum(inputs.gaussian_source(n, c, 1.0 / n) for c in table["sources"])
+            res = fgmres(lambda v: gp.A @ v, ls.apply, gp.rhs(f), tol=1e-6)
+            assert res.converged and res.relres <= 1e-6
+            its[w] = res.iterations
+            paper = row["iterations_pml_1_wavelength"] if w == 1 else row["iterations_pml_2_wavelengths"]
+            assert paper - 2 <= res.iterations <= paper + 1, (n, q, w, res.iterations)
+        assert its[2] <= its[1]
