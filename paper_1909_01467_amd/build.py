@@ -42,9 +42,7 @@ def build(verbose: bool = False) -> str:
         if proc.wait() != 0:
             raise subprocess.CalledProcessError(proc.returncode, cmd)
     tmp = LIB + ".tmp"
-    # rocBLAS supplies the batched complex GEMM of the 3D plane-block factorisation
-    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-L", "/opt/rocm/lib", "-lrocblas",
-           "-Wl,-rpath,/opt/rocm/lib", "-o", tmp]
+    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

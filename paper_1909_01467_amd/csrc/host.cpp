@@ -25,7 +25,6 @@
 #include <string>
 #include <vector>
 
-#include <rocblas/rocblas.h>
 
 #include "launch.h"
 #include "launch3d.h"
@@ -60,7 +59,6 @@ struct lsw_plan {
     int dim = 2, nz = 1, pz = 0, Nz = 1, Smax = 0;
     void* d_rhs3 = nullptr;     // [nrhs][front slot][Nz][Smax] right-hand sides of a front
     void* d_Y3 = nullptr;       // same layout: y then x
-    rocblas_handle rb = nullptr;
     double tol = 1e-6;
     hipStream_t stream = nullptr;
     // geometry
@@ -247,7 +245,6 @@ void free_plan(lsw_plan* p) {
     for (hipEvent_t e : p->kev)
         if (e) (void)hipEventDestroy(e);
     if (p->h_act_stage) (void)hipHostFree(p->h_act_stage);
-    if (p->rb) (void)rocblas_destroy_handle(p->rb);
     delete p;
 }
 
@@ -1035,26 +1032,39 @@ int check_nrhs(lsw_plan* p, int nrhs) {
 // the xy plane of the window) are inverted in batches, one batch per elimination step of
 // both halves of every subdomain, by blocked Gauss-Jordan: a panel kernel eliminates b
 // columns with row pivoting and the accumulated transformation reaches the other columns as
-// one rank-b update, a batched complex GEMM (rocBLAS).
-int setup3d_factor(lsw_plan* p) {
+// one rank-b update, a batched complex FP64 GEMM on matrix cores (k_f3_update).
+// Twisted block factorisation of every local problem by batched blocked Gauss-Jordan (Phase 2 of
+// Sec. 3): block k is grid line k of a 2D window (s = W, line = true) or xy plane k of a 3D beam
+// (s = W H).  Each elimination step of both halves of every subdomain is one batch of dense
+// blocks S_k = D_k - C G C (padded to the largest s with identity), inverted by blocked
+// Gauss-Jordan: a panel kernel eliminates b columns with row pivoting and the accumulated
+// transformation reaches the other columns as one rank-b update, a batched complex FP64 GEMM on
+// matrix cores (k_f3_update); the middle blocks of all subdomains form the last batch.
+// G_k = S_k^-1 lands column-major in G128 (FP64).
+int batched_gj(lsw_plan* p, c128* G128, bool line) {
     int rc;
-    const int nsub = (int)p->subs.size(), Nz = p->Nz, m = Nz / 2;
-    const int n = p->Smax, b = std::min(32, n);
-    c128* G128 = nullptr;
-    if ((rc = dalloc(p, &G128, p->G_elems)) != LSW_OK) return rc;
-    // batches: step t of half 0 (plane t, from below) and half 1 (plane Nz-1-t, from above), then the middle
+    const int nsub = (int)p->subs.size();
+    const int n = line ? p->Wmax : p->Smax, b = std::min(32, n);
+    auto blocks = [&](const SubDesc& s) { return line ? s.H : p->Nz; };
+    int T = 0;
+    for (const SubDesc& s : p->subs) T = std::max(T, std::max(s.mid, blocks(s) - 1 - s.mid));
+    // batches: step t of half 0 (block t, from below) and half 1 (block H-1-t, from above), then the middles
     std::vector<std::vector<Fact3Item>> batches;
-    for (int t = 0; t < std::max(m, Nz - 1 - m); ++t) {
+    for (int t = 0; t < T; ++t) {
         std::vector<Fact3Item> bt;
         for (int sidx = 0; sidx < nsub; ++sidx) {
+            const int H = blocks(p->subs[sidx]), m = p->subs[sidx].mid;
             if (t < m) bt.push_back(Fact3Item{sidx, t, t > 0 ? t - 1 : -1, -1});
-            if (t < Nz - 1 - m) bt.push_back(Fact3Item{sidx, Nz - 1 - t, -1, t > 0 ? Nz - t : -1});
+            if (t < H - 1 - m) bt.push_back(Fact3Item{sidx, H - 1 - t, -1, t > 0 ? H - t : -1});
         }
-        batches.push_back(bt);
+        if (!bt.empty()) batches.push_back(bt);
     }
     {
         std::vector<Fact3Item> bt;
-        for (int sidx = 0; sidx < nsub; ++sidx) bt.push_back(Fact3Item{sidx, m, m >= 1 ? m - 1 : -1, m + 1 <= Nz - 1 ? m + 1 : -1});
+        for (int sidx = 0; sidx < nsub; ++sidx) {
+            const int H = blocks(p->subs[sidx]), m = p->subs[sidx].mid;
+            bt.push_back(Fact3Item{sidx, m, m >= 1 ? m - 1 : -1, m + 1 <= H - 1 ? m + 1 : -1});
+        }
         batches.push_back(bt);
     }
     std::vector<Fact3Item> all;
@@ -1066,18 +1076,14 @@ int setup3d_factor(lsw_plan* p) {
         maxb = std::max(maxb, bt.size());
     }
     Fact3Item* d_items = nullptr;
-    c128 *ws = nullptr, *Pbar = nullptr, *T = nullptr;
+    c128 *ws = nullptr, *Pbar = nullptr, *Tb = nullptr;
     int* perm = nullptr;
     if ((rc = dalloc(p, &d_items, all.size())) != LSW_OK) return rc;
     if ((rc = dalloc(p, &ws, maxb * n * (size_t)n)) != LSW_OK) return rc;
     if ((rc = dalloc(p, &Pbar, maxb * n * (size_t)b)) != LSW_OK) return rc;
-    if ((rc = dalloc(p, &T, maxb * n * (size_t)b)) != LSW_OK) return rc;
+    if ((rc = dalloc(p, &Tb, maxb * n * (size_t)b)) != LSW_OK) return rc;
     if ((rc = dalloc(p, &perm, maxb * (size_t)n)) != LSW_OK) return rc;
     HIPCK(p, hipMemcpy(d_items, all.data(), sizeof(Fact3Item) * all.size(), hipMemcpyHostToDevice));
-    if (!p->rb) {
-        if (rocblas_create_handle(&p->rb) != rocblas_status_success) return fail(p, LSW_EHIP, "rocblas_create_handle failed");
-    }
-    if (rocblas_set_stream(p->rb, p->stream) != rocblas_status_success) return fail(p, LSW_EHIP, "rocblas_set_stream failed");
     Fact3Args fa{};
     fa.subs = p->d_subs;
     fa.geo = p->geo;
@@ -1086,29 +1092,21 @@ int setup3d_factor(lsw_plan* p) {
     fa.G = G128;
     fa.perm = perm;
     fa.status = p->d_status;
-    const rocblas_double_complex one(1.0, 0.0);
+    fa.line = line ? 1 : 0;
     HIPCK(p, hipStreamSynchronize(p->stream));
     const auto tf = std::chrono::steady_clock::now();
     for (size_t bi = 0; bi < batches.size(); ++bi) {
         const int nb = (int)batches[bi].size();
         fa.items = d_items + boff[bi];
-        HIPCK(p, launch_fact3_build(fa, nb, p->stream));
+        HIPCK(p, line ? launch_fact2_build(fa, nb, p->stream) : launch_fact3_build(fa, nb, p->stream));
         for (int p0 = 0; p0 < n; p0 += b) {
             const int bb = std::min(b, n - p0);
             HIPCK(p, launch_fact3_panel(fa, nb, p0, bb, p->stream));
-            HIPCK(p, launch_fact3_prep(fa, nb, p0, bb, Pbar, T, p->stream));
-            // other columns += Pbar T : columns [0, p0) and [p0 + bb, n)
+            HIPCK(p, launch_fact3_prep(fa, nb, p0, bb, Pbar, Tb, p->stream));
+            // the other columns, [0, p0) and [p0 + bb, n), take the panel's transformation
             const int parts[2][2] = {{0, p0}, {p0 + bb, n - p0 - bb}};
-            for (const auto& pt : parts) {
-                if (pt[1] <= 0) continue;
-                const rocblas_status st = rocblas_zgemm_strided_batched(
-                    p->rb, rocblas_operation_none, rocblas_operation_none, n, pt[1], bb, &one,
-                    reinterpret_cast<const rocblas_double_complex*>(Pbar), n, (rocblas_stride)n * bb,
-                    reinterpret_cast<const rocblas_double_complex*>(T + (size_t)pt[0] * bb), bb, (rocblas_stride)n * bb,
-                    &one, reinterpret_cast<rocblas_double_complex*>(ws + (size_t)pt[0] * n), n,
-                    (rocblas_stride)n * n, nb);
-                if (st != rocblas_status_success) return fail(p, LSW_EHIP, "rocblas_zgemm_strided_batched failed");
-            }
+            for (const auto& pt : parts)
+                HIPCK(p, launch_fact3_update(Pbar, Tb, ws, n, bb, p0, pt[0], pt[1], nb, p->stream));
         }
         HIPCK(p, launch_fact3_finish(fa, nb, p->stream));
     }
@@ -1116,15 +1114,25 @@ int setup3d_factor(lsw_plan* p) {
     p->t_factor_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tf).count();
     dfree(p, ws);
     dfree(p, Pbar);
-    dfree(p, T);
+    dfree(p, Tb);
     dfree(p, perm);
     dfree(p, d_items);
     std::vector<int> status(nsub);
     HIPCK(p, hipMemcpy(status.data(), p->d_status, sizeof(int) * nsub, hipMemcpyDeviceToHost));
     for (int sidx = 0; sidx < nsub; ++sidx)
         if (status[sidx])
-            return fail(p, LSW_ESINGULAR, "zero pivot in the block factorisation of beam (" +
-                                              std::to_string(p->subs[sidx].i) + "," + std::to_string(p->subs[sidx].j) + ")");
+            return fail(p, LSW_ESINGULAR, std::string("zero pivot in the block factorisation of ") +
+                                              (line ? "subdomain (" : "beam (") + std::to_string(p->subs[sidx].i) +
+                                              "," + std::to_string(p->subs[sidx].j) + ")");
+    return LSW_OK;
+}
+
+int setup3d_factor(lsw_plan* p) {
+    int rc;
+    const int nsub = (int)p->subs.size(), Nz = p->Nz;
+    c128* G128 = nullptr;
+    if ((rc = dalloc(p, &G128, p->G_elems)) != LSW_OK) return rc;
+    if ((rc = batched_gj(p, G128, false)) != LSW_OK) return rc;
     const size_t eb = p->precision == LSW_MIXED ? sizeof(c64) : sizeof(c128);
     if (p->gsym) {   // the steps read only the packed blocks
         HIPCK(p, hipMemcpy(p->d_subs, p->subs.data(), sizeof(SubDesc) * p->subs.size(), hipMemcpyHostToDevice));
@@ -1610,30 +1618,7 @@ int setup_impl(lsw_plan* p, const double* d_m, double omega, double h, const lsw
         p->ylds = want + tabb <= (size_t)max_lds ? (p->precision == LSW_MIXED ? y64 : y128) : 0;
         p->ylds128 = y128 + stat128 + tabb <= (size_t)max_lds ? y128 : 0;
     }
-    const size_t static_lds = sizeof(c128) * kMaxWindow + sizeof(int) * kMaxWindow + 64;
-    const size_t lds_bytes = sizeof(c128) * (size_t)p->Wmax * p->Wmax;
-    const bool use_lds = lds_bytes + static_lds <= (size_t)max_lds;
-    FactorArgs fa{};
-    fa.subs = p->d_subs;
-    fa.geo = p->geo;
-    fa.G = G128;
-    fa.status = p->d_status;
-    if (!use_lds) {
-        if ((rc = dalloc(p, &fa.work, (size_t)nsub * 2 * p->Wmax * p->Wmax)) != LSW_OK) return rc;
-        fa.work_stride = (size_t)p->Wmax * p->Wmax;
-    }
-    HIPCK(p, hipStreamSynchronize(p->stream));
-    const auto tf = std::chrono::steady_clock::now();
-    HIPCK(p, launch_factor(fa, nsub, use_lds, use_lds ? lds_bytes : 0, p->stream));
-    HIPCK(p, hipStreamSynchronize(p->stream));
-    p->t_factor_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tf).count();
-    if (fa.work) dfree(p, fa.work);
-    std::vector<int> status(nsub);
-    HIPCK(p, hipMemcpy(status.data(), p->d_status, sizeof(int) * nsub, hipMemcpyDeviceToHost));
-    for (int s = 0; s < nsub; ++s)
-        if (status[s])
-            return fail(p, LSW_ESINGULAR, "zero pivot in the block factorisation of subdomain (" +
-                                              std::to_string(p->subs[s].i) + "," + std::to_string(p->subs[s].j) + ")");
+    if ((rc = batched_gj(p, G128, true)) != LSW_OK) return rc;
     // Q = A_ij^-1 restricted to the trace lines: one unit solve per slot of an interior side
     if (p->sweep_mode == LSW_SWEEP_COMPRESSED) {
         // polarization terms of every sweep solve, grouped by window point for the final solve

@@ -1,9 +1,5 @@
 // HIP kernels of the L-sweeps library (gfx950).
 //
-//  k_factor   batched block-tridiagonal LU of every local problem (Phase 2, Sec. 3):
-//             S_0 = D_0, G_k = S_k^-1, S_{k+1} = D_{k+1} - C_k G_k C_k, one workgroup per
-//             subdomain, the W x W block held in LDS and inverted by Gauss-Jordan with
-//             partial pivoting in FP64; G_k stored column-major in complex64/complex128.
 //  k_chain    a batch of independent local solves A_ij U = g by block forward/back
 //             substitution streaming G_k from HBM (stage 1, the final z solve, the unit
 //             solves that build Q, and every front of the chained sweep mode).  The
@@ -57,161 +53,6 @@ __device__ inline c128 diag_coef(const c128* tab, int tx, int Px, int ty, int Py
     c128 sy = tab[ty + Py + b + 1] + tab[ty + Py + b];
     c128 d = ih2 * (sx * tab[ty + b] + sy * tab[tx + a]);
     return d - om2m * (tab[tx + a] * tab[ty + b]);
-}
-
-// ------------------------------------------------------------------ K3: factorisation
-// In-place Gauss-Jordan inversion of the W x W block S (row-major) with row pivoting.
-template <int NT>
-__device__ void gj_invert(c128* S, int W, c128* colp, int* perm, int* sh_piv, int* sh_sing) {
-    constexpr int NTX = 32, NTY = NT / 32;
-    const int tid = threadIdx.x, tx = tid % NTX, ty = tid / NTX;
-    for (int p = 0; p < W; ++p) {
-        if (tid < 64) {
-            double best = -1.0;
-            int bi = p;
-            for (int r = p + tid; r < W; r += 64) {
-                const double v = abs2(S[r * W + p]);
-                if (v > best) { best = v; bi = r; }
-            }
-            for (int off = 32; off > 0; off >>= 1) {
-                const double ob = __shfl_xor(best, off);
-                const int oi = __shfl_xor(bi, off);
-                if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
-            }
-            if (tid == 0) {
-                *sh_piv = bi;
-                perm[p] = bi;
-                if (!(best > 0.0)) *sh_sing = 1;
-            }
-        }
-        __syncthreads();
-        const int piv = *sh_piv;
-        if (piv != p)
-            for (int c = tid; c < W; c += NT) {
-                const c128 t = S[p * W + c];
-                S[p * W + c] = S[piv * W + c];
-                S[piv * W + c] = t;
-            }
-        __syncthreads();
-        const c128 inv = cinv(S[p * W + p]);
-        for (int r = tid; r < W; r += NT) colp[r] = S[r * W + p];
-        __syncthreads();
-        for (int c = tid; c < W; c += NT) S[p * W + c] = (c == p) ? inv : S[p * W + c] * inv;
-        __syncthreads();
-        for (int r = ty; r < W; r += NTY) {
-            if (r == p) continue;
-            const c128 f = colp[r];
-            for (int c = tx; c < W; c += NTX) {
-                if (c == p) S[r * W + c] = -(f * inv);
-                else S[r * W + c] = S[r * W + c] - f * S[p * W + c];
-            }
-        }
-        __syncthreads();
-    }
-    // undo the row interchanges as column interchanges, in reverse order
-    for (int p = W - 1; p >= 0; --p) {
-        const int pv = perm[p];
-        if (pv != p)
-            for (int r = tid; r < W; r += NT) {
-                const c128 t = S[r * W + p];
-                S[r * W + p] = S[r * W + pv];
-                S[r * W + pv] = t;
-            }
-        __syncthreads();
-    }
-}
-
-// D_k (tridiagonal along x) into S, minus sum over the given neighbour terms C G C.
-template <int NT>
-__device__ void build_block(c128* S, const SubDesc& s, const FactorArgs& a, int k, const c128* colA,
-                            const c128* GA, bool GA_rowmajor, const c128* colB, const c128* GB) {
-    constexpr int NTX = 32, NTY = NT / 32;
-    const int tid = threadIdx.x, tx = tid % NTX, ty = tid / NTX, W = s.W, H = s.H;
-    const c128* tab = a.geo.tab;
-    const double ih2 = 1.0 / (a.geo.h * a.geo.h), om2 = a.geo.omega * a.geo.omega;
-    const double* mrow = a.geo.m + (size_t)(s.wy0 + k) * a.geo.Nx + s.wx0;
-    for (int r = ty; r < W; r += NTY)
-        for (int c = tx; c < W; c += NTX) {
-            c128 val = mk(0.0, 0.0);
-            if (r == c) val = diag_coef(tab, s.tx, W, s.ty, H, c, k, ih2, om2 * mrow[c]);
-            else if (c == r + 1) val = coup_x(tab, s.tx, W, s.ty, r, k, ih2);
-            else if (r == c + 1) val = coup_x(tab, s.tx, W, s.ty, c, k, ih2);
-            if (GA) val = val - colA[r] * (GA_rowmajor ? GA[r * W + c] : GA[(size_t)c * W + r]) * colA[c];
-            if (GB) val = val - colB[r] * GB[(size_t)c * W + r] * colB[c];
-            S[r * W + c] = val;
-        }
-}
-
-// Twisted block factorisation of every local problem, one workgroup per (subdomain, half).
-// Half 0 eliminates upwards from block row 0:  S_0 = D_0, S_k = D_k - C_{k-1} G_{k-1} C_{k-1};
-// half 1 eliminates downwards from row H-1:  S_{H-1} = D_{H-1}, S_k = D_k - C_k G_{k+1} C_k;
-// both stop before the middle row m, which k_factor_mid completes.  G_k = S_k^-1 is stored
-// column-major; the previous block of the half stays in S (LDS) for the next Schur update.
-template <int NT, bool kLds>
-__global__ __launch_bounds__(NT) void k_factor(FactorArgs a) {
-    extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ c128 colp[kMaxWindow];
-    __shared__ int perm[kMaxWindow];
-    __shared__ int sh_piv, sh_sing;
-    const SubDesc s = a.subs[blockIdx.x];
-    const int h = blockIdx.y;
-    const int W = s.W, H = s.H, m = s.mid, tid = threadIdx.x;
-    constexpr int NTX = 32, NTY = NT / 32;
-    const int tx = tid % NTX, ty = tid / NTX;
-    c128* S = kLds ? reinterpret_cast<c128*>(smem) : a.work + ((size_t)blockIdx.x * 2 + h) * a.work_stride;
-    const c128* tab = a.geo.tab;
-    const double ih2 = 1.0 / (a.geo.h * a.geo.h);
-    c128* G = reinterpret_cast<c128*>(a.G) + s.g_off;
-    if (tid == 0) sh_sing = 0;
-    const int dk = h == 0 ? 1 : -1;
-    bool first = true;
-    for (int k = h == 0 ? 0 : H - 1; h == 0 ? k < m : k > m; k += dk) {
-        if (!first)
-            for (int x = tid; x < W; x += NT) colp[x] = coup_y(tab, s.tx, s.ty, H, x, h == 0 ? k - 1 : k, ih2);
-        __syncthreads();
-        build_block<NT>(S, s, a, k, colp, first ? nullptr : S, true, nullptr, nullptr);
-        __syncthreads();
-        gj_invert<NT>(S, W, colp, perm, &sh_piv, &sh_sing);
-        c128* Gk = G + (size_t)k * W * W;
-        for (int c = ty; c < W; c += NTY)
-            for (int t = tx; t < W; t += NTX) Gk[(size_t)c * W + t] = S[t * W + c];
-        __syncthreads();
-        first = false;
-    }
-    if (tid == 0 && sh_sing) a.status[blockIdx.x] = 1;
-}
-
-// Middle block of the twisted factorisation:
-// S_m = D_m - C_{m-1} G_{m-1} C_{m-1} - C_m G_{m+1} C_m,  G_m = S_m^-1.
-template <int NT, bool kLds>
-__global__ __launch_bounds__(NT) void k_factor_mid(FactorArgs a) {
-    extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ c128 colA[kMaxWindow], colB[kMaxWindow];
-    __shared__ int perm[kMaxWindow];
-    __shared__ int sh_piv, sh_sing;
-    const SubDesc s = a.subs[blockIdx.x];
-    const int W = s.W, H = s.H, m = s.mid, tid = threadIdx.x;
-    constexpr int NTX = 32, NTY = NT / 32;
-    const int tx = tid % NTX, ty = tid / NTX;
-    c128* S = kLds ? reinterpret_cast<c128*>(smem) : a.work + (size_t)blockIdx.x * 2 * a.work_stride;
-    const c128* tab = a.geo.tab;
-    const double ih2 = 1.0 / (a.geo.h * a.geo.h);
-    c128* G = reinterpret_cast<c128*>(a.G) + s.g_off;
-    if (tid == 0) sh_sing = 0;
-    const bool below = m >= 1, above = m + 1 <= H - 1;
-    for (int x = tid; x < W; x += NT) {
-        if (below) colA[x] = coup_y(tab, s.tx, s.ty, H, x, m - 1, ih2);
-        if (above) colB[x] = coup_y(tab, s.tx, s.ty, H, x, m, ih2);
-    }
-    __syncthreads();
-    build_block<NT>(S, s, a, m, colA, below ? G + (size_t)(m - 1) * W * W : nullptr, false, colB,
-                    above ? G + (size_t)(m + 1) * W * W : nullptr);
-    __syncthreads();
-    gj_invert<NT>(S, W, colA, perm, &sh_piv, &sh_sing);
-    c128* Gm = G + (size_t)m * W * W;
-    for (int c = ty; c < W; c += NTY)
-        for (int t = tx; t < W; t += NTX) Gm[(size_t)c * W + t] = S[t * W + c];
-    if (tid == 0 && sh_sing) a.status[blockIdx.x] = 1;
 }
 
 // ------------------------------------------------------------------ K4/K5: one sweep front
@@ -1689,24 +1530,6 @@ __global__ void k_mass_gradient(const c128* lam, const c128* u, int nrhs, Geomet
 
 // ------------------------------------------------------------------ launchers
 static inline unsigned blocks_for(size_t n, unsigned bs) { return (unsigned)((n + bs - 1) / bs); }
-
-hipError_t launch_factor(const FactorArgs& a, int nsub, bool use_lds, size_t lds_bytes, hipStream_t st) {
-    constexpr int NT = 1024;
-    if (use_lds) {
-        hipError_t e = hipFuncSetAttribute((const void*)k_factor<NT, true>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
-        if (e != hipSuccess) return e;
-        e = hipFuncSetAttribute((const void*)k_factor_mid<NT, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)lds_bytes);
-        if (e != hipSuccess) return e;
-        k_factor<NT, true><<<dim3(nsub, 2), NT, lds_bytes, st>>>(a);
-        k_factor_mid<NT, true><<<nsub, NT, lds_bytes, st>>>(a);
-    } else {
-        k_factor<NT, false><<<dim3(nsub, 2), NT, 0, st>>>(a);
-        k_factor_mid<NT, false><<<nsub, NT, 0, st>>>(a);
-    }
-    return hipGetLastError();
-}
 
 // prefetch depth: as many blocks in flight as the 128-VGPR budget of a 1024-thread
 // workgroup allows (complex64: 2 floats, complex128: 4 per element)

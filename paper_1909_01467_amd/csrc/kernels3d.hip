@@ -2,8 +2,12 @@
 //
 //  k_f3_build   S_k = D_k - C G C (App. A 7-point operator restricted to one xy plane of a
 //               beam, minus the Schur terms of the planes already eliminated), batched
-//  k_f3_panel   Gauss-Jordan elimination of one column panel of every S_k (row pivoting)
-//  k_f3_prep    operands of the rank-b update of the other columns (a batched complex GEMM)
+//  k_f2_build   the same for the line blocks of the 2D local problems (5-point operator)
+//  k_f3_panel   Gauss-Jordan elimination of one column panel of every S_k (row pivoting), in
+//               register sub-panels of 4 columns; k_f3_laswp takes its row interchanges to the
+//               other columns
+//  k_f3_prep    operands of the rank-b update of the other columns
+//  k_f3_update  that update, a batched complex FP64 GEMM on matrix cores (v_mfma_f64_16x16x4f64)
 //  k_f3_finish  column interchanges and the copy of G_k = S_k^-1 into the factor pool
 //  k_rhs3       right-hand sides of the local solves of a front (stage 1 or eq. DiscPol2)
 //  k_step3      one plane of the twisted block substitution of every solve of a front: each
@@ -101,89 +105,221 @@ __global__ void k_f3_build(Fact3Args a) {
     A[idx] = v;
 }
 
-// Gauss-Jordan on columns [p0, p0 + b) of every matrix: for each column j, choose the pivot in
-// rows >= j, swap full rows, scale the pivot row, eliminate the column from every other row.
-// Only the panel columns are updated here; the other columns receive the accumulated
-// transformation as a rank-b update.  One workgroup per matrix.
+// 2D line blocks (App. A 5-point operator restricted to grid line k of the window, x fastest):
+// S_k = D_k - C_{k-1} G_below C_{k-1} - C_k G_above C_k with C the diagonal couplings between
+// neighbouring lines, the same elimination as in 3D with lines for planes.
+__device__ inline c128 l2x(const c128* tab, const SubDesc& s, int a, int k, double ih2) {
+    return -ih2 * (tab[s.tx + s.W + a + 1] * tab[s.ty + k]);      // (a, k)-(a+1, k)
+}
+__device__ inline c128 l2y(const c128* tab, const SubDesc& s, int a, int k, double ih2) {
+    return -ih2 * (tab[s.ty + s.H + k + 1] * tab[s.tx + a]);      // (a, k)-(a, k+1)
+}
+
+__global__ void k_f2_build(Fact3Args a) {
+    const Fact3Item it = a.items[blockIdx.y];
+    const SubDesc s = a.subs[it.sub];
+    const int n = a.n, W = s.W;
+    const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (size_t)n * n) return;
+    const int p = (int)(idx % n), q = (int)(idx / n);
+    c128* A = a.ws + (size_t)blockIdx.y * n * n;
+    if (p >= W || q >= W) {
+        A[idx] = mk(p == q ? 1.0 : 0.0, 0.0);
+        return;
+    }
+    const Geometry& g = a.geo;
+    const c128* tab = g.tab;
+    const double ih2 = 1.0 / (g.h * g.h);
+    const int k = it.k;
+    c128 v = mk(0.0, 0.0);
+    if (p == q) {
+        const double m = g.m[(size_t)(s.wy0 + k) * g.Nx + s.wx0 + p];
+        const c128 sx = tab[s.tx + W + p + 1] + tab[s.tx + W + p];
+        const c128 sy = tab[s.ty + s.H + k + 1] + tab[s.ty + s.H + k];
+        v = ih2 * (sx * tab[s.ty + k] + sy * tab[s.tx + p]) - (g.omega * g.omega * m) * (tab[s.tx + p] * tab[s.ty + k]);
+    } else if (p - q == 1 || q - p == 1) {
+        v = l2x(tab, s, min(p, q), k, ih2);
+    }
+    const size_t WW = (size_t)W * W;
+    if (it.below >= 0) {
+        const c128 cp = l2y(tab, s, p, k - 1, ih2), cq = l2y(tab, s, q, k - 1, ih2);
+        v = v - cp * a.G[s.g_off + (size_t)it.below * WW + (size_t)q * W + p] * cq;
+    }
+    if (it.above >= 0) {
+        const c128 cp = l2y(tab, s, p, k, ih2), cq = l2y(tab, s, q, k, ih2);
+        v = v - cp * a.G[s.g_off + (size_t)it.above * WW + (size_t)q * W + p] * cq;
+    }
+    A[idx] = v;
+}
+
+// Gauss-Jordan on columns [p0, p0 + b) of every matrix (b <= 32): for each column j, choose the
+// pivot in rows >= j, interchange rows j and the pivot row within the panel, scale the pivot row,
+// eliminate the column from every other row.  One workgroup of 1024 lanes per matrix; lane t owns
+// rows t + 1024 r (r < RPT).  The panel is processed in sub-panels of 4 columns held in registers:
+// their pivot steps touch only registers and the pivot rows of the other panel columns, and the
+// other panel columns then receive the 4 steps at once as a rank-4 update (A[:, c] += (X - E) A[J, c],
+// X the sub-panel after elimination, J its pivot rows), so the panel is read and written once per
+// sub-panel instead of once per column.  The interchanges reach the columns outside the panel
+// afterwards (k_f3_laswp), and those columns the whole panel's transformation as one rank-b update.
+template <int RPT>
 __global__ __launch_bounds__(1024) void k_f3_panel(Fact3Args a, int p0, int b) {
-    constexpr int NT = 1024;
-    extern __shared__ __align__(16) unsigned char smem[];
-    c128* colj = reinterpret_cast<c128*>(smem);   // [n]
-    __shared__ c128 rowj[64];
+    constexpr int NT = 1024, SB = 4;
     __shared__ double wbest[NT / 64];
     __shared__ int wbi[NT / 64];
+    __shared__ c128 rowx[2][SB];       // the sub-panel entries of the two rows being interchanged
+    __shared__ c128 prow[SB];          // the scaled pivot row over the sub-panel
+    __shared__ c128 trow[SB][32];      // the sub-panel's pivot rows over the other panel columns
     __shared__ int sh_piv, sh_sing;
     const int n = a.n, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     c128* A = a.ws + (size_t)blockIdx.x * n * n;
     int* perm = a.perm + (size_t)blockIdx.x * n;
     if (tid == 0) sh_sing = 0;
-    for (int jj = 0; jj < b; ++jj) {
-        const int j = p0 + jj;
-        double best = -1.0;
-        int bi = j;
-        for (int i = j + tid; i < n; i += NT) {
-            const double v = abs2(A[i + (size_t)j * n]);
-            if (v > best) {
-                best = v;
-                bi = i;
-            }
+    for (int s0 = 0; s0 < b; s0 += SB) {
+        const int sb = min(SB, b - s0), cs = p0 + s0;   // sub-panel columns [cs, cs + sb)
+        c128 x[RPT][SB];
+#pragma unroll
+        for (int r = 0; r < RPT; ++r) {
+            const int i = tid + NT * r;
+#pragma unroll
+            for (int c = 0; c < SB; ++c) x[r][c] = (i < n && c < sb) ? A[i + (size_t)(cs + c) * n] : mk(0.0, 0.0);
         }
-        for (int off = 32; off > 0; off >>= 1) {
-            const double ob = __shfl_xor(best, off);
-            const int oi = __shfl_xor(bi, off);
-            if (ob > best || (ob == best && oi < bi)) {
-                best = ob;
-                bi = oi;
-            }
-        }
-        if (lane == 0) {
-            wbest[wv] = best;
-            wbi[wv] = bi;
-        }
-        __syncthreads();
-        if (tid == 0) {
-            double bb = wbest[0];
-            int ii = wbi[0];
-            for (int w = 1; w < NT / 64; ++w)
-                if (wbest[w] > bb || (wbest[w] == bb && wbi[w] < ii)) {
-                    bb = wbest[w];
-                    ii = wbi[w];
+#pragma unroll
+        for (int c = 0; c < SB; ++c) {   // unrolled: the register sub-panel is indexed by constants
+            if (c >= sb) break;           // (sb is the same for the whole workgroup)
+            const int j = cs + c;
+            double best = -1.0;
+            int bi = j;
+#pragma unroll
+            for (int r = 0; r < RPT; ++r) {
+                const int i = tid + NT * r;
+                const double v = abs2(x[r][c]);
+                if (i >= j && i < n && v > best) {
+                    best = v;
+                    bi = i;
                 }
-            sh_piv = ii;
-            perm[j] = ii;
-            if (!(bb > 0.0)) sh_sing = 1;
-        }
-        __syncthreads();
-        const int r = sh_piv;
-        if (r != j)
-            for (int c = tid; c < n; c += NT) {
-                const c128 t = A[j + (size_t)c * n];
-                A[j + (size_t)c * n] = A[r + (size_t)c * n];
-                A[r + (size_t)c * n] = t;
             }
-        __syncthreads();
-        const c128 piv = A[j + (size_t)j * n];
-        const c128 inv = abs2(piv) > 0.0 ? cinv(piv) : mk(0.0, 0.0);
-        for (int i = tid; i < n; i += NT) colj[i] = A[i + (size_t)j * n];
-        if (tid < b) {
-            const int c = p0 + tid;
-            const c128 v = (c == j) ? inv : A[j + (size_t)c * n] * inv;
-            rowj[tid] = v;
-            A[j + (size_t)c * n] = v;
+            for (int off = 32; off > 0; off >>= 1) {
+                const double ob = __shfl_xor(best, off);
+                const int oi = __shfl_xor(bi, off);
+                if (ob > best || (ob == best && oi < bi)) {
+                    best = ob;
+                    bi = oi;
+                }
+            }
+            if (lane == 0) {
+                wbest[wv] = best;
+                wbi[wv] = bi;
+            }
+            __syncthreads();
+            if (tid == 0) {
+                double bb = wbest[0];
+                int ii = wbi[0];
+                for (int w = 1; w < NT / 64; ++w)
+                    if (wbest[w] > bb || (wbest[w] == bb && wbi[w] < ii)) {
+                        bb = wbest[w];
+                        ii = wbi[w];
+                    }
+                sh_piv = ii;
+                perm[j] = ii;
+                if (!(bb > 0.0)) sh_sing = 1;
+            }
+            __syncthreads();
+            const int pr = sh_piv;
+            // rows j and pr: their sub-panel entries through LDS, the other panel columns in place
+#pragma unroll
+            for (int r = 0; r < RPT; ++r) {
+                const int i = tid + NT * r;
+                if (i == j || i == pr)
+#pragma unroll
+                    for (int cc = 0; cc < SB; ++cc) rowx[i == j ? 0 : 1][cc] = x[r][cc];
+            }
+            if (pr != j && tid < b && (tid < s0 || tid >= s0 + sb)) {
+                c128* e1 = A + j + (size_t)(p0 + tid) * n;
+                c128* e2 = A + pr + (size_t)(p0 + tid) * n;
+                const c128 t = *e1;
+                *e1 = *e2;
+                *e2 = t;
+            }
+            __syncthreads();
+            // after the interchange row j holds what row pr held
+            const c128 piv = rowx[pr != j ? 1 : 0][c];
+            const c128 inv = abs2(piv) > 0.0 ? cinv(piv) : mk(0.0, 0.0);
+            if (tid < SB) prow[tid] = tid == c ? inv : rowx[pr != j ? 1 : 0][tid] * inv;
+#pragma unroll
+            for (int r = 0; r < RPT; ++r) {
+                const int i = tid + NT * r;
+                if (pr != j && i == pr)
+#pragma unroll
+                    for (int cc = 0; cc < SB; ++cc) x[r][cc] = rowx[0][cc];   // row pr takes row j's old entries
+            }
+            __syncthreads();
+#pragma unroll
+            for (int r = 0; r < RPT; ++r) {
+                const int i = tid + NT * r;
+                if (i == j) {
+#pragma unroll
+                    for (int cc = 0; cc < SB; ++cc) x[r][cc] = prow[cc];
+                } else {
+                    const c128 f = x[r][c];
+#pragma unroll
+                    for (int cc = 0; cc < SB; ++cc) x[r][cc] = cc == c ? -(f * inv) : x[r][cc] - f * prow[cc];
+                }
+            }
+            __syncthreads();   // rowx / prow are rewritten by the next pivot step
+        }
+        // write the sub-panel back; the other panel columns (before and after it) take its
+        // transformation X: A[i, c] += X[i, :] T[:, c] for the rows i outside [cs, cs + sb) and
+        // A[i, c] = X[i, :] T[:, c] for those inside, T = rows [cs, cs + sb) of those columns (never
+        // X - E: with pivots far from 1, 1/pivot - 1 would cancel the pivot rows' digits)
+#pragma unroll
+        for (int r = 0; r < RPT; ++r) {
+            const int i = tid + NT * r;
+            if (i < n)
+#pragma unroll
+                for (int c = 0; c < SB; ++c)
+                    if (c < sb) A[i + (size_t)(cs + c) * n] = x[r][c];
+        }
+        for (int e = tid; e < SB * 32; e += NT) {
+            const int cc = e / 32, col = e % 32;
+            trow[cc][col] = (cc < sb && col < b && (col < s0 || col >= s0 + sb)) ? A[cs + cc + (size_t)(p0 + col) * n]
+                                                                                  : mk(0.0, 0.0);
         }
         __syncthreads();
-        for (int i = tid; i < n; i += NT) {
-            if (i == j) continue;
-            const c128 f = colj[i];
-            for (int cc = 0; cc < b; ++cc) {
-                const int c = p0 + cc;
-                c128* e = A + i + (size_t)c * n;
-                *e = (c == j) ? -(f * inv) : *e - f * rowj[cc];
+#pragma unroll
+        for (int r = 0; r < RPT; ++r) {
+            const int i = tid + NT * r;
+            if (i >= n) continue;
+            const bool pivot_row = i >= cs && i < cs + sb;
+            for (int col = 0; col < b; ++col) {
+                if (col >= s0 && col < s0 + sb) continue;
+                c128* e = A + i + (size_t)(p0 + col) * n;
+                c128 v = pivot_row ? mk(0.0, 0.0) : *e;
+#pragma unroll
+                for (int cc = 0; cc < SB; ++cc) v = cmac(v, x[r][cc], trow[cc][col]);
+                *e = v;
             }
         }
         __syncthreads();
     }
     if (tid == 0 && sh_sing) a.status[a.items[blockIdx.x].sub] = 1;
+}
+
+// The row interchanges of panel [p0, p0 + b), in order, applied to every column outside the panel
+// (one lane per column).
+__global__ void k_f3_laswp(Fact3Args a, int p0, int b) {
+    const int n = a.n;
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n || (c >= p0 && c < p0 + b)) return;
+    c128* col = a.ws + (size_t)blockIdx.y * n * n + (size_t)c * n;
+    const int* perm = a.perm + (size_t)blockIdx.y * n;
+    for (int j = p0; j < p0 + b; ++j) {
+        const int r = perm[j];
+        if (r != j) {
+            const c128 t = col[j];
+            col[j] = col[r];
+            col[r] = t;
+        }
+    }
 }
 
 __global__ void k_f3_prep(Fact3Args a, int p0, int b, c128* Pbar, c128* T) {
@@ -193,11 +329,9 @@ __global__ void k_f3_prep(Fact3Args a, int p0, int b, c128* Pbar, c128* T) {
     const c128* A = a.ws + (size_t)blockIdx.y * n * n;
     c128* P = Pbar + (size_t)blockIdx.y * n * b;
     c128* Tb = T + (size_t)blockIdx.y * n * b;
-    {   // Pbar[i, cc] = A[i, p0 + cc] - (i == p0 + cc)
+    {   // P[i, cc] = A[i, p0 + cc]: the panel's transformation, column cc
         const int i = (int)(idx % n), cc = (int)(idx / n);
-        c128 v = A[i + (size_t)(p0 + cc) * n];
-        if (i == p0 + cc) v.re -= 1.0;
-        P[idx] = v;
+        P[idx] = A[i + (size_t)(p0 + cc) * n];
     }
     {   // T[cc, c] = A[p0 + cc, c]
         const int cc = (int)(idx % b), c = (int)(idx / b);
@@ -205,10 +339,95 @@ __global__ void k_f3_prep(Fact3Args a, int p0, int b, c128* Pbar, c128* T) {
     }
 }
 
+// The rank-b update of a blocked Gauss-Jordan step on matrix cores: for every matrix of the batch
+// and c in [0, m), W[i, c0 + c] += P[i, :] T[:, c0 + c] for the rows i outside the panel's pivot rows
+// [j0, j0 + b) and W[i, c0 + c] = P[i, :] T[:, c0 + c] for those inside (P = the panel's
+// transformation, n x b column-major, ld n; T = its pivot rows of all columns, b x n, ld b).  The
+// pivot rows are overwritten, not updated by (P - E) T: the diagonal of P holds 1/pivot, and
+// 1/pivot - 1 would cancel their digits when the pivots are far from 1.  One workgroup of four waves owns a 64 x 64 tile
+// of W; each wave a 32 x 32 quarter as 2 x 2 blocks of 16 x 16 accumulated by
+// v_mfma_f64_16x16x4f64 over k in steps of 4.  A complex block product is four real ones,
+// Re += Pr Tr + (-Pi) Ti, Im += Pr Ti + Pi Tr.  Lane l holds P[16-row block row l % 16][k0 + l / 16]
+// and T[k0 + l / 16][16-column block column l % 16], and accumulator entry v of lane l is row
+// l / 16 + 4 v, column l % 16 of its block (the
+// operand and result layout of the FP64 16x16x4 instruction; the FP32 one places rows 4 (l / 16) + v).
+// The tile of W is read once into the accumulators and written once.
+typedef double mfd4 __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(256) void k_f3_update(const c128* __restrict__ P, const c128* __restrict__ T,
+                                                   c128* __restrict__ Wm, int n, int b, int j0, int c0, int m) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int li = lane & 15, lk = lane >> 4;
+    const int r0 = blockIdx.x * 64 + 32 * (wv & 1);
+    const int q0 = blockIdx.y * 64 + 32 * (wv >> 1);   // column offset within [0, m)
+    const size_t z = blockIdx.z;
+    const c128* Pz = P + z * (size_t)n * b;
+    const c128* Tz = T + z * (size_t)n * b;
+    c128* Wz = Wm + z * (size_t)n * n;
+    mfd4 acc_re[2][2], acc_im[2][2];
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj) {
+            const int col = q0 + 16 * bj + li;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = r0 + 16 * bi + lk + 4 * v;
+                c128 w = mk(0.0, 0.0);
+                if (row < n && col < m && (row < j0 || row >= j0 + b)) w = Wz[row + (size_t)(c0 + col) * n];
+                acc_re[bi][bj][v] = w.re;
+                acc_im[bi][bj][v] = w.im;
+            }
+        }
+#pragma unroll
+    for (int k0 = 0; k0 < 32; k0 += 4) {
+        if (k0 >= b) break;
+        const int k = k0 + lk;
+        double ar[2], ai[2], an[2], br[2], bim[2];
+#pragma unroll
+        for (int bi = 0; bi < 2; ++bi) {
+            const int row = r0 + 16 * bi + li;
+            c128 v = mk(0.0, 0.0);
+            if (k < b && row < n) v = Pz[row + (size_t)k * n];
+            ar[bi] = v.re;
+            ai[bi] = v.im;
+            an[bi] = -v.im;
+        }
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj) {
+            const int col = q0 + 16 * bj + li;
+            c128 v = mk(0.0, 0.0);
+            if (k < b && col < m) v = Tz[k + (size_t)(c0 + col) * b];
+            br[bj] = v.re;
+            bim[bj] = v.im;
+        }
+#pragma unroll
+        for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+            for (int bj = 0; bj < 2; ++bj) {
+                acc_re[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[bi], br[bj], acc_re[bi][bj], 0, 0, 0);
+                acc_re[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(an[bi], bim[bj], acc_re[bi][bj], 0, 0, 0);
+                acc_im[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[bi], bim[bj], acc_im[bi][bj], 0, 0, 0);
+                acc_im[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[bi], br[bj], acc_im[bi][bj], 0, 0, 0);
+            }
+    }
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj) {
+            const int col = q0 + 16 * bj + li;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = r0 + 16 * bi + lk + 4 * v;
+                if (row < n && col < m) Wz[row + (size_t)(c0 + col) * n] = mk(acc_re[bi][bj][v], acc_im[bi][bj][v]);
+            }
+        }
+}
+
 __global__ __launch_bounds__(1024) void k_f3_finish(Fact3Args a) {
     const Fact3Item it = a.items[blockIdx.x];
     const SubDesc s = a.subs[it.sub];
-    const int n = a.n, S = s.W * s.H, tid = threadIdx.x;
+    const int n = a.n, S = a.line ? s.W : s.W * s.H, tid = threadIdx.x;
     c128* A = a.ws + (size_t)blockIdx.x * n * n;
     const int* perm = a.perm + (size_t)blockIdx.x * n;
     for (int j = n - 1; j >= 0; --j) {
@@ -221,7 +440,7 @@ __global__ __launch_bounds__(1024) void k_f3_finish(Fact3Args a) {
             }
         __syncthreads();
     }
-    c128* G = a.G + s.g_off + (size_t)it.k * S * S;
+    c128* G = a.G + s.g_off + (size_t)it.k * S * S;   // S = W (2D lines) or W H (3D planes)
     for (size_t idx = tid; idx < (size_t)S * S; idx += blockDim.x) {
         const int p = (int)(idx % S), q = (int)(idx / S);
         G[idx] = A[p + (size_t)q * n];
@@ -681,16 +900,33 @@ hipError_t launch_fact3_build(const Fact3Args& a, int nbatch, hipStream_t st) {
     return hipGetLastError();
 }
 
+hipError_t launch_fact2_build(const Fact3Args& a, int nbatch, hipStream_t st) {
+    k_f2_build<<<dim3(nblk((size_t)a.n * a.n, 256), nbatch), 256, 0, st>>>(a);
+    return hipGetLastError();
+}
+
 hipError_t launch_fact3_panel(const Fact3Args& a, int nbatch, int p0, int b, hipStream_t st) {
-    const size_t lds = sizeof(c128) * (size_t)a.n;
-    hipError_t e = hipFuncSetAttribute((const void*)k_f3_panel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (b > 32 || a.n > 4096) return hipErrorInvalidValue;
+    if (a.n <= 1024) k_f3_panel<1><<<nbatch, 1024, 0, st>>>(a, p0, b);
+    else if (a.n <= 2048) k_f3_panel<2><<<nbatch, 1024, 0, st>>>(a, p0, b);
+    else k_f3_panel<4><<<nbatch, 1024, 0, st>>>(a, p0, b);
+    hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    k_f3_panel<<<nbatch, 1024, lds, st>>>(a, p0, b);
+    k_f3_laswp<<<dim3((a.n + 255) / 256, nbatch), 256, 0, st>>>(a, p0, b);
     return hipGetLastError();
 }
 
 hipError_t launch_fact3_prep(const Fact3Args& a, int nbatch, int p0, int b, c128* Pbar, c128* T, hipStream_t st) {
     k_f3_prep<<<dim3(nblk((size_t)a.n * b, 256), nbatch), 256, 0, st>>>(a, p0, b, Pbar, T);
+    return hipGetLastError();
+}
+
+hipError_t launch_fact3_update(const c128* P, const c128* T, c128* W, int n, int b, int j0, int c0, int m,
+                               int nbatch, hipStream_t st) {
+    if (m <= 0 || b <= 0) return hipSuccess;
+    if (b > 32) return hipErrorInvalidValue;   // one pass of at most 32 columns of k
+    const dim3 grid((n + 63) / 64, (m + 63) / 64, nbatch);
+    k_f3_update<<<grid, 256, 0, st>>>(P, T, W, n, b, j0, c0, m);
     return hipGetLastError();
 }
 

@@ -7,15 +7,6 @@ namespace lsw {
 
 static constexpr int kMaxWindow = 256;   // largest local window edge the kernels accept
 
-struct FactorArgs {
-    const SubDesc* subs;
-    Geometry geo;
-    void* G;              // factor pool (complex64 or complex128)
-    c128* work;           // global workspace (only when the block does not fit in LDS)
-    size_t work_stride;   // elements per (subdomain, half) in work
-    int* status;          // per subdomain: 1 if a zero pivot was met
-};
-
 struct ChainArgs {
     const SolveDesc* descs;
     const SubDesc* subs;
@@ -94,8 +85,6 @@ struct GsArgs {
     c128* partial;     // optional [nrhs][nblk] workgroup partials of the norm
 };
 
-// twisted block factorisation (complex128 factors); work: 2 blocks per subdomain when not in LDS
-hipError_t launch_factor(const FactorArgs& a, int nsub, bool use_lds, size_t lds_bytes, hipStream_t st);
 // ept = max over the launched windows of ceil(W / floor(1024 / W)) (elements per thread)
 // Two launches (forward halves, then middle + backward halves) of 2 workgroups per solve.
 // cs: 0 stage 1, 1 final z solves, 2 unit solves (Q), 3 any kind (chained sweep mode).

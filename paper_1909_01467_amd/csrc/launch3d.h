@@ -27,6 +27,7 @@ struct Fact3Args {
     c128* G;            // factor pool (complex128, column-major s x s blocks)
     int* perm;          // [batch][n] pivot rows
     int* status;        // per subdomain: 1 if a zero pivot was met
+    int line;           // 1: 2D line blocks (s = W, block k = grid line k of the window); 0: 3D planes (s = W H)
 };
 
 struct Chain3Args {
@@ -47,12 +48,20 @@ struct Chain3Args {
     int ptiles;               // tiles per plane of the largest block (partial stride)
 };
 
-// S = D_k - C G_below C - C G_above C into ws (identity padding), for every item
+// S = D_k - C G_below C - C G_above C into ws (identity padding), for every item (3D plane blocks)
 hipError_t launch_fact3_build(const Fact3Args& a, int nbatch, hipStream_t st);
-// unblocked Gauss-Jordan on columns [p0, p0 + b) of every matrix (full-row pivoting swaps)
+// the same for the 2D line blocks (a.line = 1): D_k tridiagonal along x, C the diagonal y couplings
+hipError_t launch_fact2_build(const Fact3Args& a, int nbatch, hipStream_t st);
+// Gauss-Jordan on columns [p0, p0 + b) of every matrix (b <= 32, n <= 4096; row pivoting), then its
+// row interchanges applied to all other columns
 hipError_t launch_fact3_panel(const Fact3Args& a, int nbatch, int p0, int b, hipStream_t st);
-// Pbar = panel with its diagonal block minus I (n x b), T = rows [p0, p0 + b) of all columns (b x n)
+// P = the panel's columns (its transformation, n x b), T = rows [p0, p0 + b) of all columns (b x n)
 hipError_t launch_fact3_prep(const Fact3Args& a, int nbatch, int p0, int b, c128* Pbar, c128* T, hipStream_t st);
+// W[:, c0 + c] += P T[:, c0 + c] for c in [0, m) outside the pivot rows [j0, j0 + b), which are
+// overwritten by P T instead, for every matrix (P: [batch] n x b, T: [batch] b x n, W: [batch] n x n,
+// all column-major complex128; b <= 32), on FP64 matrix cores
+hipError_t launch_fact3_update(const c128* P, const c128* T, c128* W, int n, int b, int j0, int c0, int m,
+                               int nbatch, hipStream_t st);
 // undo the row interchanges as column interchanges, then copy the s x s inverse into the pool
 hipError_t launch_fact3_finish(const Fact3Args& a, int nbatch, hipStream_t st);
 

@@ -224,6 +224,11 @@ class Solver:
             return
         raise LswError(rc, self._lib.lsw_last_error(self._h).decode())
 
+    def _handle(self):
+        if not getattr(self, "_h", None):
+            raise RuntimeError("this Solver was closed")
+        return self._h
+
     def _vec(self, x: torch.Tensor) -> tuple[torch.Tensor, int, bool]:
         single = x.dim() == 1 or tuple(x.shape) == self.shape
         x = x.to(device="cuda", dtype=torch.complex128).resolve_conj().resolve_neg()
@@ -247,7 +252,7 @@ class Solver:
     def matvec(self, x: torch.Tensor) -> torch.Tensor:
         x, k, single = self._vec(x)
         y = torch.empty_like(x)
-        self._check(self._lib.lsw_matvec(self._h, ctypes.c_void_p(_dptr(x)), ctypes.c_void_p(_dptr(y)), k))
+        self._check(self._lib.lsw_matvec(self._handle(), ctypes.c_void_p(_dptr(x)), ctypes.c_void_p(_dptr(y)), k))
         return self._out(y, single)
 
     def _krylov(self, fn, b, u0, history):
@@ -256,7 +261,7 @@ class Solver:
         rhs = (lsw_rhs_info_t * k)()
         hist = (ctypes.c_double * (k * history))() if history else None
         info = lsw_info_t(rhs, hist, history, 0.0, 0)
-        rc = fn(self._h, ctypes.c_void_p(_dptr(b)), ctypes.c_void_p(_dptr(u)), k, ctypes.byref(info))
+        rc = fn(self._handle(), ctypes.c_void_p(_dptr(b)), ctypes.c_void_p(_dptr(u)), k, ctypes.byref(info))
         self._check(rc, allow_noconv=True)
         out = {"iterations": [rhs[s].iterations for s in range(k)],
                "converged": [bool(rhs[s].converged) for s in range(k)],
@@ -280,13 +285,13 @@ class Solver:
         u, k2, _ = self._vec(u)
         assert k == k2
         g = torch.zeros(self.shape, dtype=torch.float64, device="cuda")
-        self._check(self._lib.lsw_mass_gradient(self._h, ctypes.c_void_p(_dptr(lam)), ctypes.c_void_p(_dptr(u)),
+        self._check(self._lib.lsw_mass_gradient(self._handle(), ctypes.c_void_p(_dptr(lam)), ctypes.c_void_p(_dptr(u)),
                                                 k, ctypes.c_void_p(_dptr(g))))
         return g
 
     def stats(self) -> dict:
         st = lsw_stats_t()
-        self._check(self._lib.lsw_query(self._h, ctypes.byref(st)))
+        self._check(self._lib.lsw_query(self._handle(), ctypes.byref(st)))
         out = {name: getattr(st, name) for name, _ in lsw_stats_t._fields_}
         out["tune_ms"] = list(out["tune_ms"])
         out["window_shift"] = list(out["window_shift"])
@@ -340,5 +345,6 @@ class HelmholtzSolve(torch.autograd.Function):
         _require_converged(solver, info, "adjoint solve")
         grad_m = solver.mass_gradient(torch.conj_physical(lam), u) if ctx.needs_input_grad[0] else None
         grad_f = lam.reshape(ctx.f_shape) if ctx.needs_input_grad[1] else None
-        solver.close()
+        # the handle stays open: a graph kept with retain_graph may be differentiated again; it is
+        # released with the graph (Solver.__del__)
         return grad_m, grad_f, None
