@@ -167,7 +167,12 @@ typedef struct {
     double last_dom_ms;          /* summed device time of its launches */
     int dom_launches;            /* its launches */
     double dom_bytes;            /* algorithmic bytes those launches read (factor blocks) */
+    long long noalloc_bytes;     /* scratch that lsw_apply_noalloc needs for this handle (at nrhs_max),
+                                    to be compared with LSW_NOALLOC_SCRATCH_BYTES; 0 with windows */
 } lsw_stats_t;
+
+/* Size of the per-GPU scratch array of lsw_apply_noalloc (64 MiB). */
+#define LSW_NOALLOC_SCRATCH_BYTES (64ull << 20)
 
 /*
  * lsw_setup -- Setup and Factorise phases (Sec. 3, Phases 1-2).
@@ -207,6 +212,27 @@ int lsw_setup(lsw_handle_t* out, const double* d_m, double omega, double h,
  *   1 <= nrhs <= nrhs_max.  In LSW_MIXED the sweeps run in complex64.
  */
 int lsw_apply(lsw_handle_t handle, const double* d_r, double* d_z, int nrhs);
+
+/*
+ * lsw_apply_noalloc -- lsw_apply for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.  It computes the same
+ * z = M^-1 r with the same kernels, but every per-application scratch buffer (the trace pool, the
+ * block-substitution y/x slots, the final right-hand-side terms, the per-sweep z parts, and in 3D
+ * the right-hand-side and solution slots of a front and the tile partials) lives in one file-scope
+ * device array of LSW_NOALLOC_SCRATCH_BYTES per GPU, which each GPU the library runs on holds until
+ * the process ends, instead of in the handle's workspace.
+ *   d_r, d_z, nrhs : as lsw_apply (DEVICE buffers owned by the caller).
+ *   - Allocates nothing: no hipMalloc / hipFree, no allocating library routine.
+ *   - Only queues work on opts.stream and returns without synchronising: z is ready when the stream
+ *     reaches this point.  No per-kernel times are recorded (lsw_query keeps those of lsw_apply).
+ *   - Every call on one GPU shares that GPU's array and leaves its last contents there; the parts
+ *     that must start at zero are cleared by a fill kernel at the start of every call.  Calls that
+ *     overlap on one GPU (other streams, handles or threads) race.
+ * Errors: LSW_EINVAL for a NULL argument, nrhs outside [1, nrhs_max], a windowed handle (scenario 4
+ * is not supported), or a handle whose scratch need (lsw_stats_t.noalloc_bytes, sized for nrhs_max)
+ * exceeds LSW_NOALLOC_SCRATCH_BYTES; LSW_EHIP if a launch fails.
+ */
+int lsw_apply_noalloc(lsw_handle_t handle, const double* d_r, double* d_z, int nrhs);
 
 /*
  * lsw_solve -- FGMRES(restart) for A u = f, right-preconditioned by M (Sec. 3, Phase 3).

@@ -20,6 +20,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <new>
 #include <set>
 #include <string>
@@ -143,6 +144,10 @@ struct lsw_plan {
     size_t kev_used = 0;
     double last_dom_ms = 0, dom_bytes = 0;
     int dom_launches = 0;
+    // lsw_apply_noalloc: this GPU's scratch array and the bytes of each per-application buffer
+    // (sized for nrhs_max, as the handle's own buffers)
+    void* d_scratch = nullptr;
+    size_t sz_traces = 0, sz_Y = 0, sz_fw = 0, sz_zpart = 0, sz_rhs3 = 0, sz_Y3 = 0, sz_P3 = 0;
     double apply_stage1_bytes = 0, apply_final_bytes = 0;
     // scenario 4 (Sec. 2.1): this plan is the unshifted CDD; shifted[] holds the CDDs shifted along
     // x, y and both, each a complete plan without a Krylov basis (member = true)
@@ -1146,6 +1151,7 @@ int setup3d_factor(lsw_plan* p) {
         char* P3 = nullptr;
         if ((rc = dalloc(p, &P3, (size_t)p->nrhs_max * p->max_front * 2 * p->ptiles3 * 128 * eb)) != LSW_OK) return rc;
         p->d_P3 = P3;
+        p->sz_P3 = (size_t)p->nrhs_max * p->max_front * 2 * p->ptiles3 * 128 * eb;
     } else if (p->precision == LSW_MIXED) {
         c64* G64 = nullptr;
         if ((rc = dalloc(p, &G64, p->G_elems)) != LSW_OK) return rc;
@@ -1162,6 +1168,7 @@ int setup3d_factor(lsw_plan* p) {
     if ((rc = dalloc(p, &y3, slots * eb)) != LSW_OK) return rc;
     p->d_rhs3 = r3;
     p->d_Y3 = y3;
+    p->sz_rhs3 = p->sz_Y3 = slots * eb;
     return LSW_OK;
 }
 
@@ -1545,21 +1552,25 @@ int setup_impl(lsw_plan* p, const double* d_m, double omega, double h, const lsw
     char* tr = nullptr;
     if ((rc = dalloc(p, &tr, p->trace_stride * p->nrhs_max * eb)) != LSW_OK) return rc;
     p->d_traces = tr;
+    p->sz_traces = p->trace_stride * p->nrhs_max * eb;
     HIPCK(p, hipMemset(tr, 0, p->trace_stride * p->nrhs_max * eb));
     if (p->sweep_mode == LSW_SWEEP_CHAIN) {
         p->zpart_stride = (size_t)p->nrhs_max * p->N;
         char* zp = nullptr;
         if ((rc = dalloc(p, &zp, 9 * p->zpart_stride * eb)) != LSW_OK) return rc;
         p->d_zpart = zp;
+        p->sz_zpart = 9 * p->zpart_stride * eb;
         HIPCK(p, hipMemset(zp, 0, 9 * p->zpart_stride * eb));
     } else {
         if ((rc = dalloc(p, &p->d_fw, (size_t)p->nrhs_max * p->FWT)) != LSW_OK) return rc;
+        p->sz_fw = (size_t)p->nrhs_max * p->FWT * sizeof(c128);
     }
     // y of both forward halves, then x when it does not stay in LDS
     p->Y_stride = 2 * (size_t)p->Wmax * p->Hmax;
     char* Y = nullptr;
     if ((rc = dalloc(p, &Y, p->Y_stride * p->max_front * p->nrhs_max * eb)) != LSW_OK) return rc;
     p->d_Y = Y;
+    p->sz_Y = p->Y_stride * p->max_front * p->nrhs_max * eb;
     // Krylov
     const int m = p->restart, nr = p->nrhs_max;
     const int HS = 2 * (m + 1) + 1;
@@ -1813,6 +1824,97 @@ int setup_windows(lsw_plan* p, const double* d_m, double omega, double h, const 
 }
 
 // the kernel-family times of the last timed application of one CDD (its events are complete)
+// ---------------------------------------------------------------- no-allocation application
+// lsw_apply_noalloc keeps its per-application scratch in this array: one copy per GPU, held until
+// the process ends.  In host code the name is only a stand-in; the device address of the current
+// GPU's copy comes from hipGetSymbolAddress (resolve_scratch) and only that address is used.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_addr[kMaxDevices] = {};
+
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[LSW_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+// the address of the current GPU's scratch array, looked up once per device with that device
+// current (lsw_setup, on the device of the new handle)
+int resolve_scratch(lsw_plan* p) {
+    int dev = 0;
+    HIPCK(p, hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(p, LSW_EINVAL, "device ordinal beyond the scratch table");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_addr[dev]) {
+        void* ptr = nullptr;
+        HIPCK(p, hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        if (!ptr) return fail(p, LSW_EHIP, "hipGetSymbolAddress returned no address for the scratch array");
+        g_scratch_addr[dev] = ptr;
+    }
+    p->d_scratch = g_scratch_addr[dev];
+    return LSW_OK;
+}
+
+size_t round256(size_t b) { return (b + 255) / 256 * 256; }
+
+// scratch bytes of one application at nrhs_max (every buffer 256-byte aligned); 0 with windows
+size_t noalloc_bytes(const lsw_plan* p) {
+    if (p->windows) return 0;
+    size_t b = round256(p->sz_traces) + round256(p->sz_zpart) + round256(p->sz_fw);
+    if (p->dim == 2) b += round256(p->sz_Y);
+    else b += round256(p->sz_rhs3) + round256(p->sz_Y3) + round256(p->sz_P3);
+    return b;
+}
+
+// the application of lsw_apply with the handle's per-application buffers replaced by carved
+// pieces of the scratch array for the duration of the call (the handle is single-threaded by
+// contract, so the swap is not observable); the trace pool, the z parts and the final right-hand
+// side terms start at zero, as the handle's own buffers after setup
+int apply_noalloc_impl(lsw_plan* p, const c128* d_r, c128* d_z, int nrhs) {
+    if (p->windows) return fail(p, LSW_EINVAL, "lsw_apply_noalloc does not support windowed (scenario 4) handles");
+    if (!p->d_scratch) return fail(p, LSW_EINVAL, "the scratch array of this device was not resolved at setup");
+    const size_t need = noalloc_bytes(p);
+    if (need > LSW_NOALLOC_SCRATCH_BYTES)
+        return fail(p, LSW_EINVAL, "lsw_apply_noalloc needs " + std::to_string(need) + " bytes of scratch for this "
+                                   "handle (nrhs_max " + std::to_string(p->nrhs_max) + "), more than the " +
+                                   std::to_string((unsigned long long)LSW_NOALLOC_SCRATCH_BYTES) + " bytes it has");
+    char* base = static_cast<char*>(p->d_scratch);
+    size_t off = 0;
+    auto carve = [&](size_t bytes) -> void* {
+        if (bytes == 0) return nullptr;
+        void* ptr = base + off;
+        off += round256(bytes);
+        return ptr;
+    };
+    void* saved[7] = {p->d_traces, p->d_zpart, p->d_fw, p->d_Y, p->d_rhs3, p->d_Y3, p->d_P3};
+    void* traces = carve(p->sz_traces);
+    void* zpart = carve(p->sz_zpart);
+    void* fw = carve(p->sz_fw);
+    void* Y = p->dim == 2 ? carve(p->sz_Y) : nullptr;
+    void* rhs3 = p->dim == 3 ? carve(p->sz_rhs3) : nullptr;
+    void* Y3 = p->dim == 3 ? carve(p->sz_Y3) : nullptr;
+    void* P3 = p->dim == 3 ? carve(p->sz_P3) : nullptr;
+    HIPCK(p, launch_zero16(base, round256(p->sz_traces) + round256(p->sz_zpart) + round256(p->sz_fw), p->stream));
+    p->d_traces = traces;
+    p->d_zpart = zpart;
+    p->d_fw = static_cast<c128*>(fw);
+    if (p->dim == 2) p->d_Y = Y;
+    else {
+        p->d_rhs3 = rhs3;
+        p->d_Y3 = Y3;
+        p->d_P3 = P3;
+    }
+    const int rc = apply_cdd(p, d_r, d_z, nrhs, false);
+    p->d_traces = saved[0];
+    p->d_zpart = saved[1];
+    p->d_fw = static_cast<c128*>(saved[2]);
+    p->d_Y = saved[3];
+    p->d_rhs3 = saved[4];
+    p->d_Y3 = saved[5];
+    p->d_P3 = saved[6];
+    return rc;
+}
+
 int read_apply_times(lsw_plan* p) {
     float t01 = 0, t12 = 0, t23 = 0, t34 = 0, t04 = 0;
     HIPCK(p, hipEventElapsedTime(&t01, p->ev[0], p->ev[1]));
@@ -1867,6 +1969,7 @@ int lsw_setup(lsw_handle_t* out, const double* d_m, double omega, double h, cons
     int rc;
     try {
         rc = setup_impl(p, d_m, omega, h, grid, cdd, pml, opts);
+        if (rc == LSW_OK) rc = resolve_scratch(p);   // on the device of the new handle
     } catch (const std::bad_alloc&) {
         p->err = "host allocation failed";
         rc = LSW_ENOMEM;
@@ -1921,6 +2024,13 @@ int lsw_apply(lsw_handle_t p, const double* d_r, double* d_z, int nrhs) {
     }
     HIPCK(p, hipEventSynchronize(p->ev[4]));
     return read_apply_times(p);
+}
+
+int lsw_apply_noalloc(lsw_handle_t p, const double* d_r, double* d_z, int nrhs) {
+    if (!p || !d_r || !d_z) return LSW_EINVAL;
+    const int rc = check_nrhs(p, nrhs);
+    if (rc != LSW_OK) return rc;
+    return apply_noalloc_impl(p, reinterpret_cast<const c128*>(d_r), reinterpret_cast<c128*>(d_z), nrhs);
 }
 
 int lsw_solve(lsw_handle_t p, const double* d_f, double* d_u, int nrhs, lsw_info_t* info) {
@@ -2013,6 +2123,7 @@ int lsw_query(lsw_handle_t p, lsw_stats_t* st) {
     st->last_dom_ms = p->last_dom_ms;
     st->dom_launches = p->dom_launches;
     st->dom_bytes = p->dom_bytes;
+    st->noalloc_bytes = (long long)noalloc_bytes(p);
     if (p->windows) {   // totals over the four CDDs (the setup time already covers all four)
         for (const lsw_plan* c : p->shifted) {
             if (!c) continue;

@@ -1508,6 +1508,13 @@ __global__ void k_scale(const c128* src, c128* dst, const c128* nrm2, int nstrid
     dst[(size_t)rhs * dstride + p] = mk(s * v.re, s * v.im);
 }
 
+// zero fill of n 16-byte words (a kernel rather than a memset node, so that a captured graph
+// replays it like any other launch)
+__global__ void k_zero16(uint4* p, size_t n) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        p[i] = make_uint4(0u, 0u, 0u, 0u);
+}
+
 __global__ void k_conj(const c128* src, c128* dst, size_t n) {
     const size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p < n) dst[p] = conj(src[p]);
@@ -1771,6 +1778,13 @@ hipError_t launch_scale(const c128* src, c128* dst, const c128* nrm2, int nstrid
                         size_t sstride, size_t dstride, int nrhs, hipStream_t st) {
     dim3 grid(blocks_for(N, 256), nrhs);
     k_scale<<<grid, 256, 0, st>>>(src, dst, nrm2, nstride, active, N, sstride, dstride);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero16(void* p, size_t bytes, hipStream_t st) {
+    const size_t n = bytes / 16;
+    if (n == 0) return hipSuccess;
+    k_zero16<<<(unsigned)std::min<size_t>(2048, blocks_for(n, 256)), 256, 0, st>>>(reinterpret_cast<uint4*>(p), n);
     return hipGetLastError();
 }
 

@@ -133,6 +133,8 @@ hipError_t launch_gs_update(const GsArgs& a, int nrhs, hipStream_t st);
 hipError_t launch_scale(const c128* src, c128* dst, const c128* nrm2, int nstride, const int* active, size_t N,
                         size_t sstride, size_t dstride, int nrhs, hipStream_t st);
 hipError_t launch_conj(const c128* src, c128* dst, size_t n, hipStream_t st);
+// zeros bytes / 16 16-byte words at p (16-byte aligned)
+hipError_t launch_zero16(void* p, size_t bytes, hipStream_t st);
 hipError_t launch_mass_gradient(const c128* lam, const c128* u, int nrhs, const Geometry& g, double* grad,
                                 hipStream_t st);
 

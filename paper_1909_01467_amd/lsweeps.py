@@ -27,8 +27,9 @@ LSW_FP64, LSW_MIXED = 0, 1
 LSW_SWEEP_COMPRESSED, LSW_SWEEP_CHAIN = 0, 1
 _NAMES = {0: "LSW_OK", -1: "LSW_EINVAL", -2: "LSW_ENOMEM", -3: "LSW_EHIP", -4: "LSW_ESINGULAR",
           -5: "LSW_ENAN", -6: "LSW_ENOCONV"}
-EXPORTS = ("lsw_setup", "lsw_apply", "lsw_solve", "lsw_adjoint", "lsw_matvec", "lsw_mass_gradient",
-           "lsw_query", "lsw_last_error", "lsw_destroy")
+EXPORTS = ("lsw_setup", "lsw_apply", "lsw_apply_noalloc", "lsw_solve", "lsw_adjoint", "lsw_matvec",
+           "lsw_mass_gradient", "lsw_query", "lsw_last_error", "lsw_destroy")
+NOALLOC_SCRATCH_BYTES = 64 << 20   # LSW_NOALLOC_SCRATCH_BYTES
 
 
 class lsw_grid_t(ctypes.Structure):
@@ -79,7 +80,8 @@ class lsw_stats_t(ctypes.Structure):
                 ("tune_ms", ctypes.c_double * 3), ("symmetric_factors", ctypes.c_int),
                 ("packed_factor_elems", ctypes.c_longlong), ("gemv_items", ctypes.c_int),
                 ("gemv_max_inputs", ctypes.c_int), ("cdd_count", ctypes.c_int), ("window_shift", ctypes.c_int * 2),
-                ("last_dom_ms", ctypes.c_double), ("dom_launches", ctypes.c_int), ("dom_bytes", ctypes.c_double)]
+                ("last_dom_ms", ctypes.c_double), ("dom_launches", ctypes.c_int), ("dom_bytes", ctypes.c_double),
+                ("noalloc_bytes", ctypes.c_longlong)]
 
 
 _lib = None
@@ -101,6 +103,7 @@ def load_library() -> ctypes.CDLL:
     lib.lsw_setup.argtypes = [ctypes.POINTER(vp), vp, dp, dp, ctypes.POINTER(lsw_grid_t),
                               ctypes.POINTER(lsw_cdd_t), ctypes.POINTER(lsw_pml_t), ctypes.POINTER(lsw_opts_t)]
     lib.lsw_apply.argtypes = [vp, vp, vp, ip]
+    lib.lsw_apply_noalloc.argtypes = [vp, vp, vp, ip]
     lib.lsw_solve.argtypes = [vp, vp, vp, ip, ctypes.POINTER(lsw_info_t)]
     lib.lsw_adjoint.argtypes = [vp, vp, vp, ip, ctypes.POINTER(lsw_info_t)]
     lib.lsw_matvec.argtypes = [vp, vp, vp, ip]
@@ -246,7 +249,16 @@ class Solver:
     def apply(self, r: torch.Tensor) -> torch.Tensor:
         r, k, single = self._vec(r)
         z = torch.empty_like(r)
-        self._check(self._lib.lsw_apply(self._h, ctypes.c_void_p(_dptr(r)), ctypes.c_void_p(_dptr(z)), k))
+        self._check(self._lib.lsw_apply(self._handle(), ctypes.c_void_p(_dptr(r)), ctypes.c_void_p(_dptr(z)), k))
+        return self._out(z, single)
+
+    def apply_noalloc(self, r: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        """lsw_apply_noalloc: the same z = M^-1 r with the library's scratch in its per-GPU static
+        array (no device allocation inside the call); queued on the solver's stream.  `out`, when
+        given, receives z (complex128, contiguous, the shape of r)."""
+        r, k, single = self._vec(r)
+        z = torch.empty_like(r) if out is None else out.reshape(k, self.N)
+        self._check(self._lib.lsw_apply_noalloc(self._handle(), ctypes.c_void_p(_dptr(r)), ctypes.c_void_p(_dptr(z)), k))
         return self._out(z, single)
 
     def matvec(self, x: torch.Tensor) -> torch.Tensor:
