@@ -82,21 +82,41 @@ def time_applies(solver, b, reps: int = 20):
     return med, solver.stats()
 
 
+def kernel_source_sha(path: str, name: str):
+    """SHA-256 (first 16 hex digits) of the source text of the __global__ function `name` in `path`:
+    from its template/__global__ line to the closing brace at the start of a line."""
+    import hashlib
+
+    lines = open(path).read().splitlines(keepends=True)
+    for i, line in enumerate(lines):
+        if line.startswith("__global__") and f" {name}(" in line:
+            start = i - 1 if i > 0 and lines[i - 1].startswith("template") else i
+            for j in range(i, len(lines)):
+                if lines[j].startswith("}"):
+                    return hashlib.sha256("".join(lines[start:j + 1]).encode()).hexdigest()[:16]
+    return None
+
+
 def counter_traffic(kernel: str, workload: str):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary of the
-    workload (scaled FETCH_SIZE + WRITE_SIZE), or None when there is none or the kernel source
+    workload (scaled FETCH_SIZE + WRITE_SIZE), or None when there is none or the kernel's source
     changed since the counters were taken."""
     import hashlib
 
     path = os.path.join(ROOT, "profiles", f"{workload}_mixed_hbm_traffic.txt")
-    src = os.path.join(ROOT, "paper_1909_01467_amd", "csrc", "kernels3d.hip" if workload.endswith("3d") else "kernels.hip")
+    csrc = os.path.join(ROOT, "paper_1909_01467_amd", "csrc")
     try:
         text = open(path).read()
-        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
     except OSError:
         return None
-    if f"sha256[:16] = {sha}" not in text:
-        return None
+    if workload.endswith("3d"):   # the summary records the sha of the kernel's own source text
+        sha = kernel_source_sha(os.path.join(csrc, "kernels3d.hip"), kernel.split("<")[0])
+        if sha is None or f"{kernel.split('<')[0]} source sha256[:16] = {sha}" not in text:
+            return None
+    else:
+        sha = hashlib.sha256(open(os.path.join(csrc, "kernels.hip"), "rb").read()).hexdigest()[:16]
+        if f"sha256[:16] = {sha}" not in text:
+            return None
     for line in text.splitlines():
         parts = line.split()
         if len(parts) == 3 and parts[0] == "traffic" and parts[1] == kernel:
@@ -210,6 +230,8 @@ def main():
                     help="solve for all of the workload's sources in one batch (nrhs = number of sources)")
     ap.add_argument("--maxit", type=int, default=500)
     ap.add_argument("--restart", type=int, default=50, help="FGMRES restart (the basis holds restart+1 vectors per rhs)")
+    ap.add_argument("--apply-reps", type=int, default=20,
+                    help="applications timed one by one for the per-kernel times (median)")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="first run one device copy of this many MiB (calibrates FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
@@ -241,7 +263,7 @@ def main():
         st0 = s.stats()
         log(precision, "setup ms", round(st0["t_setup_ms"], 1), "factor ms", round(st0["t_factor_ms"], 1))
         u, info, ms = time_solves(s, b, args.steps, args.warmup)
-        med, st = time_applies(s, b)
+        med, st = time_applies(s, b, max(1, args.apply_reps))
         conv = all(info["converged"]) and max(info["relres"]) <= 1e-6
         if precision == "mixed" and not conv:   # an unconverged solve time is no measurement
             raise SystemExit(f"the mixed solve did not reach 1e-6: {info}")

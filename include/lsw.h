@@ -148,9 +148,11 @@ typedef struct {
     double last_final_ms;        /* device time of the final z substitutions (2 launches) */
     double last_final_rhs_ms;    /* device time of the final right-hand-side assembly */
     int rhs_per_workgroup;       /* right-hand sides per workgroup of the stage-1 / final substitutions
-                                    (1, 2 or 4), chosen at setup by timing when nrhs_max > 1, or
-                                    fixed by the environment variable LSW_RHS_PER_WORKGROUP */
-    double tune_ms[3];           /* the timings of 1, 2 and 4 right-hand sides per workgroup (0: not tried) */
+                                    (1, 2 or 4; 16 or 32 on matrix cores, 32 in complex64 only), chosen
+                                    at setup by timing when nrhs_max > 1, or fixed by the environment
+                                    variable LSW_RHS_PER_WORKGROUP */
+    double tune_ms[5];           /* the timings of 1, 2, 4, 16 and 32 right-hand sides per workgroup
+                                    (0: not tried) */
     int symmetric_factors;       /* 1 if the substitutions read packed symmetric blocks (G_k = G_k^T; about
                                     half the bytes of the full blocks): in 2D those with one right-hand
                                     side per workgroup, in 3D every plane step (64 x 64 tiles) */

@@ -86,7 +86,7 @@ struct lsw_plan {
     int max_nin = 0;
     int sweep_depth = 0;            // dependency levels of the sweep work items (one launch each)
     int rgroup = 1;                 // right-hand sides per workgroup of the stage-1 / final substitutions
-    double rgroup_ms[3] = {0, 0, 0};   // timings of R = 1, 2, 4 when tuned
+    double rgroup_ms[5] = {0, 0, 0, 0, 0};   // timings of R = 1, 2, 4, 16, 32 when tuned
     int* d_frp = nullptr;           // final right-hand side: polarization terms per window point
     long long* d_fpool = nullptr;
     c128* d_fcoef = nullptr;
@@ -698,6 +698,7 @@ int setup_windows(lsw_plan* p, const double* d_m, double omega, double h, const 
 // workgroup on the full blocks, or one per workgroup on the packed symmetric blocks when present
 hipError_t launch_block_front(lsw_plan* p, ChainArgs a, const Front& f, int nrhs, int cs, int R) {
     const bool c64 = p->precision == LSW_MIXED;
+    if (R >= 16 && nrhs > 1) return launch_chain_mma(a, f.count, nrhs, c64, cs, R, p->stream);
     if (R > 1 && nrhs > 1) return launch_chain_mr(a, f.count, nrhs, p->ept, c64, cs, R, p->stream);
     if (p->gsym) {
         a.G = p->d_Gs;
@@ -1082,8 +1083,9 @@ int batched_gj(lsw_plan* p, c128* G128, bool line) {
     }
     Fact3Item* d_items = nullptr;
     c128 *ws = nullptr, *Pbar = nullptr, *Tb = nullptr;
-    int* perm = nullptr;
+    int *perm = nullptr, *src = nullptr;
     if ((rc = dalloc(p, &d_items, all.size())) != LSW_OK) return rc;
+    if ((rc = dalloc(p, &src, maxb * (size_t)n)) != LSW_OK) return rc;
     if ((rc = dalloc(p, &ws, maxb * n * (size_t)n)) != LSW_OK) return rc;
     if ((rc = dalloc(p, &Pbar, maxb * n * (size_t)b)) != LSW_OK) return rc;
     if ((rc = dalloc(p, &Tb, maxb * n * (size_t)b)) != LSW_OK) return rc;
@@ -1113,7 +1115,7 @@ int batched_gj(lsw_plan* p, c128* G128, bool line) {
             for (const auto& pt : parts)
                 HIPCK(p, launch_fact3_update(Pbar, Tb, ws, n, bb, p0, pt[0], pt[1], nb, p->stream));
         }
-        HIPCK(p, launch_fact3_finish(fa, nb, p->stream));
+        HIPCK(p, launch_fact3_finish(fa, nb, src, p->stream));
     }
     HIPCK(p, hipStreamSynchronize(p->stream));
     p->t_factor_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tf).count();
@@ -1121,6 +1123,7 @@ int batched_gj(lsw_plan* p, c128* G128, bool line) {
     dfree(p, Pbar);
     dfree(p, Tb);
     dfree(p, perm);
+    dfree(p, src);
     dfree(p, d_items);
     std::vector<int> status(nsub);
     HIPCK(p, hipMemcpy(status.data(), p->d_status, sizeof(int) * nsub, hipMemcpyDeviceToHost));
@@ -1225,16 +1228,17 @@ int apply3d_impl(lsw_plan* p, const c128* d_r, c128* d_z, int nrhs, bool timed) 
 
 // Autotuning of the batched substitutions: with several right-hand sides, the stage-1 and
 // final fronts can carry R = 1, 2 or 4 of them per workgroup (every factor block read once per
-// group).  Larger R reads less but holds more registers and LDS per step; each candidate is
-// timed on the real factors (zero inputs, the stage-1 and final fronts, nrhs_max right-hand
-// sides) and the fastest is kept.
+// group), or R = 16 or 32 (complex64 only) on matrix cores (k_chain_mma).  Larger R reads less
+// but holds more registers and LDS per step; each candidate is timed on the real factors (zero
+// inputs, the stage-1 and final fronts, nrhs_max right-hand sides) and the fastest is kept.
 int tune_rgroup(lsw_plan* p) {
     p->rgroup = 1;
     if (p->dim != 2 || p->sweep_mode != LSW_SWEEP_COMPRESSED || p->nrhs_max < 2) return LSW_OK;
-    // LSW_RHS_PER_WORKGROUP = 1, 2 or 4 fixes the choice (no timing)
+    const bool c64 = p->precision == LSW_MIXED;
+    // LSW_RHS_PER_WORKGROUP = 1, 2, 4, 16 or 32 (complex64) fixes the choice (no timing)
     if (const char* env = std::getenv("LSW_RHS_PER_WORKGROUP")) {
         const int R = std::atoi(env);
-        if (R == 1 || R == 2 || R == 4) {
+        if (R == 1 || R == 2 || R == 4 || R == 16 || (R == 32 && c64)) {
             p->rgroup = R;
             return LSW_OK;
         }
@@ -1246,10 +1250,11 @@ int tune_rgroup(lsw_plan* p) {
     const Front& f0 = p->fronts.front();
     const Front& f1 = p->fronts.back();
     double best = 1e30;
-    const int cands[3] = {1, 2, 4};
-    for (int ci = 0; ci < 3; ++ci) {
+    const int cands[5] = {1, 2, 4, 16, 32};
+    for (int ci = 0; ci < 5; ++ci) {
         const int R = cands[ci];
-        if (R > nrhs) break;
+        // the matrix-core groups pay off once a 16-wide block is at least a quarter full
+        if (R <= 4 ? R > nrhs : (R == 16 ? nrhs < 4 : (!c64 || nrhs <= 16))) continue;
         double tmin = 1e30;
         for (int rep = 0; rep < 3; ++rep) {
             HIPCK(p, hipEventRecord(p->ev[0], p->stream));
@@ -1711,25 +1716,45 @@ int setup_impl(lsw_plan* p, const double* d_m, double omega, double h, const lsw
                 }
             }
         }
-        const int batch = 1024;
+        // the unit solves on matrix cores: groups of up to 16 consecutive units of one subdomain, each
+        // group one workgroup pair carrying its 16 right-hand sides through every block (FP64)
+        constexpr int kGroup = 16, kGroupsPerLaunch = 64;
+        std::vector<int> groups;   // {first, count, kf0, kf1} per group
+        for (size_t u = 0; u < units.size();) {
+            size_t e = u + 1;
+            while (e < units.size() && e - u < (size_t)kGroup && units[e].sub == units[u].sub) ++e;
+            int k0 = units[u].unit_k, k1 = units[u].unit_k;
+            for (size_t v = u; v < e; ++v) {
+                k0 = std::min(k0, units[v].unit_k);
+                k1 = std::max(k1, units[v].unit_k);
+            }
+            groups.insert(groups.end(), {(int)u, (int)(e - u), k0, k1});
+            u = e;
+        }
+        const size_t ngroups = groups.size() / 4;
         SolveDesc* d_units = nullptr;
+        int* d_groups = nullptr;
         c128* Yq = nullptr;
         if (!units.empty()) {
             if ((rc = dalloc(p, &d_units, units.size())) != LSW_OK) return rc;
             HIPCK(p, hipMemcpy(d_units, units.data(), sizeof(SolveDesc) * units.size(), hipMemcpyHostToDevice));
-            if ((rc = dalloc(p, &Yq, p->Y_stride * (size_t)std::min<size_t>(batch, units.size()))) != LSW_OK) return rc;
+            if ((rc = dalloc(p, &d_groups, groups.size())) != LSW_OK) return rc;
+            HIPCK(p, hipMemcpy(d_groups, groups.data(), sizeof(int) * groups.size(), hipMemcpyHostToDevice));
+            if ((rc = dalloc(p, &Yq, p->Y_stride * (size_t)kGroup * std::min<size_t>(kGroupsPerLaunch, ngroups))) != LSW_OK)
+                return rc;
         }
         ChainArgs ua = chain_args(p, nullptr, nullptr);
         ua.G = G128;
         ua.Q = Q128;
         ua.Y = Yq;
-        for (size_t off = 0; off < units.size(); off += batch) {
-            ua.descs = d_units + off;
-            const int cnt = (int)std::min<size_t>(batch, units.size() - off);
-            HIPCK(p, launch_chain(ua, cnt, 1, p->ept, false, 2, p->ylds128, p->stream));
+        ua.descs = d_units;
+        for (size_t g0 = 0; g0 < ngroups; g0 += kGroupsPerLaunch) {
+            ua.ugroups = d_groups + 4 * g0;
+            HIPCK(p, launch_chain_mma_unit(ua, (int)std::min<size_t>(kGroupsPerLaunch, ngroups - g0), p->stream));
         }
         HIPCK(p, hipStreamSynchronize(p->stream));
         dfree(p, d_units);
+        dfree(p, d_groups);
         dfree(p, Yq);
         // fold the polarization map of every sweep solve into its trace-to-trace operator
         c128* QP128 = nullptr;
@@ -2112,7 +2137,7 @@ int lsw_query(lsw_handle_t p, lsw_stats_t* st) {
     st->last_final_ms = p->last_final_ms;
     st->last_final_rhs_ms = p->last_final_rhs_ms;
     st->rhs_per_workgroup = p->rgroup;
-    for (int i = 0; i < 3; ++i) st->tune_ms[i] = p->rgroup_ms[i];
+    for (int i = 0; i < 5; ++i) st->tune_ms[i] = p->rgroup_ms[i];
     st->symmetric_factors = p->gsym ? 1 : 0;
     st->packed_factor_elems = p->gsym ? (long long)p->GS_elems : 0;
     st->gemv_items = (int)p->gitems.size();

@@ -1631,6 +1631,306 @@ static hipError_t launch_chain_mr_t(const ChainArgs& a0, int nsolves, int nrhs, 
     return hipGetLastError();
 }
 
+// ------------------------------------------------------------------ many right-hand sides on matrix cores
+// 16 x 16 x 4 matrix-core products in the working precision.  Lane l holds A[l % 16][l / 16] and
+// B[l / 16][l % 16]; accumulator entry v is row l / 16 + 4 v (FP64) or 4 (l / 16) + v (FP32), column
+// l % 16 (established by an in-bounds probe of both instructions).
+template <typename T>
+struct Mfma;
+template <>
+struct Mfma<float> {
+    typedef float acc __attribute__((ext_vector_type(4)));
+    __device__ static inline acc mac(float a, float b, acc c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+    __device__ static inline int row(int lk, int v) { return 4 * lk + v; }
+};
+template <>
+struct Mfma<double> {
+    typedef double acc __attribute__((ext_vector_type(4)));
+    __device__ static inline acc mac(double a, double b, acc c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+    __device__ static inline int row(int lk, int v) { return lk + 4 * v; }
+};
+
+// The twisted block substitution of the stage-1 and final fronts for R = 16 RB right-hand sides per
+// workgroup, each block step a matrix-core product Y = G_k V of the W x W block with the W x R block of
+// right-hand-side columns, so that every G_k is read once per R right-hand sides and the arithmetic is
+// dense: complex products as four real ones (Re += Gr Vr + (-Gi) Vi, Im += Gr Vi + Gi Vr).  Four waves
+// share the row blocks of G_k (wave w owns 16-row blocks w, w + 4, ...); V lives in LDS, one row per
+// window column x, R entries per row; thread x forms row x of V from the right-hand side and the
+// previous block's y or x; y (phase 0) and x (phase 1) go to each right-hand side's slab of a.Y as in
+// k_chain_mr, whose phases, ranges and outputs this kernel shares.  With CS_UNIT a workgroup carries
+// a group of up to R unit solves of one subdomain (the columns of Q): right-hand side r is the unit
+// vector at window point (unit_k, unit_c) of the group's r-th unit descriptor.
+template <typename T, int CS, int RB, int PH>
+__global__ __launch_bounds__(256) void k_chain_mma(ChainArgs a) {
+    static_assert(CS == CS_STAGE1 || CS == CS_FINAL || CS == CS_UNIT, "stage-1, final and unit solves");
+    constexpr int NT = 256, R = 16 * RB;
+    using M = Mfma<T>;
+    using acc_t = typename M::acc;
+    const int sidx = blockIdx.x >> 1, h = blockIdx.x & 1, nsol = gridDim.x >> 1;
+    const int ufirst = CS == CS_UNIT ? a.ugroups[4 * sidx] : sidx;
+    const SolveDesc& dref = a.descs[ufirst];
+    const int kf0 = CS == CS_UNIT ? a.ugroups[4 * sidx + 2] : dref.kf0;
+    const int kf1 = CS == CS_UNIT ? a.ugroups[4 * sidx + 3] : dref.kf1;
+    const int kb0 = dref.kb0, kb1 = dref.kb1;
+    const SubDesc s = a.subs[dref.sub];
+    const int rhs0 = blockIdx.y * R;
+    const int nr = CS == CS_UNIT ? a.ugroups[4 * sidx + 1] : min(R, a.nrhs - rhs0);
+    __shared__ int su_k[R], su_c[R];   // CS_UNIT: the unit point of each right-hand side
+    if (CS == CS_UNIT && threadIdx.x < R) {
+        su_k[threadIdx.x] = threadIdx.x < nr ? a.descs[ufirst + threadIdx.x].unit_k : -1;
+        su_c[threadIdx.x] = threadIdx.x < nr ? a.descs[ufirst + threadIdx.x].unit_c : -1;
+    }
+    const int W = s.W, H = s.H, m = s.mid, tid = threadIdx.x;
+    const int lane = tid & 63, wv = tid >> 6, li = lane & 15, lk = lane >> 4;
+    const int NB = (W + 15) / 16;
+    __shared__ cx<T> sV[kMaxWindow][R];     // rows past W stay zero
+    __shared__ c128 a2h[kMaxWindow + 1];
+    const c128* tab = a.geo.tab;
+    const double ih2 = 1.0 / (a.geo.h * a.geo.h);
+    for (int k = tid; k <= H; k += NT) a2h[k] = tab[s.ty + H + k];
+    for (int e = tid; e < kMaxWindow * R; e += NT) sV[e / R][e % R] = cx<T>{T(0), T(0)};
+    const bool mine = tid < W;
+    const c128 ia_c = tab[s.tx + (mine ? tid : 0)];
+    const cx<T>* Gs = reinterpret_cast<const cx<T>*>(a.G) + s.g_off;
+    const size_t N = (size_t)a.geo.Nx * a.geo.Ny;
+    auto zero = []() { return cx<T>{T(0), T(0)}; };
+    auto cy = [&](int l) { return cvt<T>(-ih2 * (a2h[l + 1] * ia_c)); };
+    const bool in_cols = mine && tid >= s.c0 && tid < s.c1;
+    // g_k at my column for right-hand side r (zero outside the ranges that carry it)
+    auto rhs_at = [&](int r, int k) -> cx<T> {
+        if (!mine || r >= nr || k < kf0 || k > kf1) return zero();
+        const int rhs = rhs0 + r;
+        if constexpr (CS == CS_UNIT) return (k == su_k[r] && tid == su_c[r]) ? cx<T>{T(1), T(0)} : zero();
+        if constexpr (CS == CS_FINAL) return cvt<T>(a.fw[(size_t)rhs * a.fw_stride + s.fw_off + (size_t)k * W + tid]);
+        if (!(in_cols && k >= s.r0 && k < s.r1)) return zero();
+        return cvt<T>(a.r[(size_t)rhs * N + (size_t)(s.wy0 + k) * a.geo.Nx + s.wx0 + tid]);
+    };
+    auto slab = [&](int r) {
+        const size_t j = CS == CS_UNIT ? (size_t)sidx * R + r : (size_t)(rhs0 + r) * nsol + sidx;
+        return reinterpret_cast<cx<T>*>(a.Y) + j * a.Y_stride;
+    };
+
+    acc_t accr[4][RB], acci[4][RB];
+    // acc = G_k V over this wave's row blocks
+    auto product = [&](int k) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int bj = 0; bj < RB; ++bj) {
+                accr[q][bj] = acc_t{T(0), T(0), T(0), T(0)};
+                acci[q][bj] = acc_t{T(0), T(0), T(0), T(0)};
+            }
+        const cx<T>* Gk = Gs + (size_t)k * W * W;
+        // 32 columns of G_k per round: the loads of all 8 k-steps are issued before their products,
+        // so a block step waits for memory once per 32 columns instead of once per 4
+        constexpr int U = 8;
+        for (int c0 = 0; c0 < W; c0 += 4 * U) {
+            cx<T> g[U][4];
+            cx<T> vb[U][RB];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int c = c0 + 4 * u + lk;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int row = 16 * (wv + 4 * q) + li;
+                    g[u][q] = (c < W && row < W) ? Gk[(size_t)c * W + row] : zero();
+                }
+#pragma unroll
+                for (int bj = 0; bj < RB; ++bj) vb[u][bj] = sV[c < W ? c : kMaxWindow - 1][16 * bj + li];
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const bool live = c0 + 4 * u < W;   // the same for the whole wave
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    if (!live || wv + 4 * q >= NB) break;
+#pragma unroll
+                    for (int bj = 0; bj < RB; ++bj) {
+                        // rows c >= W of V are zero, so padded columns add nothing
+                        const T gr = g[u][q].re, gi = g[u][q].im, vr = vb[u][bj].re, vi = vb[u][bj].im;
+                        accr[q][bj] = M::mac(gr, vr, accr[q][bj]);
+                        accr[q][bj] = M::mac(-gi, vi, accr[q][bj]);
+                        acci[q][bj] = M::mac(gr, vi, acci[q][bj]);
+                        acci[q][bj] = M::mac(gi, vr, acci[q][bj]);
+                    }
+                }
+            }
+        }
+    };
+    // the product's entries (row x, right-hand side r) into sV and slab[r][off + x]; with `minus`, the
+    // result is y_k - product (y_k from slab[r][k W + x] when has_y)
+    auto store = [&](size_t off, bool minus, int k, bool has_y) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            if (wv + 4 * q >= NB) break;
+#pragma unroll
+            for (int bj = 0; bj < RB; ++bj)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int x = 16 * (wv + 4 * q) + M::row(lk, v), r = 16 * bj + li;
+                    if (x >= W) continue;
+                    cx<T> val = cx<T>{accr[q][bj][v], acci[q][bj][v]};
+                    if (minus) {
+                        const cx<T> y = (has_y && r < nr) ? slab(r)[(size_t)k * W + x] : zero();
+                        val = y - val;
+                    }
+                    sV[x][r] = val;
+                    if (r < nr) slab(r)[off + x] = val;
+                }
+        }
+    };
+    __syncthreads();
+
+    if constexpr (PH == 0) {
+        // ---- forward elimination of this half towards the middle row
+        const int kstart = h == 0 ? kf0 : kf1;
+        const int dir = h == 0 ? 1 : -1;
+        const int n = h == 0 ? m - kf0 : kf1 - m;
+        for (int i = 0; i < n; ++i) {
+            const int k = kstart + dir * i;
+            if (mine) {
+                const cx<T> c = cy(h == 0 ? k - 1 : k);
+#pragma unroll 4
+                for (int r = 0; r < R; ++r) {
+                    cx<T> g = rhs_at(r, k);
+                    if (i > 0) g = g - c * sV[tid][r];
+                    sV[tid][r] = g;
+                }
+            }
+            __syncthreads();
+            product(k);
+            __syncthreads();
+            store((size_t)k * W, false, k, false);
+            __syncthreads();
+        }
+        return;
+    }
+
+    // ---- phase 1: middle row, then back substitution of this half away from it
+    if (mine) {
+#pragma unroll 4
+        for (int r = 0; r < R; ++r) {
+            cx<T> g = rhs_at(r, m);
+            if (r < nr) {
+                if (m >= 1 && kf0 <= m - 1) g = g - cy(m - 1) * slab(r)[(size_t)(m - 1) * W + tid];
+                if (m + 1 <= H - 1 && kf1 >= m + 1) g = g - cy(m) * slab(r)[(size_t)(m + 1) * W + tid];
+            }
+            sV[tid][r] = g;
+        }
+    }
+    __syncthreads();
+    product(m);
+    __syncthreads();
+    store((size_t)H * W + (size_t)m * W, false, m, false);
+    __syncthreads();
+    {
+        const int kstart = h == 0 ? m - 1 : m + 1;
+        const int dir = h == 0 ? -1 : 1;
+        const int n = h == 0 ? m - kb0 : kb1 - m;
+        for (int i = 0; i < n; ++i) {
+            const int k = kstart + dir * i;
+            if (mine) {
+                const cx<T> c = cy(h == 0 ? k : k - 1);
+#pragma unroll 4
+                for (int r = 0; r < R; ++r) sV[tid][r] = c * sV[tid][r];
+            }
+            __syncthreads();
+            product(k);
+            __syncthreads();
+            store((size_t)H * W + (size_t)k * W, true, k, h == 0 ? k >= kf0 : k <= kf1);
+            __syncthreads();
+        }
+    }
+
+    // ---- outputs of the block rows this half owns
+    const int olo = h == 0 ? kb0 : max(kb0, m + 1);
+    const int ohi = h == 0 ? min(kb1, m) : kb1;
+    auto own = [&](int k) { return k >= olo && k <= ohi; };
+    for (int r = 0; r < nr; ++r) {
+        const int rhs = rhs0 + r;
+        const cx<T>* X = slab(r) + (size_t)H * W;
+        if constexpr (CS == CS_UNIT) {
+            // Q column: the solution at the trace-line slots (B, T lines of W, then L, R lines of H)
+            cx<T>* col = reinterpret_cast<cx<T>*>(a.Q) + a.descs[ufirst + r].q_col;
+            const int L8 = 4 * W + 4 * H;
+            for (int sl = tid; sl < L8; sl += NT) {
+                int k, c, side;
+                if (sl < 4 * W) {
+                    const int line = sl / W;
+                    c = sl - line * W;
+                    side = line < 2 ? SIDE_B : SIDE_T;
+                    k = line == 0 ? s.r0 - 1 : line == 1 ? s.r0 : line == 2 ? s.r1 - 1 : s.r1;
+                } else {
+                    const int q = sl - 4 * W, line = q / H;
+                    k = q - line * H;
+                    side = line < 2 ? SIDE_L : SIDE_R;
+                    c = line == 0 ? s.c0 - 1 : line == 1 ? s.c0 : line == 2 ? s.c1 - 1 : s.c1;
+                }
+                if (((s.sides >> side) & 1) && own(k)) col[sl] = X[(size_t)k * W + c];
+            }
+        } else if constexpr (CS == CS_FINAL) {
+            const int r0 = max(s.r0, olo), r1 = min(s.r1, ohi + 1);
+            const int nc = s.c1 - s.c0, n = max(0, r1 - r0) * nc;
+            c128* z = a.z + (size_t)rhs * N + (size_t)(s.wy0 + r0) * a.geo.Nx + s.wx0 + s.c0;
+            for (int idx = tid; idx < n; idx += NT) {
+                const int rr0 = idx / nc, cc = idx - rr0 * nc;
+                z[(size_t)rr0 * a.geo.Nx + cc] = cvt<double>(X[(size_t)(r0 + rr0) * W + s.c0 + cc]);
+            }
+        } else {
+            cx<T>* tr = reinterpret_cast<cx<T>*>(a.traces) + (size_t)rhs * a.trace_stride;
+            for (int o = 0; o < dref.nout; ++o) {
+                const int side = dref.out_side[o];
+                cx<T>* out = tr + dref.out_off[o];
+                const bool acc = dref.out_acc[o] != 0;
+                if (side == SIDE_B || side == SIDE_T) {
+                    const int l0 = (side == SIDE_B) ? s.r0 - 1 : s.r1 - 1;
+                    for (int idx = tid; idx < 2 * W; idx += NT) {
+                        const int line = idx / W, c = idx - line * W;
+                        if (!own(l0 + line)) continue;
+                        const cx<T> xv = X[(size_t)(l0 + line) * W + c];
+                        out[idx] = acc ? out[idx] + xv : xv;
+                    }
+                } else {
+                    const int l0 = (side == SIDE_L) ? s.c0 - 1 : s.c1 - 1;
+                    for (int idx = tid; idx < 2 * H; idx += NT) {
+                        const int line = idx / H, k = idx - line * H;
+                        if (!own(k)) continue;
+                        const cx<T> xv = X[(size_t)k * W + l0 + line];
+                        out[idx] = acc ? out[idx] + xv : xv;
+                    }
+                }
+            }
+        }
+    }
+}
+
+template <typename T, int CS, int RB>
+static void launch_chain_mma_c(const ChainArgs& a, dim3 grid, hipStream_t st) {
+    k_chain_mma<T, CS, RB, 0><<<grid, 256, 0, st>>>(a);
+    k_chain_mma<T, CS, RB, 1><<<grid, 256, 0, st>>>(a);
+}
+
+hipError_t launch_chain_mma_unit(const ChainArgs& a, int ngroups, hipStream_t st) {
+    if (ngroups <= 0) return hipSuccess;
+    launch_chain_mma_c<double, CS_UNIT, 1>(a, dim3(2 * ngroups, 1), st);
+    return hipGetLastError();
+}
+
+hipError_t launch_chain_mma(const ChainArgs& a0, int nsolves, int nrhs, bool c64mode, int cs, int R, hipStream_t st) {
+    if ((cs != 0 && cs != 1) || (R != 16 && R != 32) || (!c64mode && R != 16)) return hipErrorInvalidValue;
+    ChainArgs a = a0;
+    a.nrhs = nrhs;
+    const dim3 grid(2 * nsolves, (nrhs + R - 1) / R);
+    if (c64mode) {
+        if (cs == 0) R == 16 ? launch_chain_mma_c<float, CS_STAGE1, 1>(a, grid, st) : launch_chain_mma_c<float, CS_STAGE1, 2>(a, grid, st);
+        else R == 16 ? launch_chain_mma_c<float, CS_FINAL, 1>(a, grid, st) : launch_chain_mma_c<float, CS_FINAL, 2>(a, grid, st);
+    } else {
+        if (cs == 0) launch_chain_mma_c<double, CS_STAGE1, 1>(a, grid, st);
+        else launch_chain_mma_c<double, CS_FINAL, 1>(a, grid, st);
+    }
+    return hipGetLastError();
+}
+
 hipError_t launch_chain_mr(const ChainArgs& a, int nsolves, int nrhs, int ept, bool c64mode, int cs, int rgroup,
                            hipStream_t st) {
     if ((cs != 0 && cs != 1) || (rgroup != 2 && rgroup != 4)) return hipErrorInvalidValue;

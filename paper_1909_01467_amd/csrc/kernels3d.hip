@@ -304,6 +304,87 @@ __global__ __launch_bounds__(1024) void k_f3_panel(Fact3Args a, int p0, int b) {
     if (tid == 0 && sh_sing) a.status[a.items[blockIdx.x].sub] = 1;
 }
 
+// The same panel elimination for n <= 256 (2D line blocks): the whole n x b panel lives in LDS
+// (128 KB at n = 256, b = 32), so every pivot step is an LDS pass between barriers.
+__global__ __launch_bounds__(1024) void k_f3_panel_lds(Fact3Args a, int p0, int b) {
+    constexpr int NT = 1024;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int n = a.n, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    c128* sp = reinterpret_cast<c128*>(smem);   // [b][n] column-major panel
+    c128* colf = sp + (size_t)b * n;            // the multipliers of the current pivot column
+    __shared__ double wbest[NT / 64];
+    __shared__ int wbi[NT / 64];
+    __shared__ int sh_piv, sh_sing;
+    c128* A = a.ws + (size_t)blockIdx.x * n * n;
+    int* perm = a.perm + (size_t)blockIdx.x * n;
+    if (tid == 0) sh_sing = 0;
+    for (int e = tid; e < n * b; e += NT) {
+        const int c = e / n, i = e - c * n;
+        sp[e] = A[i + (size_t)(p0 + c) * n];
+    }
+    __syncthreads();
+    for (int jj = 0; jj < b; ++jj) {
+        const int j = p0 + jj;
+        double best = -1.0;
+        int bi = j;
+        if (tid >= j && tid < n) {
+            best = abs2(sp[jj * n + tid]);
+            bi = tid;
+        }
+        for (int off = 32; off > 0; off >>= 1) {
+            const double ob = __shfl_xor(best, off);
+            const int oi = __shfl_xor(bi, off);
+            if (ob > best || (ob == best && oi < bi)) {
+                best = ob;
+                bi = oi;
+            }
+        }
+        if (lane == 0) {
+            wbest[wv] = best;
+            wbi[wv] = bi;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            double bb = wbest[0];
+            int ii = wbi[0];
+            for (int w = 1; w < NT / 64; ++w)
+                if (wbest[w] > bb || (wbest[w] == bb && wbi[w] < ii)) {
+                    bb = wbest[w];
+                    ii = wbi[w];
+                }
+            sh_piv = ii;
+            perm[j] = ii;
+            if (!(bb > 0.0)) sh_sing = 1;
+        }
+        __syncthreads();
+        const int pr = sh_piv;
+        if (pr != j && tid < b) {
+            const c128 t = sp[tid * n + j];
+            sp[tid * n + j] = sp[tid * n + pr];
+            sp[tid * n + pr] = t;
+        }
+        __syncthreads();
+        const c128 piv = sp[jj * n + j];
+        const c128 inv = abs2(piv) > 0.0 ? cinv(piv) : mk(0.0, 0.0);
+        if (tid < n) colf[tid] = sp[jj * n + tid];
+        __syncthreads();
+        if (tid < b) sp[tid * n + j] = tid == jj ? inv : sp[tid * n + j] * inv;
+        __syncthreads();
+        for (int e = tid; e < n * b; e += NT) {
+            const int c = e / n, i = e - c * n;
+            if (i == j) continue;
+            const c128 f = colf[i];
+            sp[e] = c == jj ? -(f * inv) : sp[e] - f * sp[c * n + j];
+        }
+        __syncthreads();
+    }
+    for (int e = tid; e < n * b; e += NT) {
+        const int c = e / n, i = e - c * n;
+        A[i + (size_t)(p0 + c) * n] = sp[e];
+    }
+    if (tid == 0 && sh_sing) a.status[a.items[blockIdx.x].sub] = 1;
+}
+
 // The row interchanges of panel [p0, p0 + b), in order, applied to every column outside the panel
 // (one lane per column).
 __global__ void k_f3_laswp(Fact3Args a, int p0, int b) {
@@ -358,9 +439,16 @@ __global__ __launch_bounds__(256) void k_f3_update(const c128* __restrict__ P, c
                                                    c128* __restrict__ Wm, int n, int b, int j0, int c0, int m) {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int li = lane & 15, lk = lane >> 4;
-    const int r0 = blockIdx.x * 64 + 32 * (wv & 1);
-    const int q0 = blockIdx.y * 64 + 32 * (wv >> 1);   // column offset within [0, m)
-    const size_t z = blockIdx.z;
+    // Workgroup L runs on XCD L mod 8.  Each XCD takes a contiguous range of the tiles (matrix
+    // slowest, then column tile, then row tile), so the workgroups that read the same matrix's P and
+    // T share one XCD's L2.
+    const uint32_t total = gridDim.x, L = blockIdx.x;
+    const uint32_t per = total / 8, extra = total % 8, xcd = L % 8;
+    const uint32_t t = xcd * per + min(xcd, extra) + L / 8;
+    const uint32_t nrt = (uint32_t)(n + 63) / 64, nct = (uint32_t)(m + 63) / 64;
+    const int r0 = (int)(t % nrt) * 64 + 32 * (wv & 1);
+    const int q0 = (int)((t / nrt) % nct) * 64 + 32 * (wv >> 1);   // column offset within [0, m)
+    const size_t z = t / (nrt * nct);
     const c128* Pz = P + z * (size_t)n * b;
     const c128* Tz = T + z * (size_t)n * b;
     c128* Wz = Wm + z * (size_t)n * n;
@@ -424,26 +512,36 @@ __global__ __launch_bounds__(256) void k_f3_update(const c128* __restrict__ P, c
         }
 }
 
-__global__ __launch_bounds__(1024) void k_f3_finish(Fact3Args a) {
-    const Fact3Item it = a.items[blockIdx.x];
-    const SubDesc s = a.subs[it.sub];
-    const int n = a.n, S = a.line ? s.W : s.W * s.H, tid = threadIdx.x;
-    c128* A = a.ws + (size_t)blockIdx.x * n * n;
+// The row interchanges undone as column interchanges, in reverse order, composed into one column
+// permutation per matrix: column q of the inverse is column src[q] of the eliminated matrix.
+__global__ void k_f3_perm(Fact3Args a, int* src) {
+    if (threadIdx.x != 0) return;
+    const int n = a.n;
     const int* perm = a.perm + (size_t)blockIdx.x * n;
+    int* sq = src + (size_t)blockIdx.x * n;
+    for (int q = 0; q < n; ++q) sq[q] = q;
     for (int j = n - 1; j >= 0; --j) {
         const int r = perm[j];
-        if (r != j)
-            for (int i = tid; i < n; i += blockDim.x) {
-                const c128 t = A[i + (size_t)j * n];
-                A[i + (size_t)j * n] = A[i + (size_t)r * n];
-                A[i + (size_t)r * n] = t;
-            }
-        __syncthreads();
+        if (r != j) {
+            const int t = sq[j];
+            sq[j] = sq[r];
+            sq[r] = t;
+        }
     }
+}
+
+// G_k = the s x s inverse (column-major), gathered through the column permutation
+__global__ void k_f3_finish(Fact3Args a, const int* src) {
+    const Fact3Item it = a.items[blockIdx.y];
+    const SubDesc s = a.subs[it.sub];
+    const int n = a.n, S = a.line ? s.W : s.W * s.H;
+    const c128* A = a.ws + (size_t)blockIdx.y * n * n;
+    const int* sq = src + (size_t)blockIdx.y * n;
     c128* G = a.G + s.g_off + (size_t)it.k * S * S;   // S = W (2D lines) or W H (3D planes)
-    for (size_t idx = tid; idx < (size_t)S * S; idx += blockDim.x) {
+    const size_t SS = (size_t)S * S;
+    for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < SS; idx += (size_t)gridDim.x * blockDim.x) {
         const int p = (int)(idx % S), q = (int)(idx / S);
-        G[idx] = A[p + (size_t)q * n];
+        G[idx] = A[p + (size_t)sq[q] * n];
     }
 }
 
@@ -907,7 +1005,13 @@ hipError_t launch_fact2_build(const Fact3Args& a, int nbatch, hipStream_t st) {
 
 hipError_t launch_fact3_panel(const Fact3Args& a, int nbatch, int p0, int b, hipStream_t st) {
     if (b > 32 || a.n > 4096) return hipErrorInvalidValue;
-    if (a.n <= 1024) k_f3_panel<1><<<nbatch, 1024, 0, st>>>(a, p0, b);
+    if (a.n <= 256) {
+        const size_t lds = sizeof(c128) * (size_t)(b + 1) * a.n;
+        hipError_t e = hipFuncSetAttribute((const void*)k_f3_panel_lds, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)lds);
+        if (e != hipSuccess) return e;
+        k_f3_panel_lds<<<nbatch, 1024, lds, st>>>(a, p0, b);
+    } else if (a.n <= 1024) k_f3_panel<1><<<nbatch, 1024, 0, st>>>(a, p0, b);
     else if (a.n <= 2048) k_f3_panel<2><<<nbatch, 1024, 0, st>>>(a, p0, b);
     else k_f3_panel<4><<<nbatch, 1024, 0, st>>>(a, p0, b);
     hipError_t e = hipGetLastError();
@@ -925,13 +1029,18 @@ hipError_t launch_fact3_update(const c128* P, const c128* T, c128* W, int n, int
                                int nbatch, hipStream_t st) {
     if (m <= 0 || b <= 0) return hipSuccess;
     if (b > 32) return hipErrorInvalidValue;   // one pass of at most 32 columns of k
-    const dim3 grid((n + 63) / 64, (m + 63) / 64, nbatch);
-    k_f3_update<<<grid, 256, 0, st>>>(P, T, W, n, b, j0, c0, m);
+    const size_t tiles = (size_t)((n + 63) / 64) * ((m + 63) / 64) * nbatch;
+    if (tiles > 0x7fffffffu) return hipErrorInvalidValue;
+    k_f3_update<<<(unsigned)tiles, 256, 0, st>>>(P, T, W, n, b, j0, c0, m);
     return hipGetLastError();
 }
 
-hipError_t launch_fact3_finish(const Fact3Args& a, int nbatch, hipStream_t st) {
-    k_f3_finish<<<nbatch, 1024, 0, st>>>(a);
+hipError_t launch_fact3_finish(const Fact3Args& a, int nbatch, int* src, hipStream_t st) {
+    k_f3_perm<<<nbatch, 64, 0, st>>>(a, src);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const unsigned blocks = (unsigned)std::min<size_t>(1024, ((size_t)a.n * a.n + 255) / 256);
+    k_f3_finish<<<dim3(blocks, nbatch), 256, 0, st>>>(a, src);
     return hipGetLastError();
 }
 

@@ -27,6 +27,7 @@ struct ChainArgs {
     c128* fw;               // right-hand sides of the final z solves, window layout [nrhs][sum H*W]
     size_t fw_stride;       // sum over windows of H*W
     int nrhs;               // set by launch_chain_mr: right-hand sides of the launch
+    const int* ugroups;     // launch_chain_mma_unit: per group of unit solves {first desc, count, kf0, kf1}
 };
 
 struct GemvArgs {
@@ -106,6 +107,13 @@ inline int sym_ept(int W) { return (tile_count(W) + 255) / 256; }
 // (Y_stride >= 2 H_max W_max)
 int sym_max_ept(bool c64mode);
 hipError_t prepare_chain_sym(int ept, bool c64mode, size_t lds);
+// The stage-1 (cs 0) or final (cs 1) substitutions with R = 16 or 32 right-hand sides per workgroup
+// on matrix cores (full blocks in a.G; R = 32 in complex64 only); two launches like launch_chain_mr.
+hipError_t launch_chain_mma(const ChainArgs& a, int nsolves, int nrhs, bool c64mode, int cs, int R, hipStream_t st);
+// The unit solves that build Q (complex128, full blocks in a.G): groups of up to 16 unit right-hand
+// sides of one subdomain (a.descs = the unit descriptors, a.ugroups = ngroups groups), group g's
+// right-hand side r using the y/x slab g * 16 + r of a.Y; each writes its column of a.Q.
+hipError_t launch_chain_mma_unit(const ChainArgs& a, int ngroups, hipStream_t st);
 hipError_t launch_chain_sym(const ChainArgs& a, int nsolves, int nrhs, int ept, bool c64mode, int cs, size_t lds,
                             hipStream_t st);
 // packed symmetric copy (complex64 or complex128) of the FP64 factor pool

@@ -63,7 +63,8 @@ hipError_t launch_fact3_prep(const Fact3Args& a, int nbatch, int p0, int b, c128
 hipError_t launch_fact3_update(const c128* P, const c128* T, c128* W, int n, int b, int j0, int c0, int m,
                                int nbatch, hipStream_t st);
 // undo the row interchanges as column interchanges, then copy the s x s inverse into the pool
-hipError_t launch_fact3_finish(const Fact3Args& a, int nbatch, hipStream_t st);
+// (src: [batch][n] ints of workspace for the composed column permutation)
+hipError_t launch_fact3_finish(const Fact3Args& a, int nbatch, int* src, hipStream_t st);
 
 // right-hand sides of a front's solves (stage 1: r on Omega; sweeps: polarized sources)
 hipError_t launch_rhs3(const Chain3Args& a, int smax, int nrhs, bool f32, hipStream_t st);

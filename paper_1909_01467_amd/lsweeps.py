@@ -77,7 +77,7 @@ class lsw_stats_t(ctypes.Structure):
                 ("apply_stage1_bytes", ctypes.c_double), ("apply_final_bytes", ctypes.c_double),
                 ("last_stage1_ms", ctypes.c_double), ("last_final_ms", ctypes.c_double),
                 ("last_final_rhs_ms", ctypes.c_double), ("rhs_per_workgroup", ctypes.c_int),
-                ("tune_ms", ctypes.c_double * 3), ("symmetric_factors", ctypes.c_int),
+                ("tune_ms", ctypes.c_double * 5), ("symmetric_factors", ctypes.c_int),
                 ("packed_factor_elems", ctypes.c_longlong), ("gemv_items", ctypes.c_int),
                 ("gemv_max_inputs", ctypes.c_int), ("cdd_count", ctypes.c_int), ("window_shift", ctypes.c_int * 2),
                 ("last_dom_ms", ctypes.c_double), ("dom_launches", ctypes.c_int), ("dom_bytes", ctypes.c_double),

