@@ -171,6 +171,13 @@ typedef struct {
     double dom_bytes;            /* algorithmic bytes those launches read (factor blocks) */
     long long noalloc_bytes;     /* scratch that lsw_apply_noalloc needs for this handle (at nrhs_max),
                                     to be compared with LSW_NOALLOC_SCRATCH_BYTES; 0 with windows */
+    /* shape of the 2D packed one-right-hand-side substitutions (0 when they are not used): lanes per
+     * workgroup, 4x4 tiles per lane, factor blocks in flight per lane, lanes per row of the
+     * reduction; chosen at setup by timing every shape the widest window fits (the first CDD's
+     * with windows), or fixed by the environment variable LSW_SYM_CONFIG */
+    int sym_threads, sym_tiles_per_lane, sym_ring, sym_lanes_per_row;
+    int sym_shapes_timed;        /* shapes timed at setup (0: one fits, or fixed) */
+    double sym_tune_best_ms, sym_tune_worst_ms;   /* their fastest and slowest time (both fronts) */
 } lsw_stats_t;
 
 /* Size of the per-GPU scratch array of lsw_apply_noalloc (64 MiB). */

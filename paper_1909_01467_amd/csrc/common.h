@@ -127,6 +127,12 @@ __host__ __device__ inline int tile_count(int W) { return tile_nt(W) * (tile_nt(
 __host__ __device__ inline long long sym_block(int W) { return 16LL * tile_count(W); }
 // row stride of the per-tile-column partial sums in the substitution kernel (4 mod 16 entries)
 __host__ __device__ inline int sym_cstride(int W) { return 4 * tile_nt(W) + ((4 - 4 * tile_nt(W)) % 16 + 16) % 16; }
+// largest nt whose upper triangle has at most `tiles` tiles
+__host__ __device__ constexpr int sym_nt_max(int tiles) {
+    int nt = 0;
+    while ((nt + 1) * (nt + 2) / 2 <= tiles) ++nt;
+    return nt;
+}
 
 // Packed storage of a complex symmetric plane block of a 3D beam (s = W*H unknowns, G = G^T):
 // the upper triangle in 64 x 64 tiles, nb = ceil(s/64) tile rows, tiles (I, J) with I <= J numbered

@@ -97,7 +97,9 @@ struct lsw_plan {
     // packed symmetric factors (2D): the stage-1 and final substitutions of one right-hand side
     // per workgroup read these; d_G (full blocks) stays only where something else needs it
     bool gsym = false;
-    int sym_ept = 0;                // packed rows per thread (max over the windows)
+    int sym_cfg = -1;               // shape of the packed substitutions (kSymCfgs index)
+    double sym_tune_best_ms = 0, sym_tune_worst_ms = 0;
+    int sym_timed = 0;              // shapes timed at setup
     size_t sym_lds = 0;             // dynamic LDS of the packed substitutions: the widest window's column sums
     void* d_Gs = nullptr;
     size_t GS_elems = 0;
@@ -702,7 +704,7 @@ hipError_t launch_block_front(lsw_plan* p, ChainArgs a, const Front& f, int nrhs
     if (R > 1 && nrhs > 1) return launch_chain_mr(a, f.count, nrhs, p->ept, c64, cs, R, p->stream);
     if (p->gsym) {
         a.G = p->d_Gs;
-        return launch_chain_sym(a, f.count, nrhs, p->sym_ept, c64, cs, p->sym_lds, p->stream);
+        return launch_chain_sym(a, f.count, nrhs, p->sym_cfg, cs, p->sym_lds, p->stream);
     }
     return launch_chain(a, f.count, nrhs, p->ept, c64, cs, p->ylds, p->stream);
 }
@@ -1231,6 +1233,61 @@ int apply3d_impl(lsw_plan* p, const c128* d_r, c128* d_z, int nrhs, bool timed) 
 // group), or R = 16 or 32 (complex64 only) on matrix cores (k_chain_mma).  Larger R reads less
 // but holds more registers and LDS per step; each candidate is timed on the real factors (zero
 // inputs, the stage-1 and final fronts, nrhs_max right-hand sides) and the fastest is kept.
+// The shape of the packed one-right-hand-side substitutions (lanes, tiles per lane, ring depth,
+// lanes per row of the reduction): every shape the widest window fits is timed on the real
+// blocks (zero right-hand side, the first stage-1 and the last final front) and the fastest kept.
+// LSW_SYM_CONFIG = i fixes kSymCfgs[i] if the windows fit it.
+int tune_sym(lsw_plan* p) {
+    p->sym_timed = 0;
+    p->sym_tune_best_ms = p->sym_tune_worst_ms = 0;
+    if (!p->gsym) return LSW_OK;
+    const bool c64 = p->precision == LSW_MIXED;
+    if (const char* env = std::getenv("LSW_SYM_CONFIG")) {
+        const int c = std::atoi(env);
+        if (c >= 0 && c < kSymCfgCount && sym_cfg_fits(c, c64, p->Wmax)) {
+            p->sym_cfg = c;
+            return LSW_OK;
+        }
+    }
+    int ncand = 0;
+    for (int c = 0; c < kSymCfgCount; ++c) ncand += sym_cfg_fits(c, c64, p->Wmax) ? 1 : 0;
+    if (ncand < 2) return LSW_OK;
+    HIPCK(p, hipMemsetAsync(p->d_tmp1, 0, sizeof(c128) * p->N, p->stream));
+    HIPCK(p, hipMemsetAsync(p->d_fw, 0, sizeof(c128) * p->FWT, p->stream));
+    ChainArgs a = chain_args(p, p->d_tmp1, p->d_tmp2);
+    a.G = p->d_Gs;
+    const Front& f0 = p->fronts.front();
+    const Front& f1 = p->fronts.back();
+    double best = 1e30, worst = 0;
+    int pick = p->sym_cfg;
+    for (int c = 0; c < kSymCfgCount; ++c) {
+        if (!sym_cfg_fits(c, c64, p->Wmax)) continue;
+        double tmin = 1e30;
+        for (int rep = 0; rep < 3; ++rep) {
+            HIPCK(p, hipEventRecord(p->ev[0], p->stream));
+            for (const Front* f : {&f0, &f1}) {
+                a.descs = p->d_descs + f->offset;
+                HIPCK(p, launch_chain_sym(a, f->count, 1, c, f == &f0 ? 0 : 1, p->sym_lds, p->stream));
+            }
+            HIPCK(p, hipEventRecord(p->ev[1], p->stream));
+            HIPCK(p, hipEventSynchronize(p->ev[1]));
+            float ms = 0;
+            HIPCK(p, hipEventElapsedTime(&ms, p->ev[0], p->ev[1]));
+            if (rep > 0) tmin = std::min(tmin, (double)ms);   // the first run warms up
+        }
+        ++p->sym_timed;
+        worst = std::max(worst, tmin);
+        if (tmin < best) {
+            best = tmin;
+            pick = c;
+        }
+    }
+    p->sym_cfg = pick;
+    p->sym_tune_best_ms = best;
+    p->sym_tune_worst_ms = worst;
+    return LSW_OK;
+}
+
 int tune_rgroup(lsw_plan* p) {
     p->rgroup = 1;
     if (p->dim != 2 || p->sweep_mode != LSW_SWEEP_COMPRESSED || p->nrhs_max < 2) return LSW_OK;
@@ -1392,7 +1449,7 @@ int setup_impl(lsw_plan* p, const double* d_m, double omega, double h, const lsw
     p->subs.clear();
     p->G_elems = 0;
     p->GS_elems = 0;
-    p->sym_ept = 0;
+    p->sym_cfg = -1;
     p->sym_lds = 0;
     p->hbase.clear();
     p->vbase.clear();
@@ -1420,7 +1477,6 @@ int setup_impl(lsw_plan* p, const double* d_m, double omega, double h, const lsw
             s.g_off = (long long)p->G_elems;
             s.gs_off = (long long)p->GS_elems;
             p->GS_elems += (size_t)s.H * sym_block(s.W);
-            p->sym_ept = std::max(p->sym_ept, sym_ept(s.W));
             p->sym_lds = std::max(p->sym_lds, (size_t)tile_nt(s.W) * sym_cstride(s.W));   // column sums c
             const size_t S3 = (size_t)s.W * s.H;
             p->G_elems += p->dim == 3 ? (size_t)p->Nz * S3 * S3 : (size_t)s.H * s.W * s.W;
@@ -1462,9 +1518,15 @@ int setup_impl(lsw_plan* p, const double* d_m, double omega, double h, const lsw
         int dev = 0, max_lds = 0;
         HIPCK(p, hipGetDevice(&dev));
         HIPCK(p, hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
-        p->gsym = !off && p->dim == 2 && p->sweep_mode == LSW_SWEEP_COMPRESSED && p->sym_ept <= sym_max_ept(mixed) &&
+        // the first shape every window fits is the default; the rest are timed once the blocks exist
+        p->sym_cfg = -1;
+        for (int c = 0; c < kSymCfgCount && p->sym_cfg < 0; ++c)
+            if (sym_cfg_fits(c, mixed, p->Wmax)) p->sym_cfg = c;
+        p->gsym = !off && p->dim == 2 && p->sweep_mode == LSW_SWEEP_COMPRESSED && p->sym_cfg >= 0 &&
                   p->sym_lds + stat <= (size_t)max_lds;
-        if (p->gsym) HIPCK(p, prepare_chain_sym(p->sym_ept, mixed, p->sym_lds));
+        if (p->gsym)
+            for (int c = 0; c < kSymCfgCount; ++c)
+                if (sym_cfg_fits(c, mixed, p->Wmax)) HIPCK(p, prepare_chain_sym(c, p->sym_lds));
         if (p->dim == 3) {   // packed 64 x 64 tiles of every plane block (k_tile3 / k_red3)
             p->gsym = !off;
             p->GS_elems = 0;
@@ -1804,6 +1866,7 @@ int setup_impl(lsw_plan* p, const double* d_m, double omega, double h, const lsw
     } else {
         p->d_G = G128;
     }
+    if ((rc = tune_sym(p)) != LSW_OK) return rc;
     if ((rc = tune_rgroup(p)) != LSW_OK) return rc;
     if (p->windows && (rc = setup_windows(p, d_m, omega, h, grid, cdd, pml, opts)) != LSW_OK) return rc;
     p->t_setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
@@ -2109,6 +2172,7 @@ int lsw_mass_gradient(lsw_handle_t p, const double* d_lam, const double* d_u, in
 
 int lsw_query(lsw_handle_t p, lsw_stats_t* st) {
     if (!p || !st) return LSW_EINVAL;
+    std::memset(st, 0, sizeof(*st));
     st->q = p->q;
     st->r = p->r;
     st->n_subdomains = (int)p->subs.size();
@@ -2139,6 +2203,16 @@ int lsw_query(lsw_handle_t p, lsw_stats_t* st) {
     st->rhs_per_workgroup = p->rgroup;
     for (int i = 0; i < 5; ++i) st->tune_ms[i] = p->rgroup_ms[i];
     st->symmetric_factors = p->gsym ? 1 : 0;
+    if (p->gsym && p->dim == 2 && p->sym_cfg >= 0) {
+        const SymCfg& c = kSymCfgs[p->sym_cfg];
+        st->sym_threads = c.threads;
+        st->sym_tiles_per_lane = c.tiles_per_lane;
+        st->sym_ring = c.ring;
+        st->sym_lanes_per_row = c.lanes_per_row;
+    }
+    st->sym_shapes_timed = p->sym_timed;
+    st->sym_tune_best_ms = p->sym_tune_best_ms;
+    st->sym_tune_worst_ms = p->sym_tune_worst_ms;
     st->packed_factor_elems = p->gsym ? (long long)p->GS_elems : 0;
     st->gemv_items = (int)p->gitems.size();
     st->gemv_max_inputs = p->max_nin;

@@ -769,16 +769,17 @@ __device__ inline double lane_sum(double x, int RS) {
 
 // The twisted block substitution of k_chain (stage 1 and final solves, one right-hand side per
 // workgroup) on the factors in the packed symmetric tile layout (tile_nt / sym_block): about
-// half the bytes of the full blocks.  256 lanes; lane l holds the tiles tau = l + 256 m
-// (m < TPL).  For its tile (I, J) it forms the row sums A v_J (into c[J][4I..4I+3]) and, off the
-// diagonal, the column sums A^T v_I (into c[I][4J..4J+3]), so every entry read from HBM is used
-// twice from registers.  c (LDS, [nt][4 nt]) is then summed over J by RS lanes per row (LDS
-// reads, then DPP).  A register ring keeps PD blocks in flight; scheduling barriers keep the
-// issue order of the loads, so each wait covers only the block in use.
-template <typename T, int TPL, int PD, int CS, int PH>
-__global__ __launch_bounds__(256) void k_chain_sym(ChainArgs a) {
+// half the bytes of the full blocks.  NT lanes; lane l holds the tiles tau = l + NT m (m < TPL).
+// For its tile (I, J) it forms the row sums A v_J (into c[J][4I..4I+3]) and, off the diagonal,
+// the column sums A^T v_I (into c[I][4J..4J+3]), so every entry read from HBM is used twice from
+// registers.  c (LDS, [nt][4 nt]) is then summed over J by RS lanes per row (unrolled LDS reads
+// into two accumulators, then DPP).  A register ring keeps PD blocks in flight; scheduling
+// barriers keep the issue order of the loads, so each wait covers only the block in use.  The
+// shapes (NT, TPL, PD, RS) a window width allows are listed in kSymCfgs and timed at setup.
+template <typename T, int NT, int TPL, int PD, int RS, int CS, int PH>
+__global__ __launch_bounds__(NT) void k_chain_sym(ChainArgs a) {
     static_assert(CS == CS_STAGE1 || CS == CS_FINAL, "stage 1 and final solves only");
-    constexpr int NT = 256;
+    static_assert(RS == 1 || RS == 2 || RS == 4, "1, 2 or 4 lanes per row");
     extern __shared__ __align__(16) unsigned char dyn[];
     cx<T>* cs = reinterpret_cast<cx<T>*>(dyn);   // c[J][r] at J * Wp + r
     const int sidx = blockIdx.x >> 1, h = blockIdx.x & 1, nsol = gridDim.x >> 1;
@@ -792,7 +793,6 @@ __global__ __launch_bounds__(256) void k_chain_sym(ChainArgs a) {
     const int nt = tile_nt(W), Wp = sym_cstride(W), NTL = tile_count(W);
     const uint32_t BSb = (uint32_t)sym_block(W) * (uint32_t)sizeof(cx<T>);   // bytes per block
     // the reduction of row t: lanes RS t .. RS t + RS-1; the first of them owns the row
-    const int RS = W <= 64 ? 4 : (W <= 128 ? 2 : 1);
     const int tr = min(tid / RS, W - 1), rq = tid % RS;
     const bool mine = rq == 0 && tid / RS < W;
     __shared__ __align__(16) cx<T> v[kMaxWindow + 4];   // zero past W
@@ -898,10 +898,17 @@ __global__ __launch_bounds__(256) void k_chain_sym(ChainArgs a) {
         }
     };
     // (G_k v)_t for the row owners (every lane takes part: the group sums are lane exchanges)
+    // every lane's share of the reduction is at most NRED partial sums (nt <= sym_nt_max(NT TPL))
+    constexpr int NRED = (sym_nt_max(NT * TPL) + RS - 1) / RS;
     auto reduce = [&]() {
-        cx<T> y = zero();
-#pragma unroll 4
-        for (int J = rq; J < nt; J += RS) y = y + cs[J * Wp + tr];
+        cx<T> y0 = zero(), y1 = zero();
+#pragma unroll
+        for (int it = 0; it < NRED; it += 2) {
+            const int J0 = rq + RS * it, J1 = J0 + RS;
+            if (J0 < nt) y0 = y0 + cs[J0 * Wp + tr];
+            if (it + 1 < NRED && J1 < nt) y1 = y1 + cs[J1 * Wp + tr];
+        }
+        cx<T> y = y0 + y1;
         y.re = lane_sum(y.re, RS);
         y.im = lane_sum(y.im, RS);
         return y;
@@ -1938,52 +1945,51 @@ hipError_t launch_chain_mr(const ChainArgs& a, int nsolves, int nrhs, int ept, b
                    : launch_chain_mr_t<double>(a, nsolves, nrhs, ept, cs, rgroup, st);
 }
 
-// register ring of k_chain_sym: a tile is 32 VGPRs in complex64 and 64 in complex128.  Measured at
-// W = 88 (one tile per lane): 2 or 3 blocks in flight are equal, 4 is 2% and 6 is 11% slower (the
-// loads of later blocks then compete with the step in use)
-template <typename T, int CS, int PH, typename F>
-static void sym_dispatch(int ept, F&& f) {
-    if constexpr (sizeof(T) == 4) {
-        if (ept <= 1) f(k_chain_sym<T, 1, 3, CS, PH>);
-        else if (ept <= 2) f(k_chain_sym<T, 2, 2, CS, PH>);
-        else f(k_chain_sym<T, 3, 1, CS, PH>);
-    } else {
-        f(k_chain_sym<T, 1, 2, CS, PH>);
+// k_chain_sym in the shape kSymCfgs[cfg] (a tile is 32 VGPRs in complex64 and 64 in complex128;
+// with 512 lanes two waves share a SIMD, so a wave keeps at most 256 registers: the shapes listed
+// are those that compile without spills)
+template <int CS, int PH, typename F>
+static void sym_dispatch(int cfg, F&& f) {
+    switch (cfg) {
+        case 0: f(k_chain_sym<float, 256, 1, 3, 4, CS, PH>); break;
+        case 1: f(k_chain_sym<float, 256, 1, 3, 2, CS, PH>); break;
+        case 2: f(k_chain_sym<float, 512, 1, 3, 4, CS, PH>); break;
+        case 3: f(k_chain_sym<float, 512, 1, 2, 4, CS, PH>); break;
+        case 4: f(k_chain_sym<float, 256, 2, 2, 2, CS, PH>); break;
+        case 5: f(k_chain_sym<float, 256, 3, 1, 1, CS, PH>); break;
+        case 6: f(k_chain_sym<float, 512, 2, 1, 2, CS, PH>); break;
+        case 7: f(k_chain_sym<double, 256, 1, 2, 4, CS, PH>); break;
+        case 8: f(k_chain_sym<double, 256, 1, 2, 2, CS, PH>); break;
+        case 9: f(k_chain_sym<double, 512, 1, 1, 4, CS, PH>); break;
+        default: break;
     }
 }
+static_assert(kSymCfgCount == 10, "sym_dispatch covers every shape of kSymCfgs");
 
-int sym_max_ept(bool c64mode) { return c64mode ? 3 : 1; }
-
-hipError_t prepare_chain_sym(int ept, bool c64mode, size_t lds) {
+hipError_t prepare_chain_sym(int cfg, size_t lds) {
+    if (cfg < 0 || cfg >= kSymCfgCount) return hipErrorInvalidValue;
     hipError_t e = hipSuccess;
     auto set = [&](auto kern) {
         if (e == hipSuccess)
             e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     };
-    if (c64mode) {
-        sym_dispatch<float, CS_STAGE1, 0>(ept, set); sym_dispatch<float, CS_STAGE1, 1>(ept, set);
-        sym_dispatch<float, CS_FINAL, 0>(ept, set); sym_dispatch<float, CS_FINAL, 1>(ept, set);
-    } else {
-        sym_dispatch<double, CS_STAGE1, 0>(ept, set); sym_dispatch<double, CS_STAGE1, 1>(ept, set);
-        sym_dispatch<double, CS_FINAL, 0>(ept, set); sym_dispatch<double, CS_FINAL, 1>(ept, set);
-    }
+    sym_dispatch<CS_STAGE1, 0>(cfg, set); sym_dispatch<CS_STAGE1, 1>(cfg, set);
+    sym_dispatch<CS_FINAL, 0>(cfg, set); sym_dispatch<CS_FINAL, 1>(cfg, set);
     return e;
 }
 
-hipError_t launch_chain_sym(const ChainArgs& a, int nsolves, int nrhs, int ept, bool c64mode, int cs, size_t lds,
-                            hipStream_t st) {
-    if ((cs != CS_STAGE1 && cs != CS_FINAL) || ept < 1 || ept > sym_max_ept(c64mode)) return hipErrorInvalidValue;
-    dim3 grid(2 * nsolves, nrhs);
-    auto go = [&](auto kern) { kern<<<grid, 256, lds, st>>>(a); };
-#define LSW_GO(T, CSV, PHV) if (cs == CSV) sym_dispatch<T, CSV, PHV>(ept, go);
-    if (c64mode) {
-        LSW_GO(float, CS_STAGE1, 0) LSW_GO(float, CS_FINAL, 0)
-        LSW_GO(float, CS_STAGE1, 1) LSW_GO(float, CS_FINAL, 1)
+hipError_t launch_chain_sym(const ChainArgs& a, int nsolves, int nrhs, int cfg, int cs, size_t lds, hipStream_t st) {
+    if ((cs != CS_STAGE1 && cs != CS_FINAL) || cfg < 0 || cfg >= kSymCfgCount) return hipErrorInvalidValue;
+    const dim3 grid(2 * nsolves, nrhs);
+    const int nt = kSymCfgs[cfg].threads;
+    auto go = [&](auto kern) { kern<<<grid, nt, lds, st>>>(a); };
+    if (cs == CS_STAGE1) {
+        sym_dispatch<CS_STAGE1, 0>(cfg, go);
+        sym_dispatch<CS_STAGE1, 1>(cfg, go);
     } else {
-        LSW_GO(double, CS_STAGE1, 0) LSW_GO(double, CS_FINAL, 0)
-        LSW_GO(double, CS_STAGE1, 1) LSW_GO(double, CS_FINAL, 1)
+        sym_dispatch<CS_FINAL, 0>(cfg, go);
+        sym_dispatch<CS_FINAL, 1>(cfg, go);
     }
-#undef LSW_GO
     return hipGetLastError();
 }
 

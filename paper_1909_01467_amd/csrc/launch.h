@@ -98,15 +98,30 @@ hipError_t launch_chain(const ChainArgs& a, int nsolves, int nrhs, int ept, bool
 // workgroup; y and x in a.Y (Y_stride >= 2 H_max W_max)
 hipError_t launch_chain_mr(const ChainArgs& a, int nsolves, int nrhs, int ept, bool c64mode, int cs, int rgroup,
                            hipStream_t st);
-// tiles per lane of k_chain_sym (256 lanes) for a window of width W
-inline int sym_ept(int W) { return (tile_count(W) + 255) / 256; }
+// Shapes of the packed substitution kernel k_chain_sym: lanes per workgroup, tiles per lane,
+// blocks in flight in the register ring, lanes per row of the reduction, and the precision.  A
+// window of width W fits a shape when its tiles fit the lanes (tile_count(W) <= threads x
+// tiles_per_lane) and every row has its reduction lanes (lanes_per_row x W <= threads).
+struct SymCfg {
+    int threads, tiles_per_lane, ring, lanes_per_row;
+    bool c64;
+};
+inline constexpr SymCfg kSymCfgs[] = {
+    {256, 1, 3, 4, true},  {256, 1, 3, 2, true},  {512, 1, 3, 4, true}, {512, 1, 2, 4, true},
+    {256, 2, 2, 2, true},  {256, 3, 1, 1, true},  {512, 2, 1, 2, true},
+    {256, 1, 2, 4, false}, {256, 1, 2, 2, false}, {512, 1, 1, 4, false},
+};
+inline constexpr int kSymCfgCount = (int)(sizeof(kSymCfgs) / sizeof(kSymCfgs[0]));
+inline bool sym_cfg_fits(int cfg, bool c64mode, int W) {
+    const SymCfg& c = kSymCfgs[cfg];
+    return c.c64 == c64mode && tile_count(W) <= c.threads * c.tiles_per_lane && c.lanes_per_row * W <= c.threads;
+}
 // stage 1 (cs 0) or final (cs 1) substitutions, one right-hand side per workgroup, on the packed
-// symmetric factors (a.G = packed pool, SubDesc::gs_off); ept = tiles per lane (sym_ept, at most
-// sym_max_ept); lds = dynamic LDS bytes, >= the column sums of the widest window,
-// tile_nt(W) sym_cstride(W) entries (set once with prepare_chain_sym); y and x in a.Y
+// symmetric factors (a.G = packed pool, SubDesc::gs_off) with shape kSymCfgs[cfg], which every
+// window must fit; lds = dynamic LDS bytes, >= the column sums of the widest window,
+// tile_nt(W) sym_cstride(W) entries (set once per shape with prepare_chain_sym); y and x in a.Y
 // (Y_stride >= 2 H_max W_max)
-int sym_max_ept(bool c64mode);
-hipError_t prepare_chain_sym(int ept, bool c64mode, size_t lds);
+hipError_t prepare_chain_sym(int cfg, size_t lds);
 // The stage-1 (cs 0) or final (cs 1) substitutions with R = 16 or 32 right-hand sides per workgroup
 // on matrix cores (full blocks in a.G; R = 32 in complex64 only); two launches like launch_chain_mr.
 hipError_t launch_chain_mma(const ChainArgs& a, int nsolves, int nrhs, bool c64mode, int cs, int R, hipStream_t st);
@@ -114,8 +129,7 @@ hipError_t launch_chain_mma(const ChainArgs& a, int nsolves, int nrhs, bool c64m
 // sides of one subdomain (a.descs = the unit descriptors, a.ugroups = ngroups groups), group g's
 // right-hand side r using the y/x slab g * 16 + r of a.Y; each writes its column of a.Q.
 hipError_t launch_chain_mma_unit(const ChainArgs& a, int ngroups, hipStream_t st);
-hipError_t launch_chain_sym(const ChainArgs& a, int nsolves, int nrhs, int ept, bool c64mode, int cs, size_t lds,
-                            hipStream_t st);
+hipError_t launch_chain_sym(const ChainArgs& a, int nsolves, int nrhs, int cfg, int cs, size_t lds, hipStream_t st);
 // packed symmetric copy (complex64 or complex128) of the FP64 factor pool
 hipError_t launch_pack_sym(const SubDesc* subs, int nsub, const c128* G, void* Gp, bool c64mode, hipStream_t st);
 hipError_t launch_gemv(const GemvArgs& a, bool c64mode, hipStream_t st);

@@ -81,7 +81,10 @@ class lsw_stats_t(ctypes.Structure):
                 ("packed_factor_elems", ctypes.c_longlong), ("gemv_items", ctypes.c_int),
                 ("gemv_max_inputs", ctypes.c_int), ("cdd_count", ctypes.c_int), ("window_shift", ctypes.c_int * 2),
                 ("last_dom_ms", ctypes.c_double), ("dom_launches", ctypes.c_int), ("dom_bytes", ctypes.c_double),
-                ("noalloc_bytes", ctypes.c_longlong)]
+                ("noalloc_bytes", ctypes.c_longlong), ("sym_threads", ctypes.c_int),
+                ("sym_tiles_per_lane", ctypes.c_int), ("sym_ring", ctypes.c_int), ("sym_lanes_per_row", ctypes.c_int),
+                ("sym_shapes_timed", ctypes.c_int), ("sym_tune_best_ms", ctypes.c_double),
+                ("sym_tune_worst_ms", ctypes.c_double)]
 
 
 _lib = None

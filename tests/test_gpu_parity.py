@@ -84,6 +84,7 @@ CASES = {
     "no_pml": Case("no_pml", 33, 29, 0, 0, 2, 2, C=1.0),
     "wide_4x5": Case("wide_4x5", 150, 131, 10, 10, 4, 5),
     "wide_windows_2x2": Case("wide_windows_2x2", 250, 180, 10, 10, 2, 2),   # windows 147 x 112
+    "widest_windows_2x2": Case("widest_windows_2x2", 280, 90, 10, 10, 2, 2),   # windows 162 x 67
 }
 
 
@@ -421,6 +422,54 @@ def test_packed_factors_of_wide_windows(monkeypatch):
     for k in range(2):
         check("wide windows packed vs full blocks", Z[k], Z0[k], 2e-6, cdd=c.oracle, shape=c.m.shape)
     check("wide windows packed vs oracle", Z[0], zo, 2e-6, cdd=c.oracle, shape=c.m.shape)
+
+
+SYM_SHAPE_INDICES = range(10)   # the shapes of the packed substitution kernel (LSW_SYM_CONFIG)
+
+
+@pytest.mark.parametrize("name,precision,min_shapes", [
+    ("ragged_45x38_3x2", "mixed", 7), ("ragged_45x38_3x2", "fp64", 3), ("wide_4x5", "mixed", 5),
+    ("wide_windows_2x2", "mixed", 2), ("widest_windows_2x2", "mixed", 1)])
+def test_every_packed_kernel_shape_gives_the_oracle_application(name, precision, min_shapes, monkeypatch):
+    """Each shape of the one-right-hand-side packed substitutions (lanes per workgroup, tiles per
+    lane, ring depth, lanes per row) that the windows fit, forced with LSW_SYM_CONFIG, against the
+    oracle's application and against each other; widest_windows_2x2 has windows 162 wide."""
+    c = CASES[name]
+    X = torch.from_numpy(inputs.complex_normal((2, c.N), 8)).cuda()
+    zo = c.oracle.apply(X[1].cpu().numpy())
+    monkeypatch.setenv("LSW_RHS_PER_WORKGROUP", "1")
+    bar = 1e-12 if precision == "fp64" else 2e-6
+    seen = {}
+    for i in SYM_SHAPE_INDICES:
+        monkeypatch.setenv("LSW_SYM_CONFIG", str(i))
+        s = c.solver(precision=precision, nrhs_max=2)
+        st = s.stats()
+        assert st["symmetric_factors"] == 1
+        shape = (st["sym_threads"], st["sym_tiles_per_lane"], st["sym_ring"], st["sym_lanes_per_row"])
+        if shape in seen:
+            s.close()
+            continue
+        Z = s.apply(X).cpu().numpy().reshape(2, -1)
+        s.close()
+        check(f"{name} {precision} packed shape {shape} vs oracle", Z[1], zo, bar, cdd=c.oracle, shape=c.m.shape)
+        seen[shape] = Z
+    say(name, precision, "shapes", sorted(seen))
+    assert len(seen) >= min_shapes
+    first = next(iter(seen.values()))
+    for shape, Z in seen.items():
+        for k in range(2):
+            assert rel(Z[k], first[k]) < (1e-13 if precision == "fp64" else 2e-6), (shape, k)
+
+
+def test_packed_kernel_shape_is_tuned_at_setup(monkeypatch):
+    monkeypatch.delenv("LSW_SYM_CONFIG", raising=False)
+    c = CASES["const127_4x4"]
+    s = c.solver(precision="mixed", nrhs_max=1)
+    st = s.stats()
+    s.close()
+    say("packed shape", st["sym_threads"], st["sym_tiles_per_lane"], st["sym_ring"], st["sym_lanes_per_row"],
+        "timed", st["sym_shapes_timed"], st["sym_tune_best_ms"], st["sym_tune_worst_ms"])
+    assert st["sym_shapes_timed"] >= 2 and 0 < st["sym_tune_best_ms"] <= st["sym_tune_worst_ms"]
 
 
 def test_rhs_per_workgroup_is_tuned_at_setup():
