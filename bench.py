@@ -101,22 +101,17 @@ def counter_traffic(kernel: str, workload: str):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary of the
     workload (scaled FETCH_SIZE + WRITE_SIZE), or None when there is none or the kernel's source
     changed since the counters were taken."""
-    import hashlib
-
     path = os.path.join(ROOT, "profiles", f"{workload}_mixed_hbm_traffic.txt")
     csrc = os.path.join(ROOT, "paper_1909_01467_amd", "csrc")
     try:
         text = open(path).read()
     except OSError:
         return None
-    if workload.endswith("3d"):   # the summary records the sha of the kernel's own source text
-        sha = kernel_source_sha(os.path.join(csrc, "kernels3d.hip"), kernel.split("<")[0])
-        if sha is None or f"{kernel.split('<')[0]} source sha256[:16] = {sha}" not in text:
-            return None
-    else:
-        sha = hashlib.sha256(open(os.path.join(csrc, "kernels.hip"), "rb").read()).hexdigest()[:16]
-        if f"sha256[:16] = {sha}" not in text:
-            return None
+    # the summary records the sha of the kernel's own source text
+    base = kernel.split("<")[0]
+    sha = kernel_source_sha(os.path.join(csrc, "kernels3d.hip" if workload.endswith("3d") else "kernels.hip"), base)
+    if sha is None or f"{base} source sha256[:16] = {sha}" not in text:
+        return None
     for line in text.splitlines():
         parts = line.split()
         if len(parts) == 3 and parts[0] == "traffic" and parts[1] == kernel:
@@ -300,21 +295,33 @@ def main():
                                 ms=med["last_dom_ms"]),
             }
     else:
-        # the one-right-hand-side substitutions read the packed symmetric factors when built;
-        # with windows every family runs once per CDD (four times)
+        # the substitutions: one right-hand side per workgroup on the packed symmetric factors
+        # (k_chain_sym, every right-hand side reads every block), or R per workgroup on the full
+        # blocks (k_chain_mr, R = 2 or 4; k_chain_mma on matrix cores, R = 16 or 32), each block
+        # read once per group of R; the sweeps read Q' once per launch for the whole batch.  With
+        # windows every family runs once per CDD (four times).
         sym = bool(st.get("symmetric_factors"))
         ncdd = st["cdd_count"]
-        chain = "k_chain_sym" if sym else "k_chain"
-        layout = ("packed symmetric factors, 4x4 tiles of the upper triangle" if sym else "full factor blocks")
+        R = st["rhs_per_workgroup"] if nrhs > 1 else 1
+        if R == 1:
+            chain = "k_chain_sym" if sym else "k_chain"
+            layout = ("packed symmetric factors, 4x4 tiles of the upper triangle" if sym else "full factor blocks")
+            s1_bytes, fi_bytes = nrhs * st["apply_stage1_bytes"], nrhs * st["apply_final_bytes"]
+        else:
+            groups = -(-nrhs // R)
+            chain = "k_chain_mma" if R >= 16 else "k_chain_mr"
+            layout = (f"full factor blocks, {R} right-hand sides per workgroup"
+                      + (" as W x W by W x R products on matrix cores" if R >= 16 else ""))
+            s1_bytes, fi_bytes = groups * st["apply_stage1_full_bytes"], groups * st["apply_final_full_bytes"]
         kernels = {
             f"{chain}<CS_STAGE1>": dict(desc=f"stage-1 block substitutions, twisted (forward halves; middle + backward "
                                              f"halves), {layout}",
-                                        launches=2 * ncdd, bytes=st["apply_stage1_bytes"], ms=med["last_stage1_ms"]),
+                                        launches=2 * ncdd, bytes=s1_bytes, ms=med["last_stage1_ms"]),
             "k_gemv": dict(desc="trace-compressed sweep fronts: out = Q' u~ per solve (batched GEMV)",
                            launches=st["gemv_launches"], bytes=st["apply_gemv_bytes"], ms=med["last_gemv_ms"]),
             f"{chain}<CS_FINAL>": dict(desc=f"final z block substitutions, twisted (forward halves; middle + backward "
                                             f"halves), {layout}",
-                                       launches=2 * ncdd, bytes=st["apply_final_bytes"], ms=med["last_final_ms"]),
+                                       launches=2 * ncdd, bytes=fi_bytes, ms=med["last_final_ms"]),
         }
     for k in kernels.values():
         k["bytes_per_launch"] = k["bytes"] / max(1, k["launches"])
@@ -323,7 +330,7 @@ def main():
     dom_name = max((n for n in kernels if kernels[n]["launches"]), key=lambda n: kernels[n]["ms"])
     dom = kernels[dom_name]
     achieved = dom["gbps"]
-    apply_bytes = st["apply_chain_bytes"] + st["apply_gemv_bytes"]
+    apply_bytes = sum(k["bytes"] for k in kernels.values())   # algorithmic bytes of one application of the batch
     out = {
         "metric": METRIC,
         "value": round(main_r["ms"], 3),

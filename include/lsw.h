@@ -178,6 +178,9 @@ typedef struct {
     int sym_threads, sym_tiles_per_lane, sym_ring, sym_lanes_per_row;
     int sym_shapes_timed;        /* shapes timed at setup (0: one fits, or fixed) */
     double sym_tune_best_ms, sym_tune_worst_ms;   /* their fastest and slowest time (both fronts) */
+    /* 2D: apply_stage1_bytes and apply_final_bytes on the full W x W blocks, which the substitutions
+     * with R > 1 right-hand sides per workgroup read once per group of R */
+    double apply_stage1_full_bytes, apply_final_full_bytes;
 } lsw_stats_t;
 
 /* Size of the per-GPU scratch array of lsw_apply_noalloc (64 MiB). */

@@ -151,6 +151,7 @@ struct lsw_plan {
     void* d_scratch = nullptr;
     size_t sz_traces = 0, sz_Y = 0, sz_fw = 0, sz_zpart = 0, sz_rhs3 = 0, sz_Y3 = 0, sz_P3 = 0;
     double apply_stage1_bytes = 0, apply_final_bytes = 0;
+    double apply_stage1_full_bytes = 0, apply_final_full_bytes = 0;   // the same on the full blocks
     // scenario 4 (Sec. 2.1): this plan is the unshifted CDD; shifted[] holds the CDDs shifted along
     // x, y and both, each a complete plan without a Krylov basis (member = true)
     int windows = 0, shift_x = 0, shift_y = 0;
@@ -1542,6 +1543,7 @@ int setup_impl(lsw_plan* p, const double* d_m, double omega, double h, const lsw
     }
     const size_t eb = p->precision == LSW_MIXED ? sizeof(c64) : sizeof(c128);
     p->apply_chain_bytes = p->apply_gemv_bytes = p->apply_stage1_bytes = p->apply_final_bytes = 0;
+    p->apply_stage1_full_bytes = p->apply_final_full_bytes = 0;
     p->chain_launches = p->gemv_launches = 0;
     for (const Front& f : p->fronts) {
         if (f.gemv) {
@@ -1574,9 +1576,15 @@ int setup_impl(lsw_plan* p, const double* d_m, double omega, double h, const lsw
                 // full blocks W^2 entries; packed blocks 16 per 4x4 tile of the upper triangle
                 const double per = p->gsym ? (double)sym_block(s.W) : s.W * (double)s.W;
                 const double bytes = blocks * per * eb;
+                const double full = blocks * s.W * (double)s.W * eb;
                 p->apply_chain_bytes += bytes;
-                if (&f == &p->fronts.front()) p->apply_stage1_bytes += bytes;
-                else if (&f == &p->fronts.back()) p->apply_final_bytes += bytes;
+                if (&f == &p->fronts.front()) {
+                    p->apply_stage1_bytes += bytes;
+                    p->apply_stage1_full_bytes += full;
+                } else if (&f == &p->fronts.back()) {
+                    p->apply_final_bytes += bytes;
+                    p->apply_final_full_bytes += full;
+                }
             }
         }
     }
@@ -2211,6 +2219,8 @@ int lsw_query(lsw_handle_t p, lsw_stats_t* st) {
         st->sym_lanes_per_row = c.lanes_per_row;
     }
     st->sym_shapes_timed = p->sym_timed;
+    st->apply_stage1_full_bytes = p->apply_stage1_full_bytes;
+    st->apply_final_full_bytes = p->apply_final_full_bytes;
     st->sym_tune_best_ms = p->sym_tune_best_ms;
     st->sym_tune_worst_ms = p->sym_tune_worst_ms;
     st->packed_factor_elems = p->gsym ? (long long)p->GS_elems : 0;
@@ -2240,6 +2250,8 @@ int lsw_query(lsw_handle_t p, lsw_stats_t* st) {
             st->t_q_ms += c->t_q_ms;
             st->apply_stage1_bytes += c->apply_stage1_bytes;
             st->apply_final_bytes += c->apply_final_bytes;
+            st->apply_stage1_full_bytes += c->apply_stage1_full_bytes;
+            st->apply_final_full_bytes += c->apply_final_full_bytes;
             st->packed_factor_elems += c->gsym ? (long long)c->GS_elems : 0;
             st->gemv_items += (int)c->gitems.size();
             st->gemv_max_inputs = std::max(st->gemv_max_inputs, c->max_nin);

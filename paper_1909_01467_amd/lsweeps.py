@@ -84,7 +84,8 @@ class lsw_stats_t(ctypes.Structure):
                 ("noalloc_bytes", ctypes.c_longlong), ("sym_threads", ctypes.c_int),
                 ("sym_tiles_per_lane", ctypes.c_int), ("sym_ring", ctypes.c_int), ("sym_lanes_per_row", ctypes.c_int),
                 ("sym_shapes_timed", ctypes.c_int), ("sym_tune_best_ms", ctypes.c_double),
-                ("sym_tune_worst_ms", ctypes.c_double)]
+                ("sym_tune_worst_ms", ctypes.c_double), ("apply_stage1_full_bytes", ctypes.c_double),
+                ("apply_final_full_bytes", ctypes.c_double)]
 
 
 _lib = None

@@ -21,18 +21,16 @@ def test_counter_summary_is_read_for_the_current_kernels():
     """bench.py's roofline traffic comes from the committed counter summary when it was taken on
     the current kernels; the scaled bytes per launch then lie within 1x-1.5x of the algorithmic
     bytes of the packed substitutions (158.3 MB per launch at 511^2, 8x8)."""
-    import hashlib
-
     import pytest
 
     sys.path.insert(0, ROOT)
     import bench
 
-    src = os.path.join(ROOT, "paper_1909_01467_amd", "csrc", "kernels.hip")
-    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    sha = bench.kernel_source_sha(os.path.join(ROOT, "paper_1909_01467_amd", "csrc", "kernels.hip"), "k_chain_sym")
+    assert sha is not None
     text = open(os.path.join(ROOT, "profiles", "lens2d_mixed_hbm_traffic.txt")).read()
-    if f"sha256[:16] = {sha}" not in text:
-        pytest.skip("the counters predate the current kernels (bench.py reports traffic null)")
+    if f"k_chain_sym source sha256[:16] = {sha}" not in text:
+        pytest.skip("the counters predate the current k_chain_sym (bench.py reports traffic null)")
     for kernel in ("k_chain_sym<CS_STAGE1>", "k_chain_sym<CS_FINAL>"):
         t = bench.counter_traffic(kernel, "lens2d")
         assert t is not None and 1.0 <= t / 158292992 <= 1.5, (kernel, t)
