@@ -181,6 +181,11 @@ typedef struct {
     /* 2D: apply_stage1_bytes and apply_final_bytes on the full W x W blocks, which the substitutions
      * with R > 1 right-hand sides per workgroup read once per group of R */
     double apply_stage1_full_bytes, apply_final_full_bytes;
+    /* 2D, nrhs_max > 1: 1 if the sweep levels of several right-hand sides run on matrix cores
+     * (Q' read once per work item for 16 or 32 right-hand sides), chosen at setup by timing every
+     * level both ways at nrhs_max, or fixed by the environment variable LSW_GEMV_MMA */
+    int gemv_mma;
+    double gemv_tune_ms[2];      /* those timings: batched GEMVs, matrix cores (0: not timed) */
 } lsw_stats_t;
 
 /* Size of the per-GPU scratch array of lsw_apply_noalloc (64 MiB). */

@@ -87,6 +87,8 @@ struct lsw_plan {
     int sweep_depth = 0;            // dependency levels of the sweep work items (one launch each)
     int rgroup = 1;                 // right-hand sides per workgroup of the stage-1 / final substitutions
     double rgroup_ms[5] = {0, 0, 0, 0, 0};   // timings of R = 1, 2, 4, 16, 32 when tuned
+    bool gemv_mma = false;                    // sweep levels of several right-hand sides on matrix cores
+    double gemv_ms[2] = {0, 0};               // setup timings of the sweep levels: k_gemv, k_gemv_mma
     int* d_frp = nullptr;           // final right-hand side: polarization terms per window point
     long long* d_fpool = nullptr;
     c128* d_fcoef = nullptr;
@@ -747,7 +749,7 @@ int apply_cdd(lsw_plan* p, const c128* d_r, c128* d_z, int nrhs, bool timed) {
             if (f.gemv) {
                 ga.items = p->d_gitems + f.ioffset;
                 ga.nitems = f.icount;
-                HIPCK(p, launch_gemv(ga, c64, p->stream));
+                HIPCK(p, p->gemv_mma && nrhs > 1 ? launch_gemv_mma(ga, c64, p->stream) : launch_gemv(ga, c64, p->stream));
             } else {
                 if (fi == nf - 1 && timed) HIPCK(p, hipEventRecord(p->ev[3], p->stream));
                 a.descs = p->d_descs + f.offset;
@@ -1286,6 +1288,46 @@ int tune_sym(lsw_plan* p) {
     p->sym_cfg = pick;
     p->sym_tune_best_ms = best;
     p->sym_tune_worst_ms = worst;
+    return LSW_OK;
+}
+
+// Whether the sweep levels of several right-hand sides run on matrix cores (k_gemv_mma, Q' read
+// once per item for 16 or 32 right-hand sides) or as batched GEMVs (k_gemv, 4 per pass over Q'):
+// every level is timed both ways at nrhs_max on the real Q' and the faster kept.  LSW_GEMV_MMA = 0
+// or 1 fixes the choice.
+int tune_gemv(lsw_plan* p) {
+    p->gemv_mma = false;
+    p->gemv_ms[0] = p->gemv_ms[1] = 0;
+    if (p->dim != 2 || p->sweep_mode != LSW_SWEEP_COMPRESSED || p->nrhs_max < 2) return LSW_OK;
+    if (const char* env = std::getenv("LSW_GEMV_MMA")) {
+        p->gemv_mma = std::atoi(env) != 0;
+        return LSW_OK;
+    }
+    const bool c64 = p->precision == LSW_MIXED;
+    GemvArgs ga{};
+    ga.nrhs = p->nrhs_max;
+    ga.Q = p->d_Q;
+    ga.traces = p->d_traces;
+    ga.trace_stride = p->trace_stride;
+    for (int mode = 0; mode < 2; ++mode) {
+        double tmin = 1e30;
+        for (int rep = 0; rep < 3; ++rep) {
+            HIPCK(p, hipEventRecord(p->ev[0], p->stream));
+            for (const Front& f : p->fronts) {
+                if (!f.gemv) continue;
+                ga.items = p->d_gitems + f.ioffset;
+                ga.nitems = f.icount;
+                HIPCK(p, mode ? launch_gemv_mma(ga, c64, p->stream) : launch_gemv(ga, c64, p->stream));
+            }
+            HIPCK(p, hipEventRecord(p->ev[1], p->stream));
+            HIPCK(p, hipEventSynchronize(p->ev[1]));
+            float ms = 0;
+            HIPCK(p, hipEventElapsedTime(&ms, p->ev[0], p->ev[1]));
+            if (rep > 0) tmin = std::min(tmin, (double)ms);   // the first run warms up
+        }
+        p->gemv_ms[mode] = tmin;
+    }
+    p->gemv_mma = p->gemv_ms[1] < p->gemv_ms[0];
     return LSW_OK;
 }
 
@@ -1876,6 +1918,7 @@ int setup_impl(lsw_plan* p, const double* d_m, double omega, double h, const lsw
     }
     if ((rc = tune_sym(p)) != LSW_OK) return rc;
     if ((rc = tune_rgroup(p)) != LSW_OK) return rc;
+    if ((rc = tune_gemv(p)) != LSW_OK) return rc;
     if (p->windows && (rc = setup_windows(p, d_m, omega, h, grid, cdd, pml, opts)) != LSW_OK) return rc;
     p->t_setup_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     return LSW_OK;
@@ -2220,6 +2263,9 @@ int lsw_query(lsw_handle_t p, lsw_stats_t* st) {
     }
     st->sym_shapes_timed = p->sym_timed;
     st->apply_stage1_full_bytes = p->apply_stage1_full_bytes;
+    st->gemv_mma = p->gemv_mma ? 1 : 0;
+    st->gemv_tune_ms[0] = p->gemv_ms[0];
+    st->gemv_tune_ms[1] = p->gemv_ms[1];
     st->apply_final_full_bytes = p->apply_final_full_bytes;
     st->sym_tune_best_ms = p->sym_tune_best_ms;
     st->sym_tune_worst_ms = p->sym_tune_worst_ms;

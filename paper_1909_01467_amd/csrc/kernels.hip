@@ -1911,6 +1911,112 @@ __global__ __launch_bounds__(256) void k_chain_mma(ChainArgs a) {
     }
 }
 
+// The sweep levels for many right-hand sides on matrix cores: per work item (at most 64 output
+// rows of one sweep solve) out[rows x R] = Q'[rows x nin] U[nin x R], U the incoming trace values
+// of R = 16 RB right-hand sides, gathered into LDS in chunks of KC inputs (zero past nin and past
+// the batch); wave w owns the 16-row block w.  Q' (column-pair layout of k_gemv) is read once per
+// item for all R right-hand sides, where k_gemv reads it once per chunk of 4.  Complex products as
+// four real ones; the outputs are written (or added, out_acc) as in k_gemv.
+template <typename T, int RB>
+__global__ __launch_bounds__(256) void k_gemv_mma(GemvArgs a) {
+    constexpr int NT = 256, R = 16 * RB, KC = 64;
+    // LDS row stride: the four 16-entry rows one MFMA step reads fall in different banks (float)
+    constexpr int SR = (sizeof(T) == 4 && R == 32) ? 48 : R;
+    using M = Mfma<T>;
+    using acc_t = typename M::acc;
+    __shared__ T sUr[KC][SR], sUi[KC][SR];
+    __shared__ long long sOff[KC];
+    const GemvItem& it = a.items[blockIdx.x];
+    const int rhs0 = blockIdx.y * R, nr = min(R, a.nrhs - rhs0);
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, li = lane & 15, lk = lane >> 4;
+    const int nin = it.nin, ld = it.ld, nrow = it.nrow;
+    const __amdgpu_buffer_rsrc_t qr =
+        make_rsrc(reinterpret_cast<const cx<T>*>(a.Q) + it.qoff, (uint32_t)((size_t)it.qlen * sizeof(cx<T>)));
+    const int row = 16 * wv + li;   // the A-operand row of this lane
+    // Q'[row][k] sits at (k / 2) 2 ld + 2 row + k % 2; rows past the item read nothing
+    auto qload = [&](int k) -> cx<T> {
+        const uint32_t off = (row < nrow && k < nin)
+                                 ? (uint32_t)(((size_t)(k >> 1) * 2 * ld + 2 * row + (k & 1)) * sizeof(cx<T>))
+                                 : kOob;
+        return bload<T>(qr, off);
+    };
+    const cx<T>* trg = reinterpret_cast<const cx<T>*>(a.traces) + (size_t)rhs0 * a.trace_stride;
+    acc_t accr[RB], acci[RB];
+#pragma unroll
+    for (int bj = 0; bj < RB; ++bj) {
+        accr[bj] = acc_t{T(0), T(0), T(0), T(0)};
+        acci[bj] = acc_t{T(0), T(0), T(0), T(0)};
+    }
+    for (int c0 = 0; c0 < nin; c0 += KC) {
+        const int kc = min(KC, nin - c0);
+        for (int e = tid; e < KC; e += NT) {   // trace-pool offset of each input of the chunk
+            long long off = -1;
+            if (e < kc) {
+                int rg = 0, o = c0 + e;
+                while (o >= it.rng_len[rg]) {
+                    o -= it.rng_len[rg];
+                    ++rg;
+                }
+                off = it.rng_off[rg] + o;
+            }
+            sOff[e] = off;
+        }
+        __syncthreads();
+        for (int q = tid; q < KC * R; q += NT) {   // consecutive lanes: consecutive inputs of one rhs
+            const int r = q / KC, e = q - r * KC;
+            cx<T> v{T(0), T(0)};
+            if (r < nr && sOff[e] >= 0) v = trg[(size_t)r * a.trace_stride + sOff[e]];
+            sUr[e][r] = v.re;
+            sUi[e][r] = v.im;
+        }
+        __syncthreads();
+        // 16 inputs per round: the four Q' loads are issued before their products
+        for (int k16 = 0; k16 < kc; k16 += 16) {
+            cx<T> qv[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) qv[u] = qload(c0 + k16 + 4 * u + lk);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int e = k16 + 4 * u + lk;
+                if (k16 + 4 * u >= kc) break;
+#pragma unroll
+                for (int bj = 0; bj < RB; ++bj) {
+                    const T ur = sUr[e][16 * bj + li], ui = sUi[e][16 * bj + li];
+                    accr[bj] = M::mac(qv[u].re, ur, accr[bj]);
+                    accr[bj] = M::mac(-qv[u].im, ui, accr[bj]);
+                    acci[bj] = M::mac(qv[u].re, ui, acci[bj]);
+                    acci[bj] = M::mac(qv[u].im, ur, acci[bj]);
+                }
+            }
+        }
+        __syncthreads();
+    }
+    // accumulator entry v of lane l: row M::row(l / 16, v) of the wave's block, column l % 16
+    cx<T>* trw = reinterpret_cast<cx<T>*>(a.traces) + (size_t)rhs0 * a.trace_stride;
+#pragma unroll
+    for (int bj = 0; bj < RB; ++bj)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int orow = 16 * wv + M::row(lk, v), col = 16 * bj + li;
+            if (orow < nrow && col < nr) {
+                cx<T>* t = trw + (size_t)col * a.trace_stride + it.out_off + orow;
+                const cx<T> val{accr[bj][v], acci[bj][v]};
+                *t = it.out_acc ? *t + val : val;
+            }
+        }
+}
+
+hipError_t launch_gemv_mma(const GemvArgs& a, bool c64mode, hipStream_t st) {
+    if (a.nitems <= 0) return hipSuccess;
+    if (c64mode) {
+        if (a.nrhs > 16) k_gemv_mma<float, 2><<<dim3(a.nitems, (a.nrhs + 31) / 32), 256, 0, st>>>(a);
+        else k_gemv_mma<float, 1><<<dim3(a.nitems, 1), 256, 0, st>>>(a);
+    } else {
+        k_gemv_mma<double, 1><<<dim3(a.nitems, (a.nrhs + 15) / 16), 256, 0, st>>>(a);
+    }
+    return hipGetLastError();
+}
+
 template <typename T, int CS, int RB>
 static void launch_chain_mma_c(const ChainArgs& a, dim3 grid, hipStream_t st) {
     k_chain_mma<T, CS, RB, 0><<<grid, 256, 0, st>>>(a);

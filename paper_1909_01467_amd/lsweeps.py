@@ -85,7 +85,8 @@ class lsw_stats_t(ctypes.Structure):
                 ("sym_tiles_per_lane", ctypes.c_int), ("sym_ring", ctypes.c_int), ("sym_lanes_per_row", ctypes.c_int),
                 ("sym_shapes_timed", ctypes.c_int), ("sym_tune_best_ms", ctypes.c_double),
                 ("sym_tune_worst_ms", ctypes.c_double), ("apply_stage1_full_bytes", ctypes.c_double),
-                ("apply_final_full_bytes", ctypes.c_double)]
+                ("apply_final_full_bytes", ctypes.c_double), ("gemv_mma", ctypes.c_int),
+                ("gemv_tune_ms", ctypes.c_double * 2)]
 
 
 _lib = None
@@ -311,6 +312,7 @@ class Solver:
         out = {name: getattr(st, name) for name, _ in lsw_stats_t._fields_}
         out["tune_ms"] = list(out["tune_ms"])
         out["window_shift"] = list(out["window_shift"])
+        out["gemv_tune_ms"] = list(out["gemv_tune_ms"])
         return out
 
     def close(self):

@@ -472,6 +472,40 @@ def test_packed_kernel_shape_is_tuned_at_setup(monkeypatch):
     assert st["sym_shapes_timed"] >= 2 and 0 < st["sym_tune_best_ms"] <= st["sym_tune_worst_ms"]
 
 
+@pytest.mark.parametrize("nrhs", [5, 19])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_sweep_levels_on_matrix_cores(nrhs, precision, monkeypatch):
+    """The sweep levels of several right-hand sides on matrix cores (LSW_GEMV_MMA=1; 19 right-hand
+    sides take two 16-wide groups in complex128 and one 32-wide group in complex64) against the
+    batched GEMVs (LSW_GEMV_MMA=0) and the oracle's application."""
+    c = CASES["wide_4x5"]
+    X = torch.from_numpy(inputs.complex_normal((nrhs, c.N), 10)).cuda()
+    out = {}
+    for mode in ("0", "1"):
+        monkeypatch.setenv("LSW_GEMV_MMA", mode)
+        s = c.solver(precision=precision, nrhs_max=nrhs)
+        assert s.stats()["gemv_mma"] == int(mode)
+        out[mode] = s.apply(X).cpu().numpy().reshape(nrhs, -1)
+        s.close()
+    bar = 1e-12 if precision == "fp64" else 2e-6
+    for k in range(nrhs):
+        assert rel(out["1"][k], out["0"][k]) < bar, k
+    zo = c.oracle.apply(X[nrhs - 1].cpu().numpy())
+    check(f"wide_4x5 {nrhs} rhs sweeps on matrix cores {precision}", out["1"][nrhs - 1], zo, bar,
+          cdd=c.oracle, shape=c.m.shape)
+
+
+def test_sweep_kernel_is_tuned_at_setup(monkeypatch):
+    monkeypatch.delenv("LSW_GEMV_MMA", raising=False)
+    c = CASES["const127_4x4"]
+    s = c.solver(precision="mixed", nrhs_max=8)
+    st = s.stats()
+    s.close()
+    say("sweeps on matrix cores", st["gemv_mma"], st["gemv_tune_ms"])
+    assert all(t > 0 for t in st["gemv_tune_ms"])
+    assert st["gemv_mma"] == (1 if st["gemv_tune_ms"][1] < st["gemv_tune_ms"][0] else 0)
+
+
 def test_rhs_per_workgroup_is_tuned_at_setup():
     c = CASES["const127_4x4"]
     s = c.solver(precision="mixed", nrhs_max=8)
