@@ -31,6 +31,7 @@ METRIC = "L-sweep GMRES solve time to 1e-6 rel. residual; subdomain-apply HBM GB
 MEDIA = {"const2d": "c = 1", "lens2d": "lens + 5% smooth noise", "layered2d": "12 dipping layers + 3 faults",
          "fwi2d": "lens + 5% Gaussian blobs", "lens3d": "Gaussian lens"}
 HBM_PEAK_GBS = 8000.0
+FP32_MATRIX_PEAK_TFLOPS = 157.3   # dense FP32 matrix-core peak of MI355X
 
 
 def log(*a):
@@ -313,23 +314,39 @@ def main():
             layout = (f"full factor blocks, {R} right-hand sides per workgroup"
                       + (" as W x W by W x R products on matrix cores" if R >= 16 else ""))
             s1_bytes, fi_bytes = groups * st["apply_stage1_full_bytes"], groups * st["apply_final_full_bytes"]
+        gemv_mma = nrhs > 1 and bool(st.get("gemv_mma"))
+        gemv = "k_gemv_mma" if gemv_mma else "k_gemv"
         kernels = {
             f"{chain}<CS_STAGE1>": dict(desc=f"stage-1 block substitutions, twisted (forward halves; middle + backward "
                                              f"halves), {layout}",
                                         launches=2 * ncdd, bytes=s1_bytes, ms=med["last_stage1_ms"]),
-            "k_gemv": dict(desc="trace-compressed sweep fronts: out = Q' u~ per solve (batched GEMV)",
-                           launches=st["gemv_launches"], bytes=st["apply_gemv_bytes"], ms=med["last_gemv_ms"]),
+            gemv: dict(desc=("trace-compressed sweep fronts: out = Q' u~ per solve, " +
+                             ("16 or 32 right-hand sides per workgroup on matrix cores" if gemv_mma else
+                              "batched GEMV")),
+                       launches=st["gemv_launches"], bytes=st["apply_gemv_bytes"], ms=med["last_gemv_ms"]),
             f"{chain}<CS_FINAL>": dict(desc=f"final z block substitutions, twisted (forward halves; middle + backward "
                                             f"halves), {layout}",
                                        launches=2 * ncdd, bytes=fi_bytes, ms=med["last_final_ms"]),
         }
+        # matrix-core kernels: 8 real flops per complex entry read and right-hand side (complex64
+        # entries of 8 bytes: flops = bytes read per group x right-hand sides)
+        if R >= 16:
+            kernels[f"{chain}<CS_STAGE1>"]["flops"] = st["apply_stage1_full_bytes"] * nrhs
+            kernels[f"{chain}<CS_FINAL>"]["flops"] = st["apply_final_full_bytes"] * nrhs
+        if gemv_mma:
+            kernels[gemv]["flops"] = st["apply_gemv_bytes"] * nrhs
     for k in kernels.values():
         k["bytes_per_launch"] = k["bytes"] / max(1, k["launches"])
         k["avg_launch_ms"] = k["ms"] / max(1, k["launches"])
         k["gbps"] = k["bytes_per_launch"] / max(1e-12, k["avg_launch_ms"] * 1e-3) / 1e9 if k["launches"] else 0.0
+        if k.get("flops"):
+            k["tflops"] = k["flops"] / max(1, k["launches"]) / max(1e-12, k["avg_launch_ms"] * 1e-3) / 1e12
     dom_name = max((n for n in kernels if kernels[n]["launches"]), key=lambda n: kernels[n]["ms"])
     dom = kernels[dom_name]
     achieved = dom["gbps"]
+    mfma = dom.get("flops", 0) > 0   # a matrix-core kernel: priced against the FP32 matrix peak
+    if mfma:
+        achieved = dom["flops"] / max(1, dom["launches"]) / max(1e-12, dom["avg_launch_ms"] * 1e-3) / 1e12
     apply_bytes = sum(k["bytes"] for k in kernels.values())   # algorithmic bytes of one application of the batch
     out = {
         "metric": METRIC,
@@ -367,12 +384,12 @@ def main():
                         for n, k in kernels.items()},
         },
         "roofline": {
-            "bound": "hbm",
+            "bound": "mfma" if mfma else "hbm",
             "kernel": f"{dom_name}: {dom['desc']}",
             "achieved": round(achieved, 1),
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "peak": FP32_MATRIX_PEAK_TFLOPS if mfma else HBM_PEAK_GBS,
+            "unit": "TFLOP/s" if mfma else "GB/s",
+            "frac": round(achieved / (FP32_MATRIX_PEAK_TFLOPS if mfma else HBM_PEAK_GBS), 4),
             "traffic": (counter_traffic(dom_name, args.workload)
                         if not args.windows and not args.all_sources else None),
             "algorithmic_bytes_per_launch": round(dom["bytes_per_launch"]),
