@@ -93,6 +93,12 @@ def test_setup_rejects_bad_geometry_before_touching_memory():
     rc = lib.lsw_setup(ctypes.byref(h), ctypes.c_void_p(1), 10.0, 0.1, ctypes.byref(grid), ctypes.byref(cdd),
                        None, None)
     assert rc == lsweeps.LSW_EINVAL and b"4096" in lib.lsw_last_error(None)
+    grid = lsweeps.lsw_grid_t(2, (ctypes.c_int * 3)(486, 30, 0), (ctypes.c_int * 3)(6, 6, 0))
+    cdd = lsweeps.lsw_cdd_t(1, 2)     # windows of 257 points, one past the largest the kernels take
+    pml = lsweeps.lsw_pml_t(0.0, 6)
+    rc = lib.lsw_setup(ctypes.byref(h), ctypes.c_void_p(1), 10.0, 0.1, ctypes.byref(grid), ctypes.byref(cdd),
+                       ctypes.byref(pml), None)
+    assert rc == lsweeps.LSW_EINVAL and b"wider than 256" in lib.lsw_last_error(None)
     grid = lsweeps.lsw_grid_t(2, (ctypes.c_int * 3)(20, 20, 0), (ctypes.c_int * 3)(5, 5, 0))
     cdd = lsweeps.lsw_cdd_t(16, 16)   # groups of a single point
     rc = lib.lsw_setup(ctypes.byref(h), ctypes.c_void_p(1), 10.0, 0.1, ctypes.byref(grid), ctypes.byref(cdd),

@@ -124,6 +124,26 @@ def test_apply3_single_beam_is_the_exact_inverse():
     check("single beam apply3 = A^-1", z, u, 1e-12)
 
 
+def test_apply3_on_planes_of_the_largest_size():
+    """One beam whose xy planes hold 4096 points, the largest the kernels take (more are refused:
+    test_abi): the application is A^-1, checked through its residual with the oracle's assembled
+    7-point operator, and the complex64 application against the FP64 one."""
+    c = Case3("max_plane", (56, 56, 4), (4, 4, 3), 1, 1)
+    r = inputs.complex_normal(c.m.size, 55)
+    s = c.solver()
+    st = s.stats()
+    assert st["W_max"] * st["H_max"] == 4096
+    z = s.apply(torch.from_numpy(r).cuda()).cpu().numpy().ravel()
+    s.close()
+    res = float(np.linalg.norm(c.gp.A @ z - r) / np.linalg.norm(r))
+    say("max plane (4096 points) apply3 fp64 residual", res)
+    assert res < 1e-9
+    s = c.solver(precision="mixed")
+    zm = s.apply(torch.from_numpy(r).cuda()).cpu().numpy().ravel()
+    s.close()
+    check("max plane (4096 points) apply3 mixed vs fp64", zm, z, 5e-6)
+
+
 def test_apply3_batches_rhs_and_is_deterministic():
     c = CASES["ragged_3x2"]
     R = torch.from_numpy(np.stack([inputs.complex_normal(c.m.size, 60 + k) for k in range(3)])).cuda()

@@ -506,6 +506,23 @@ def test_sweep_kernel_is_tuned_at_setup(monkeypatch):
     assert st["gemv_mma"] == (1 if st["gemv_tune_ms"][1] < st["gemv_tune_ms"][0] else 0)
 
 
+def test_windows_of_the_largest_width():
+    """Windows exactly 256 points wide, the largest the kernels take (257 is refused: test_abi): the
+    blocked Gauss-Jordan on 256 x 256 line blocks, the unit solves for Q on matrix cores and the
+    full-block substitutions (wider than the packed kernel takes), against the oracle's application
+    in both precisions."""
+    c = Case("max_window_1x2", 484, 30, 6, 6, 1, 2, pl=6)   # windows of 256 x 42 points
+    x = inputs.complex_normal(c.N, 11)
+    zo = c.oracle.apply(x)
+    for precision, bar in (("fp64", 1e-12), ("mixed", 2e-6)):
+        s = c.solver(precision=precision)
+        st = s.stats()
+        assert st["W_max"] == 256 and st["symmetric_factors"] == 0
+        z = s.apply(torch.from_numpy(x).cuda()).cpu().numpy().ravel()
+        s.close()
+        check(f"max_window_1x2 (W = 256) apply {precision}", z, zo, bar, cdd=c.oracle, shape=c.m.shape)
+
+
 def test_rhs_per_workgroup_is_tuned_at_setup():
     c = CASES["const127_4x4"]
     s = c.solver(precision="mixed", nrhs_max=8)
