@@ -703,7 +703,7 @@ int setup_windows(lsw_plan* p, const double* d_m, double omega, double h, const 
 // workgroup on the full blocks, or one per workgroup on the packed symmetric blocks when present
 hipError_t launch_block_front(lsw_plan* p, ChainArgs a, const Front& f, int nrhs, int cs, int R) {
     const bool c64 = p->precision == LSW_MIXED;
-    if (R >= 16 && nrhs > 1) return launch_chain_mma(a, f.count, nrhs, c64, cs, R, p->stream);
+    if (R >= 16 && nrhs > 1) return launch_chain_mma(a, f.count, nrhs, c64, cs, R, p->Wmax, p->stream);
     if (R > 1 && nrhs > 1) return launch_chain_mr(a, f.count, nrhs, p->ept, c64, cs, R, p->stream);
     if (p->gsym) {
         a.G = p->d_Gs;
@@ -1862,7 +1862,7 @@ int setup_impl(lsw_plan* p, const double* d_m, double omega, double h, const lsw
         ua.descs = d_units;
         for (size_t g0 = 0; g0 < ngroups; g0 += kGroupsPerLaunch) {
             ua.ugroups = d_groups + 4 * g0;
-            HIPCK(p, launch_chain_mma_unit(ua, (int)std::min<size_t>(kGroupsPerLaunch, ngroups - g0), p->stream));
+            HIPCK(p, launch_chain_mma_unit(ua, (int)std::min<size_t>(kGroupsPerLaunch, ngroups - g0), p->Wmax, p->stream));
         }
         HIPCK(p, hipStreamSynchronize(p->stream));
         dfree(p, d_units);

@@ -1667,7 +1667,7 @@ struct Mfma<double> {
 // k_chain_mr, whose phases, ranges and outputs this kernel shares.  With CS_UNIT a workgroup carries
 // a group of up to R unit solves of one subdomain (the columns of Q): right-hand side r is the unit
 // vector at window point (unit_k, unit_c) of the group's r-th unit descriptor.
-template <typename T, int CS, int RB, int PH>
+template <typename T, int CS, int RB, int PH, int QM>
 __global__ __launch_bounds__(256) void k_chain_mma(ChainArgs a) {
     static_assert(CS == CS_STAGE1 || CS == CS_FINAL || CS == CS_UNIT, "stage-1, final and unit solves");
     constexpr int NT = 256, R = 16 * RB;
@@ -1689,7 +1689,7 @@ __global__ __launch_bounds__(256) void k_chain_mma(ChainArgs a) {
     }
     const int W = s.W, H = s.H, m = s.mid, tid = threadIdx.x;
     const int lane = tid & 63, wv = tid >> 6, li = lane & 15, lk = lane >> 4;
-    const int NB = (W + 15) / 16;
+    const int NB = (W + 15) / 16;   // row blocks of 16, at most 4 QM (wave w owns w, w + 4, ...)
     __shared__ cx<T> sV[kMaxWindow][R];     // rows past W stay zero
     __shared__ c128 a2h[kMaxWindow + 1];
     const c128* tab = a.geo.tab;
@@ -1717,44 +1717,48 @@ __global__ __launch_bounds__(256) void k_chain_mma(ChainArgs a) {
         return reinterpret_cast<cx<T>*>(a.Y) + j * a.Y_stride;
     };
 
-    acc_t accr[4][RB], acci[4][RB];
+    acc_t accr[QM][RB], acci[QM][RB];
     // acc = G_k V over this wave's row blocks
     auto product = [&](int k) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q)
+        for (int q = 0; q < QM; ++q)
 #pragma unroll
             for (int bj = 0; bj < RB; ++bj) {
                 accr[q][bj] = acc_t{T(0), T(0), T(0), T(0)};
                 acci[q][bj] = acc_t{T(0), T(0), T(0), T(0)};
             }
         const cx<T>* Gk = Gs + (size_t)k * W * W;
-        // 32 columns of G_k per round: the loads of all 8 k-steps are issued before their products,
-        // so a block step waits for memory once per 32 columns instead of once per 4
-        constexpr int U = 8;
+        // 32 columns of G_k per round (24 in complex128): the loads of all U k-steps are issued
+        // before their products, so a block step waits for memory once per round instead of once
+        // per 4 columns; the columns of V come from LDS at the product.  Both keep a wave within
+        // 256 registers, so two waves share a SIMD
+        constexpr int U = sizeof(T) == 8 ? 6 : 8;
         for (int c0 = 0; c0 < W; c0 += 4 * U) {
-            cx<T> g[U][4];
-            cx<T> vb[U][RB];
+            cx<T> g[U][QM];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const int c = c0 + 4 * u + lk;
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
+                for (int q = 0; q < QM; ++q) {
                     const int row = 16 * (wv + 4 * q) + li;
                     g[u][q] = (c < W && row < W) ? Gk[(size_t)c * W + row] : zero();
                 }
-#pragma unroll
-                for (int bj = 0; bj < RB; ++bj) vb[u][bj] = sV[c < W ? c : kMaxWindow - 1][16 * bj + li];
             }
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const bool live = c0 + 4 * u < W;   // the same for the whole wave
+                if (!live) break;
+                const int c = c0 + 4 * u + lk;
+                cx<T> vb[RB];
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    if (!live || wv + 4 * q >= NB) break;
+                for (int bj = 0; bj < RB; ++bj) vb[bj] = sV[c < W ? c : kMaxWindow - 1][16 * bj + li];
+#pragma unroll
+                for (int q = 0; q < QM; ++q) {
+                    if (wv + 4 * q >= NB) break;
 #pragma unroll
                     for (int bj = 0; bj < RB; ++bj) {
                         // rows c >= W of V are zero, so padded columns add nothing
-                        const T gr = g[u][q].re, gi = g[u][q].im, vr = vb[u][bj].re, vi = vb[u][bj].im;
+                        const T gr = g[u][q].re, gi = g[u][q].im, vr = vb[bj].re, vi = vb[bj].im;
                         accr[q][bj] = M::mac(gr, vr, accr[q][bj]);
                         accr[q][bj] = M::mac(-gi, vi, accr[q][bj]);
                         acci[q][bj] = M::mac(gr, vi, acci[q][bj]);
@@ -1768,7 +1772,7 @@ __global__ __launch_bounds__(256) void k_chain_mma(ChainArgs a) {
     // result is y_k - product (y_k from slab[r][k W + x] when has_y)
     auto store = [&](size_t off, bool minus, int k, bool has_y) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
+        for (int q = 0; q < QM; ++q) {
             if (wv + 4 * q >= NB) break;
 #pragma unroll
             for (int bj = 0; bj < RB; ++bj)
@@ -2017,29 +2021,37 @@ hipError_t launch_gemv_mma(const GemvArgs& a, bool c64mode, hipStream_t st) {
     return hipGetLastError();
 }
 
+// QM: row blocks of 16 per wave, 3 for windows up to 192 points wide, 4 up to kMaxWindow (fewer
+// accumulators leave room for two waves per SIMD)
 template <typename T, int CS, int RB>
-static void launch_chain_mma_c(const ChainArgs& a, dim3 grid, hipStream_t st) {
-    k_chain_mma<T, CS, RB, 0><<<grid, 256, 0, st>>>(a);
-    k_chain_mma<T, CS, RB, 1><<<grid, 256, 0, st>>>(a);
+static void launch_chain_mma_c(const ChainArgs& a, dim3 grid, int wmax, hipStream_t st) {
+    if (wmax <= 192) {
+        k_chain_mma<T, CS, RB, 0, 3><<<grid, 256, 0, st>>>(a);
+        k_chain_mma<T, CS, RB, 1, 3><<<grid, 256, 0, st>>>(a);
+    } else {
+        k_chain_mma<T, CS, RB, 0, 4><<<grid, 256, 0, st>>>(a);
+        k_chain_mma<T, CS, RB, 1, 4><<<grid, 256, 0, st>>>(a);
+    }
 }
 
-hipError_t launch_chain_mma_unit(const ChainArgs& a, int ngroups, hipStream_t st) {
+hipError_t launch_chain_mma_unit(const ChainArgs& a, int ngroups, int wmax, hipStream_t st) {
     if (ngroups <= 0) return hipSuccess;
-    launch_chain_mma_c<double, CS_UNIT, 1>(a, dim3(2 * ngroups, 1), st);
+    launch_chain_mma_c<double, CS_UNIT, 1>(a, dim3(2 * ngroups, 1), wmax, st);
     return hipGetLastError();
 }
 
-hipError_t launch_chain_mma(const ChainArgs& a0, int nsolves, int nrhs, bool c64mode, int cs, int R, hipStream_t st) {
+hipError_t launch_chain_mma(const ChainArgs& a0, int nsolves, int nrhs, bool c64mode, int cs, int R, int wmax,
+                            hipStream_t st) {
     if ((cs != 0 && cs != 1) || (R != 16 && R != 32) || (!c64mode && R != 16)) return hipErrorInvalidValue;
     ChainArgs a = a0;
     a.nrhs = nrhs;
     const dim3 grid(2 * nsolves, (nrhs + R - 1) / R);
     if (c64mode) {
-        if (cs == 0) R == 16 ? launch_chain_mma_c<float, CS_STAGE1, 1>(a, grid, st) : launch_chain_mma_c<float, CS_STAGE1, 2>(a, grid, st);
-        else R == 16 ? launch_chain_mma_c<float, CS_FINAL, 1>(a, grid, st) : launch_chain_mma_c<float, CS_FINAL, 2>(a, grid, st);
+        if (cs == 0) R == 16 ? launch_chain_mma_c<float, CS_STAGE1, 1>(a, grid, wmax, st) : launch_chain_mma_c<float, CS_STAGE1, 2>(a, grid, wmax, st);
+        else R == 16 ? launch_chain_mma_c<float, CS_FINAL, 1>(a, grid, wmax, st) : launch_chain_mma_c<float, CS_FINAL, 2>(a, grid, wmax, st);
     } else {
-        if (cs == 0) launch_chain_mma_c<double, CS_STAGE1, 1>(a, grid, st);
-        else launch_chain_mma_c<double, CS_FINAL, 1>(a, grid, st);
+        if (cs == 0) launch_chain_mma_c<double, CS_STAGE1, 1>(a, grid, wmax, st);
+        else launch_chain_mma_c<double, CS_FINAL, 1>(a, grid, wmax, st);
     }
     return hipGetLastError();
 }

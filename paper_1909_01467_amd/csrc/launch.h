@@ -123,8 +123,10 @@ inline bool sym_cfg_fits(int cfg, bool c64mode, int W) {
 // (Y_stride >= 2 H_max W_max)
 hipError_t prepare_chain_sym(int cfg, size_t lds);
 // The stage-1 (cs 0) or final (cs 1) substitutions with R = 16 or 32 right-hand sides per workgroup
-// on matrix cores (full blocks in a.G; R = 32 in complex64 only); two launches like launch_chain_mr.
-hipError_t launch_chain_mma(const ChainArgs& a, int nsolves, int nrhs, bool c64mode, int cs, int R, hipStream_t st);
+// on matrix cores (full blocks in a.G; R = 32 in complex64 only); two launches like launch_chain_mr;
+// wmax = the widest window of the launch (sizes the per-wave accumulators).
+hipError_t launch_chain_mma(const ChainArgs& a, int nsolves, int nrhs, bool c64mode, int cs, int R, int wmax,
+                            hipStream_t st);
 // One dependency level of the trace-compressed sweeps for many right-hand sides on matrix cores
 // (k_gemv_mma: 16 or 32 right-hand sides per workgroup, Q' read once per item and group); the
 // same outputs as launch_gemv.
@@ -132,7 +134,7 @@ hipError_t launch_gemv_mma(const GemvArgs& a, bool c64mode, hipStream_t st);
 // The unit solves that build Q (complex128, full blocks in a.G): groups of up to 16 unit right-hand
 // sides of one subdomain (a.descs = the unit descriptors, a.ugroups = ngroups groups), group g's
 // right-hand side r using the y/x slab g * 16 + r of a.Y; each writes its column of a.Q.
-hipError_t launch_chain_mma_unit(const ChainArgs& a, int ngroups, hipStream_t st);
+hipError_t launch_chain_mma_unit(const ChainArgs& a, int ngroups, int wmax, hipStream_t st);
 hipError_t launch_chain_sym(const ChainArgs& a, int nsolves, int nrhs, int cfg, int cs, size_t lds, hipStream_t st);
 // packed symmetric copy (complex64 or complex128) of the FP64 factor pool
 hipError_t launch_pack_sym(const SubDesc* subs, int nsub, const c128* G, void* Gp, bool c64mode, hipStream_t st);
