@@ -1690,7 +1690,9 @@ __global__ __launch_bounds__(256) void k_chain_mma(ChainArgs a) {
     const int W = s.W, H = s.H, m = s.mid, tid = threadIdx.x;
     const int lane = tid & 63, wv = tid >> 6, li = lane & 15, lk = lane >> 4;
     const int NB = (W + 15) / 16;   // row blocks of 16, at most 4 QM (wave w owns w, w + 4, ...)
-    __shared__ cx<T> sV[kMaxWindow][R];     // rows past W stay zero
+    // rows past W stay zero; one padding entry per row, so that the row owners (thread x updates
+    // sV[x][.]) hit different LDS banks
+    __shared__ cx<T> sV[kMaxWindow][R + 1];
     __shared__ c128 a2h[kMaxWindow + 1];
     const c128* tab = a.geo.tab;
     const double ih2 = 1.0 / (a.geo.h * a.geo.h);
