@@ -88,6 +88,7 @@ struct lsw_plan {
     int rgroup = 1;                 // right-hand sides per workgroup of the stage-1 / final substitutions
     double rgroup_ms[5] = {0, 0, 0, 0, 0};   // timings of R = 1, 2, 4, 16, 32 when tuned
     bool gemv_mma = false;                    // sweep levels of several right-hand sides on matrix cores
+    int gs_fused = -1;                        // Gram-Schmidt in three sweeps over V: 1, four: 0, by size: -1
     double gemv_ms[2] = {0, 0};               // setup timings of the sweep levels: k_gemv, k_gemv_mma
     int* d_frp = nullptr;           // final right-hand side: polarization terms per window point
     long long* d_fpool = nullptr;
@@ -868,6 +869,11 @@ int solve_impl(lsw_plan* p, const c128* d_b, c128* d_x, int nrhs, lsw_info_t* in
     int applies = 0;
     c128* V = p->d_V;
     c128* Z = p->d_Z;
+    // The one-pass Gram-Schmidt kernels give every right-hand side d.nblk workgroups (the point
+    // order of the dot products), against nblk per column and up to 1024 for the updates in the
+    // four-sweep form: they pay once the batch holds a few million points (measured: 32 x 2077^2
+    // gains 7% of the solve, one 531^2 vector loses 2.5%).
+    const bool gs3 = p->gs_fused > 0 || (p->gs_fused < 0 && (double)N * nrhs >= 4.0e6);
     while (true) {
         // r = b - A x into V_0, beta = ||r||
         if ((rc = matvec_impl(p, d_x, V, d_b, nrhs)) != LSW_OK) return rc;
@@ -903,7 +909,22 @@ int solve_impl(lsw_plan* p, const c128* d_b, c128* d_x, int nrhs, lsw_info_t* in
             if ((rc2 = apply_impl(p, Vk, Zk, nrhs, false)) != LSW_OK) return rc2;
             applies++;
             if ((rc2 = matvec_impl(p, Zk, p->d_w, nullptr, nrhs)) != LSW_OK) return rc2;
-            for (int pass = 0; pass < 2; ++pass) {
+            const bool fused = gs3 && k + 1 <= kFusedGsMax;
+            if (fused) {
+                // the same two passes in three sweeps over V: the dots of pass 1 reading w once, the
+                // update of pass 1 fused with the dots of pass 2, the update of pass 2 with ||w||^2
+                c128* h1 = p->d_hbuf;
+                c128* h2 = p->d_hbuf + (m + 1);
+                DotsArgs d1{V, vl, N, p->d_w, N, p->N, k + 1, p->nblk, p->d_partial, h1, HS, 0};
+                HIPCK(p, launch_dots_w(d1, nrhs, p->stream));
+                GsArgs g1{V, vl, p->N, h1, HS, p->d_w, p->N, p->N, k + 1, -1, p->d_active, p->gsblk, nullptr, HS,
+                          nullptr};
+                DotsArgs d2{V, vl, N, p->d_w, N, p->N, k + 1, p->nblk, p->d_partial, h2, HS, 0};
+                HIPCK(p, launch_gs_dots(g1, d2, nrhs, p->stream));
+                if ((rc2 = gs_impl(p, V, vl, h2, HS, p->d_w, k + 1, -1, nrhs, p->d_hbuf + 2 * (m + 1), HS)) != LSW_OK)
+                    return rc2;
+            }
+            for (int pass = 0; pass < 2 && !fused; ++pass) {
                 c128* hcoef = p->d_hbuf + pass * (m + 1);
                 if ((rc2 = dots_impl(p, V, vl, N, p->d_w, N, k + 1, nrhs, hcoef, HS)) != LSW_OK) return rc2;
                 if ((rc2 = gs_impl(p, V, vl, hcoef, HS, p->d_w, k + 1, -1, nrhs,
@@ -1414,6 +1435,7 @@ int setup_impl(lsw_plan* p, const double* d_m, double omega, double h, const lsw
         own_sy = cdd->shift[1];
         if (own_sx < 0 || own_sy < 0) return fail(p, LSW_EINVAL, "cdd.shift must be >= 0");
     }
+    if (const char* env = std::getenv("LSW_FUSED_GS")) p->gs_fused = std::atoi(env) != 0 ? 1 : 0;
     p->omega = omega;
     p->h = h;
     p->C = (pml && pml->C > 0) ? pml->C : 16.0 * std::log(omega);

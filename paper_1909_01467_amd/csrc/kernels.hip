@@ -1503,6 +1503,80 @@ __global__ void k_gs_update(GsArgs a) {
     if (threadIdx.x == 0) a.partial[(size_t)rhs * gridDim.x + blockIdx.x] = part;
 }
 
+// All nv <= LC dot products <V_l, w> of one right-hand side in one pass over the points: w is read
+// once instead of once per column.  Points, workgroups and the partial layout are those of
+// k_dots_partial (same per-thread order, same tree), so the sums are bitwise the same.
+template <int LC>
+__global__ __launch_bounds__(256) void k_dots_w(DotsArgs a) {
+    __shared__ c128 red[256];
+    const int blk = blockIdx.x, rhs = blockIdx.y, nv = a.nv;
+    const c128* V = a.V + (size_t)rhs * a.vstride_rhs;
+    const c128* w = a.w + (size_t)rhs * a.wstride;
+    c128 acc[LC];
+#pragma unroll
+    for (int l = 0; l < LC; ++l) acc[l] = mk(0.0, 0.0);
+    for (size_t p = (size_t)blk * blockDim.x + threadIdx.x; p < a.N; p += (size_t)gridDim.x * blockDim.x) {
+        const c128 wp = w[p];
+#pragma unroll
+        for (int l = 0; l < LC; ++l)
+            if (l < nv) acc[l] = acc[l] + conj(V[(size_t)l * a.vstride_l + p]) * wp;
+    }
+#pragma unroll
+    for (int l = 0; l < LC; ++l) {
+        if (l < nv) {   // uniform
+            const c128 part = block_sum(acc[l], red);
+            if (threadIdx.x == 0) a.partial[((size_t)rhs * a.nv + l) * gridDim.x + blk] = part;
+            __syncthreads();   // red[0] read before the next sum overwrites it
+        }
+    }
+}
+
+// The first Gram-Schmidt update fused with the second pass's dot products (CGS2): per point,
+// w <- w + sign V c (as k_gs_update, active right-hand sides only) and then the partials of
+// <V_l, w> of the updated w, with the V_l of the point still in registers, so V is read once for
+// both.  Points, workgroups and the partial layout are those of k_dots_partial (d.nblk
+// workgroups per right-hand side), so the partials are bitwise those of a separate pass.
+template <int LC>
+__global__ __launch_bounds__(256) void k_gs_dots(GsArgs g, DotsArgs d) {
+    __shared__ c128 red[256];
+    const int blk = blockIdx.x, rhs = blockIdx.y, nv = d.nv;
+    const bool on = !(g.active && !g.active[rhs]);
+    const c128* cf = g.coef + (size_t)rhs * g.cstride;
+    const c128* V = g.V + (size_t)rhs * g.vstride_rhs;
+    c128* w = g.w + (size_t)rhs * g.wstride;
+    c128 c[LC], acc[LC];
+#pragma unroll
+    for (int l = 0; l < LC; ++l) {
+        c[l] = l < nv ? cf[l] : mk(0.0, 0.0);
+        acc[l] = mk(0.0, 0.0);
+    }
+    for (size_t p = (size_t)blk * blockDim.x + threadIdx.x; p < d.N; p += (size_t)gridDim.x * blockDim.x) {
+        c128 v[LC];
+#pragma unroll
+        for (int l = 0; l < LC; ++l) v[l] = l < nv ? V[(size_t)l * g.vstride_l + p] : mk(0.0, 0.0);
+        c128 wp = w[p];
+        if (on) {
+            c128 s = mk(0.0, 0.0);
+#pragma unroll
+            for (int l = 0; l < LC; ++l)
+                if (l < nv) s = s + v[l] * c[l];
+            wp = g.sign > 0 ? wp + s : wp - s;
+            w[p] = wp;
+        }
+#pragma unroll
+        for (int l = 0; l < LC; ++l)
+            if (l < nv) acc[l] = acc[l] + conj(v[l]) * wp;
+    }
+#pragma unroll
+    for (int l = 0; l < LC; ++l) {
+        if (l < nv) {   // uniform
+            const c128 part = block_sum(acc[l], red);
+            if (threadIdx.x == 0) d.partial[((size_t)rhs * nv + l) * gridDim.x + blk] = part;
+            __syncthreads();
+        }
+    }
+}
+
 // dst = src / sqrt(nrm2[rhs * nstride].re) (0 if the norm is 0), masked rhs skipped
 __global__ void k_scale(const c128* src, c128* dst, const c128* nrm2, int nstride, const int* active, size_t N,
                         size_t sstride, size_t dstride) {
@@ -2191,6 +2265,31 @@ hipError_t launch_matvec(const MatvecArgs& a, int nrhs, hipStream_t st) {
 hipError_t launch_dots(const DotsArgs& a, int nrhs, hipStream_t st) {
     k_dots_partial<<<dim3(a.nblk, a.nv, nrhs), 256, 0, st>>>(a);
     k_dots_finish<<<dim3(a.nv, nrhs), 256, 0, st>>>(a.partial, a.nblk, a.nv, a.out, a.ostride, a.accumulate);
+    return hipGetLastError();
+}
+
+template <typename F>
+static bool with_lc(int nv, F f) {
+    if (nv <= 4) f(std::integral_constant<int, 4>{});
+    else if (nv <= 8) f(std::integral_constant<int, 8>{});
+    else if (nv <= 16) f(std::integral_constant<int, 16>{});
+    else if (nv <= kFusedGsMax) f(std::integral_constant<int, kFusedGsMax>{});
+    else return false;
+    return true;
+}
+
+hipError_t launch_dots_w(const DotsArgs& a, int nrhs, hipStream_t st) {
+    if (!with_lc(a.nv, [&](auto lc) { k_dots_w<decltype(lc)::value><<<dim3(a.nblk, nrhs), 256, 0, st>>>(a); }))
+        return hipErrorInvalidValue;
+    k_dots_finish<<<dim3(a.nv, nrhs), 256, 0, st>>>(a.partial, a.nblk, a.nv, a.out, a.ostride, a.accumulate);
+    return hipGetLastError();
+}
+
+hipError_t launch_gs_dots(const GsArgs& g, const DotsArgs& d, int nrhs, hipStream_t st) {
+    if (g.nv != d.nv) return hipErrorInvalidValue;
+    if (!with_lc(d.nv, [&](auto lc) { k_gs_dots<decltype(lc)::value><<<dim3(d.nblk, nrhs), 256, 0, st>>>(g, d); }))
+        return hipErrorInvalidValue;
+    k_dots_finish<<<dim3(d.nv, nrhs), 256, 0, st>>>(d.partial, d.nblk, d.nv, d.out, d.ostride, d.accumulate);
     return hipGetLastError();
 }
 

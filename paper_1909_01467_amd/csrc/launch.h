@@ -157,6 +157,12 @@ hipError_t launch_matvec(const MatvecArgs& a, int nrhs, hipStream_t st);
 hipError_t launch_dots(const DotsArgs& a, int nrhs, hipStream_t st);
 // w -= V c (or +=), optionally followed by ||w||^2 (same point order as launch_dots)
 hipError_t launch_gs_update(const GsArgs& a, int nrhs, hipStream_t st);
+// the one-pass forms for nv <= kFusedGsMax columns (hipErrorInvalidValue above): launch_dots_w is
+// launch_dots reading w once; launch_gs_dots is launch_gs_update without the norm followed by
+// launch_dots of the updated w (d.w = g.w), reading V once; both give launch_dots' sums bitwise
+constexpr int kFusedGsMax = 24;
+hipError_t launch_dots_w(const DotsArgs& a, int nrhs, hipStream_t st);
+hipError_t launch_gs_dots(const GsArgs& g, const DotsArgs& d, int nrhs, hipStream_t st);
 // dst = src / ||.|| with the squared norm read from nrm2[rhs * nstride] on the device
 hipError_t launch_scale(const c128* src, c128* dst, const c128* nrm2, int nstride, const int* active, size_t N,
                         size_t sstride, size_t dstride, int nrhs, hipStream_t st);
