@@ -1542,7 +1542,8 @@ int setup_impl(lsw_plan* p, const double* d_m, double omega, double h, const lsw
             s.g_off = (long long)p->G_elems;
             s.gs_off = (long long)p->GS_elems;
             p->GS_elems += (size_t)s.H * sym_block(s.W);
-            p->sym_lds = std::max(p->sym_lds, (size_t)tile_nt(s.W) * sym_cstride(s.W));   // column sums c
+            // column sums c, and one zero row that the reduction reads past the last one
+            p->sym_lds = std::max(p->sym_lds, (size_t)(tile_nt(s.W) + 1) * sym_cstride(s.W));
             const size_t S3 = (size_t)s.W * s.H;
             p->G_elems += p->dim == 3 ? (size_t)p->Nz * S3 * S3 : (size_t)s.H * s.W * s.W;
             p->Smax = std::max(p->Smax, (int)S3);

@@ -781,7 +781,7 @@ __global__ __launch_bounds__(NT) void k_chain_sym(ChainArgs a) {
     static_assert(CS == CS_STAGE1 || CS == CS_FINAL, "stage 1 and final solves only");
     static_assert(RS == 1 || RS == 2 || RS == 4, "1, 2 or 4 lanes per row");
     extern __shared__ __align__(16) unsigned char dyn[];
-    cx<T>* cs = reinterpret_cast<cx<T>*>(dyn);   // c[J][r] at J * Wp + r
+    cx<T>* cs = reinterpret_cast<cx<T>*>(dyn);   // c[J][r] at J * Wp + r, J <= nt (row nt zero)
     const int sidx = blockIdx.x >> 1, h = blockIdx.x & 1, nsol = gridDim.x >> 1;
     const SolveDesc& dref = a.descs[sidx];
     const int kf0 = dref.kf0, kf1 = dref.kf1, kb0 = dref.kb0, kb1 = dref.kb1;
@@ -900,13 +900,16 @@ __global__ __launch_bounds__(NT) void k_chain_sym(ChainArgs a) {
     // (G_k v)_t for the row owners (every lane takes part: the group sums are lane exchanges)
     // every lane's share of the reduction is at most NRED partial sums (nt <= sym_nt_max(NT TPL))
     constexpr int NRED = (sym_nt_max(NT * TPL) + RS - 1) / RS;
+    // Every read and add is unconditional: a row index past nt reads row nt of c, which is zero, so all
+    // NRED reads are issued before the first wait (guarded reads compile to one branch and one LDS
+    // round trip each).
     auto reduce = [&]() {
         cx<T> y0 = zero(), y1 = zero();
 #pragma unroll
         for (int it = 0; it < NRED; it += 2) {
             const int J0 = rq + RS * it, J1 = J0 + RS;
-            if (J0 < nt) y0 = y0 + cs[J0 * Wp + tr];
-            if (it + 1 < NRED && J1 < nt) y1 = y1 + cs[J1 * Wp + tr];
+            y0 = y0 + cs[min(J0, nt) * Wp + tr];
+            if (it + 1 < NRED) y1 = y1 + cs[min(J1, nt) * Wp + tr];
         }
         cx<T> y = y0 + y1;
         y.re = lane_sum(y.re, RS);
@@ -918,7 +921,8 @@ __global__ __launch_bounds__(NT) void k_chain_sym(ChainArgs a) {
     c128 rr[PD + 1];
     cx<T> yr[PD + 1];
     cx<T> yv = zero();   // y (phase 0) or x (phase 1) of my row at the previous block row
-    __syncthreads();     // ay, ax, zero tail of v
+    for (int c = tid; c < Wp; c += NT) cs[nt * Wp + c] = zero();   // row nt of c: the reduction's padding
+    __syncthreads();     // ay, ax, zero tail of v, zero row of c
     iax = ax[tr];        // from LDS: no global load older than the ring is left for the loop to wait on
 
     if constexpr (PH == 0) {

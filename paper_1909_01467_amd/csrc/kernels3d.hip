@@ -878,16 +878,17 @@ __global__ __launch_bounds__(256) void k_red3(Chain3Args a, int smax, int phase,
     cx<T> acc{T(0), T(0)};
     for (int e0 = w; e0 < nb; e0 += 4 * EPW) {
         cx<T> v[EPW];
+        // every load is unconditional, so all EPW are in flight together (guarded loads compile to
+        // one branch and one wait each): an entry past nb reads the first one and is scaled by 0
 #pragma unroll
         for (int u = 0; u < EPW; ++u) {
-            const int e = e0 + 4 * u;
-            v[u] = cx<T>{T(0), T(0)};
-            if (e < nrow) {
-                v[u] = P[(size_t)(diag + e) * 128 + lane];
-            } else if (e < nb) {
-                const int I = e - nrow;
-                v[u] = P[(size_t)(I * nb - I * (I - 1) / 2 + (bI - I)) * 128 + 64 + lane];
-            }
+            const int e = e0 + 4 * u, I = e - nrow;
+            const size_t off = e < nrow ? (size_t)(diag + e) * 128 + lane
+                               : e < nb ? (size_t)(I * nb - I * (I - 1) / 2 + (bI - I)) * 128 + 64 + lane
+                                        : (size_t)diag * 128 + lane;
+            const T f = e < nb ? T(1) : T(0);
+            const cx<T> x = P[off];
+            v[u] = cx<T>{x.re * f, x.im * f};
         }
 #pragma unroll
         for (int u = 0; u < EPW; ++u) acc = acc + v[u];

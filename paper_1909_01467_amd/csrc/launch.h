@@ -119,7 +119,7 @@ inline bool sym_cfg_fits(int cfg, bool c64mode, int W) {
 // stage 1 (cs 0) or final (cs 1) substitutions, one right-hand side per workgroup, on the packed
 // symmetric factors (a.G = packed pool, SubDesc::gs_off) with shape kSymCfgs[cfg], which every
 // window must fit; lds = dynamic LDS bytes, >= the column sums of the widest window,
-// tile_nt(W) sym_cstride(W) entries (set once per shape with prepare_chain_sym); y and x in a.Y
+// (tile_nt(W) + 1) sym_cstride(W) entries (set once per shape with prepare_chain_sym); y and x in a.Y
 // (Y_stride >= 2 H_max W_max)
 hipError_t prepare_chain_sym(int cfg, size_t lds);
 // The stage-1 (cs 0) or final (cs 1) substitutions with R = 16 or 32 right-hand sides per workgroup
