@@ -1796,6 +1796,26 @@ __global__ __launch_bounds__(256) void k_chain_mma(ChainArgs a) {
         const size_t j = CS == CS_UNIT ? (size_t)sidx * R + r : (size_t)(rhs0 + r) * nsol + sidx;
         return reinterpret_cast<cx<T>*>(a.Y) + j * a.Y_stride;
     };
+    // rhs_at for the right-hand sides r0 .. r0 + 7 of an owner lane, with every load unconditional
+    // (an entry outside the ranges reads a valid one of right-hand side rhs0 and is scaled by 0), so
+    // that the eight are in flight together; guarded loads compile to one wait each
+    auto rhs_at8 = [&](int r0, int k, cx<T>* g) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int r = r0 + u;
+            if constexpr (CS == CS_UNIT) {
+                g[u] = rhs_at(r, k);
+            } else {
+                bool ok = r < nr && k >= kf0 && k <= kf1;
+                if constexpr (CS == CS_STAGE1) ok = ok && in_cols && k >= s.r0 && k < s.r1;
+                const size_t rhs = (size_t)rhs0 + (r < nr ? r : 0);
+                const c128 v = CS == CS_FINAL ? a.fw[rhs * a.fw_stride + s.fw_off + (size_t)k * W + tid]
+                                              : a.r[rhs * N + (size_t)(s.wy0 + k) * a.geo.Nx + s.wx0 + tid];
+                const double f = ok ? 1.0 : 0.0;
+                g[u] = cvt<T>(c128{v.re * f, v.im * f});
+            }
+        }
+    };
 
     acc_t accr[QM][RB], acci[QM][RB];
     // acc = G_k V over this wave's row blocks
@@ -1851,6 +1871,23 @@ __global__ __launch_bounds__(256) void k_chain_mma(ChainArgs a) {
     // the product's entries (row x, right-hand side r) into sV and slab[r][off + x]; with `minus`, the
     // result is y_k - product (y_k from slab[r][k W + x] when has_y)
     auto store = [&](size_t off, bool minus, int k, bool has_y) {
+        // with `minus`, the y entries first, all loads unconditional (an entry outside reads a valid one
+        // and is scaled by 0) so that they are in flight together
+        cx<T> yv[QM][RB][4];
+        if (minus) {
+#pragma unroll
+            for (int q = 0; q < QM; ++q)
+#pragma unroll
+                for (int bj = 0; bj < RB; ++bj)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int x = 16 * (wv + 4 * q) + M::row(lk, v), r = 16 * bj + li;
+                        const bool ok = has_y && r < nr && x < W && wv + 4 * q < NB;
+                        const cx<T> t = slab(r < nr ? r : 0)[(size_t)k * W + (x < W ? x : 0)];
+                        const T f = ok ? T(1) : T(0);
+                        yv[q][bj][v] = cx<T>{t.re * f, t.im * f};
+                    }
+        }
 #pragma unroll
         for (int q = 0; q < QM; ++q) {
             if (wv + 4 * q >= NB) break;
@@ -1861,10 +1898,7 @@ __global__ __launch_bounds__(256) void k_chain_mma(ChainArgs a) {
                     const int x = 16 * (wv + 4 * q) + M::row(lk, v), r = 16 * bj + li;
                     if (x >= W) continue;
                     cx<T> val = cx<T>{accr[q][bj][v], acci[q][bj][v]};
-                    if (minus) {
-                        const cx<T> y = (has_y && r < nr) ? slab(r)[(size_t)k * W + x] : zero();
-                        val = y - val;
-                    }
+                    if (minus) val = yv[q][bj][v] - val;
                     sV[x][r] = val;
                     if (r < nr) slab(r)[off + x] = val;
                 }
@@ -1881,11 +1915,15 @@ __global__ __launch_bounds__(256) void k_chain_mma(ChainArgs a) {
             const int k = kstart + dir * i;
             if (mine) {
                 const cx<T> c = cy(h == 0 ? k - 1 : k);
-#pragma unroll 4
-                for (int r = 0; r < R; ++r) {
-                    cx<T> g = rhs_at(r, k);
-                    if (i > 0) g = g - c * sV[tid][r];
-                    sV[tid][r] = g;
+                for (int r0 = 0; r0 < R; r0 += 8) {
+                    cx<T> g8[8];
+                    rhs_at8(r0, k, g8);
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        cx<T> g = g8[u];
+                        if (i > 0) g = g - c * sV[tid][r0 + u];
+                        sV[tid][r0 + u] = g;
+                    }
                 }
             }
             __syncthreads();
