@@ -1309,30 +1309,49 @@ __global__ __launch_bounds__(512) void k_gemv(GemvArgs a) {
     // columns c, c + 1 (c even) of this wave's share at my row, or nothing (no overlap with the
     // next wave's share, no rows past the chunk)
     auto qoff = [&](int c) { return (valid && c < i1) ? lo + (uint32_t)(c >> 1) * cs : kOob; };
+    // Gather of u~ (and of the outputs' old values when they are accumulated) for right-hand sides
+    // rc0 .. rc0 + RC - 1, as buffer loads from the trace pool of each: input idx lies in range rg
+    // when it is past the first rg ranges, at rng_off[rg] + idx - (lengths of ranges < rg) (unused
+    // ranges have length 0); an input past nin or a right-hand side past the batch reads zero (kOob).
+    // No load is guarded, so all of them are in flight together.
+    constexpr int GI = (4 * kMaxWindow + KB * NW + NT - 1) / NT;   // gather loads per lane
+    const int c1 = it.rng_len[0], c2 = c1 + it.rng_len[1], c3 = c2 + it.rng_len[2];
+    const long long d0 = it.rng_off[0], d1 = it.rng_off[1] - c1, d2 = it.rng_off[2] - c2, d3 = it.rng_off[3] - c3;
+    const uint32_t tbytes = (uint32_t)(a.trace_stride * sizeof(cx<T>));
+    cx<T> gl[RC][GI], old[RC];
+    auto gather = [&](int rc0) {
+#pragma unroll
+        for (int r = 0; r < RC; ++r) {
+            const bool live = rc0 + r < a.nrhs;
+            const __amdgpu_buffer_rsrc_t tr =
+                make_rsrc(reinterpret_cast<cx<T>*>(a.traces) + (size_t)(live ? rc0 + r : 0) * a.trace_stride, tbytes);
+#pragma unroll
+            for (int j = 0; j < GI; ++j) {
+                const int idx = tid + NT * j;
+                const long long e = (idx < c1 ? d0 : idx < c2 ? d1 : idx < c3 ? d2 : d3) + idx;
+                gl[r][j] = bload<T>(tr, (live && idx < nin) ? (uint32_t)(e * (long long)sizeof(cx<T>)) : kOob);
+            }
+            const bool acc = live && it.out_acc && wv == 0;
+            old[r] = bload<T>(tr, acc ? (uint32_t)((it.out_off + (valid ? lane : 0)) * (long long)sizeof(cx<T>)) : kOob);
+        }
+    };
+    // the first chunk's gather before the Q' loads: waiting for it leaves those in flight
+    gather(0);
     Pair<T> q[KP];
 #pragma unroll
     for (int u = 0; u < KP; ++u) q[u] = bload2<T>(qr, qoff(i0 + 2 * u));
-    for (int rc0 = 0; rc0 < a.nrhs; rc0 += RC) {
+    // one chunk of right-hand sides, its gather already issued; the first chunk is peeled off the loop
+    // so that the wait for its gather counts only the loads issued before the Q' loads
+    auto chunk = [&](int rc0) __attribute__((always_inline)) {
         const int nrc = min(RC, a.nrhs - rc0);
-        cx<T> old[RC];
-        // gather u~ of this chunk of right-hand sides (zero past nin so that the tail of a batch adds nothing)
+        // (zero past nin, so that the tail of a wave's share adds nothing)
 #pragma unroll
-        for (int r = 0; r < RC; ++r) {
-            old[r] = cx<T>{T(0), T(0)};
-            if (r < nrc) {
-                cx<T>* tr = reinterpret_cast<cx<T>*>(a.traces) + (size_t)(rc0 + r) * a.trace_stride;
-                if (it.out_acc && wv == 0) old[r] = tr[it.out_off + (valid ? lane : 0)];
-                for (int idx = tid; idx < per * NW; idx += NT) {
-                    cx<T> v{T(0), T(0)};
-                    if (idx < nin) {
-                        int rg = 0, off = idx;
-                        while (off >= it.rng_len[rg]) { off -= it.rng_len[rg]; ++rg; }
-                        v = tr[it.rng_off[rg] + off];
-                    }
-                    gv[r][idx] = v;
-                }
+        for (int r = 0; r < RC; ++r)
+#pragma unroll
+            for (int j = 0; j < GI; ++j) {
+                const int idx = tid + NT * j;
+                if (idx < per * NW) gv[r][idx] = gl[r][j];
             }
-        }
         __syncthreads();
         cx<T> acc[RC];
 #pragma unroll
@@ -1369,6 +1388,11 @@ __global__ __launch_bounds__(512) void k_gemv(GemvArgs a) {
             }
             __syncthreads();
         }
+    };
+    chunk(0);
+    for (int rc0 = RC; rc0 < a.nrhs; rc0 += RC) {
+        gather(rc0);
+        chunk(rc0);
     }
 }
 
