@@ -2071,7 +2071,6 @@ __global__ __launch_bounds__(256) void k_gemv_mma(GemvArgs a) {
     using M = Mfma<T>;
     using acc_t = typename M::acc;
     __shared__ T sUr[KC][SR], sUi[KC][SR];
-    __shared__ long long sOff[KC];
     const GemvItem& it = a.items[blockIdx.x];
     const int rhs0 = blockIdx.y * R, nr = min(R, a.nrhs - rhs0);
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, li = lane & 15, lk = lane >> 4;
@@ -2086,34 +2085,40 @@ __global__ __launch_bounds__(256) void k_gemv_mma(GemvArgs a) {
                                  : kOob;
         return bload<T>(qr, off);
     };
-    const cx<T>* trg = reinterpret_cast<const cx<T>*>(a.traces) + (size_t)rhs0 * a.trace_stride;
     acc_t accr[RB], acci[RB];
 #pragma unroll
     for (int bj = 0; bj < RB; ++bj) {
         accr[bj] = acc_t{T(0), T(0), T(0), T(0)};
         acci[bj] = acc_t{T(0), T(0), T(0), T(0)};
     }
+    // The gather of a chunk: lane l of wave w reads input e = l of the chunk for the right-hand sides
+    // w, w + 4, ... of the group (consecutive lanes, consecutive inputs of one right-hand side).  Input
+    // i lies in range rg when it is past the first rg ranges, at rng_off[rg] + i - (lengths of ranges
+    // < rg) (unused ranges have length 0).  Every load is a buffer load over one right-hand side's trace
+    // pool that reads zero past the inputs or the batch (kOob), so the GJ of a lane are in flight together.
+    constexpr int GJ = KC * R / NT;
+    static_assert(KC == 64 && NT == 256, "one input per lane, four right-hand sides per pass");
+    const int c1 = it.rng_len[0], c2 = c1 + it.rng_len[1], c3 = c2 + it.rng_len[2];
+    const long long d0 = it.rng_off[0], d1 = it.rng_off[1] - c1, d2 = it.rng_off[2] - c2, d3 = it.rng_off[3] - c3;
+    const uint32_t tbytes = (uint32_t)(a.trace_stride * sizeof(cx<T>));
     for (int c0 = 0; c0 < nin; c0 += KC) {
         const int kc = min(KC, nin - c0);
-        for (int e = tid; e < KC; e += NT) {   // trace-pool offset of each input of the chunk
-            long long off = -1;
-            if (e < kc) {
-                int rg = 0, o = c0 + e;
-                while (o >= it.rng_len[rg]) {
-                    o -= it.rng_len[rg];
-                    ++rg;
-                }
-                off = it.rng_off[rg] + o;
+        {
+            const int e = lane, ie = c0 + e;
+            const long long off = (ie < c1 ? d0 : ie < c2 ? d1 : ie < c3 ? d2 : d3) + ie;
+            cx<T> g[GJ];
+#pragma unroll
+            for (int j = 0; j < GJ; ++j) {
+                const int r = wv + 4 * j;   // the same for the whole wave
+                const __amdgpu_buffer_rsrc_t tr = make_rsrc(
+                    reinterpret_cast<const cx<T>*>(a.traces) + (size_t)(rhs0 + (r < nr ? r : 0)) * a.trace_stride, tbytes);
+                g[j] = bload<T>(tr, (r < nr && e < kc) ? (uint32_t)(off * (long long)sizeof(cx<T>)) : kOob);
             }
-            sOff[e] = off;
-        }
-        __syncthreads();
-        for (int q = tid; q < KC * R; q += NT) {   // consecutive lanes: consecutive inputs of one rhs
-            const int r = q / KC, e = q - r * KC;
-            cx<T> v{T(0), T(0)};
-            if (r < nr && sOff[e] >= 0) v = trg[(size_t)r * a.trace_stride + sOff[e]];
-            sUr[e][r] = v.re;
-            sUi[e][r] = v.im;
+#pragma unroll
+            for (int j = 0; j < GJ; ++j) {
+                sUr[e][wv + 4 * j] = g[j].re;
+                sUi[e][wv + 4 * j] = g[j].im;
+            }
         }
         __syncthreads();
         // 16 inputs per round: the four Q' loads are issued before their products
