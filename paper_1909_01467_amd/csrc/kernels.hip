@@ -1285,8 +1285,8 @@ __global__ void k_pmap(const GemvSolve* gsv, int max_nin, const SubDesc* subs, G
 // work item of the level is one workgroup computing up to 64 outgoing trace values
 // out = Q'_s[rows, :] u~ (one per lane, the waves splitting the input entries) for every
 // right-hand side.  Levels are separate launches, so every trace an item reads or updates was
-// completed by an earlier launch.  The Q' loads depend only on the work item and start at
-// once, next to the gather of u~.  Right-hand sides go in chunks of four through every
+// completed by an earlier launch.  The first chunk's gather of u~ and the Q' loads depend only
+// on the work item and are all issued at once, the gather first.  Right-hand sides go in chunks of four through every
 // loaded Q' batch, and the Q' share of a wave stays in registers across the chunks when it
 // fits, so a batch of sources reads Q' about nrhs/4 times.
 template <typename T, int RC>   // RC: right-hand sides per pass over Q'
