@@ -533,6 +533,61 @@ int fail(lsw_plan* p, int code, const std::string& msg) {
     return code;
 }
 
+// Chained sweep mode (3D, and 2D with sweep_mode = chain): the sweep solves of the fronts above
+// regrouped by data flow, as compress_schedule groups the compressed sweeps.  A solve waits for the
+// last writer of every trace it reads or updates (stage 1 writes first), so independent sweeps of
+// Alg. Scenario3 share a front: the first diagonal fronts run beside the last cardinal ones (7 fronts
+// instead of 9 at q = r = 4).  Solves of one level touch disjoint traces, z parts and slots.  If a
+// trace were written after a solve read it, the front order is kept.
+void dataflow_fronts(lsw_plan* p) {
+    if (p->fronts.size() <= 2) return;
+    const Front f0 = p->fronts[0];
+    std::vector<SolveDesc> sweeps;   // in the front order
+    for (size_t fi = 1; fi < p->fronts.size(); ++fi)
+        for (int n = 0; n < p->fronts[fi].count; ++n) sweeps.push_back(p->descs[p->fronts[fi].offset + n]);
+    std::map<long long, int> last_writer;   // trace offset -> level of its last writer (stage 1: level 0)
+    std::set<long long> read;
+    for (int n = 0; n < f0.count; ++n) {
+        const SolveDesc& d = p->descs[f0.offset + n];
+        for (int o = 0; o < d.nout; ++o) last_writer[d.out_off[o]] = 0;
+    }
+    std::vector<int> level(sweeps.size(), 1);
+    for (size_t k = 0; k < sweeps.size(); ++k) {
+        const SolveDesc& d = sweeps[k];
+        int lv = 1;
+        auto dep = [&](long long off) {
+            const auto w = last_writer.find(off);
+            if (w != last_writer.end()) lv = std::max(lv, w->second + 1);
+        };
+        for (long long off : {d.in_h, d.in_v})
+            if (off >= 0) {
+                dep(off);
+                read.insert(off);
+            }
+        for (int o = 0; o < d.nout; ++o) {
+            if (read.count(d.out_off[o])) return;
+            dep(d.out_off[o]);
+        }
+        for (int o = 0; o < d.nout; ++o) last_writer[d.out_off[o]] = lv;
+        level[k] = lv;
+    }
+    const int depth = *std::max_element(level.begin(), level.end());
+    std::vector<SolveDesc> descs(p->descs.begin() + f0.offset, p->descs.begin() + f0.offset + f0.count);
+    std::vector<Front> fronts{Front{0, 0, f0.count, 0, 0}};
+    p->max_front = f0.count;
+    for (int lv = 1; lv <= depth; ++lv) {
+        const int start = (int)descs.size();
+        for (size_t k = 0; k < sweeps.size(); ++k)
+            if (level[k] == lv) descs.push_back(sweeps[k]);
+        const int count = (int)descs.size() - start;
+        if (count == 0) continue;
+        fronts.push_back(Front{0, start, count, 0, 0});
+        p->max_front = std::max(p->max_front, count);
+    }
+    p->descs = descs;
+    p->fronts = fronts;
+}
+
 // Trace-compressed schedule: stage 1 as block substitutions (traces only), all sweep fronts as
 // one dataflow launch of GEMV work items with Q', and a final block substitution per window.
 int compress_schedule(lsw_plan* p) {
@@ -1570,7 +1625,10 @@ int setup_impl(lsw_plan* p, const double* d_m, double omega, double h, const lsw
         const int rc0 = compress_schedule(p);
         if (rc0 != LSW_OK) return rc0;
     }
-    else p->Q_elems = 0;
+    else {
+        p->Q_elems = 0;
+        dataflow_fronts(p);
+    }
     // packed symmetric factors where the substitution kernel's registers allow (LSW_SYMMETRIC_FACTORS=0
     // keeps the full blocks)
     {
