@@ -98,10 +98,11 @@ def kernel_source_sha(path: str, name: str):
     return None
 
 
-def counter_traffic(kernel: str, workload: str):
+def counter_traffic(kernel: str, workload: str, algorithmic_bytes_per_launch: float | None = None):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary of the
-    workload (scaled FETCH_SIZE + WRITE_SIZE), or None when there is none or the kernel's source
-    changed since the counters were taken."""
+    workload (scaled FETCH_SIZE + WRITE_SIZE), or None when there is none, when the kernel's source
+    changed since the counters were taken, or when the summary records another amount of work per
+    launch than this run's algorithmic bytes (a schedule that launches the kernel differently)."""
     path = os.path.join(ROOT, "profiles", f"{workload}_mixed_hbm_traffic.txt")
     csrc = os.path.join(ROOT, "paper_1909_01467_amd", "csrc")
     try:
@@ -113,6 +114,11 @@ def counter_traffic(kernel: str, workload: str):
     sha = kernel_source_sha(os.path.join(csrc, "kernels3d.hip" if workload.endswith("3d") else "kernels.hip"), base)
     if sha is None or f"{base} source sha256[:16] = {sha}" not in text:
         return None
+    if algorithmic_bytes_per_launch is not None:
+        recorded = [float(l.split()[2]) for l in text.splitlines()
+                    if len(l.split()) == 3 and l.split()[0] == "algorithmic" and l.split()[1] == kernel]
+        if not recorded or abs(recorded[0] - algorithmic_bytes_per_launch) > 0.01 * recorded[0]:
+            return None
     for line in text.splitlines():
         parts = line.split()
         if len(parts) == 3 and parts[0] == "traffic" and parts[1] == kernel:
@@ -390,7 +396,7 @@ def main():
             "peak": FP32_MATRIX_PEAK_TFLOPS if mfma else HBM_PEAK_GBS,
             "unit": "TFLOP/s" if mfma else "GB/s",
             "frac": round(achieved / (FP32_MATRIX_PEAK_TFLOPS if mfma else HBM_PEAK_GBS), 4),
-            "traffic": (counter_traffic(dom_name, args.workload)
+            "traffic": (counter_traffic(dom_name, args.workload, dom["bytes_per_launch"])
                         if not args.windows and not args.all_sources else None),
             "algorithmic_bytes_per_launch": round(dom["bytes_per_launch"]),
             "avg_launch_ms": round(dom["avg_launch_ms"], 5),
