@@ -125,8 +125,8 @@ struct SubDesc {
 __host__ __device__ inline int tile_nt(int W) { return (W + 3) / 4; }
 __host__ __device__ inline int tile_count(int W) { return tile_nt(W) * (tile_nt(W) + 1) / 2; }
 __host__ __device__ inline long long sym_block(int W) { return 16LL * tile_count(W); }
-// row stride of the per-tile-column partial sums in the substitution kernel (4 mod 16 entries)
-__host__ __device__ inline int sym_cstride(int W) { return 4 * tile_nt(W) + ((4 - 4 * tile_nt(W)) % 16 + 16) % 16; }
+// row stride of the per-tile-column partial sums in the substitution kernel (10 mod 16 entries)
+__host__ __device__ inline int sym_cstride(int W) { return 4 * tile_nt(W) + ((10 - 4 * tile_nt(W)) % 16 + 16) % 16; }
 // largest nt whose upper triangle has at most `tiles` tiles
 __host__ __device__ constexpr int sym_nt_max(int tiles) {
     int nt = 0;

@@ -788,8 +788,9 @@ __global__ __launch_bounds__(NT) void k_chain_sym(ChainArgs a) {
     const SubDesc s = a.subs[dref.sub];
     const int rhs = blockIdx.y;
     const int W = s.W, H = s.H, m = s.mid, tid = threadIdx.x;
-    // c rows are Wp apart, Wp = 4 (mod 16) entries: the 4 row sums of consecutive tiles (J, J+1,
-    // ...) land in different LDS banks
+    // c rows are Wp apart, Wp = 10 (mod 16) entries (80 bytes mod 128 in complex64): the 16-byte
+    // row-sum writes of eight consecutive tiles (J, J+1, ...) cover all LDS banks, and the RS lanes
+    // of a row read rows of c 80 bytes apart in the reduction
     const int nt = tile_nt(W), Wp = sym_cstride(W), NTL = tile_count(W);
     const uint32_t BSb = (uint32_t)sym_block(W) * (uint32_t)sizeof(cx<T>);   // bytes per block
     // the reduction of row t: lanes RS t .. RS t + RS-1; the first of them owns the row
