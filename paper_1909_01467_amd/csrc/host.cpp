@@ -124,6 +124,7 @@ struct lsw_plan {
     c128* d_Z = nullptr;
     c128* d_w = nullptr;
     c128* d_partial = nullptr;
+    c128* d_npart = nullptr;        // [nrhs][gsblk] norm partials while d_partial holds dot-product partials
     c128* d_hbuf = nullptr;
     c128* d_coef = nullptr;
     c128* d_tmp1 = nullptr;
@@ -965,6 +966,9 @@ int solve_impl(lsw_plan* p, const c128* d_b, c128* d_x, int nrhs, lsw_info_t* in
             applies++;
             if ((rc2 = matvec_impl(p, Zk, p->d_w, nullptr, nrhs)) != LSW_OK) return rc2;
             const bool fused = gs3 && k + 1 <= kFusedGsMax;
+            // Every form leaves the workgroup partials of ||w||^2 (after the second pass) in d_npart; the
+            // scaling of v_{k+1} sums them itself and stores the norm into the column.
+            c128* nrm = p->d_hbuf + 2 * (m + 1);
             if (fused) {
                 // the same two passes in three sweeps over V: the dots of pass 1 reading w once, the
                 // update of pass 1 fused with the dots of pass 2, the update of pass 2 with ||w||^2
@@ -976,19 +980,31 @@ int solve_impl(lsw_plan* p, const c128* d_b, c128* d_x, int nrhs, lsw_info_t* in
                           nullptr};
                 DotsArgs d2{V, vl, N, p->d_w, N, p->N, k + 1, p->nblk, p->d_partial, h2, HS, 0};
                 HIPCK(p, launch_gs_dots(g1, d2, nrhs, p->stream));
-                if ((rc2 = gs_impl(p, V, vl, h2, HS, p->d_w, k + 1, -1, nrhs, p->d_hbuf + 2 * (m + 1), HS)) != LSW_OK)
-                    return rc2;
+                GsArgs g2{V, vl, p->N, h2, HS, p->d_w, p->N, p->N, k + 1, -1, p->d_active, p->gsblk, nullptr, HS,
+                          p->d_npart};
+                HIPCK(p, launch_gs_update(g2, nrhs, p->stream));
             }
             for (int pass = 0; pass < 2 && !fused; ++pass) {
                 c128* hcoef = p->d_hbuf + pass * (m + 1);
+                c128* npart = pass == 1 ? p->d_npart : nullptr;
+                if (k + 1 <= kGsFinishMax) {
+                    // the update sums the coefficients from the dot products' partials itself (and stores
+                    // them in the column): no finishing launch between the two
+                    DotsArgs d{V, vl, N, p->d_w, N, p->N, k + 1, p->nblk, p->d_partial, hcoef, HS, 0};
+                    HIPCK(p, launch_dots_partial(d, nrhs, p->stream));
+                    GsArgs g{V, vl, p->N, nullptr, HS, p->d_w, p->N, p->N, k + 1, -1, p->d_active, p->gsblk,
+                             nullptr, HS, npart, p->d_partial, p->nblk, hcoef, HS, 0};
+                    HIPCK(p, launch_gs_update(g, nrhs, p->stream));
+                    continue;
+                }
                 if ((rc2 = dots_impl(p, V, vl, N, p->d_w, N, k + 1, nrhs, hcoef, HS)) != LSW_OK) return rc2;
-                if ((rc2 = gs_impl(p, V, vl, hcoef, HS, p->d_w, k + 1, -1, nrhs,
-                                   pass == 1 ? p->d_hbuf + 2 * (m + 1) : nullptr, HS)) != LSW_OK)
-                    return rc2;
+                GsArgs g{V, vl, p->N, hcoef, HS, p->d_w, p->N, p->N, k + 1, -1, p->d_active, p->gsblk, nullptr, HS,
+                         npart};
+                HIPCK(p, launch_gs_update(g, nrhs, p->stream));
             }
             // (v_{k+1} is unused if every right-hand side stops here; V has room for m + 1 vectors)
-            HIPCK(p, launch_scale(p->d_w, V + (size_t)(k + 1) * vl, p->d_hbuf + 2 * (m + 1), HS, p->d_active, N, N,
-                                  N, nrhs, p->stream));
+            HIPCK(p, launch_scale_partials(p->d_w, V + (size_t)(k + 1) * vl, p->d_npart, p->gsblk, nrm, HS,
+                                           p->d_active, N, N, N, nrhs, p->stream));
             HIPCK(p, hipMemcpyAsync(p->h_hbuf + (size_t)(k & 1) * nrhs * HS, p->d_hbuf, sizeof(c128) * HS * nrhs,
                                     hipMemcpyDeviceToHost, p->stream));
             HIPCK(p, hipEventRecord(p->ev_step[k & 1], p->stream));
@@ -1782,6 +1798,7 @@ int setup_impl(lsw_plan* p, const double* d_m, double omega, double h, const lsw
     p->gsblk = (int)std::min<size_t>(1024, (p->N + 255) / 256);
     if ((rc = dalloc(p, &p->d_partial, (size_t)nr * std::max<size_t>((size_t)(m + 1) * p->nblk, p->gsblk))) != LSW_OK)
         return rc;
+    if ((rc = dalloc(p, &p->d_npart, (size_t)nr * p->gsblk)) != LSW_OK) return rc;
     if ((rc = dalloc(p, &p->d_hbuf, (size_t)nr * HS)) != LSW_OK) return rc;
     if ((rc = dalloc(p, &p->d_coef, (size_t)nr * m)) != LSW_OK) return rc;
     if ((rc = dalloc(p, &p->d_active, (size_t)nr)) != LSW_OK) return rc;

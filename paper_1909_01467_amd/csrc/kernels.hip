@@ -1467,8 +1467,9 @@ __global__ void k_matvec(MatvecArgs a) {
 }
 
 // ------------------------------------------------------------------ K7: Krylov BLAS (FP64)
-// Reductions are two launches: workgroup partials, then one workgroup per sum adds them in a fixed
-// order (a device-wide completion count would need an L2 write-back per workgroup on this chip).
+// Reductions are two launches: workgroup partials, then one wave per sum adds them in a fixed order
+// (a device-wide completion count would need an L2 write-back per workgroup on this chip); the
+// Gram-Schmidt update can instead sum its own coefficients in every workgroup, in the same order.
 __device__ inline c128 block_sum(c128 acc, c128* red) {
     red[threadIdx.x] = acc;
     __syncthreads();
@@ -1492,14 +1493,35 @@ __global__ void k_dots_partial(DotsArgs a) {
     if (threadIdx.x == 0) a.partial[((size_t)rhs * a.nv + l) * gridDim.x + blk] = part;
 }
 
-// out[rhs * ostride + l] (+)= sum_blk partial ; one workgroup per (l, rhs), fixed order
-__global__ void k_dots_finish(const c128* partial, int nblk, int nv, c128* out, int ostride, int accumulate) {
-    __shared__ c128 red[256];
-    const int l = blockIdx.x, rhs = blockIdx.y;
-    const c128* pp = partial + ((size_t)rhs * nv + l) * nblk;
+// pp[0] + ... + pp[n - 1] by one whole wave in a fixed order: lane i adds pp[i], pp[i + 64], ... in
+// turn (four loads issued together per pass), then an xor butterfly over the 64 lanes, after which
+// every lane holds the same bits (each level adds the same two values in either order)
+__device__ inline c128 wave_finish(const c128* pp, int n, int lane) {
     c128 acc = mk(0.0, 0.0);
-    for (int b = threadIdx.x; b < nblk; b += blockDim.x) acc = acc + pp[b];
-    const c128 sum = block_sum(acc, red);
+    for (int b0 = 0; b0 < n; b0 += 256) {
+        c128 v[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int b = b0 + lane + 64 * j;
+            const c128 x = pp[min(b, n - 1)];
+            v[j] = b < n ? x : mk(0.0, 0.0);
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc = acc + v[j];
+    }
+#pragma unroll
+    for (int m = 32; m > 0; m >>= 1) {
+        acc.re += __shfl_xor(acc.re, m);
+        acc.im += __shfl_xor(acc.im, m);
+    }
+    return acc;
+}
+
+// out[rhs * ostride + l] (+)= sum_blk partial ; one wave per (l, rhs), the order of wave_finish
+__global__ __launch_bounds__(64) void k_dots_finish(const c128* partial, int nblk, int nv, c128* out, int ostride,
+                                                    int accumulate) {
+    const int l = blockIdx.x, rhs = blockIdx.y;
+    const c128 sum = wave_finish(partial + ((size_t)rhs * nv + l) * nblk, nblk, threadIdx.x);
     if (threadIdx.x == 0) {
         c128* o = out + (size_t)rhs * ostride + l;
         *o = accumulate ? *o + sum : sum;
@@ -1507,13 +1529,36 @@ __global__ void k_dots_finish(const c128* partial, int nblk, int nv, c128* out, 
 }
 
 // w -= sum_l V_l c_l (c = coefficients on the device, [rhs * cstride + l]; masked rhs skipped); with
-// partial, also the workgroup partials of ||w||^2 after the update, partial[rhs * nblk + blk]
-__global__ void k_gs_update(GsArgs a) {
+// partial, also the workgroup partials of ||w||^2 after the update, partial[rhs * nblk + blk].
+// FIN: the coefficients are first summed from the dot products' workgroup partials
+// (a.cpart[(rhs * nv + l) * cnblk + b]) by the waves of every workgroup, as k_dots_finish sums them,
+// into LDS; workgroup 0 also stores them (out[rhs * costride + l], added when caccum), so that the
+// dot products need no finishing launch of their own.
+template <bool FIN>
+__global__ __launch_bounds__(256) void k_gs_update(GsArgs a) {
     __shared__ c128 red[256];
+    __shared__ c128 cl[FIN ? kGsFinishMax : 1];
     const int rhs = blockIdx.y;
     const bool on = !(a.active && !a.active[rhs]);
+    const c128* cf;
+    if constexpr (FIN) {
+        const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+        for (int l = wv; l < a.nv; l += 4) {
+            const c128 s = wave_finish(a.cpart + ((size_t)rhs * a.nv + l) * a.cnblk, a.cnblk, lane);
+            if (lane == 0) {
+                cl[l] = s;
+                if (blockIdx.x == 0) {
+                    c128* o = a.cout + (size_t)rhs * a.costride + l;
+                    *o = a.caccum ? *o + s : s;
+                }
+            }
+        }
+        __syncthreads();
+        cf = cl;
+    } else {
+        cf = a.coef + (size_t)rhs * a.cstride;
+    }
     if (!on && !a.partial) return;
-    const c128* cf = a.coef + (size_t)rhs * a.cstride;
     c128* w = a.w + (size_t)rhs * a.wstride;
     c128 nacc = mk(0.0, 0.0);
     for (size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x; p < a.N; p += (size_t)gridDim.x * blockDim.x) {
@@ -1606,13 +1651,31 @@ __global__ __launch_bounds__(256) void k_gs_dots(GsArgs g, DotsArgs d) {
     }
 }
 
-// dst = src / sqrt(nrm2[rhs * nstride].re) (0 if the norm is 0), masked rhs skipped
-__global__ void k_scale(const c128* src, c128* dst, const c128* nrm2, int nstride, const int* active, size_t N,
-                        size_t sstride, size_t dstride) {
+// dst = src / sqrt(nrm2[rhs * nstride].re) (0 if the norm is 0), masked rhs skipped.  FIN: the squared
+// norm is first summed from the update's workgroup partials npart[rhs * nnblk + b] by one wave of
+// every workgroup, as k_dots_finish sums them; workgroup 0 stores it to nrm2[rhs * nstride].
+template <bool FIN>
+__global__ __launch_bounds__(256) void k_scale(const c128* src, c128* dst, c128* nrm2, int nstride, const int* active,
+                                               size_t N, size_t sstride, size_t dstride, const c128* npart,
+                                               int nnblk) {
     const size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int rhs = blockIdx.y;
+    double n2 = 0.0;
+    if constexpr (FIN) {
+        __shared__ double sh;
+        if (threadIdx.x < 64) {   // one whole wave
+            const c128 s = wave_finish(npart + (size_t)rhs * nnblk, nnblk, threadIdx.x);
+            if (threadIdx.x == 0) {
+                sh = s.re;
+                if (blockIdx.x == 0) nrm2[(size_t)rhs * nstride] = s;
+            }
+        }
+        __syncthreads();
+        n2 = sh;
+    }
     if (p >= N || (active && !active[rhs])) return;
-    const double nr = sqrt(fmax(0.0, nrm2[(size_t)rhs * nstride].re));
+    if constexpr (!FIN) n2 = nrm2[(size_t)rhs * nstride].re;
+    const double nr = sqrt(fmax(0.0, n2));
     const double s = nr > 0 ? 1.0 / nr : 0.0;
     const c128 v = src[(size_t)rhs * sstride + p];
     dst[(size_t)rhs * dstride + p] = mk(s * v.re, s * v.im);
@@ -2336,7 +2399,12 @@ hipError_t launch_matvec(const MatvecArgs& a, int nrhs, hipStream_t st) {
 
 hipError_t launch_dots(const DotsArgs& a, int nrhs, hipStream_t st) {
     k_dots_partial<<<dim3(a.nblk, a.nv, nrhs), 256, 0, st>>>(a);
-    k_dots_finish<<<dim3(a.nv, nrhs), 256, 0, st>>>(a.partial, a.nblk, a.nv, a.out, a.ostride, a.accumulate);
+    k_dots_finish<<<dim3(a.nv, nrhs), 64, 0, st>>>(a.partial, a.nblk, a.nv, a.out, a.ostride, a.accumulate);
+    return hipGetLastError();
+}
+
+hipError_t launch_dots_partial(const DotsArgs& a, int nrhs, hipStream_t st) {
+    k_dots_partial<<<dim3(a.nblk, a.nv, nrhs), 256, 0, st>>>(a);
     return hipGetLastError();
 }
 
@@ -2353,7 +2421,7 @@ static bool with_lc(int nv, F f) {
 hipError_t launch_dots_w(const DotsArgs& a, int nrhs, hipStream_t st) {
     if (!with_lc(a.nv, [&](auto lc) { k_dots_w<decltype(lc)::value><<<dim3(a.nblk, nrhs), 256, 0, st>>>(a); }))
         return hipErrorInvalidValue;
-    k_dots_finish<<<dim3(a.nv, nrhs), 256, 0, st>>>(a.partial, a.nblk, a.nv, a.out, a.ostride, a.accumulate);
+    k_dots_finish<<<dim3(a.nv, nrhs), 64, 0, st>>>(a.partial, a.nblk, a.nv, a.out, a.ostride, a.accumulate);
     return hipGetLastError();
 }
 
@@ -2361,20 +2429,38 @@ hipError_t launch_gs_dots(const GsArgs& g, const DotsArgs& d, int nrhs, hipStrea
     if (g.nv != d.nv) return hipErrorInvalidValue;
     if (!with_lc(d.nv, [&](auto lc) { k_gs_dots<decltype(lc)::value><<<dim3(d.nblk, nrhs), 256, 0, st>>>(g, d); }))
         return hipErrorInvalidValue;
-    k_dots_finish<<<dim3(d.nv, nrhs), 256, 0, st>>>(d.partial, d.nblk, d.nv, d.out, d.ostride, d.accumulate);
+    k_dots_finish<<<dim3(d.nv, nrhs), 64, 0, st>>>(d.partial, d.nblk, d.nv, d.out, d.ostride, d.accumulate);
     return hipGetLastError();
 }
 
 hipError_t launch_gs_update(const GsArgs& a, int nrhs, hipStream_t st) {
-    k_gs_update<<<dim3(a.nblk, nrhs), 256, 0, st>>>(a);
-    if (a.partial) k_dots_finish<<<dim3(1, nrhs), 256, 0, st>>>(a.partial, a.nblk, 1, a.norm_out, a.nstride, 0);
+    if (a.partial && !a.norm_out && a.nblk > kScaleFinishMax) return hipErrorInvalidValue;
+    if (a.cpart) {
+        // the norm's partials must not share memory with the coefficients' partials read by the launch
+        if (a.nv > kGsFinishMax || a.partial == a.cpart) return hipErrorInvalidValue;
+        k_gs_update<true><<<dim3(a.nblk, nrhs), 256, 0, st>>>(a);
+    } else {
+        k_gs_update<false><<<dim3(a.nblk, nrhs), 256, 0, st>>>(a);
+    }
+    if (a.partial && a.norm_out)
+        k_dots_finish<<<dim3(1, nrhs), 64, 0, st>>>(a.partial, a.nblk, 1, a.norm_out, a.nstride, 0);
     return hipGetLastError();
 }
 
 hipError_t launch_scale(const c128* src, c128* dst, const c128* nrm2, int nstride, const int* active, size_t N,
                         size_t sstride, size_t dstride, int nrhs, hipStream_t st) {
     dim3 grid(blocks_for(N, 256), nrhs);
-    k_scale<<<grid, 256, 0, st>>>(src, dst, nrm2, nstride, active, N, sstride, dstride);
+    k_scale<false><<<grid, 256, 0, st>>>(src, dst, const_cast<c128*>(nrm2), nstride, active, N, sstride, dstride,
+                                         nullptr, 0);
+    return hipGetLastError();
+}
+
+hipError_t launch_scale_partials(const c128* src, c128* dst, const c128* npart, int nnblk, c128* nrm2, int nstride,
+                                 const int* active, size_t N, size_t sstride, size_t dstride, int nrhs,
+                                 hipStream_t st) {
+    if (nnblk < 1 || nnblk > kScaleFinishMax) return hipErrorInvalidValue;
+    dim3 grid(blocks_for(N, 256), nrhs);
+    k_scale<true><<<grid, 256, 0, st>>>(src, dst, nrm2, nstride, active, N, sstride, dstride, npart, nnblk);
     return hipGetLastError();
 }
 

@@ -81,10 +81,20 @@ struct GsArgs {
     int sign;          // -1: w -= V c ; +1: w += V c
     const int* active; // optional per-rhs mask
     int nblk;          // workgroups per rhs (grid-stride over the points)
-    c128* norm_out;    // with partial: ||w||^2 after the update into norm_out[rhs * nstride]
+    c128* norm_out;    // with partial: ||w||^2 after the update into norm_out[rhs * nstride] (null: the
+                       // partials are left for launch_scale_partials)
     int nstride;
     c128* partial;     // optional [nrhs][nblk] workgroup partials of the norm
+    // optional: the coefficients as unfinished dot products, cpart[(rhs * nv + l) * cnblk + b] (the
+    // partials of launch_dots_partial; coef unused), stored once finished to cout[rhs * costride + l]
+    // (added to it when caccum); nv <= kGsFinishMax, and partial must be another buffer
+    const c128* cpart;
+    int cnblk;
+    c128* cout;
+    int costride;
+    int caccum;
 };
+constexpr int kGsFinishMax = 64;
 
 // ept = max over the launched windows of ceil(W / floor(1024 / W)) (elements per thread)
 // Two launches (forward halves, then middle + backward halves) of 2 workgroups per solve.
@@ -155,7 +165,10 @@ hipError_t launch_zsum(const ZsumArgs& a, int nrhs, bool c64mode, hipStream_t st
 hipError_t launch_matvec(const MatvecArgs& a, int nrhs, hipStream_t st);
 // out[rhs * ostride + l] (+)= <V_l, w> for l < nv (workgroup partials, then a fixed-order sum)
 hipError_t launch_dots(const DotsArgs& a, int nrhs, hipStream_t st);
-// w -= V c (or +=), optionally followed by ||w||^2 (same point order as launch_dots)
+// only the workgroup partials of launch_dots (for launch_gs_update with GsArgs::cpart)
+hipError_t launch_dots_partial(const DotsArgs& a, int nrhs, hipStream_t st);
+// w -= V c (or +=), optionally followed by ||w||^2 (same point order as launch_dots); with
+// GsArgs::cpart, c is first summed from the dot products' partials (bitwise what launch_dots gives)
 hipError_t launch_gs_update(const GsArgs& a, int nrhs, hipStream_t st);
 // the one-pass forms for nv <= kFusedGsMax columns (hipErrorInvalidValue above): launch_dots_w is
 // launch_dots reading w once; launch_gs_dots is launch_gs_update without the norm followed by
@@ -166,6 +179,13 @@ hipError_t launch_gs_dots(const GsArgs& g, const DotsArgs& d, int nrhs, hipStrea
 // dst = src / ||.|| with the squared norm read from nrm2[rhs * nstride] on the device
 hipError_t launch_scale(const c128* src, c128* dst, const c128* nrm2, int nstride, const int* active, size_t N,
                         size_t sstride, size_t dstride, int nrhs, hipStream_t st);
+// the same with the squared norm summed from the nnblk <= kScaleFinishMax workgroup partials
+// npart[rhs * nnblk + b] of launch_gs_update (GsArgs::partial set, norm_out null) and stored to
+// nrm2[rhs * nstride]: bitwise what launch_gs_update's own norm gives, one launch fewer
+constexpr int kScaleFinishMax = 1024;
+hipError_t launch_scale_partials(const c128* src, c128* dst, const c128* npart, int nnblk, c128* nrm2, int nstride,
+                                 const int* active, size_t N, size_t sstride, size_t dstride, int nrhs,
+                                 hipStream_t st);
 hipError_t launch_conj(const c128* src, c128* dst, size_t n, hipStream_t st);
 // zeros bytes / 16 16-byte words at p (16-byte aligned)
 hipError_t launch_zero16(void* p, size_t bytes, hipStream_t st);
