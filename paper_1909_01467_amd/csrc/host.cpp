@@ -89,6 +89,7 @@ struct lsw_plan {
     double rgroup_ms[5] = {0, 0, 0, 0, 0};   // timings of R = 1, 2, 4, 16, 32 when tuned
     bool gemv_mma = false;                    // sweep levels of several right-hand sides on matrix cores
     int gs_fused = -1;                        // Gram-Schmidt in three sweeps over V: 1, four: 0, by size: -1
+    int gs_finish_max = kGsFinishMax;         // four sweeps: the update sums its coefficients up to this many
     double gemv_ms[2] = {0, 0};               // setup timings of the sweep levels: k_gemv, k_gemv_mma
     int* d_frp = nullptr;           // final right-hand side: polarization terms per window point
     long long* d_fpool = nullptr;
@@ -987,7 +988,7 @@ int solve_impl(lsw_plan* p, const c128* d_b, c128* d_x, int nrhs, lsw_info_t* in
             for (int pass = 0; pass < 2 && !fused; ++pass) {
                 c128* hcoef = p->d_hbuf + pass * (m + 1);
                 c128* npart = pass == 1 ? p->d_npart : nullptr;
-                if (k + 1 <= kGsFinishMax) {
+                if (k + 1 <= p->gs_finish_max) {
                     // the update sums the coefficients from the dot products' partials itself (and stores
                     // them in the column): no finishing launch between the two
                     DotsArgs d{V, vl, N, p->d_w, N, p->N, k + 1, p->nblk, p->d_partial, hcoef, HS, 0};
@@ -1507,6 +1508,8 @@ int setup_impl(lsw_plan* p, const double* d_m, double omega, double h, const lsw
         if (own_sx < 0 || own_sy < 0) return fail(p, LSW_EINVAL, "cdd.shift must be >= 0");
     }
     if (const char* env = std::getenv("LSW_FUSED_GS")) p->gs_fused = std::atoi(env) != 0 ? 1 : 0;
+    if (const char* env = std::getenv("LSW_GS_FINISH_MAX"))
+        p->gs_finish_max = std::clamp(std::atoi(env), 0, kGsFinishMax);
     p->omega = omega;
     p->h = h;
     p->C = (pml && pml->C > 0) ? pml->C : 16.0 * std::log(omega);

@@ -245,6 +245,36 @@ def test_gram_schmidt_in_three_sweeps_equals_four(monkeypatch, precision):
         assert rel(out["1"][0][0], res.x) < 1e-8
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_gram_schmidt_update_sums_its_own_coefficients(monkeypatch, precision):
+    """The four-sweep Gram-Schmidt passes with the coefficients summed from the dot products'
+    workgroup partials inside the update (up to 64 basis vectors) against a finishing launch for
+    every sum (LSW_GS_FINISH_MAX=0, the form beyond 64 basis vectors): the same partials added in
+    the same order, so bitwise the same iterates (32 steps in one restart cycle)."""
+    c = CASES["no_pml"]
+    B = inputs.complex_normal((3, c.N), 7)
+    monkeypatch.setenv("LSW_SYM_CONFIG", "0" if precision == "mixed" else "7")
+    monkeypatch.setenv("LSW_RHS_PER_WORKGROUP", "1")
+    monkeypatch.setenv("LSW_GEMV_MMA", "0")
+    monkeypatch.setenv("LSW_FUSED_GS", "0")
+    out = {}
+    for mode in ("0", "64"):
+        monkeypatch.setenv("LSW_GS_FINISH_MAX", mode)
+        s = c.solver(tol=1e-10, restart=40, nrhs_max=3, precision=precision)
+        U, info = s.solve(torch.from_numpy(B).cuda())
+        out[mode] = (U.cpu().numpy(), info["iterations"])
+        s.close()
+    monkeypatch.delenv("LSW_GS_FINISH_MAX", raising=False)
+    say("gram-schmidt coefficients in the update", precision, "iterations", out["64"][1])
+    assert out["64"][1] == out["0"][1]
+    assert max(out["64"][1]) > 24
+    assert np.array_equal(out["64"][0], out["0"][0])
+    if precision == "fp64":
+        res = fgmres(lambda v: c.gp.A @ v, c.oracle.apply, B[0], tol=1e-10, restart=40)
+        assert out["64"][1][0] == res.iterations
+        assert rel(out["64"][0][0], res.x) < 1e-8
+
+
 def test_adjoint_solves_the_conjugate_transpose_system():
     c = CASES["ragged_45x38_3x2"]
     g = inputs.complex_normal(c.N, 8)
