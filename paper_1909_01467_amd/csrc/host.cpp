@@ -865,11 +865,10 @@ int dots_impl(lsw_plan* p, const c128* V, size_t vl, size_t vr, const c128* w, s
     return LSW_OK;
 }
 
-// w -= V c (sign -1) or += (sign +1) for nv columns; with norm, ||w||^2 after it into norm[rhs * nstride]
+// w -= V c (sign -1) or += (sign +1) for nv columns
 int gs_impl(lsw_plan* p, const c128* V, size_t vl, const c128* coef, int cstride, c128* w, int nv, int sign,
-            int nrhs, c128* norm, int nstride) {
-    GsArgs a{V, vl, p->N, coef, cstride, w, p->N, p->N, nv, sign, p->d_active, p->gsblk, norm, nstride,
-             norm ? p->d_partial : nullptr};
+            int nrhs) {
+    GsArgs a{V, vl, p->N, coef, cstride, w, p->N, p->N, nv, sign, p->d_active, p->gsblk, nullptr, 0, nullptr};
     HIPCK(p, launch_gs_update(a, nrhs, p->stream));
     return LSW_OK;
 }
@@ -1088,7 +1087,7 @@ int solve_impl(lsw_plan* p, const c128* d_b, c128* d_x, int nrhs, lsw_info_t* in
         if (kmax > 0) {
             HIPCK(p, hipMemcpyAsync(p->d_coef, p->h_coef, sizeof(c128) * m * nrhs, hipMemcpyHostToDevice, p->stream));
             if ((rc = sync_active(p, nrhs)) != LSW_OK) return rc;
-            if ((rc = gs_impl(p, Z, vl, p->d_coef, m, d_x, kmax, +1, nrhs, nullptr, 0)) != LSW_OK) return rc;
+            if ((rc = gs_impl(p, Z, vl, p->d_coef, m, d_x, kmax, +1, nrhs)) != LSW_OK) return rc;
         }
         bool any_left = false;
         for (int s = 0; s < nrhs; ++s) any_left |= (!conv[s] && its[s] < p->maxit);
