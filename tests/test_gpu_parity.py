@@ -275,6 +275,24 @@ def test_gram_schmidt_update_sums_its_own_coefficients(monkeypatch, precision):
         assert rel(out["64"][0][0], res.x) < 1e-8
 
 
+@pytest.mark.parametrize("restart", [2, 3])
+def test_restarted_fgmres_follows_the_oracle_across_cycles(restart):
+    """FGMRES(restart) over several restart cycles (the thin local PML case takes 7 iterations with
+    either restart, the oracle's as well) against the oracle's FGMRES with the same restart: the
+    same iteration count and solution, each cycle starting again from the true residual (FP64)."""
+    c = CASES["thin_local_pml"]
+    b = inputs.complex_normal(c.N, 9)
+    s = c.solver(tol=1e-10, restart=restart, maxit=100, precision="fp64")
+    u, info = s.solve(torch.from_numpy(b).cuda())
+    s.close()
+    res = fgmres(lambda v: c.gp.A @ v, c.oracle.apply, b, tol=1e-10, restart=restart, maxit=100)
+    say("restarted fgmres", restart, "iterations", info["iterations"], "oracle", res.iterations)
+    assert info["converged"] == [True] and res.converged
+    assert info["iterations"][0] > 2 * restart
+    assert info["iterations"][0] == res.iterations
+    assert rel(to_np(u), res.x) < 1e-8
+
+
 def test_adjoint_solves_the_conjugate_transpose_system():
     c = CASES["ragged_45x38_3x2"]
     g = inputs.complex_normal(c.N, 8)
