@@ -930,6 +930,9 @@ int solve_impl(lsw_plan* p, const c128* d_b, c128* d_x, int nrhs, lsw_info_t* in
     // four-sweep form: they pay once the batch holds a few million points (measured: 32 x 2077^2
     // gains 7% of the solve, one 531^2 vector loses 2.5%).
     const bool gs3 = p->gs_fused > 0 || (p->gs_fused < 0 && (double)N * nrhs >= 4.0e6);
+    // below that size the Krylov kernels are launch-bound, and their consumers finish the reductions
+    // themselves (every consumer workgroup re-reads the partials; above it a finishing launch is cheaper)
+    const bool fin_inline = (double)N * nrhs < 4.0e6;
     while (true) {
         // r = b - A x into V_0, beta = ||r||
         if ((rc = matvec_impl(p, d_x, V, d_b, nrhs)) != LSW_OK) return rc;
@@ -966,9 +969,11 @@ int solve_impl(lsw_plan* p, const c128* d_b, c128* d_x, int nrhs, lsw_info_t* in
             applies++;
             if ((rc2 = matvec_impl(p, Zk, p->d_w, nullptr, nrhs)) != LSW_OK) return rc2;
             const bool fused = gs3 && k + 1 <= kFusedGsMax;
-            // Every form leaves the workgroup partials of ||w||^2 (after the second pass) in d_npart; the
-            // scaling of v_{k+1} sums them itself and stores the norm into the column.
+            // Every form leaves the workgroup partials of ||w||^2 (after the second pass) in d_npart. With
+            // fin_inline the scaling of v_{k+1} sums them itself and stores the norm into the column;
+            // otherwise the update finishes the norm with a launch of its own.
             c128* nrm = p->d_hbuf + 2 * (m + 1);
+            c128* nrm_gs = fin_inline ? nullptr : nrm;
             if (fused) {
                 // the same two passes in three sweeps over V: the dots of pass 1 reading w once, the
                 // update of pass 1 fused with the dots of pass 2, the update of pass 2 with ||w||^2
@@ -980,31 +985,36 @@ int solve_impl(lsw_plan* p, const c128* d_b, c128* d_x, int nrhs, lsw_info_t* in
                           nullptr};
                 DotsArgs d2{V, vl, N, p->d_w, N, p->N, k + 1, p->nblk, p->d_partial, h2, HS, 0};
                 HIPCK(p, launch_gs_dots(g1, d2, nrhs, p->stream));
-                GsArgs g2{V, vl, p->N, h2, HS, p->d_w, p->N, p->N, k + 1, -1, p->d_active, p->gsblk, nullptr, HS,
+                GsArgs g2{V, vl, p->N, h2, HS, p->d_w, p->N, p->N, k + 1, -1, p->d_active, p->gsblk, nrm_gs, HS,
                           p->d_npart};
                 HIPCK(p, launch_gs_update(g2, nrhs, p->stream));
             }
             for (int pass = 0; pass < 2 && !fused; ++pass) {
                 c128* hcoef = p->d_hbuf + pass * (m + 1);
                 c128* npart = pass == 1 ? p->d_npart : nullptr;
-                if (k + 1 <= p->gs_finish_max) {
+                c128* nout = pass == 1 ? nrm_gs : nullptr;
+                if (fin_inline && k + 1 <= p->gs_finish_max) {
                     // the update sums the coefficients from the dot products' partials itself (and stores
                     // them in the column): no finishing launch between the two
                     DotsArgs d{V, vl, N, p->d_w, N, p->N, k + 1, p->nblk, p->d_partial, hcoef, HS, 0};
                     HIPCK(p, launch_dots_partial(d, nrhs, p->stream));
                     GsArgs g{V, vl, p->N, nullptr, HS, p->d_w, p->N, p->N, k + 1, -1, p->d_active, p->gsblk,
-                             nullptr, HS, npart, p->d_partial, p->nblk, hcoef, HS, 0};
+                             nout, HS, npart, p->d_partial, p->nblk, hcoef, HS, 0};
                     HIPCK(p, launch_gs_update(g, nrhs, p->stream));
                     continue;
                 }
                 if ((rc2 = dots_impl(p, V, vl, N, p->d_w, N, k + 1, nrhs, hcoef, HS)) != LSW_OK) return rc2;
-                GsArgs g{V, vl, p->N, hcoef, HS, p->d_w, p->N, p->N, k + 1, -1, p->d_active, p->gsblk, nullptr, HS,
+                GsArgs g{V, vl, p->N, hcoef, HS, p->d_w, p->N, p->N, k + 1, -1, p->d_active, p->gsblk, nout, HS,
                          npart};
                 HIPCK(p, launch_gs_update(g, nrhs, p->stream));
             }
             // (v_{k+1} is unused if every right-hand side stops here; V has room for m + 1 vectors)
-            HIPCK(p, launch_scale_partials(p->d_w, V + (size_t)(k + 1) * vl, p->d_npart, p->gsblk, nrm, HS,
-                                           p->d_active, N, N, N, nrhs, p->stream));
+            if (fin_inline)
+                HIPCK(p, launch_scale_partials(p->d_w, V + (size_t)(k + 1) * vl, p->d_npart, p->gsblk, nrm, HS,
+                                               p->d_active, N, N, N, nrhs, p->stream));
+            else
+                HIPCK(p, launch_scale(p->d_w, V + (size_t)(k + 1) * vl, nrm, HS, p->d_active, N, N, N, nrhs,
+                                      p->stream));
             HIPCK(p, hipMemcpyAsync(p->h_hbuf + (size_t)(k & 1) * nrhs * HS, p->d_hbuf, sizeof(c128) * HS * nrhs,
                                     hipMemcpyDeviceToHost, p->stream));
             HIPCK(p, hipEventRecord(p->ev_step[k & 1], p->stream));

@@ -1651,14 +1651,14 @@ __global__ __launch_bounds__(256) void k_gs_dots(GsArgs g, DotsArgs d) {
     }
 }
 
-// dst = src / sqrt(nrm2[rhs * nstride].re) (0 if the norm is 0), masked rhs skipped.  FIN: the squared
-// norm is first summed from the update's workgroup partials npart[rhs * nnblk + b] by one wave of
-// every workgroup, as k_dots_finish sums them; workgroup 0 stores it to nrm2[rhs * nstride].
+// dst = src / sqrt(nrm2[rhs * nstride].re) (0 if the norm is 0), masked rhs skipped, grid-stride over
+// the points.  FIN: the squared norm is first summed from the update's workgroup partials
+// npart[rhs * nnblk + b] by one wave of every workgroup, as k_dots_finish sums them; workgroup 0
+// stores it to nrm2[rhs * nstride].
 template <bool FIN>
 __global__ __launch_bounds__(256) void k_scale(const c128* src, c128* dst, c128* nrm2, int nstride, const int* active,
                                                size_t N, size_t sstride, size_t dstride, const c128* npart,
                                                int nnblk) {
-    const size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int rhs = blockIdx.y;
     double n2 = 0.0;
     if constexpr (FIN) {
@@ -1673,12 +1673,14 @@ __global__ __launch_bounds__(256) void k_scale(const c128* src, c128* dst, c128*
         __syncthreads();
         n2 = sh;
     }
-    if (p >= N || (active && !active[rhs])) return;
+    if (active && !active[rhs]) return;
     if constexpr (!FIN) n2 = nrm2[(size_t)rhs * nstride].re;
     const double nr = sqrt(fmax(0.0, n2));
     const double s = nr > 0 ? 1.0 / nr : 0.0;
-    const c128 v = src[(size_t)rhs * sstride + p];
-    dst[(size_t)rhs * dstride + p] = mk(s * v.re, s * v.im);
+    for (size_t p = (size_t)blockIdx.x * blockDim.x + threadIdx.x; p < N; p += (size_t)gridDim.x * blockDim.x) {
+        const c128 v = src[(size_t)rhs * sstride + p];
+        dst[(size_t)rhs * dstride + p] = mk(s * v.re, s * v.im);
+    }
 }
 
 // zero fill of n 16-byte words (a kernel rather than a memset node, so that a captured graph
@@ -2459,7 +2461,8 @@ hipError_t launch_scale_partials(const c128* src, c128* dst, const c128* npart, 
                                  const int* active, size_t N, size_t sstride, size_t dstride, int nrhs,
                                  hipStream_t st) {
     if (nnblk < 1 || nnblk > kScaleFinishMax) return hipErrorInvalidValue;
-    dim3 grid(blocks_for(N, 256), nrhs);
+    // at most 1024 workgroups per right-hand side, each summing the partials once
+    dim3 grid((unsigned)std::min<size_t>(blocks_for(N, 256), 1024), nrhs);
     k_scale<true><<<grid, 256, 0, st>>>(src, dst, nrm2, nstride, active, N, sstride, dstride, npart, nnblk);
     return hipGetLastError();
 }

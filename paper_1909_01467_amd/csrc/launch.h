@@ -181,7 +181,8 @@ hipError_t launch_scale(const c128* src, c128* dst, const c128* nrm2, int nstrid
                         size_t sstride, size_t dstride, int nrhs, hipStream_t st);
 // the same with the squared norm summed from the nnblk <= kScaleFinishMax workgroup partials
 // npart[rhs * nnblk + b] of launch_gs_update (GsArgs::partial set, norm_out null) and stored to
-// nrm2[rhs * nstride]: bitwise what launch_gs_update's own norm gives, one launch fewer
+// nrm2[rhs * nstride]: bitwise what launch_gs_update's own norm gives, one launch fewer (every
+// workgroup re-reads the partials, so it pays only where launches, not bytes, set the time)
 constexpr int kScaleFinishMax = 1024;
 hipError_t launch_scale_partials(const c128* src, c128* dst, const c128* npart, int nnblk, c128* nrm2, int nstride,
                                  const int* active, size_t N, size_t sstride, size_t dstride, int nrhs,
