@@ -1532,7 +1532,7 @@ __global__ __launch_bounds__(64) void k_dots_finish(const c128* partial, int nbl
 // partial, also the workgroup partials of ||w||^2 after the update, partial[rhs * nblk + blk].
 // FIN: the coefficients are first summed from the dot products' workgroup partials
 // (a.cpart[(rhs * nv + l) * cnblk + b]) by the waves of every workgroup, as k_dots_finish sums them,
-// into LDS; workgroup 0 also stores them (out[rhs * costride + l], added when caccum), so that the
+// into LDS; workgroup 0 also stores them (a.cout[rhs * costride + l], added when caccum), so that the
 // dot products need no finishing launch of their own.
 template <bool FIN>
 __global__ __launch_bounds__(256) void k_gs_update(GsArgs a) {
